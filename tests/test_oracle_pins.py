@@ -1,0 +1,394 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Every test here checks the oracle against something other than itself: closed forms,
+identities between independently computed matrices, a different algorithm (Lagrange), numpy's
+own routines, finite differences, or inequalities the optimisation must satisfy.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bopt, direct, grad, kb, lagrange, nfft
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b))
+
+
+# ------------------------------------------------------------------ window (Remark 2.1 reading)
+
+def test_i0_series_matches_numpy():
+    z = np.linspace(0.0, 60.0, 241)
+    assert np.max(np.abs(kb.i0_series(z) / np.i0(z) - 1)) < 1e-14
+
+
+def test_window_closed_form_values():
+    m, b = 6, kb.shape_b(2.0)
+    assert kb.window(np.array([0.0]), m, b)[0] == pytest.approx(np.sinh(b * m) / (np.pi * m), rel=1e-15)
+    # edge of the closed support: the limit b/pi; beyond it zero
+    assert kb.window(np.array([m, -m]), m, b) == pytest.approx([b / np.pi, b / np.pi], rel=1e-15)
+    assert np.all(kb.window(np.array([m + 1e-12, -m - 0.5, 7.0]), m, b) == 0)
+    v = np.linspace(-m, m, 101)
+    assert np.allclose(kb.window(v, m, b), kb.window(-v, m, b), rtol=0, atol=0)
+
+
+def test_window_derivative_matches_central_differences():
+    m, b = 4, kb.shape_b(2.0)
+    v = np.linspace(-m + 0.01, m - 0.01, 77)
+    h = 1e-6
+    fd = (kb.window(v + h, m, b) - kb.window(v - h, m, b)) / (2 * h)
+    an = kb.window_deriv(v, m, b)
+    assert np.max(np.abs(fd - an)) / np.max(np.abs(an)) < 1e-8
+    # near the edge the small-argument series takes over; check continuity across it
+    ve = m - np.array([1e-9, 1e-7, 1e-5, 1e-4])
+    fd = (kb.window(ve + 1e-11, m, b) - kb.window(ve - 1e-11, m, b)) / 2e-11
+    assert np.allclose(kb.window_deriv(ve, m, b), fd, rtol=1e-3)
+
+
+# ------------------------------------------------------------------ direct sums (1.1)-(1.3)
+
+@pytest.mark.parametrize("N,M", [(16, 16), (32, 8), (8, 32), (24, 48)])
+def test_equispaced_exact_inverse(N, M):
+    """Section 3.2: A^*A = N I_M for M <= N and A A^* = M I_N for M >= N, N | M."""
+    x = W.equispaced_nodes(N)
+    A = direct.ndft_matrix(x, (M,))
+    if M <= N:
+        assert np.max(np.abs(A.conj().T @ A - N * np.eye(M))) < 1e-12 * N
+    if M >= N and M % N == 0:
+        assert np.max(np.abs(A @ A.conj().T - M * np.eye(N))) < 1e-12 * M
+
+
+def test_direct_sum_functions_match_dense_matrix_1d_2d():
+    g = W.rng(3)
+    for d, M in ((1, (12,)), (2, (6, 8))):
+        x = W.uniform_nodes(g, 17, d)
+        fh = W.complex_normal(g, (2,) + M)
+        A = direct.ndft_matrix(x, M)
+        f = direct.ndft(x, fh)
+        assert rel(f, fh.reshape(2, -1) @ A.T) < 1e-14
+        fr = W.complex_normal(g, (2, 17))
+        h = direct.ndft_adjoint(x, fr, M)
+        assert rel(h.reshape(2, -1), fr @ A.conj()) < 1e-14
+
+
+@pytest.mark.parametrize("N", [8, 12, 32, 64])
+def test_lagrange_formula_pins_direct_sums(N):
+    """(3.5) with (3.4) evaluated directly reproduces f(x_l) of the direct sum, and
+    Algorithm 3.3 step 6 returns the coefficients (jittered nodes (3.8))."""
+    g = W.rng(N)
+    y = W.jittered_nodes_paper(g, N)[:, 0]
+    fh = W.complex_normal(g, (N,))
+    f = direct.ndft(y[:, None], fh)
+    xl = lagrange.aux_nodes(N)
+    gl = lagrange.lagrange_values(y, f, xl)
+    assert rel(gl, direct.ndft(xl[:, None], fh)) < 1e-12
+    assert rel(lagrange.inverse(y, f), fh) < 1e-12
+
+
+def test_dense_pseudoinverse_recovers_coefficients():
+    g = W.rng(5)
+    x = W.jittered_nodes(g, 64)
+    fh = W.complex_normal(g, (24,))
+    A = direct.ndft_matrix(x, (24,))
+    f = direct.ndft(x, fh)
+    assert rel(np.linalg.pinv(A) @ f, fh) < 1e-12 * np.linalg.cond(A)
+
+
+def test_exact_phase_reduction_large_k():
+    """The split-product phase keeps full accuracy where a naive k*x loses digits."""
+    x = np.array([0.123456789012345, -0.4999999999, 0.3333333333333333])
+    k = np.array([2 ** 15 - 1, -(2 ** 15)], dtype=np.int64)
+    E = direct.phase_matrix(x, k)
+    from fractions import Fraction
+    for i, xv in enumerate(x):
+        for c, kv in enumerate(k):
+            fr = Fraction(xv) * kv
+            fr = fr - (fr.numerator // fr.denominator)
+            ref = np.exp(2j * np.pi * float(fr))
+            assert abs(E[i, c] - ref) < 4e-16
+
+
+# ------------------------------------------------------------------ NFFT (Section 2)
+
+@pytest.mark.parametrize("d,M,N", [(1, (16,), 23), (2, (6, 8), 19)])
+def test_nfft_equals_dense_factor_product(d, M, N):
+    """trafo == B F D fhat and adjoint == D^* F^* B^* f with the factors built entry by entry
+    from (2.4)-(2.6)."""
+    g = W.rng(11)
+    p = nfft.Params(M, 2.0, 2)
+    x = W.uniform_nodes(g, N, d)
+    fh = W.complex_normal(g, M)
+    B, F, D = nfft.dense_B(x, p), nfft.dense_F(p), nfft.dense_D(p)
+    assert rel(nfft.trafo(x, fh, p), B @ F @ D @ fh.ravel()) < 1e-13
+    f = W.complex_normal(g, (N,))
+    h = nfft.adjoint(x, f, p)
+    assert rel(h.ravel(), D.conj().T @ F.conj().T @ B.T @ f) < 1e-13
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_nfft_adjointness(d):
+    g = W.rng(12)
+    M = (32,) if d == 1 else (12, 16)
+    p = nfft.Params(M, 2.0, 4)
+    x = W.uniform_nodes(g, 200, d)
+    fh = W.complex_normal(g, M)
+    f = W.complex_normal(g, (200,))
+    lhs = np.vdot(f, nfft.trafo(x, fh, p))
+    rhs = np.vdot(nfft.adjoint(x, f, p), fh)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+def envelope(m, sigma):
+    """Window-error envelope for the Kaiser-Bessel NFFT in the form usually quoted in the NFFT
+    literature (d = 1): 4 pi (sqrt(m) + m) (1 - 1/sigma)^(1/4) exp(-2 pi m sqrt(1 - 1/sigma))."""
+    return 4 * np.pi * (np.sqrt(m) + m) * (1 - 1 / sigma) ** 0.25 * np.exp(-2 * np.pi * m * np.sqrt(1 - 1 / sigma))
+
+
+def test_nfft_error_envelope_and_rate_1d():
+    g = W.rng(13)
+    M, N, sigma = 256, 512, 2.0
+    x = W.uniform_nodes(g, N, 1)
+    fh = W.complex_normal(g, (M,))
+    f0 = direct.ndft(x, fh)
+    errs = []
+    for m in range(2, 8):
+        p = nfft.Params((M,), sigma, m)
+        e = np.max(np.abs(nfft.trafo(x, fh, p) - f0)) / np.sum(np.abs(fh))
+        assert e <= envelope(m, sigma)
+        errs.append(e)
+    ratios = np.array(errs[:-1]) / np.array(errs[1:])
+    rate = np.exp(2 * np.pi * np.sqrt(1 - 1 / sigma))   # ~ 85 per unit m at sigma = 2
+    assert np.all(ratios > rate / 4) and np.all(ratios < rate * 4)
+
+
+def test_nfft_error_envelope_2d_and_adjoint():
+    g = W.rng(14)
+    M = (24, 32)
+    x = W.uniform_nodes(g, 300, 2)
+    fh = W.complex_normal(g, M)
+    f = W.complex_normal(g, (300,))
+    for m in (3, 5):
+        p = nfft.Params(M, 2.0, m)
+        e = np.max(np.abs(nfft.trafo(x, fh, p) - direct.ndft(x, fh))) / np.sum(np.abs(fh))
+        assert e <= 2 * envelope(m, 2.0)
+        h = nfft.adjoint(x, f, p)
+        e2 = np.max(np.abs(h - direct.ndft_adjoint(x, f, M))) / np.sum(np.abs(f))
+        assert e2 <= 2 * envelope(m, 2.0)
+
+
+def test_equispaced_adjoint_of_trafo_is_identity_within_envelope():
+    """(1/N) A^* A = I for equispaced nodes, M = N (Section 3.2), through the NFFT pair."""
+    N = 64
+    x = W.equispaced_nodes(N)
+    fh = W.complex_normal(W.rng(15), (N,))
+    p = nfft.Params((N,), 2.0, 6)
+    back = nfft.adjoint(x, nfft.trafo(x, fh, p), p) / N
+    assert np.max(np.abs(back - fh)) < 4 * envelope(6, 2.0) * np.sum(np.abs(fh))
+
+
+# ------------------------------------------------------------------ B_opt (Algorithm 3.17)
+
+def _dense_K(x, p):
+    """K = A D^* F^* (3.14) as a product of the dense factors."""
+    A = direct.ndft_matrix(x, p.M)
+    return A @ nfft.dense_D(p).conj().T @ nfft.dense_F(p).conj().T
+
+
+@pytest.mark.parametrize("d,M", [(1, (10,)), (2, (4, 6))])
+def test_kernel_formula_matches_dense_product_and_frame_identities(d, M):
+    """(3.15): K(x_j - l/M_sigma) equals (A D^* F^*)[j, l]; hence Phi_l2 of (4.6) satisfies
+    Phi B^* = (B K^*)^T and B^* Phi = (K^* B)^T (Section 4.2.2)."""
+    g = W.rng(21)
+    p = nfft.Params(M, 2.0, 1 if d == 2 else 2)
+    x = W.uniform_nodes(g, 9, d)
+    Kd = _dense_K(x, p)
+    S = bopt._grid_points(p)
+    xw, _, _ = nfft.prepare_nodes(x, p)
+    Kf = np.stack([bopt.kernel_K(xw[j][None, :] - S, p) for j in range(x.shape[0])])
+    assert rel(Kf, Kd) < 1e-13
+    Phi = np.conj(Kf)
+    B = nfft.dense_B(x, p)
+    Ks = Kd.conj().T
+    assert rel(Phi @ B.T, (B @ Ks).T) < 1e-13
+    assert rel(B.T @ Phi, (Ks @ B).T) < 1e-13
+
+
+def _tiny_problem(seed=31, d=1):
+    g = W.rng(seed)
+    if d == 1:
+        p = nfft.Params((8,), 2.0, 2)
+        x = W.uniform_nodes(g, 22, 1)
+    else:
+        p = nfft.Params((4, 4), 2.0, 1)
+        x = W.uniform_nodes(g, 30, 2)
+    return x, p
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_separability_dense_problem_equals_per_column_solutions(d):
+    """(3.29)-(3.30): min ||K^*B - I||_F^2 + lambda ||B||_F^2 over all entries of B on the
+    sparsity pattern at once equals the per-l solutions."""
+    x, p = _tiny_problem(d=d)
+    rho = 1e-6
+    mem = bopt.Members(x, p)
+    Ks = _dense_K(x, p).conj().T                     # K^* = F D A^*, (G x N)
+    G = Ks.shape[0]
+    pairs = [(j, l) for l in range(G) for j in mem.of(l)[0]]
+    # vec(K^* B): entry (s, l) = sum_j Ks[s, j] B[j, l]
+    nvar = len(pairs)
+    Amat = np.zeros((G * G, nvar), dtype=np.complex128)
+    for c, (j, l) in enumerate(pairs):
+        Amat[np.arange(G) * G + l, c] = Ks[:, j]
+    col_norm2 = np.real(np.sum(np.abs(Ks) ** 2, axis=0))   # ||L_l e_j||^2 = column norm of K^*
+    lam = rho * np.mean(col_norm2)
+    big = np.vstack([Amat, np.sqrt(lam) * np.eye(nvar)])
+    rhs = np.concatenate([np.eye(G).ravel(), np.zeros(nvar)])
+    sol = np.linalg.lstsq(big, rhs, rcond=None)[0]
+    rows, _ = bopt.bopt_rows(x, p, rho, route="E", members=mem)
+    Bd = bopt.dense_from_rows(x, rows, p)
+    ref = np.array([Bd[j, l] for (j, l) in pairs])
+    assert rel(ref, sol) < 1e-9
+
+
+@pytest.mark.parametrize("route", ["E", "R", "G"])
+def test_optimality_conditions(route):
+    """Normal equations of the ridge problem: L^*(L b - e_l) + lambda b = 0 (P8)."""
+    x, p = _tiny_problem(seed=32)
+    rho = 1e-6
+    mem = bopt.Members(x, p)
+    for l in range(mem.G):
+        js, _, _ = mem.of(l)
+        if len(js) == 0:
+            continue
+        b = bopt.ROUTES[route](x, l, js, p, rho)
+        L = bopt.L_matrix(x, js, p)
+        e = np.zeros(L.shape[0]); e[l] = 1
+        lam = rho * np.real(np.trace(L.conj().T @ L)) / len(js)
+        resid = L.conj().T @ (L @ b - e) + lam * b
+        assert np.linalg.norm(resid) <= 1e-7 * np.linalg.norm(L.conj().T @ e)
+
+
+@pytest.mark.parametrize("nodes,rho", [("jittered", 1e-6), ("jittered", 1e-10), ("uniform", 1e-6)])
+def test_three_routes_agree(nodes, rho):
+    """Routes E, R and G solve the same ridge problem.  The local problems carry more nodes than
+    their band resolves, so cond(L_l^* L_l + lambda I) ~ 1/rho and the large least-squares
+    residual makes every route accurate to ~ eps/rho only; a wrong term in any route would show
+    as an O(1) difference."""
+    g = W.rng(33)
+    p = nfft.Params((16,), 2.0, 3)
+    x = W.jittered_nodes(g, 48) if nodes == "jittered" else W.uniform_nodes(g, 48, 1)
+    mem = bopt.Members(x, p)
+    rE, _ = bopt.bopt_rows(x, p, rho, "E", members=mem)
+    rR, _ = bopt.bopt_rows(x, p, rho, "R", members=mem)
+    rG, _ = bopt.bopt_rows(x, p, rho, "G", members=mem)
+    tol = 100 * 2.2e-16 / rho
+    assert rel(rR, rE) < tol and rel(rG, rE) < tol
+
+
+def test_three_routes_agree_2d():
+    g = W.rng(34)
+    p = nfft.Params((6, 8), 2.0, 2)
+    x = W.uniform_nodes(g, 60, 2)
+    mem = bopt.Members(x, p)
+    rE, _ = bopt.bopt_rows(x, p, 1e-6, "E", members=mem)
+    rG, _ = bopt.bopt_rows(x, p, 1e-6, "G", members=mem)
+    rR, _ = bopt.bopt_rows(x, p, 1e-6, "R", members=mem)
+    assert rel(rG, rE) < 1e-8 and rel(rR, rE) < 1e-8
+
+
+def test_single_member_closed_form():
+    """|I(l)| = 1: b = <L e, e_l> / (||L e||^2 + lambda), a scalar projection."""
+    p = nfft.Params((8,), 2.0, 2)
+    x = np.array([[0.013], [0.26], [-0.31]])     # well separated: some grid indices see one node
+    mem = bopt.Members(x, p)
+    found = 0
+    for l in range(mem.G):
+        js, _, _ = mem.of(l)
+        if len(js) != 1:
+            continue
+        found += 1
+        c = bopt.L_matrix(x, js, p)[:, 0]
+        lam = 1e-4 * np.real(np.vdot(c, c))
+        expect = np.conj(c[l]) / (np.real(np.vdot(c, c)) + lam)
+        for route in "ERG":
+            assert abs(bopt.ROUTES[route](x, l, js, p, 1e-4)[0] - expect) < 1e-12 * abs(expect)
+    assert found > 0
+
+
+def test_frobenius_monotone_and_rank_bound():
+    """(3.34): the optimised B never does worse than B on the ridge objective, and the
+    objective is bounded below by M_sigma - M since rank(K^*B) <= M."""
+    for d in (1, 2):
+        x, p = _tiny_problem(seed=35, d=d)
+        B = nfft.dense_B(x, p)
+        rho = 1e-9
+        rows, _ = bopt.bopt_rows(x, p, rho, "E")
+        Bo = bopt.dense_from_rows(x, rows, p)
+        f_B = bopt.frobenius_objective(x, B, p)
+        f_O = bopt.frobenius_objective(x, Bo, p)
+        Ks = _dense_K(x, p).conj().T
+        lam = rho * np.mean(np.real(np.sum(np.abs(Ks) ** 2, axis=0)))
+        assert f_O ** 2 + lam * np.sum(np.abs(Bo) ** 2) <= f_B ** 2 + lam * np.sum(np.abs(B) ** 2) + 1e-9
+        Gs, P = int(np.prod(p.Ms)), int(np.prod(p.M))
+        assert f_O ** 2 >= Gs - P - 1e-9
+        assert f_B ** 2 >= Gs - P - 1e-9
+
+
+def test_apply_equals_dense_product_and_is_adjoint_of_inverse_adjoint():
+    for d in (1, 2):
+        x, p = _tiny_problem(seed=36, d=d)
+        rows, _ = bopt.bopt_rows(x, p, 1e-8, "G")
+        Bo = bopt.dense_from_rows(x, rows, p)
+        g = W.rng(37)
+        f = W.complex_normal(g, (x.shape[0],))
+        D, F = nfft.dense_D(p), nfft.dense_F(p)
+        h = bopt.apply(x, f, rows, p)
+        assert rel(h.ravel(), D.conj().T @ F.conj().T @ Bo.conj().T @ f) < 1e-13
+        hh = W.complex_normal(g, p.M)
+        ff = bopt.apply_adjoint(x, hh, rows, p)
+        assert rel(ff, Bo @ F @ D @ hh.ravel()) < 1e-13
+        assert abs(np.vdot(f, ff) - np.vdot(h, hh)) < 1e-12 * abs(np.vdot(f, ff))
+
+
+def test_optimisation_improves_reconstruction_jittered():
+    """Example 3.23 qualitatively: for jittered nodes with N = 2M the modified adjoint
+    reconstructs fhat far better than the scaled plain adjoint (no figure data: the size of the
+    error is reported, not pinned)."""
+    g = W.rng(38)
+    M, N = 64, 128
+    p = nfft.Params((M,), 2.0, 4)
+    x = W.jittered_nodes(g, N)
+    fh = W.complex_normal(g, (M,))
+    f = direct.ndft(x, fh)
+    rows, _ = bopt.bopt_rows(x, p, 1e-12, "R")
+    e_opt = rel(bopt.apply(x, f, rows, p), fh)
+    e_plain = rel(nfft.adjoint(x, f, p) / N, fh)
+    assert e_opt < 1e-3 and e_opt < 1e-2 * e_plain
+
+
+# ------------------------------------------------------------------ gradients
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_node_gradient_matches_finite_differences(d):
+    g = W.rng(41 + d)
+    M = (16,) if d == 1 else (8, 10)
+    p = nfft.Params(M, 2.0, 4)
+    x = W.uniform_nodes(g, 7, d)
+    fh = W.complex_normal(g, (2,) + M)
+    gf = W.complex_normal(g, (2, 7))
+    an = grad.nfft_grad_x(x, fh, gf, p)
+
+    def loss(xx):
+        return np.sum(np.real(np.conj(gf) * nfft.trafo(xx, fh, p)))
+
+    h = 1e-7
+    fd = np.zeros_like(an)
+    for j in range(x.shape[0]):
+        for t in range(d):
+            xp = x.copy(); xp[j, t] += h
+            xm = x.copy(); xm[j, t] -= h
+            fd[j, t] = (loss(xp) - loss(xm)) / (2 * h)
+    assert np.max(np.abs(fd - an)) < 1e-6 * np.max(np.abs(an))
+    # and the NFFT derivative approximates the exact derivative of the trigonometric sum
+    exact = np.sum(np.real(np.conj(gf)[:, :, None] * direct.ndft_grad_x(x, fh)), axis=0)
+    assert np.max(np.abs(exact - an)) < 1e-4 * np.max(np.abs(exact))

@@ -1,0 +1,149 @@
+/*
+ * infft.h -- C ABI of the MI355X (gfx950) direct inverse NFFT library.
+ *
+ * Method: M. Kircheis, D. Potts, "Direct inversion of the nonequispaced fast Fourier
+ * transform".  Notation follows the paper:
+ *   M      number of Fourier coefficients per dimension (even), k = -M/2 .. M/2-1
+ *   N      number of nodes x_j in [-1/2, 1/2)^d (nodes outside are wrapped onto the torus)
+ *   sigma  oversampling factor, M_sigma = sigma M (must be an even integer)
+ *   m      window cut-off: the truncated window reaches 2m+1 grid points per dimension
+ *   A      nonequispaced Fourier matrix (1.3);  A ~ B F D  (Section 2.1, (2.4)-(2.6))
+ *
+ * Window: Kaiser-Bessel with shape b = pi (2 - 1/sigma); D = diag(1/I_0(m sqrt(b^2 -
+ * (2 pi k / M_sigma)^2))) (the paper names the window family in Remark 2.1 without a formula).
+ * d-dimensional problems (d = 1, 2) use the tensor product of the 1-D factors.
+ *
+ * Data layouts (all device pointers unless stated otherwise):
+ *   x      float64 [N][d], caller order, row-major.
+ *   fhat   coefficients, [nrhs][M_0]...[M_{d-1}], centred index k_t + M_t/2 ascending,
+ *          last dimension fastest, right-hand sides outermost.
+ *   f      samples, [nrhs][N] in the caller's node order.
+ *   complex numbers are interleaved (re, im): complex64 for INFFT_F32 plans, complex128 for
+ *          INFFT_F64 plans.
+ *
+ * Ownership: the caller owns every buffer it passes; pointers are only read/written during the
+ * call's stream work.  A plan owns its device workspace (allocated by nfft_plan, freed by
+ * nfft_plan_destroy) and keeps a copy of the nodes, so `x` may be freed after nfft_plan /
+ * nfft_set_nodes return.
+ *
+ * Streams: every call enqueues work on the plan's stream (a hipStream_t passed as void*; NULL =
+ * the default stream) and returns without synchronising, except nfft_plan_status,
+ * nfft_plan_destroy and nfft_plan (which waits for its own set-up work).
+ *
+ * Errors: every call returns INFFT_OK (0) or a negative code; nothing throws across the ABI.
+ * infft_last_error() returns a thread-local message for the last failing call.  Conditions found
+ * on the device (non-finite nodes, failed local solves, empty I(l)) are counted in a device
+ * status block read by nfft_plan_status.
+ */
+#ifndef INFFT_H
+#define INFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define INFFT_OK 0
+#define INFFT_EINVAL (-1)    /* invalid argument: M odd or <= 0, sigma M not an even integer,
+                                m outside 2..8, 2m+2 > M_sigma, N <= 0, d not 1 or 2, null
+                                pointer, nrhs < 1, unsupported FFT length */
+#define INFFT_ENOMEM (-2)    /* device allocation failed */
+#define INFFT_EDEVICE (-3)   /* HIP runtime error */
+#define INFFT_ESINGULAR (-4) /* status: a local solve met a non-positive pivot */
+#define INFFT_ESTATE (-5)    /* call out of order, e.g. infft_apply before infft_precompute_B */
+
+#define INFFT_F32 0 /* complex64 data; FP32 spreading, FFT and accumulation */
+#define INFFT_F64 1 /* complex128 data; FP64 throughout */
+
+typedef struct infft_plan_s* infft_plan;
+
+typedef struct {
+    int precision;   /* INFFT_F32 or INFFT_F64 (default INFFT_F64) */
+    int max_rhs;     /* right-hand sides processed per internal pass (default 1); larger nrhs
+                        are processed in chunks */
+    double rho;      /* ridge of the local least-squares problems (default 1e-8): the solve
+                        minimises ||L_l b - e_l||^2 + lambda ||b||^2 with
+                        lambda = rho * trace(L_l^* L_l) / |I(l)| */
+    int tile[2];     /* spreading tile in grid cells per dimension (0 = automatic) */
+    int reserved[6];
+} infft_options;
+
+typedef struct {
+    int64_t nonfinite_nodes;  /* nodes rejected as NaN/Inf (their samples are set to 0) */
+    int64_t failed_solves;    /* local problems whose Cholesky met a pivot <= 0 */
+    int64_t empty_columns;    /* grid indices l with empty I(l): zero column of B_opt */
+    int64_t oversized;        /* local problems with |I(l)| above the supported size */
+    int64_t min_members;      /* min |I(l)| over non-empty l of the last precompute */
+    int64_t max_members;      /* max |I(l)| */
+    int32_t bopt_ready;       /* 1 after a successful infft_precompute_B for the current nodes */
+    int32_t max_supported;    /* largest |I(l)| the local solver handles */
+} infft_status;
+
+/* Fills *o with the defaults listed above. */
+void infft_default_options(infft_options* o);
+
+/* Creates a plan for d-dimensional problems with M[0..d-1] coefficients, N nodes,
+ * oversampling sigma and cut-off m, and runs the node preprocessing for x (N x d float64,
+ * device).  Precomputes the deconvolution factors D (2.4), FFT twiddles and the kernel tables
+ * used by infft_precompute_B.  stream: hipStream_t (void*), NULL for the default stream.
+ * On success *out holds the plan; on failure *out is NULL. */
+int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma, int m,
+              const double* x, const infft_options* opts, void* stream);
+
+/* Replaces the node set (same N) and reruns the node preprocessing: wrap onto the torus,
+ * stencil base l0 = ceil(M_sigma x - m) and offset per dimension, sort into grid tiles, and the
+ * grid-index -> node lists I(l) of (3.29).  Invalidates B_opt. */
+int nfft_set_nodes(infft_plan p, const double* x);
+
+/* Changes the stream subsequent calls enqueue on. */
+int nfft_set_stream(infft_plan p, void* stream);
+
+/* NFFT: f = B F D fhat ~ A fhat (Section 2.1).  fhat [nrhs][M...], f [nrhs][N]. */
+int nfft_trafo(infft_plan p, const void* fhat, void* f, int nrhs);
+
+/* Adjoint NFFT: h~ = D^* F^* B^* f ~ A^* f ((2.8)).  f [nrhs][N], h [nrhs][M...]. */
+int nfft_adjoint(infft_plan p, const void* f, void* h, int nrhs);
+
+/* Algorithm 3.17: optimises the nonzero entries of B, one regularised least-squares problem
+ * per oversampled grid index l over the nodes I(l) of (3.29), solved through its normal
+ * equations in FP64 on the GPU (whatever the plan precision).  Stores B_opt in the plan. */
+int infft_precompute_B(infft_plan p);
+
+/* Modified adjoint NFFT (3.32): fcheck = D^* F^* B_opt^* f ~ fhat.  f [nrhs][N],
+ * fcheck [nrhs][M...].  Returns INFFT_ESTATE before infft_precompute_B. */
+int infft_apply(infft_plan p, const void* f, void* fcheck, int nrhs);
+
+/* Adjoint of infft_apply: f = B_opt F D h (the inverse adjoint NFFT of Remark 3.24).
+ * h [nrhs][M...], f [nrhs][N].  Returns INFFT_ESTATE before infft_precompute_B. */
+int infft_apply_adjoint(infft_plan p, const void* h, void* f, int nrhs);
+
+/* Gradient of a real loss through the NFFT with respect to the nodes:
+ * gradx[j][t] = sum_r Re( conj(gradf[r][j]) * d f_{r,j} / d x_{j,t} ), with f = B(x) F D fhat
+ * and the derivative of the window inside its support.  fhat [nrhs][M...], gradf [nrhs][N]
+ * (plan precision), gradx float64 [N][d]. */
+int nfft_grad_x(infft_plan p, const void* fhat, const void* gradf, double* gradx, int nrhs);
+
+/* Copies B_opt to `rows` (device, complex128 [N][(2m+1)^d], caller node order, tap index
+ * tau flattened with the first dimension slowest; entry (j, tau) multiplies grid index
+ * (l0_j + tau) mod M_sigma).  Returns INFFT_ESTATE before infft_precompute_B. */
+int infft_get_B(infft_plan p, void* rows);
+
+/* Synchronises the plan's stream and reports the device status block. */
+int nfft_plan_status(infft_plan p, infft_status* out);
+
+/* Bytes of device memory the plan holds. */
+int64_t nfft_plan_device_bytes(infft_plan p);
+
+/* Releases the plan and its device workspace (waits for the plan's stream first). */
+void nfft_plan_destroy(infft_plan p);
+
+/* Thread-local description of the last error (empty string if none). */
+const char* infft_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INFFT_H */

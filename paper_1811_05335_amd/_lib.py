@@ -1,0 +1,99 @@
+"""ctypes loader for libinfft.so (built in-tree by paper_1811_05335_amd.build)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libinfft.so")
+
+INFFT_OK = 0
+INFFT_EINVAL = -1
+INFFT_ENOMEM = -2
+INFFT_EDEVICE = -3
+INFFT_ESINGULAR = -4
+INFFT_ESTATE = -5
+INFFT_F32 = 0
+INFFT_F64 = 1
+
+ERROR_NAMES = {
+    INFFT_EINVAL: "INFFT_EINVAL",
+    INFFT_ENOMEM: "INFFT_ENOMEM",
+    INFFT_EDEVICE: "INFFT_EDEVICE",
+    INFFT_ESINGULAR: "INFFT_ESINGULAR",
+    INFFT_ESTATE: "INFFT_ESTATE",
+}
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("precision", C.c_int),
+        ("max_rhs", C.c_int),
+        ("rho", C.c_double),
+        ("tile", C.c_int * 2),
+        ("reserved", C.c_int * 6),
+    ]
+
+
+class Status(C.Structure):
+    _fields_ = [
+        ("nonfinite_nodes", C.c_int64),
+        ("failed_solves", C.c_int64),
+        ("empty_columns", C.c_int64),
+        ("oversized", C.c_int64),
+        ("min_members", C.c_int64),
+        ("max_members", C.c_int64),
+        ("bopt_ready", C.c_int32),
+        ("max_supported", C.c_int32),
+    ]
+
+
+class InfftError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Loads the HIP library; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1811_05335_amd.build` "
+            "(the library has no CPU fallback)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    sig = {
+        "infft_default_options": (None, [C.POINTER(Options)]),
+        "nfft_plan": (i32, [C.POINTER(vp), i32, C.POINTER(i64), i64, dbl, i32, vp, C.POINTER(Options), vp]),
+        "nfft_set_nodes": (i32, [vp, vp]),
+        "nfft_set_stream": (i32, [vp, vp]),
+        "nfft_trafo": (i32, [vp, vp, vp, i32]),
+        "nfft_adjoint": (i32, [vp, vp, vp, i32]),
+        "infft_precompute_B": (i32, [vp]),
+        "infft_apply": (i32, [vp, vp, vp, i32]),
+        "infft_apply_adjoint": (i32, [vp, vp, vp, i32]),
+        "nfft_grad_x": (i32, [vp, vp, vp, vp, i32]),
+        "infft_get_B": (i32, [vp, vp]),
+        "nfft_plan_status": (i32, [vp, C.POINTER(Status)]),
+        "nfft_plan_device_bytes": (i64, [vp]),
+        "nfft_plan_destroy": (None, [vp]),
+        "infft_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(code: int) -> None:
+    if code != INFFT_OK:
+        msg = load().infft_last_error().decode(errors="replace")
+        raise InfftError(code, msg)

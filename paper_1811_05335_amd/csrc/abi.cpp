@@ -1,0 +1,690 @@
+// C ABI of libinfft: argument validation, the plan (geometry, device workspace, FFT schedule)
+// and the order of kernel launches for each entry point declared in include/infft.h.
+#include "infft.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace infft;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(INFFT_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCH_CHECK()                                                                     \
+    do {                                                                                   \
+        hipError_t e_ = hipGetLastError();                                                 \
+        if (e_ != hipSuccess) return fail(INFFT_EDEVICE, "kernel launch: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+// radices the LDS Stockham kernel implements, largest first
+bool factor_radices(int n, std::vector<int>& rad) {
+    rad.clear();
+    for (int r : {8, 4, 2}) {
+        while (n % r == 0 && n > 1) {
+            rad.push_back(r);
+            n /= r;
+        }
+    }
+    for (int r : {7, 5, 3}) {
+        while (n % r == 0) {
+            rad.push_back(r);
+            n /= r;
+        }
+    }
+    return n == 1 && (int)rad.size() <= FFT_MAX_STAGES;
+}
+
+struct TwTable {
+    int64_t n = 0;
+    double2* t64 = nullptr;
+    float2* t32 = nullptr;
+};
+
+struct FftStep {
+    FftPass pass;
+    int ld, st;
+    int in_buf, out_buf;   // 0 = caller's array, 1 = grid, 2 = scratch grid
+};
+
+}  // namespace
+
+struct infft_plan_s {
+    Geo g{};
+    int prec = INFFT_F64;
+    int max_rhs = 1;
+    double rho = 1e-8;
+    double sigma = 2.0;
+    hipStream_t stream = nullptr;
+    std::vector<void*> allocs;
+    int64_t bytes = 0;
+
+    NodesDev nd{};
+    int* counts = nullptr;
+    int* fill = nullptr;
+    int* bsum = nullptr;
+    long long* status = nullptr;
+
+    double* D64[MAX_D] = {nullptr, nullptr};
+    float* D32[MAX_D] = {nullptr, nullptr};
+    double2* Ktab[MAX_D] = {nullptr, nullptr};
+    double2* Qtab[MAX_D] = {nullptr, nullptr};
+    int qK = 0, qQ = 0;
+    double lam = 0.0;
+
+    std::vector<TwTable> tw;
+    TwTable split_lo, split_hi;
+    std::vector<FftStep> to_grid;    // coefficients -> grid (sign +1, with D)
+    std::vector<FftStep> to_coeff;   // grid + halos -> coefficients (sign -1, with D^*)
+
+    void* grid = nullptr;
+    void* grid2 = nullptr;
+    void* h0 = nullptr;
+    void* h1 = nullptr;
+    void* h01 = nullptr;
+    int64_t hrs0 = 0, hrs1 = 0, hrs01 = 0;
+    int rchunk = 1;
+
+    double2* B64 = nullptr;
+    float2* B32 = nullptr;
+    int* lists = nullptr;      // one list of grid indices for problems passed to the wider tier
+    int* lcount = nullptr;
+    bool bopt_ready = false;
+
+    size_t csize() const { return prec == INFFT_F32 ? sizeof(float2) : sizeof(double2); }
+    int taps() const { return g.d == 1 ? 2 * g.m + 1 : (2 * g.m + 1) * (2 * g.m + 1); }
+
+    template <typename T>
+    int alloc(T** p, int64_t count) {
+        void* q = nullptr;
+        const size_t nb = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+        hipError_t e = hipMalloc(&q, nb);
+        if (e != hipSuccess) return fail(INFFT_ENOMEM, "hipMalloc(%zu) failed: %s", nb, hipGetErrorString(e));
+        allocs.push_back(q);
+        bytes += (int64_t)nb;
+        *p = (T*)q;
+        return INFFT_OK;
+    }
+
+    ~infft_plan_s() {
+        for (void* p : allocs) (void)hipFree(p);
+    }
+};
+
+namespace {
+
+const TwTable* find_tw(const infft_plan_s* P, int64_t n) {
+    for (const TwTable& t : P->tw)
+        if (t.n == n) return &t;
+    return nullptr;
+}
+
+int ensure_tw(infft_plan_s* P, int64_t n) {
+    if (find_tw(P, n)) return INFFT_OK;
+    TwTable t;
+    t.n = n;
+    int rc = P->alloc(&t.t64, n);
+    if (rc) return rc;
+    if (P->prec == INFFT_F32 && (rc = P->alloc(&t.t32, n))) return rc;
+    launch_twiddles(n, t.t64, t.t32, P->stream);
+    P->tw.push_back(t);
+    return INFFT_OK;
+}
+
+const void* tw_ptr(const infft_plan_s* P, int64_t n) {
+    const TwTable* t = find_tw(P, n);
+    return P->prec == INFFT_F32 ? (const void*)t->t32 : (const void*)t->t64;
+}
+
+int choose_rows(int64_t n, int64_t nseq, int cap) {
+    int64_t rows = std::max<int64_t>(1, nseq / 1024);
+    rows = std::min<int64_t>(rows, cap / n);
+    rows = std::min<int64_t>(rows, 16);
+    return (int)std::max<int64_t>(rows, 1);
+}
+
+void fill_radices(FftPass& p) {
+    std::vector<int> rad;
+    factor_radices(p.n, rad);
+    p.nst = (int)rad.size();
+    for (int i = 0; i < p.nst; ++i) p.rad[i] = rad[i];
+}
+
+// Builds the two transform schedules for `nrhs` right-hand sides.
+int build_schedule(infft_plan_s* P, int nrhs, std::vector<FftStep>& to_grid, std::vector<FftStep>& to_coeff) {
+    const Geo& g = P->g;
+    const int cap = fft_capacity(P->prec == INFFT_F64);
+    to_grid.clear();
+    to_coeff.clear();
+    auto base = [&](int64_t n, int64_t nq) {
+        FftStep s{};
+        std::memset(&s.pass, 0, sizeof(s.pass));
+        s.pass.n = (int)n;
+        s.pass.nq = nq;
+        s.pass.nseq = nq * nrhs;
+        s.pass.rows = choose_rows(n, s.pass.nseq, cap);
+        s.pass.tw = tw_ptr(P, n);
+        fill_radices(s.pass);
+        return s;
+    };
+    if (g.d == 1 && g.Ms[0] <= cap) {
+        FftStep s = base(g.Ms[0], 1);
+        s.pass.in_is = 1;
+        s.pass.out_ks = 1;
+        FftStep a = s, b = s;
+        a.pass.sign = +1; a.ld = LD_DECONV; a.st = ST_GRID; a.in_buf = 0; a.out_buf = 1;
+        a.pass.in_rs = g.P; a.pass.out_rs = g.G;
+        b.pass.sign = -1; b.ld = LD_HALO; b.st = ST_DECONV; b.in_buf = 1; b.out_buf = 0;
+        b.pass.in_rs = g.G; b.pass.out_rs = g.P;
+        to_grid.push_back(a);
+        to_coeff.push_back(b);
+    } else if (g.d == 1) {
+        // four-step split n = n1 * n2 chosen at plan time (n1 kept in split_hi.n)
+        const int64_t n1 = P->split_hi.n;     // sub-length of the first pass
+        const int64_t n2 = g.Ms[0] / n1;
+        FftStep A = base(n1, n2), B = base(n2, n1);
+        A.pass.in_qs = 1; A.pass.in_is = n2; A.pass.in_rowfast = 1;
+        A.pass.out_qs = 1; A.pass.out_ks = n2; A.pass.out_rowfast = 1; A.pass.out_rs = g.G;
+        A.pass.twN = g.Ms[0]; A.pass.twB = (int)P->split_lo.n;
+        A.pass.twLo = P->prec == INFFT_F32 ? (const void*)P->split_lo.t32 : (const void*)P->split_lo.t64;
+        A.pass.twHi = P->prec == INFFT_F32 ? (const void*)P->split_hi.t32 : (const void*)P->split_hi.t64;
+        B.pass.in_qs = n2; B.pass.in_is = 1; B.pass.in_rowfast = 0; B.pass.in_rs = g.G;
+        B.pass.out_qs = 1; B.pass.out_ks = n1; B.pass.out_rowfast = 1;
+        FftStep a1 = A, a2 = B, b1 = A, b2 = B;
+        a1.pass.sign = +1; a1.ld = LD_DECONV; a1.st = ST_TWIDDLE; a1.in_buf = 0; a1.out_buf = 2; a1.pass.in_rs = g.P;
+        a2.pass.sign = +1; a2.ld = LD_GRID; a2.st = ST_GRID; a2.in_buf = 2; a2.out_buf = 1; a2.pass.out_rs = g.G;
+        b1.pass.sign = -1; b1.ld = LD_HALO; b1.st = ST_TWIDDLE; b1.in_buf = 1; b1.out_buf = 2; b1.pass.in_rs = g.G;
+        b2.pass.sign = -1; b2.ld = LD_GRID; b2.st = ST_DECONV; b2.in_buf = 2; b2.out_buf = 0; b2.pass.out_rs = g.P;
+        to_grid.push_back(a1);
+        to_grid.push_back(a2);
+        to_coeff.push_back(b1);
+        to_coeff.push_back(b2);
+    } else {
+        const int64_t n0 = g.Ms[0], n1 = g.Ms[1];
+        FftStep Rw = base(n1, n0), Cl = base(n0, n1);
+        Rw.pass.in_qs = n1; Rw.pass.in_is = 1; Rw.pass.out_qs = n1; Rw.pass.out_ks = 1;
+        Cl.pass.in_qs = 1; Cl.pass.in_is = n1; Cl.pass.in_rowfast = 1;
+        Cl.pass.out_qs = 1; Cl.pass.out_ks = n1; Cl.pass.out_rowfast = 1;
+        FftStep a1 = Rw, a2 = Cl, b1 = Rw, b2 = Cl;
+        a1.pass.sign = +1; a1.ld = LD_DECONV; a1.st = ST_GRID; a1.in_buf = 0; a1.out_buf = 2;
+        a1.pass.in_rs = g.P; a1.pass.out_rs = g.G;
+        a2.pass.sign = +1; a2.ld = LD_GRID; a2.st = ST_GRID; a2.in_buf = 2; a2.out_buf = 1;
+        a2.pass.in_rs = g.G; a2.pass.out_rs = g.G;
+        b1.pass.sign = -1; b1.ld = LD_HALO; b1.st = ST_GRID; b1.in_buf = 1; b1.out_buf = 2;
+        b1.pass.in_rs = g.G; b1.pass.out_rs = g.G;
+        b2.pass.sign = -1; b2.ld = LD_GRID; b2.st = ST_DECONV; b2.in_buf = 2; b2.out_buf = 0;
+        b2.pass.in_rs = g.G; b2.pass.out_rs = g.P;
+        to_grid.push_back(a1);
+        to_grid.push_back(a2);
+        to_coeff.push_back(b1);
+        to_coeff.push_back(b2);
+    }
+    return INFFT_OK;
+}
+
+int run_fft(infft_plan_s* P, const std::vector<FftStep>& steps, const void* user_in, void* user_out) {
+    const Geo& g = P->g;
+    for (const FftStep& s : steps) {
+        FftIO io{};
+        auto buf = [&](int which, bool input) -> void* {
+            if (which == 0) return input ? (void*)user_in : user_out;
+            return which == 1 ? P->grid : P->grid2;
+        };
+        io.in = buf(s.in_buf, true);
+        io.out = buf(s.out_buf, false);
+        const bool f32 = P->prec == INFFT_F32;
+        io.D0 = f32 ? (const void*)P->D32[0] : (const void*)P->D64[0];
+        io.D1 = f32 ? (const void*)P->D32[1] : (const void*)P->D64[1];
+        io.h0 = P->h0;
+        io.h1 = P->h1;
+        io.h01 = P->h01;
+        io.halo_rs0 = P->hrs0;
+        io.halo_rs1 = P->hrs1;
+        io.halo_rs01 = P->hrs01;
+        if (f32) launch_fft_pass<float>(s.pass, io, g, s.ld, s.st, P->stream);
+        else launch_fft_pass<double>(s.pass, io, g, s.ld, s.st, P->stream);
+        LAUNCH_CHECK();
+    }
+    return INFFT_OK;
+}
+
+int auto_tile(int Ms, int m, int want) {
+    for (int t = std::min(Ms, want); t >= 2 * m; --t)
+        if (Ms % t == 0) return t;
+    return 0;
+}
+
+int set_nodes_impl(infft_plan_s* P, const double* x) {
+    const Geo& g = P->g;
+    hipStream_t s = P->stream;
+    launch_fill_bytes0(P->status, sizeof(long long) * STATUS_WORDS, s);
+    launch_status_init(P->status, 0, s);
+    launch_fill_i32(P->counts, g.G + 1, 0, s);
+    launch_fill_i32(P->fill, g.G, 0, s);
+    launch_prep_nodes(g, x, P->nd, P->counts, P->status, s);
+    launch_exclusive_scan(P->counts, P->nd.start, g.G, P->bsum, s);
+    launch_scatter_nodes(g, P->nd, P->fill, s);
+    LAUNCH_CHECK();
+    P->bopt_ready = false;
+    return INFFT_OK;
+}
+
+int check_rhs(infft_plan_s* P, int nrhs) {
+    if (!P) return fail(INFFT_EINVAL, "null plan");
+    if (nrhs < 1) return fail(INFFT_EINVAL, "nrhs must be >= 1 (got %d)", nrhs);
+    return INFFT_OK;
+}
+
+// Schedules are built per chunk size (the number of sequences enters the pass descriptors).
+int schedule_for(infft_plan_s* P, int rc) {
+    return build_schedule(P, rc, P->to_grid, P->to_coeff);
+}
+
+}  // namespace
+
+// =====================================================================================  C ABI
+
+extern "C" {
+
+void infft_default_options(infft_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = INFFT_F64;
+    o->max_rhs = 1;
+    o->rho = 1e-8;
+}
+
+const char* infft_last_error(void) { return g_err.c_str(); }
+
+int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma, int m, const double* x,
+              const infft_options* opts, void* stream) {
+    g_err.clear();
+    if (!out) return fail(INFFT_EINVAL, "out is null");
+    *out = nullptr;
+    if (d < 1 || d > 2) return fail(INFFT_EINVAL, "d must be 1 or 2 (got %d)", d);
+    if (!M) return fail(INFFT_EINVAL, "M is null");
+    if (!x) return fail(INFFT_EINVAL, "x is null");
+    if (N <= 0 || N >= (int64_t)1 << 31) return fail(INFFT_EINVAL, "N out of range (%lld)", (long long)N);
+    if (m < MIN_M_CUT || m > MAX_M_CUT) return fail(INFFT_EINVAL, "m must be in %d..%d (got %d)", MIN_M_CUT, MAX_M_CUT, m);
+    if (!(sigma >= 1.0) || !std::isfinite(sigma)) return fail(INFFT_EINVAL, "sigma must be >= 1");
+    infft_options o;
+    infft_default_options(&o);
+    if (opts) o = *opts;
+    if (o.precision != INFFT_F32 && o.precision != INFFT_F64) return fail(INFFT_EINVAL, "bad precision");
+    if (o.max_rhs < 1 || o.max_rhs > 64) return fail(INFFT_EINVAL, "max_rhs must be in 1..64");
+    if (!(o.rho >= 0.0) || !std::isfinite(o.rho)) return fail(INFFT_EINVAL, "rho must be finite and >= 0");
+
+    Geo g{};
+    g.d = d;
+    g.m = m;
+    g.N = N;
+    g.b = M_PI * (2.0 - 1.0 / sigma);
+    g.G = 1;
+    g.P = 1;
+    for (int t = 0; t < MAX_D; ++t) {
+        g.M[t] = g.Ms[t] = g.TS[t] = g.ntile[t] = 1;
+    }
+    for (int t = 0; t < d; ++t) {
+        if (M[t] <= 0 || M[t] % 2 || M[t] > (1 << 24))
+            return fail(INFFT_EINVAL, "M[%d] must be a positive even integer (got %lld)", t, (long long)M[t]);
+        const double msd = sigma * (double)M[t];
+        const int64_t ms = (int64_t)std::llround(msd);
+        if (std::fabs(msd - (double)ms) > 1e-9 * msd || ms % 2)
+            return fail(INFFT_EINVAL, "sigma*M[%d] = %g must be an even integer", t, msd);
+        if (2 * m + 2 > ms) return fail(INFFT_EINVAL, "2m+2 = %d exceeds M_sigma = %lld", 2 * m + 2, (long long)ms);
+        g.M[t] = (int)M[t];
+        g.Ms[t] = (int)ms;
+        g.G *= ms;
+        g.P *= M[t];
+    }
+    if (g.G > ((int64_t)1 << 22)) return fail(INFFT_EINVAL, "oversampled grid too large (%lld points)", (long long)g.G);
+    // tiles
+    for (int t = 0; t < d; ++t) {
+        const int want = o.tile[t] > 0 ? o.tile[t] : (d == 1 ? 256 : 32);
+        const int ts = auto_tile(g.Ms[t], m, want);
+        if (ts == 0 || g.Ms[t] % ts) return fail(INFFT_EINVAL, "no spreading tile >= 2m divides M_sigma[%d]", t);
+        g.TS[t] = ts;
+        g.ntile[t] = g.Ms[t] / ts;
+    }
+    // FFT feasibility
+    const int cap = fft_capacity(o.precision == INFFT_F64);
+    int64_t n1_split = 0;
+    for (int t = 0; t < d; ++t) {
+        std::vector<int> rad;
+        if (!factor_radices(g.Ms[t], rad))
+            return fail(INFFT_EINVAL, "M_sigma[%d] = %d is not a product of 2, 3, 5, 7", t, g.Ms[t]);
+        if (g.Ms[t] > cap) {
+            if (d == 2) return fail(INFFT_EINVAL, "2-D grids need M_sigma <= %d per dimension", cap);
+            // split n = n1 n2 with both factors <= cap, as balanced as possible
+            int64_t best = 0;
+            for (int64_t a = 2; a <= cap; ++a) {
+                if (g.Ms[t] % a) continue;
+                const int64_t b = g.Ms[t] / a;
+                if (b > cap) continue;
+                std::vector<int> ra, rb;
+                if (!factor_radices((int)a, ra) || !factor_radices((int)b, rb)) continue;
+                if (!best || std::llabs(a - b) < std::llabs(best - g.Ms[t] / best)) best = a;
+            }
+            if (!best) return fail(INFFT_EINVAL, "M_sigma = %d cannot be split into two FFT passes", g.Ms[t]);
+            n1_split = best;
+        }
+    }
+
+    infft_plan_s* P = new infft_plan_s();
+    P->g = g;
+    P->prec = o.precision;
+    P->max_rhs = o.max_rhs;
+    P->rho = o.rho;
+    P->sigma = sigma;
+    P->stream = (hipStream_t)stream;
+    int rc = INFFT_OK;
+#define TRY(e)                     \
+    do {                           \
+        if ((rc = (e)) != 0) {     \
+            delete P;              \
+            return rc;             \
+        }                          \
+    } while (0)
+    const int64_t Nd = N * d;
+    const int T = P->taps();
+    double* xw = nullptr;
+    TRY(P->alloc(&xw, Nd));
+    P->nd.xw = xw;
+    TRY(P->alloc(&P->nd.l0c, Nd));
+    TRY(P->alloc(&P->nd.uc, Nd));
+    TRY(P->alloc(&P->nd.key, N));
+    TRY(P->alloc(&P->nd.perm, N));
+    TRY(P->alloc(&P->nd.l0s, Nd));
+    TRY(P->alloc(&P->nd.us, Nd));
+    TRY(P->alloc(&P->nd.start, g.G + 1));
+    TRY(P->alloc(&P->counts, g.G + 1));
+    TRY(P->alloc(&P->fill, g.G));
+    TRY(P->alloc(&P->bsum, scan_blocksum_len(g.G) + 1));
+    TRY(P->alloc(&P->status, STATUS_WORDS));
+    // deconvolution factors and kernel tables
+    P->qK = m * TAY_S + 1;
+    P->qQ = 2 * m * TAY_S + 1;
+    for (int t = 0; t < d; ++t) {
+        TRY(P->alloc(&P->D64[t], g.M[t]));
+        if (P->prec == INFFT_F32) TRY(P->alloc(&P->D32[t], g.M[t]));
+        TRY(P->alloc(&P->Ktab[t], (int64_t)(P->qK + 1) * TAY_NC));
+        TRY(P->alloc(&P->Qtab[t], (int64_t)(P->qQ + 1) * TAY_NC));
+        launch_deconv_table(g.M[t], g.Ms[t], m, g.b, P->D64[t], P->D32[t], P->stream);
+        launch_taylor_table(g.M[t], g.Ms[t], P->D64[t], 1, P->qK, P->Ktab[t], P->stream);
+        launch_taylor_table(g.M[t], g.Ms[t], P->D64[t], 2, P->qQ, P->Qtab[t], P->stream);
+        if (hipGetLastError() != hipSuccess) TRY(fail(INFFT_EDEVICE, "table kernels failed to launch"));
+    }
+    // FFT twiddles
+    for (int t = 0; t < d; ++t) {
+        if (g.Ms[t] <= cap) {
+            TRY(ensure_tw(P, g.Ms[t]));
+        } else {
+            TRY(ensure_tw(P, n1_split));
+            TRY(ensure_tw(P, g.Ms[t] / n1_split));
+            const int64_t Bsz = (int64_t)std::ceil(std::sqrt((double)g.Ms[t]));
+            P->split_lo.n = Bsz;
+            P->split_hi.n = n1_split;  // remembered sub-length of the first pass
+            const int64_t nhi = (g.Ms[t] + Bsz - 1) / Bsz;
+            TRY(P->alloc(&P->split_lo.t64, Bsz));
+            TRY(P->alloc(&P->split_hi.t64, nhi));
+            if (P->prec == INFFT_F32) {
+                TRY(P->alloc(&P->split_lo.t32, Bsz));
+                TRY(P->alloc(&P->split_hi.t32, nhi));
+            }
+            launch_twiddles_strided(g.Ms[t], Bsz, 1, P->split_lo.t64, P->split_lo.t32, P->stream);
+            launch_twiddles_strided(g.Ms[t], nhi, Bsz, P->split_hi.t64, P->split_hi.t32, P->stream);
+        }
+    }
+    // grids, halos, B_opt, solver lists
+    const size_t cs = P->csize();
+    const int64_t ntiles = (int64_t)g.ntile[0] * g.ntile[1];
+    const int w2 = 2 * m;
+    P->hrs0 = ntiles * w2 * (d == 2 ? g.TS[1] : 1);
+    P->hrs1 = d == 2 ? ntiles * g.TS[0] * w2 : 0;
+    P->hrs01 = d == 2 ? ntiles * w2 * w2 : 0;
+    char* tmp = nullptr;
+    TRY(P->alloc(&tmp, (int64_t)cs * g.G * P->max_rhs));
+    P->grid = tmp;
+    TRY(P->alloc(&tmp, (int64_t)cs * g.G * P->max_rhs));
+    P->grid2 = tmp;
+    TRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs0, 1) * P->max_rhs));
+    P->h0 = tmp;
+    TRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs1, 1) * P->max_rhs));
+    P->h1 = tmp;
+    TRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs01, 1) * P->max_rhs));
+    P->h01 = tmp;
+    P->rchunk = spread_rhs_chunk(g, P->prec == INFFT_F64);
+    TRY(P->alloc(&P->B64, (int64_t)T * N));
+    if (P->prec == INFFT_F32) TRY(P->alloc(&P->B32, (int64_t)T * N));
+    TRY(P->alloc(&P->lists, g.G));
+    TRY(P->alloc(&P->lcount, 4));
+    // ridge: lambda = rho * (diagonal of G_l) = rho * prod_t M_sigma_t Q_t(0)
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    double q0 = 1.0;
+    for (int t = 0; t < d; ++t) {
+        double2 v;
+        if (hipMemcpy(&v, P->Qtab[t], sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
+            TRY(fail(INFFT_EDEVICE, "reading the kernel table failed"));
+        q0 *= v.x * (double)g.Ms[t];
+    }
+    P->lam = P->rho * q0;
+    TRY(set_nodes_impl(P, x));
+    if (hipStreamSynchronize(P->stream) != hipSuccess) TRY(fail(INFFT_EDEVICE, "plan set-up failed on the device"));
+#undef TRY
+    *out = P;
+    return INFFT_OK;
+}
+
+int nfft_set_nodes(infft_plan p, const double* x) {
+    if (!p) return fail(INFFT_EINVAL, "null plan");
+    if (!x) return fail(INFFT_EINVAL, "x is null");
+    return set_nodes_impl(p, x);
+}
+
+int nfft_set_stream(infft_plan p, void* stream) {
+    if (!p) return fail(INFFT_EINVAL, "null plan");
+    p->stream = (hipStream_t)stream;
+    return INFFT_OK;
+}
+
+static const char* cptr(const infft_plan_s* P, const void* base, int64_t elem_off) {
+    return (const char*)base + (int64_t)P->csize() * elem_off;
+}
+
+int nfft_trafo(infft_plan p, const void* fhat, void* f, int nrhs) {
+    int rc = check_rhs(p, nrhs);
+    if (rc) return rc;
+    if (!fhat || !f) return fail(INFFT_EINVAL, "null data pointer");
+    const Geo& g = p->g;
+    for (int r0 = 0; r0 < nrhs; r0 += p->max_rhs) {
+        const int c = std::min(p->max_rhs, nrhs - r0);
+        if ((rc = schedule_for(p, c))) return rc;
+        if ((rc = run_fft(p, p->to_grid, cptr(p, fhat, r0 * g.P), nullptr))) return rc;
+        void* fo = (void*)cptr(p, f, r0 * g.N);
+        if (p->prec == INFFT_F32)
+            launch_interp<float>(g, p->nd, (const float2*)p->grid, g.G, (float2*)fo, c, p->stream);
+        else
+            launch_interp<double>(g, p->nd, (const double2*)p->grid, g.G, (double2*)fo, c, p->stream);
+        LAUNCH_CHECK();
+    }
+    return INFFT_OK;
+}
+
+static int spread_then_coeffs(infft_plan_s* p, const void* f, void* h, int nrhs, bool useB) {
+    const Geo& g = p->g;
+    int rc;
+    for (int r0 = 0; r0 < nrhs; r0 += p->max_rhs) {
+        const int c = std::min(p->max_rhs, nrhs - r0);
+        if ((rc = schedule_for(p, c))) return rc;
+        const void* fi = cptr(p, f, r0 * g.N);
+        if (p->prec == INFFT_F32)
+            launch_spread<float>(g, p->nd, (const float2*)fi, useB ? p->B32 : nullptr, (float2*)p->grid, g.G,
+                                 (float2*)p->h0, (float2*)p->h1, (float2*)p->h01, p->hrs0, p->hrs1, p->hrs01, c,
+                                 p->rchunk, p->stream);
+        else
+            launch_spread<double>(g, p->nd, (const double2*)fi, useB ? p->B64 : nullptr, (double2*)p->grid, g.G,
+                                  (double2*)p->h0, (double2*)p->h1, (double2*)p->h01, p->hrs0, p->hrs1,
+                                  p->hrs01, c, p->rchunk, p->stream);
+        LAUNCH_CHECK();
+        if ((rc = run_fft(p, p->to_coeff, nullptr, (void*)cptr(p, h, r0 * g.P)))) return rc;
+    }
+    return INFFT_OK;
+}
+
+int nfft_adjoint(infft_plan p, const void* f, void* h, int nrhs) {
+    int rc = check_rhs(p, nrhs);
+    if (rc) return rc;
+    if (!f || !h) return fail(INFFT_EINVAL, "null data pointer");
+    return spread_then_coeffs(p, f, h, nrhs, false);
+}
+
+int infft_precompute_B(infft_plan p) {
+    if (!p) return fail(INFFT_EINVAL, "null plan");
+    const Geo& g = p->g;
+    const int64_t TN = (int64_t)p->taps() * g.N;
+    launch_status_init(p->status, 1, p->stream);
+    launch_fill_bytes0(p->B64, TN * (int64_t)sizeof(double2), p->stream);
+    if (p->B32) launch_fill_bytes0(p->B32, TN * (int64_t)sizeof(float2), p->stream);
+    launch_fill_i32(p->lcount, 4, 0, p->stream);
+    KTabDev kt{};
+    for (int t = 0; t < MAX_D; ++t) {
+        kt.K[t] = p->Ktab[t];
+        kt.Q[t] = p->Qtab[t];
+    }
+    kt.qK = p->qK;
+    kt.qQ = p->qQ;
+    kt.lam = p->lam;
+    kt.scaleG = (double)g.G;
+    SolveArgs a{};
+    a.B64 = p->B64;
+    a.B32 = p->B32;
+    a.status = p->status;
+    a.in_list = nullptr;
+    a.in_count = nullptr;
+    a.out_list = p->lists;
+    a.out_count = p->lcount;
+    launch_solve_tier(g, p->nd, kt, a, 16, p->stream);
+    LAUNCH_CHECK();
+    a.in_list = p->lists;
+    a.in_count = p->lcount;
+    a.out_list = nullptr;
+    a.out_count = nullptr;
+    launch_solve_tier(g, p->nd, kt, a, 32, p->stream);
+    LAUNCH_CHECK();
+    p->bopt_ready = true;
+    return INFFT_OK;
+}
+
+int infft_apply(infft_plan p, const void* f, void* fcheck, int nrhs) {
+    int rc = check_rhs(p, nrhs);
+    if (rc) return rc;
+    if (!f || !fcheck) return fail(INFFT_EINVAL, "null data pointer");
+    if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_apply before infft_precompute_B");
+    return spread_then_coeffs(p, f, fcheck, nrhs, true);
+}
+
+int infft_apply_adjoint(infft_plan p, const void* h, void* f, int nrhs) {
+    int rc = check_rhs(p, nrhs);
+    if (rc) return rc;
+    if (!h || !f) return fail(INFFT_EINVAL, "null data pointer");
+    if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_apply_adjoint before infft_precompute_B");
+    const Geo& g = p->g;
+    for (int r0 = 0; r0 < nrhs; r0 += p->max_rhs) {
+        const int c = std::min(p->max_rhs, nrhs - r0);
+        if ((rc = schedule_for(p, c))) return rc;
+        if ((rc = run_fft(p, p->to_grid, cptr(p, h, r0 * g.P), nullptr))) return rc;
+        void* fo = (void*)cptr(p, f, r0 * g.N);
+        if (p->prec == INFFT_F32)
+            launch_interp_B<float>(g, p->nd, (const float2*)p->grid, g.G, p->B32, (float2*)fo, c, p->stream);
+        else
+            launch_interp_B<double>(g, p->nd, (const double2*)p->grid, g.G, p->B64, (double2*)fo, c, p->stream);
+        LAUNCH_CHECK();
+    }
+    return INFFT_OK;
+}
+
+int nfft_grad_x(infft_plan p, const void* fhat, const void* gradf, double* gradx, int nrhs) {
+    int rc = check_rhs(p, nrhs);
+    if (rc) return rc;
+    if (!fhat || !gradf || !gradx) return fail(INFFT_EINVAL, "null data pointer");
+    const Geo& g = p->g;
+    for (int r0 = 0; r0 < nrhs; r0 += p->max_rhs) {
+        const int c = std::min(p->max_rhs, nrhs - r0);
+        if ((rc = schedule_for(p, c))) return rc;
+        if ((rc = run_fft(p, p->to_grid, cptr(p, fhat, r0 * g.P), nullptr))) return rc;
+        const void* gf = cptr(p, gradf, r0 * g.N);
+        if (p->prec == INFFT_F32)
+            launch_grad_x<float>(g, p->nd, (const float2*)p->grid, g.G, (const float2*)gf, gradx, c, r0 > 0,
+                                 p->stream);
+        else
+            launch_grad_x<double>(g, p->nd, (const double2*)p->grid, g.G, (const double2*)gf, gradx, c, r0 > 0,
+                                  p->stream);
+        LAUNCH_CHECK();
+    }
+    return INFFT_OK;
+}
+
+int infft_get_B(infft_plan p, void* rows) {
+    if (!p) return fail(INFFT_EINVAL, "null plan");
+    if (!rows) return fail(INFFT_EINVAL, "rows is null");
+    if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_get_B before infft_precompute_B");
+    launch_export_B(p->g, p->nd.perm, p->B64, (double2*)rows, p->stream);
+    LAUNCH_CHECK();
+    return INFFT_OK;
+}
+
+int nfft_plan_status(infft_plan p, infft_status* out) {
+    if (!p || !out) return fail(INFFT_EINVAL, "null argument");
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    long long st[STATUS_WORDS];
+    HIP_TRY(hipMemcpy(st, p->status, sizeof(st), hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof(*out));
+    out->nonfinite_nodes = st[ST_NONFINITE];
+    out->failed_solves = st[ST_FAILED];
+    out->empty_columns = st[ST_EMPTY];
+    out->oversized = st[ST_OVERSIZED];
+    out->min_members = st[ST_MIN_N] == LLONG_MAX ? 0 : st[ST_MIN_N];
+    out->max_members = st[ST_MAX_N];
+    out->bopt_ready = p->bopt_ready ? 1 : 0;
+    out->max_supported = solve_max_supported();
+    if (p->bopt_ready && st[ST_FAILED] > 0)
+        return fail(INFFT_ESINGULAR, "%lld local solves met a non-positive pivot", st[ST_FAILED]);
+    return INFFT_OK;
+}
+
+int64_t nfft_plan_device_bytes(infft_plan p) { return p ? p->bytes : 0; }
+
+void nfft_plan_destroy(infft_plan p) {
+    if (!p) return;
+    (void)hipStreamSynchronize(p->stream);
+    delete p;
+}
+
+}  // extern "C"

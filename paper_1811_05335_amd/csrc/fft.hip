@@ -1,0 +1,324 @@
+// Oversampled FFT F / F^* of the NFFT (2.5): unnormalised, exponent sign +1 for F and -1 for F^*.
+//
+// One kernel launch computes `nseq` independent sub-transforms of length n, `rows` of them per
+// workgroup, entirely in LDS with mixed-radix (2, 3, 4, 5, 7, 8) Stockham autosort stages.  A
+// length that does not fit one workgroup is split four-step style (n = n1 n2, twiddle between
+// the passes, applied at the first pass's store); 2-D grids transform rows then columns.  The
+// first load and the last store of a transform carry the work around it:
+//   LD_DECONV  zero-padding of the centred coefficients onto the M_sigma grid, scaled by D (2.4)
+//   LD_HALO    the spread grid plus the halo strips its neighbouring tiles wrote
+//   ST_DECONV  truncation to the centred M range and scaling by D^* (2.8)
+#include "internal.hpp"
+
+namespace infft {
+
+constexpr int FFT_E32 = 16;  // complex elements per thread (LDS buffer = 256 * E elements)
+constexpr int FFT_E64 = 8;
+
+int fft_capacity(bool fp64) { return FFT_THREADS * (fp64 ? FFT_E64 : FFT_E32); }
+
+// ------------------------------------------------------------------ radix-r DFT, sign -1
+
+template <typename C> __device__ inline C mul_mi(C a) {  // a * (-i)
+    C r;
+    r.x = a.y;
+    r.y = -a.x;
+    return r;
+}
+
+template <typename C, int RADIX> struct Dft;
+
+template <typename C> struct Dft<C, 2> {
+    __device__ static void run(C* v) {
+        const C a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <typename C> struct Dft<C, 4> {
+    __device__ static void run(C* v) {
+        const C t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        const C t2 = cadd(v[1], v[3]), t3 = mul_mi(csub(v[1], v[3]));
+        v[0] = cadd(t0, t2);
+        v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[3] = csub(t1, t3);
+    }
+};
+
+template <typename C> struct Dft<C, 8> {
+    __device__ static void run(C* v) {
+        C e[4] = {v[0], v[2], v[4], v[6]};
+        C o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<C, 4>::run(e);
+        Dft<C, 4>::run(o);
+        using R = decltype(v[0].x);
+        const R h = (R)0.70710678118654752440;
+        // o[k] * e^{-2 pi i k / 8}
+        C o1, o3;
+        o1.x = h * (o[1].x + o[1].y);
+        o1.y = h * (o[1].y - o[1].x);
+        const C o2 = mul_mi(o[2]);
+        o3.x = h * (o[3].y - o[3].x);
+        o3.y = -h * (o[3].x + o[3].y);
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);
+        v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);
+        v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);
+        v[7] = csub(e[3], o3);
+    }
+};
+
+// Odd radices: direct O(r^2) sum with W_r^j = cw[j] + i sw[j] = e^{-2 pi i j / r}
+// (cos and sin of 2 pi j / r from their closed forms: sqrt(3)/2, (sqrt(5) -+ 1)/4, ...).
+template <int RADIX> struct OddW;
+template <> struct OddW<3> {
+    static constexpr double c1 = -0.5, s1 = 0.86602540378443864676;
+    __device__ static double c(int j) { return j == 0 ? 1.0 : c1; }
+    __device__ static double s(int j) { return j == 0 ? 0.0 : (j == 1 ? -s1 : s1); }
+};
+template <> struct OddW<5> {
+    static constexpr double c1 = 0.30901699437494742410, s1 = 0.95105651629515357212;
+    static constexpr double c2 = -0.80901699437494742410, s2 = 0.58778525229247312917;
+    __device__ static double c(int j) { return j == 0 ? 1.0 : (j == 1 || j == 4) ? c1 : c2; }
+    __device__ static double s(int j) {
+        return j == 0 ? 0.0 : j == 1 ? -s1 : j == 2 ? -s2 : j == 3 ? s2 : s1;
+    }
+};
+template <> struct OddW<7> {
+    static constexpr double c1 = 0.62348980185873353053, s1 = 0.78183148246802980871;
+    static constexpr double c2 = -0.22252093395631440429, s2 = 0.97492791218182360702;
+    static constexpr double c3 = -0.90096886790241912624, s3 = 0.43388373911755812048;
+    __device__ static double c(int j) {
+        return j == 0 ? 1.0 : (j == 1 || j == 6) ? c1 : (j == 2 || j == 5) ? c2 : c3;
+    }
+    __device__ static double s(int j) {
+        return j == 0 ? 0.0 : j == 1 ? -s1 : j == 2 ? -s2 : j == 3 ? -s3 : j == 4 ? s3 : j == 5 ? s2 : s1;
+    }
+};
+
+template <typename C, int RADIX> struct DftOdd {
+    __device__ static void run(C* v) {
+        using R = decltype(v[0].x);
+        C out[RADIX];
+#pragma unroll
+        for (int q = 0; q < RADIX; ++q) {
+            C acc = v[0];
+#pragma unroll
+            for (int p = 1; p < RADIX; ++p) {
+                const int j = (p * q) % RADIX;
+                const R cw = (R)OddW<RADIX>::c(j), sw = (R)OddW<RADIX>::s(j);
+                acc.x += v[p].x * cw - v[p].y * sw;
+                acc.y += v[p].x * sw + v[p].y * cw;
+            }
+            out[q] = acc;
+        }
+#pragma unroll
+        for (int q = 0; q < RADIX; ++q) v[q] = out[q];
+    }
+};
+template <typename C> struct Dft<C, 3> : DftOdd<C, 3> {};
+template <typename C> struct Dft<C, 5> : DftOdd<C, 5> {};
+template <typename C> struct Dft<C, 7> : DftOdd<C, 7> {};
+
+// ------------------------------------------------------------------ one Stockham stage in LDS
+
+template <typename R, int RADIX, int E>
+__device__ inline void stage(cx<R>* lds, int ld, int rows, int n, int Ns, int sign,
+                             const cx<R>* __restrict__ tw) {
+    using C = cx<R>;
+    constexpr int CM = (E + RADIX - 1) / RADIX;
+    const int nbr = n / RADIX;
+    const int nb = rows * nbr;
+    C v[CM][RADIX];
+#pragma unroll
+    for (int ci = 0; ci < CM; ++ci) {
+        const int b = threadIdx.x + ci * FFT_THREADS;
+        if (b < nb) {
+            const int row = b / nbr, j = b - row * nbr;
+#pragma unroll
+            for (int q = 0; q < RADIX; ++q) v[ci][q] = lds[row * ld + j + q * nbr];
+        }
+    }
+    __syncthreads();
+    const int tstride = n / (Ns * RADIX);
+#pragma unroll
+    for (int ci = 0; ci < CM; ++ci) {
+        const int b = threadIdx.x + ci * FFT_THREADS;
+        if (b < nb) {
+            const int row = b / nbr, j = b - row * nbr;
+            const int jm = j % Ns;
+#pragma unroll
+            for (int q = 1; q < RADIX; ++q) {
+                C w = tw[q * jm * tstride];
+                if (sign > 0) w.y = -w.y;
+                v[ci][q] = cmul(v[ci][q], w);
+            }
+            if (sign > 0) {
+#pragma unroll
+                for (int q = 0; q < RADIX; ++q) v[ci][q].y = -v[ci][q].y;
+            }
+            Dft<C, RADIX>::run(v[ci]);
+            if (sign > 0) {
+#pragma unroll
+                for (int q = 0; q < RADIX; ++q) v[ci][q].y = -v[ci][q].y;
+            }
+            const int idxD = (j / Ns) * Ns * RADIX + jm;
+#pragma unroll
+            for (int q = 0; q < RADIX; ++q) lds[row * ld + idxD + q * Ns] = v[ci][q];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename R, int E>
+__device__ inline void lds_fft(cx<R>* lds, int ld, int rows, const FftPass& P) {
+    const cx<R>* tw = (const cx<R>*)P.tw;
+    int Ns = 1;
+    for (int s = 0; s < P.nst; ++s) {
+        const int r = P.rad[s];
+        switch (r) {
+            case 2: stage<R, 2, E>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
+            case 3: stage<R, 3, E>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
+            case 4: stage<R, 4, E>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
+            case 5: stage<R, 5, E>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
+            case 7: stage<R, 7, E>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
+            default: stage<R, 8, E>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
+        }
+        Ns *= r;
+    }
+}
+
+// ------------------------------------------------------------------ fused loads / stores
+
+// centred coefficient index of grid position p (or -1 when the frequency is outside the M range)
+__device__ inline int coeff_index(int p, int Ms, int M) {
+    const int k = (p < Ms / 2) ? p : p - Ms;
+    return (k >= -M / 2 && k < M / 2) ? k + M / 2 : -1;
+}
+
+template <typename R, int LD>
+__device__ inline cx<R> load_elem(const FftIO& io, const FftPass& P, const Geo& g, int64_t r, int64_t pos) {
+    using C = cx<R>;
+    if (LD == LD_GRID) {
+        return ((const C*)io.in)[r * P.in_rs + pos];
+    } else if (LD == LD_DECONV) {
+        int p0, p1 = 0;
+        if (g.d == 1) p0 = (int)pos;
+        else { p0 = (int)(pos / g.Ms[1]); p1 = (int)(pos - (int64_t)p0 * g.Ms[1]); }
+        const int i0 = coeff_index(p0, g.Ms[0], g.M[0]);
+        const int i1 = (g.d == 1) ? 0 : coeff_index(p1, g.Ms[1], g.M[1]);
+        if (i0 < 0 || i1 < 0) return cmake((R)0, (R)0);
+        R s = ((const R*)io.D0)[i0];
+        if (g.d == 2) s *= ((const R*)io.D1)[i1];
+        const C v = ((const C*)io.in)[r * P.in_rs + (int64_t)i0 * g.M[1] + i1];
+        return cscale(v, s);
+    } else {  // LD_HALO
+        C v = ((const C*)io.in)[r * P.in_rs + pos];
+        const int w2 = 2 * g.m;
+        int p0, p1 = 0;
+        if (g.d == 1) p0 = (int)pos;
+        else { p0 = (int)(pos / g.Ms[1]); p1 = (int)(pos - (int64_t)p0 * g.Ms[1]); }
+        const int t0 = p0 / g.TS[0], o0 = p0 - t0 * g.TS[0];
+        const int t1 = p1 / g.TS[1], o1 = p1 - t1 * g.TS[1];
+        const int tm0 = (t0 == 0) ? g.ntile[0] - 1 : t0 - 1;
+        const int tm1 = (t1 == 0) ? g.ntile[1] - 1 : t1 - 1;
+        if (o0 < w2) {
+            const int64_t tile = (int64_t)tm0 * g.ntile[1] + t1;
+            v = cadd(v, ((const C*)io.h0)[r * io.halo_rs0 + (tile * w2 + o0) * g.TS[1] + o1]);
+        }
+        if (g.d == 2 && o1 < w2) {
+            const int64_t tile = (int64_t)t0 * g.ntile[1] + tm1;
+            v = cadd(v, ((const C*)io.h1)[r * io.halo_rs1 + (tile * g.TS[0] + o0) * w2 + o1]);
+            if (o0 < w2) {
+                const int64_t tc = (int64_t)tm0 * g.ntile[1] + tm1;
+                v = cadd(v, ((const C*)io.h01)[r * io.halo_rs01 + (tc * w2 + o0) * w2 + o1]);
+            }
+        }
+        return v;
+    }
+}
+
+template <typename R, int ST>
+__device__ inline void store_elem(const FftIO& io, const FftPass& P, const Geo& g, int64_t r, int64_t pos,
+                                  int64_t q, int k, cx<R> v) {
+    using C = cx<R>;
+    if (ST == ST_GRID) {
+        ((C*)io.out)[r * P.out_rs + pos] = v;
+    } else if (ST == ST_TWIDDLE) {
+        const int64_t e = (q * (int64_t)k) % P.twN;
+        const int64_t hi = e / P.twB, lo = e - hi * P.twB;
+        C w = cmul(((const C*)P.twHi)[hi], ((const C*)P.twLo)[lo]);
+        if (P.sign > 0) w.y = -w.y;
+        ((C*)io.out)[r * P.out_rs + pos] = cmul(v, w);
+    } else {  // ST_DECONV
+        int p0, p1 = 0;
+        if (g.d == 1) p0 = (int)pos;
+        else { p0 = (int)(pos / g.Ms[1]); p1 = (int)(pos - (int64_t)p0 * g.Ms[1]); }
+        const int i0 = coeff_index(p0, g.Ms[0], g.M[0]);
+        const int i1 = (g.d == 1) ? 0 : coeff_index(p1, g.Ms[1], g.M[1]);
+        if (i0 < 0 || i1 < 0) return;
+        R s = ((const R*)io.D0)[i0];
+        if (g.d == 2) s *= ((const R*)io.D1)[i1];
+        ((C*)io.out)[r * P.out_rs + (int64_t)i0 * g.M[1] + i1] = cscale(v, s);
+    }
+}
+
+template <typename R, int E, int LD, int ST>
+__global__ void __launch_bounds__(FFT_THREADS) k_fft(FftPass P, FftIO io, Geo g) {
+    extern __shared__ char smem_raw[];
+    cx<R>* lds = (cx<R>*)smem_raw;
+    const int ld = P.n + 1;
+    const int64_t seq0 = blockIdx.x * (int64_t)P.rows;
+    const int rows = (int)min((int64_t)P.rows, P.nseq - seq0);
+    const int tot = rows * P.n;
+    for (int L = threadIdx.x; L < tot; L += FFT_THREADS) {
+        int row, i;
+        if (P.in_rowfast) { row = L % rows; i = L / rows; }
+        else { row = L / P.n; i = L - row * P.n; }
+        const int64_t s = seq0 + row;
+        const int64_t r = s / P.nq, q = s - r * P.nq;
+        lds[row * ld + i] = load_elem<R, LD>(io, P, g, r, q * P.in_qs + (int64_t)i * P.in_is);
+    }
+    __syncthreads();
+    lds_fft<R, E>(lds, ld, rows, P);
+    for (int L = threadIdx.x; L < tot; L += FFT_THREADS) {
+        int row, k;
+        if (P.out_rowfast) { row = L % rows; k = L / rows; }
+        else { row = L / P.n; k = L - row * P.n; }
+        const int64_t s = seq0 + row;
+        const int64_t r = s / P.nq, q = s - r * P.nq;
+        store_elem<R, ST>(io, P, g, r, q * P.out_qs + (int64_t)k * P.out_ks, q, k, lds[row * ld + k]);
+    }
+}
+
+template <typename R>
+void launch_fft_pass(const FftPass& p, const FftIO& io, const Geo& g, int ld, int st, hipStream_t s) {
+    constexpr int E = (sizeof(R) == 8) ? FFT_E64 : FFT_E32;
+    const unsigned blocks = (unsigned)((p.nseq + p.rows - 1) / p.rows);
+    const size_t shm = (size_t)p.rows * (p.n + 1) * sizeof(cx<R>);
+#define INFFT_FFT_CASE(L_, S_)                                                                  \
+    if (ld == L_ && st == S_) {                                                                 \
+        hipLaunchKernelGGL((k_fft<R, E, L_, S_>), dim3(blocks), dim3(FFT_THREADS), shm, s, p, io, g); \
+        return;                                                                                 \
+    }
+    INFFT_FFT_CASE(LD_GRID, ST_GRID)
+    INFFT_FFT_CASE(LD_GRID, ST_TWIDDLE)
+    INFFT_FFT_CASE(LD_GRID, ST_DECONV)
+    INFFT_FFT_CASE(LD_DECONV, ST_GRID)
+    INFFT_FFT_CASE(LD_DECONV, ST_TWIDDLE)
+    INFFT_FFT_CASE(LD_HALO, ST_GRID)
+    INFFT_FFT_CASE(LD_HALO, ST_TWIDDLE)
+    INFFT_FFT_CASE(LD_HALO, ST_DECONV)
+    INFFT_FFT_CASE(LD_DECONV, ST_DECONV)
+#undef INFFT_FFT_CASE
+}
+
+template void launch_fft_pass<float>(const FftPass&, const FftIO&, const Geo&, int, int, hipStream_t);
+template void launch_fft_pass<double>(const FftPass&, const FftIO&, const Geo&, int, int, hipStream_t);
+
+}  // namespace infft

@@ -1,0 +1,199 @@
+// Internal declarations shared by the HIP translation units of libinfft.
+//
+// Grid conventions (Section 2.1 of the paper, tensor product for d = 2):
+//   grid index l_t in 0..M_sigma_t-1 (l mod M_sigma, FFT storage order), row-major over
+//   dimensions (dimension 0 slowest).  Coefficients are centred: index k_t + M_t/2.
+//   Node stencil per dimension: t = x M_sigma, l0 = ceil(t - m), u = t - l0 in (m-1, m];
+//   taps tau = 0..2m reach grid index (l0 + tau) mod M_sigma with window argument u - tau;
+//   a tap is inside the truncated window when |u - tau| <= m.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace infft {
+
+// ------------------------------------------------------------------ complex helpers
+
+template <typename R> struct CxT;
+template <> struct CxT<float> { using T = float2; };
+template <> struct CxT<double> { using T = double2; };
+template <typename R> using cx = typename CxT<R>::T;
+
+__host__ __device__ inline float2 cmake(float a, float b) { return make_float2(a, b); }
+__host__ __device__ inline double2 cmake(double a, double b) { return make_double2(a, b); }
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__host__ __device__ inline float2 cmulc(float2 a, float2 b) {
+    return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__host__ __device__ inline double2 cmulc(double2 a, double2 b) {
+    return make_double2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+__host__ __device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__host__ __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__host__ __device__ inline double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// ------------------------------------------------------------------ plan geometry
+
+constexpr int MAX_D = 2;
+constexpr int MIN_M_CUT = 2;
+constexpr int MAX_M_CUT = 8;   // window cut-off m supported by the compiled kernels
+constexpr int STATUS_WORDS = 8;
+enum StatusWord {
+    ST_NONFINITE = 0,
+    ST_FAILED = 1,
+    ST_EMPTY = 2,
+    ST_OVERSIZED = 3,
+    ST_MIN_N = 4,
+    ST_MAX_N = 5,
+};
+
+struct Geo {
+    int d;
+    int m;
+    int M[MAX_D];      // coefficients per dimension (1 for unused dimensions)
+    int Ms[MAX_D];     // oversampled grid per dimension (1 for unused dimensions)
+    int TS[MAX_D];     // spreading tile, cells per dimension (1 for unused dimensions)
+    int ntile[MAX_D];  // Ms / TS
+    int64_t N;
+    int64_t G;         // prod Ms
+    int64_t P;         // prod M
+    double b;          // Kaiser-Bessel shape pi (2 - 1/sigma)
+};
+
+// Sort key of grid cell (c0, c1): tile-major, row-major inside a tile, so that the nodes of one
+// spreading tile form a contiguous range in sorted order.
+__host__ __device__ inline int64_t cell_key(const Geo& g, int c0, int c1) {
+    if (g.d == 1) return c0;
+    const int t0 = c0 / g.TS[0], t1 = c1 / g.TS[1];
+    const int o0 = c0 - t0 * g.TS[0], o1 = c1 - t1 * g.TS[1];
+    return ((int64_t)t0 * g.ntile[1] + t1) * ((int64_t)g.TS[0] * g.TS[1]) + (int64_t)o0 * g.TS[1] + o1;
+}
+
+struct NodesDev {
+    const double* xw;  // [N][d] wrapped nodes, caller order
+    int* l0c;          // [N][d] stencil base mod M_sigma, caller order
+    double* uc;        // [N][d] offsets u = x M_sigma - l0, caller order
+    int* key;          // [N]    cell key per node, caller order
+    int* perm;         // [N]    sorted position -> caller index
+    int* l0s;          // [N][d] stencil base, sorted order
+    double* us;        // [N][d] offsets, sorted order
+    int* start;        // [G+1]  CSR over cell keys: nodes of key c are start[c]..start[c+1)-1
+};
+
+// Taylor tables of the kernels K (coefficients D_k) and Q (coefficients D_k^2), per dimension,
+// on the grid z = q / TAY_S (grid units), q = 0..qmax; negative arguments use conjugate symmetry.
+constexpr int TAY_S = 16;
+constexpr int TAY_NC = 10;
+struct KTabDev {
+    const double2* K[MAX_D];
+    const double2* Q[MAX_D];
+    int qK, qQ;        // largest table index for K and Q
+    double lam;        // ridge lambda (the same for every l: all diagonal entries of G_l agree)
+    double scaleG;     // prod M_sigma
+};
+
+// ------------------------------------------------------------------ FFT pass description
+
+constexpr int FFT_THREADS = 256;
+constexpr int FFT_MAX_STAGES = 16;
+enum LoadMode { LD_GRID = 0, LD_DECONV = 1, LD_HALO = 2 };
+enum StoreMode { ST_GRID = 0, ST_TWIDDLE = 1, ST_DECONV = 2 };
+
+struct FftPass {
+    int n;             // sub-transform length
+    int rows;          // sub-transforms per workgroup
+    int nst;           // number of Stockham stages
+    int rad[FFT_MAX_STAGES];
+    int sign;          // exponent sign: +1 (F) or -1 (F^*)
+    int64_t nq;        // sub-transforms per right-hand side
+    int64_t nseq;      // total sub-transforms (nq * nrhs)
+    int64_t in_rs, in_qs, in_is;    // input offset  = r*in_rs + q*in_qs + i*in_is
+    int64_t out_rs, out_qs, out_ks; // output offset = r*out_rs + q*out_qs + k*out_ks
+    int in_rowfast, out_rowfast;    // thread mapping for coalescing
+    const void* tw;    // e^{-2 pi i e / n}, e = 0..n-1
+    // inter-pass twiddle omega_N^{sign * q * k}, from two tables: e = hi * twB + lo
+    int64_t twN;
+    int twB;
+    const void* twLo;  // e^{-2 pi i lo / N}, lo < twB
+    const void* twHi;  // e^{-2 pi i hi twB / N}
+};
+
+struct FftIO {
+    const void* in;
+    void* out;
+    const void* D0;    // deconvolution factors (plan precision), length M0
+    const void* D1;    // length M1 (d = 2)
+    const void* h0;    // halo overflowing dimension 0: [r][tile][2m][TS1]
+    const void* h1;    // halo overflowing dimension 1: [r][tile][TS0][2m]
+    const void* h01;   // corner: [r][tile][2m][2m]
+    int64_t halo_rs0, halo_rs1, halo_rs01;  // per right-hand side strides of the halos
+};
+
+// ------------------------------------------------------------------ launchers (per .hip file)
+
+// nodes.hip
+void launch_fill_i32(int* p, int64_t n, int v, hipStream_t s);
+void launch_fill_bytes0(void* p, int64_t nbytes, hipStream_t s);
+void launch_prep_nodes(const Geo& g, const double* x, NodesDev nd, int* counts, long long* status,
+                       hipStream_t s);
+void launch_exclusive_scan(const int* in, int* out, int64_t n, int* blocksums, hipStream_t s);
+int64_t scan_blocksum_len(int64_t n);
+void launch_scatter_nodes(const Geo& g, NodesDev nd, int* fill, hipStream_t s);
+void launch_export_B(const Geo& g, const int* perm, const double2* B, double2* rows, hipStream_t s);
+void launch_status_init(long long* status, int keep_node_words, hipStream_t s);
+
+// tables.hip
+void launch_deconv_table(int M, int Ms, int m, double b, double* D64, float* D32, hipStream_t s);
+void launch_twiddles(int64_t n, double2* t64, float2* t32, hipStream_t s);
+void launch_twiddles_strided(int64_t N, int64_t count, int64_t step, double2* t64, float2* t32,
+                             hipStream_t s);
+void launch_taylor_table(int M, int Ms, const double* D, int power, int qmax, double2* tab,
+                         hipStream_t s);
+
+// fft.hip
+template <typename R>
+void launch_fft_pass(const FftPass& p, const FftIO& io, const Geo& g, int ld, int st, hipStream_t s);
+int fft_capacity(bool fp64);   // elements of one workgroup's LDS transform buffer
+
+// spread.hip
+template <typename R>
+void launch_interp(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grid_rs, cx<R>* f,
+                   int nrhs, hipStream_t s);
+template <typename R>
+void launch_spread(const Geo& g, NodesDev nd, const cx<R>* f, const cx<R>* B, cx<R>* grid,
+                   int64_t grid_rs, cx<R>* h0, cx<R>* h1, cx<R>* h01, int64_t hrs0, int64_t hrs1,
+                   int64_t hrs01, int nrhs, int rchunk, hipStream_t s);
+template <typename R>
+void launch_interp_B(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grid_rs, const cx<R>* B,
+                     cx<R>* f, int nrhs, hipStream_t s);
+template <typename R>
+void launch_grad_x(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grid_rs, const cx<R>* gradf,
+                   double* gradx, int nrhs, int accumulate, hipStream_t s);
+int spread_rhs_chunk(const Geo& g, bool fp64);
+
+// solve.hip
+struct SolveArgs {
+    const int* in_list;     // nullptr: all grid indices in order
+    const int* in_count;
+    int* out_list;          // problems too large for this tier
+    int* out_count;
+    double2* B64;           // [T][N] sorted order
+    float2* B32;            // [T][N] sorted order (nullptr for FP64 plans)
+    long long* status;
+};
+void launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl, hipStream_t s);
+int solve_max_supported();
+
+}  // namespace infft

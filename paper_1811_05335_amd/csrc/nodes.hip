@@ -1,0 +1,222 @@
+// Node preprocessing: wrap onto the torus, stencil base and offset per dimension, counting sort
+// of the nodes by grid cell (tile-major keys), and the CSR over cells from which both the
+// spreading tiles and the grid-index -> node lists I(l) of (3.29) are read.
+#include "internal.hpp"
+
+#include <limits.h>
+
+namespace infft {
+
+__global__ void k_fill_i32(int* p, int64_t n, int v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u32(uint32_t* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+static int grid_for(int64_t n, int threads, int cap = 65536) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+void launch_fill_i32(int* p, int64_t n, int v, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, p, n, v);
+}
+
+void launch_fill_bytes0(void* p, int64_t nbytes, hipStream_t s) {
+    if (nbytes <= 0) return;
+    // all workspace regions are 4-byte multiples
+    const int64_t n = nbytes / 4;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, (uint32_t*)p, n);
+}
+
+__global__ void k_status_init(long long* st, int keep_node_words) {
+    const int i = threadIdx.x;
+    if (i >= STATUS_WORDS || (keep_node_words && i == ST_NONFINITE)) return;
+    st[i] = (i == ST_MIN_N) ? LLONG_MAX : 0;
+}
+
+void launch_status_init(long long* status, int keep_node_words, hipStream_t s) {
+    hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, s, status, keep_node_words);
+}
+
+// Per node: wrap, t = x M_sigma, l0 = ceil(t - m), u = t - l0.  The float64 operations are
+// kept separate (no contraction into fused multiply-adds) so the stencil, and therefore the
+// sparsity pattern of B and B_opt, follows exactly these roundings.
+template <int D>
+__global__ void k_prep(Geo g, const double* __restrict__ x, NodesDev nd, int* __restrict__ counts,
+                       long long* status) {
+#pragma clang fp contract(off)
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= g.N) return;
+    int c[2] = {0, 0};
+    bool bad = false;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        double xv = x[j * D + t];
+        if (!isfinite(xv)) {
+            bad = true;
+            xv = 0.0;
+        }
+        const double xw = xv - floor(xv + 0.5);
+        const double tt = xw * (double)g.Ms[t];
+        const double l0 = ceil(tt - (double)g.m);
+        const double u = tt - l0;
+        int lm = (int)l0 % g.Ms[t];
+        if (lm < 0) lm += g.Ms[t];
+        ((double*)nd.xw)[j * D + t] = xw;
+        nd.l0c[j * D + t] = lm;
+        nd.uc[j * D + t] = u;
+        c[t] = lm;
+    }
+    if (bad) atomicAdd((unsigned long long*)&status[ST_NONFINITE], 1ull);
+    const int key = (int)cell_key(g, c[0], c[1]);
+    nd.key[j] = key;
+    atomicAdd(&counts[key], 1);
+}
+
+void launch_prep_nodes(const Geo& g, const double* x, NodesDev nd, int* counts, long long* status,
+                       hipStream_t s) {
+    const int blocks = (int)((g.N + 255) / 256);
+    if (g.d == 1)
+        hipLaunchKernelGGL(k_prep<1>, dim3(blocks), dim3(256), 0, s, g, x, nd, counts, status);
+    else
+        hipLaunchKernelGGL(k_prep<2>, dim3(blocks), dim3(256), 0, s, g, x, nd, counts, status);
+}
+
+template <int D>
+__global__ void k_scatter(Geo g, NodesDev nd, int* __restrict__ fill) {
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= g.N) return;
+    const int key = nd.key[j];
+    const int pos = nd.start[key] + atomicAdd(&fill[key], 1);
+    nd.perm[pos] = (int)j;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        nd.l0s[(int64_t)pos * D + t] = nd.l0c[j * D + t];
+        nd.us[(int64_t)pos * D + t] = nd.uc[j * D + t];
+    }
+}
+
+void launch_scatter_nodes(const Geo& g, NodesDev nd, int* fill, hipStream_t s) {
+    const int blocks = (int)((g.N + 255) / 256);
+    if (g.d == 1)
+        hipLaunchKernelGGL(k_scatter<1>, dim3(blocks), dim3(256), 0, s, g, nd, fill);
+    else
+        hipLaunchKernelGGL(k_scatter<2>, dim3(blocks), dim3(256), 0, s, g, nd, fill);
+}
+
+// ------------------------------------------------------------------ exclusive scan
+// Three passes: per-block scan (256 threads x 8 items), scan of the block totals in one block,
+// then the block offsets are added.  out has n+1 entries (out[n] = total).
+
+constexpr int SCAN_T = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_BLOCK = SCAN_T * SCAN_ITEMS;
+
+__device__ inline int block_exclusive_scan(int v, int* sh, int* total) {
+    // inclusive scan inside each wave, then across the 4 wave totals
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) sh[wave] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_T / 64; ++w) {
+        const int s = sh[w];
+        if (w < wave) off += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ void k_scan1(const int* __restrict__ in, int* __restrict__ out, int64_t n, int* bsum) {
+    __shared__ int sh[SCAN_T / 64];
+    const int64_t base = blockIdx.x * (int64_t)SCAN_BLOCK + threadIdx.x * SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = (base + i < n) ? in[base + i] : 0;
+        s += v[i];
+    }
+    int total;
+    int run = block_exclusive_scan(s, sh, &total);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ void k_scan2(int* bsum, int64_t nb) {
+    __shared__ int sh[SCAN_T / 64];
+    const int64_t base = threadIdx.x * (int64_t)SCAN_ITEMS;
+    int v[SCAN_ITEMS];
+    int s = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        v[i] = (base + i < nb) ? bsum[base + i] : 0;
+        s += v[i];
+    }
+    int total;
+    int run = block_exclusive_scan(s, sh, &total);
+#pragma unroll
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        if (base + i < nb) bsum[base + i] = run;
+        run += v[i];
+    }
+    if (threadIdx.x == 0) bsum[nb] = total;
+}
+
+__global__ void k_scan3(int* __restrict__ out, int64_t n, const int* __restrict__ bsum, int64_t nb) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) out[i] += bsum[i / SCAN_BLOCK];
+    if (i == n) out[n] = bsum[nb];
+}
+
+int64_t scan_blocksum_len(int64_t n) { return (n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1; }
+
+void launch_exclusive_scan(const int* in, int* out, int64_t n, int* blocksums, hipStream_t s) {
+    const int64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    hipLaunchKernelGGL(k_scan1, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, out, n, blocksums);
+    hipLaunchKernelGGL(k_scan2, dim3(1), dim3(SCAN_T), 0, s, blocksums, nb);
+    hipLaunchKernelGGL(k_scan3, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s, out, n,
+                       (const int*)blocksums, nb);
+}
+
+// ------------------------------------------------------------------ B_opt export
+
+__global__ void k_export_B(int64_t N, int T, const int* __restrict__ perm, const double2* __restrict__ B,
+                           double2* __restrict__ rows) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= N * T) return;
+    const int64_t tau = i / N, p = i - tau * N;
+    rows[(int64_t)perm[p] * T + tau] = B[i];
+}
+
+void launch_export_B(const Geo& g, const int* perm, const double2* B, double2* rows, hipStream_t s) {
+    int T = 2 * g.m + 1;
+    if (g.d == 2) T *= T;
+    const int64_t n = g.N * T;
+    hipLaunchKernelGGL(k_export_B, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, g.N, T, perm, B,
+                       rows);
+}
+
+}  // namespace infft

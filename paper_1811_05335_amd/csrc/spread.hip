@@ -1,0 +1,397 @@
+// The sparse factor B of the NFFT (2.6) and its optimised replacement B_opt (Algorithm 3.17):
+//   interp     f_j = sum_tau g[l0_j + tau] w~_m(x_j - l/M_sigma)           (last step of A ~ BFD)
+//   spread     g~_l = sum_j f_j w~_m(x_j - l/M_sigma)  or  sum_j conj(B_opt[j,l]) f_j
+//              (first step of the adjoint (2.8) and of the modified adjoint (3.32))
+//   interp_B   f_j = sum_tau B_opt[j, tau] g[l0_j + tau]                    (B_opt F D, Remark 3.24)
+//   grad_x     d/dx_j of the interpolation through the window derivative
+//
+// The Kaiser-Bessel window w(v) = sinh(b sqrt(m^2 - v^2)) / (pi sqrt(m^2 - v^2)) is evaluated in
+// registers; whether a tap lies in the closed support |v| <= m is decided in float64 from the
+// stored offsets for both precisions.
+//
+// Spreading runs one workgroup per grid tile (TS0 x TS1 cells).  The nodes of a tile are a
+// contiguous range of the sorted node order; their contributions are accumulated with LDS
+// atomics into the tile plus a 2m-wide halo on the + side of each dimension.  The tile interior
+// is then written with plain stores and the halo strips to separate buffers, which the first
+// pass of the following FFT adds in (no global atomics, no zero-fill of the grid).
+#include "internal.hpp"
+
+namespace infft {
+
+template <typename R> __device__ inline R kb_window(R v, int m, R b);
+
+template <> __device__ inline float kb_window<float>(float v, int m, float b) {
+    const float t2 = ((float)m - v) * ((float)m + v);
+    const float t = sqrtf(fmaxf(t2, 0.0f));
+    return t > 0.0f ? sinhf(b * t) / (3.14159265358979323846f * t) : b / 3.14159265358979323846f;
+}
+template <> __device__ inline double kb_window<double>(double v, int m, double b) {
+    const double t2 = ((double)m - v) * ((double)m + v);
+    const double t = sqrt(fmax(t2, 0.0));
+    return t > 0.0 ? sinh(b * t) / (M_PI * t) : b / M_PI;
+}
+
+// d w / d v inside the support: -v (x cosh x - sinh x) / (pi t^3) with x = b t, t = sqrt(m^2 - v^2),
+// written as
+// -v b^3 r(x) / pi, r(x) = (x cosh x - sinh x)/x^3 = sum_{n>=1} 2n x^(2n-2) / (2n+1)!.
+template <typename R> __device__ inline R kb_window_deriv(R v, int m, R b) {
+    const R t2 = ((R)m - v) * ((R)m + v);
+    const R t = sqrt(t2 > (R)0 ? t2 : (R)0);
+    const R x = b * t;
+    const R thr = (sizeof(R) == 8) ? (R)0.1 : (R)0.5;
+    R r;
+    if (x < thr) {
+        const R x2 = x * x;
+        r = (R)(1.0 / 3) + x2 * ((R)(1.0 / 30) + x2 * ((R)(1.0 / 840) + x2 * ((R)(1.0 / 45360) + x2 * (R)(1.0 / 3991680))));
+    } else {
+        r = (x * cosh(x) - sinh(x)) / (x * x * x);
+    }
+    return -v * b * b * b * r / (R)M_PI;
+}
+
+template <typename R, int W>
+__device__ inline void window_row(double u, int m, R b, R* w) {
+#pragma unroll
+    for (int tau = 0; tau < W; ++tau) {
+        const double vd = u - (double)tau;
+        w[tau] = (fabs(vd) <= (double)m) ? kb_window<R>((R)vd, m, b) : (R)0;
+    }
+}
+
+template <typename R, int W>
+__device__ inline void window_deriv_row(double u, int m, R b, R scale, R* dw) {
+#pragma unroll
+    for (int tau = 0; tau < W; ++tau) {
+        const double vd = u - (double)tau;
+        dw[tau] = (fabs(vd) <= (double)m) ? scale * kb_window_deriv<R>((R)vd, m, b) : (R)0;
+    }
+}
+
+__device__ inline int wrap_add(int a, int t, int Ms) {
+    const int v = a + t;
+    return v >= Ms ? v - Ms : v;
+}
+
+// ------------------------------------------------------------------ interpolation (trafo)
+
+template <typename R, int D, int W>
+__global__ void __launch_bounds__(256) k_interp(Geo g, NodesDev nd, const cx<R>* __restrict__ grid,
+                                                int64_t grs, cx<R>* __restrict__ f, int nrhs) {
+    using C = cx<R>;
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= g.N) return;
+    const R b = (R)g.b;
+    R w0[W], w1[W];
+    window_row<R, W>(nd.uc[j * D], g.m, b, w0);
+    const int a0 = nd.l0c[j * D];
+    int a1 = 0;
+    if (D == 2) {
+        window_row<R, W>(nd.uc[j * D + 1], g.m, b, w1);
+        a1 = nd.l0c[j * D + 1];
+    }
+    for (int r = 0; r < nrhs; ++r) {
+        const C* gr = grid + r * grs;
+        C acc = cmake((R)0, (R)0);
+        if (D == 1) {
+#pragma unroll
+            for (int t = 0; t < W; ++t) {
+                const C v = gr[wrap_add(a0, t, g.Ms[0])];
+                acc.x += w0[t] * v.x;
+                acc.y += w0[t] * v.y;
+            }
+        } else {
+#pragma unroll
+            for (int t0 = 0; t0 < W; ++t0) {
+                const C* row = gr + (int64_t)wrap_add(a0, t0, g.Ms[0]) * g.Ms[1];
+                C s = cmake((R)0, (R)0);
+#pragma unroll
+                for (int t1 = 0; t1 < W; ++t1) {
+                    const C v = row[wrap_add(a1, t1, g.Ms[1])];
+                    s.x += w1[t1] * v.x;
+                    s.y += w1[t1] * v.y;
+                }
+                acc.x += w0[t0] * s.x;
+                acc.y += w0[t0] * s.y;
+            }
+        }
+        f[r * g.N + j] = acc;
+    }
+}
+
+// ------------------------------------------------------------------ interpolation with B_opt
+
+template <typename R, int D, int W>
+__global__ void __launch_bounds__(256) k_interp_B(Geo g, NodesDev nd, const cx<R>* __restrict__ grid,
+                                                  int64_t grs, const cx<R>* __restrict__ B,
+                                                  cx<R>* __restrict__ f, int nrhs) {
+    using C = cx<R>;
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= g.N) return;
+    const int j = nd.perm[p];
+    const int a0 = nd.l0s[p * D];
+    const int a1 = (D == 2) ? nd.l0s[p * D + 1] : 0;
+    for (int r = 0; r < nrhs; ++r) {
+        const C* gr = grid + r * grs;
+        C acc = cmake((R)0, (R)0);
+#pragma unroll
+        for (int t0 = 0; t0 < W; ++t0) {
+            if (D == 1) {
+                const C wv = B[(int64_t)t0 * g.N + p];
+                const C v = gr[wrap_add(a0, t0, g.Ms[0])];
+                acc = cadd(acc, cmul(wv, v));
+            } else {
+                const C* row = gr + (int64_t)wrap_add(a0, t0, g.Ms[0]) * g.Ms[1];
+#pragma unroll
+                for (int t1 = 0; t1 < W; ++t1) {
+                    const C wv = B[(int64_t)(t0 * W + t1) * g.N + p];
+                    acc = cadd(acc, cmul(wv, row[wrap_add(a1, t1, g.Ms[1])]));
+                }
+            }
+        }
+        f[r * g.N + j] = acc;
+    }
+}
+
+// ------------------------------------------------------------------ tiled spreading
+
+template <typename R> __device__ inline void lds_add(R* p, R v) { atomicAdd(p, v); }
+
+template <typename R, int D, int W, bool USEB>
+__global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>* __restrict__ f,
+                                                const cx<R>* __restrict__ B, cx<R>* __restrict__ grid,
+                                                int64_t grs, cx<R>* __restrict__ h0, cx<R>* __restrict__ h1,
+                                                cx<R>* __restrict__ h01, int64_t hrs0, int64_t hrs1,
+                                                int64_t hrs01, int nrhs, int rchunk) {
+    using C = cx<R>;
+    extern __shared__ char smem_raw[];
+    R* acc = (R*)smem_raw;  // [rc][E0][E1][2]
+    const int w2 = 2 * g.m;
+    const int tile = blockIdx.x;
+    const int t0 = (D == 2) ? tile / g.ntile[1] : tile;
+    const int t1 = (D == 2) ? tile - t0 * g.ntile[1] : 0;
+    const int TS0 = g.TS[0], TS1 = (D == 2) ? g.TS[1] : 1;
+    const int E0 = TS0 + w2, E1 = (D == 2) ? TS1 + w2 : 1;
+    const int cells = E0 * E1;
+    const int base0 = t0 * TS0, base1 = t1 * TS1;
+    const int64_t kbeg = (int64_t)tile * TS0 * TS1;
+    const int pbeg = nd.start[kbeg], pend = nd.start[kbeg + (int64_t)TS0 * TS1];
+    const R b = (R)g.b;
+
+    for (int r0 = 0; r0 < nrhs; r0 += rchunk) {
+        const int rc = min(rchunk, nrhs - r0);
+        for (int c = threadIdx.x; c < 2 * rc * cells; c += blockDim.x) acc[c] = (R)0;
+        __syncthreads();
+        for (int p = pbeg + threadIdx.x; p < pend; p += blockDim.x) {
+            const int j = nd.perm[p];
+            const int a0 = nd.l0s[(int64_t)p * D] - base0;
+            const int a1 = (D == 2) ? nd.l0s[(int64_t)p * D + 1] - base1 : 0;
+            R w0[W], w1[W];
+            if (!USEB) {
+                window_row<R, W>(nd.us[(int64_t)p * D], g.m, b, w0);
+                if (D == 2) window_row<R, W>(nd.us[(int64_t)p * D + 1], g.m, b, w1);
+            }
+            for (int rr = 0; rr < rc; ++rr) {
+                const C fv = f[(int64_t)(r0 + rr) * g.N + j];
+                R* a = acc + (int64_t)rr * cells * 2;
+                if (D == 1) {
+#pragma unroll
+                    for (int t = 0; t < W; ++t) {
+                        C v;
+                        if (USEB) v = cmulc(fv, B[(int64_t)t * g.N + p]);
+                        else v = cscale(fv, w0[t]);
+                        lds_add(&a[2 * (a0 + t)], v.x);
+                        lds_add(&a[2 * (a0 + t) + 1], v.y);
+                    }
+                } else {
+#pragma unroll
+                    for (int s0 = 0; s0 < W; ++s0) {
+                        C fs;
+                        if (!USEB) fs = cscale(fv, w0[s0]);
+#pragma unroll
+                        for (int s1 = 0; s1 < W; ++s1) {
+                            C v;
+                            if (USEB) v = cmulc(fv, B[(int64_t)(s0 * W + s1) * g.N + p]);
+                            else v = cscale(fs, w1[s1]);
+                            const int cidx = (a0 + s0) * E1 + (a1 + s1);
+                            lds_add(&a[2 * cidx], v.x);
+                            lds_add(&a[2 * cidx + 1], v.y);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < rc * cells; c += blockDim.x) {
+            const int rr = c / cells, cc = c - rr * cells;
+            const int e0 = cc / E1, e1 = cc - e0 * E1;
+            const C v = cmake(acc[2 * c], acc[2 * c + 1]);
+            const int64_t r = r0 + rr;
+            if (e0 < TS0 && e1 < TS1) {
+                grid[r * grs + (int64_t)(base0 + e0) * g.Ms[1] + (base1 + e1)] = v;
+            } else if (e0 >= TS0 && e1 < TS1) {
+                h0[r * hrs0 + ((int64_t)tile * w2 + (e0 - TS0)) * TS1 + e1] = v;
+            } else if (e0 < TS0) {
+                h1[r * hrs1 + ((int64_t)tile * TS0 + e0) * w2 + (e1 - TS1)] = v;
+            } else {
+                h01[r * hrs01 + ((int64_t)tile * w2 + (e0 - TS0)) * w2 + (e1 - TS1)] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ gradient with respect to x
+
+template <typename R, int D, int W>
+__global__ void __launch_bounds__(256) k_grad_x(Geo g, NodesDev nd, const cx<R>* __restrict__ grid,
+                                                int64_t grs, const cx<R>* __restrict__ gradf,
+                                                double* __restrict__ gradx, int nrhs, int accumulate) {
+    using C = cx<R>;
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= g.N) return;
+    const R b = (R)g.b;
+    R w0[W], w1[W], d0[W], d1[W];
+    window_row<R, W>(nd.uc[j * D], g.m, b, w0);
+    window_deriv_row<R, W>(nd.uc[j * D], g.m, b, (R)g.Ms[0], d0);
+    const int a0 = nd.l0c[j * D];
+    int a1 = 0;
+    if (D == 2) {
+        window_row<R, W>(nd.uc[j * D + 1], g.m, b, w1);
+        window_deriv_row<R, W>(nd.uc[j * D + 1], g.m, b, (R)g.Ms[1], d1);
+        a1 = nd.l0c[j * D + 1];
+    }
+    R gx0 = 0, gx1 = 0;
+    for (int r = 0; r < nrhs; ++r) {
+        const C* gr = grid + r * grs;
+        C s0 = cmake((R)0, (R)0), s1 = cmake((R)0, (R)0);
+        if (D == 1) {
+#pragma unroll
+            for (int t = 0; t < W; ++t) {
+                const C v = gr[wrap_add(a0, t, g.Ms[0])];
+                s0.x += d0[t] * v.x;
+                s0.y += d0[t] * v.y;
+            }
+        } else {
+#pragma unroll
+            for (int t0 = 0; t0 < W; ++t0) {
+                const C* row = gr + (int64_t)wrap_add(a0, t0, g.Ms[0]) * g.Ms[1];
+                C sw = cmake((R)0, (R)0), sd = cmake((R)0, (R)0);
+#pragma unroll
+                for (int t1 = 0; t1 < W; ++t1) {
+                    const C v = row[wrap_add(a1, t1, g.Ms[1])];
+                    sw.x += w1[t1] * v.x;
+                    sw.y += w1[t1] * v.y;
+                    sd.x += d1[t1] * v.x;
+                    sd.y += d1[t1] * v.y;
+                }
+                s0.x += d0[t0] * sw.x;
+                s0.y += d0[t0] * sw.y;
+                s1.x += w0[t0] * sd.x;
+                s1.y += w0[t0] * sd.y;
+            }
+        }
+        const C gf = gradf[r * g.N + j];
+        gx0 += gf.x * s0.x + gf.y * s0.y;
+        if (D == 2) gx1 += gf.x * s1.x + gf.y * s1.y;
+    }
+    if (accumulate) {
+        gradx[j * D] += (double)gx0;
+        if (D == 2) gradx[j * D + 1] += (double)gx1;
+    } else {
+        gradx[j * D] = (double)gx0;
+        if (D == 2) gradx[j * D + 1] = (double)gx1;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+#define INFFT_DISPATCH_W(m, ...)                 \
+    switch (m) {                                 \
+        case 2: { constexpr int W = 5; __VA_ARGS__; } break;  \
+        case 3: { constexpr int W = 7; __VA_ARGS__; } break;  \
+        case 4: { constexpr int W = 9; __VA_ARGS__; } break;  \
+        case 5: { constexpr int W = 11; __VA_ARGS__; } break; \
+        case 6: { constexpr int W = 13; __VA_ARGS__; } break; \
+        case 7: { constexpr int W = 15; __VA_ARGS__; } break; \
+        default: { constexpr int W = 17; __VA_ARGS__; } break; \
+    }
+
+template <typename R>
+void launch_interp(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grs, cx<R>* f, int nrhs,
+                   hipStream_t s) {
+    const unsigned blocks = (unsigned)((g.N + 255) / 256);
+    if (g.d == 1) {
+        INFFT_DISPATCH_W(g.m, hipLaunchKernelGGL((k_interp<R, 1, W>), dim3(blocks), dim3(256), 0, s, g, nd,
+                                                 grid, grs, f, nrhs))
+    } else {
+        INFFT_DISPATCH_W(g.m, hipLaunchKernelGGL((k_interp<R, 2, W>), dim3(blocks), dim3(256), 0, s, g, nd,
+                                                 grid, grs, f, nrhs))
+    }
+}
+
+template <typename R>
+void launch_interp_B(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grs, const cx<R>* B, cx<R>* f,
+                     int nrhs, hipStream_t s) {
+    const unsigned blocks = (unsigned)((g.N + 255) / 256);
+    if (g.d == 1) {
+        INFFT_DISPATCH_W(g.m, hipLaunchKernelGGL((k_interp_B<R, 1, W>), dim3(blocks), dim3(256), 0, s, g,
+                                                 nd, grid, grs, B, f, nrhs))
+    } else {
+        INFFT_DISPATCH_W(g.m, hipLaunchKernelGGL((k_interp_B<R, 2, W>), dim3(blocks), dim3(256), 0, s, g,
+                                                 nd, grid, grs, B, f, nrhs))
+    }
+}
+
+int spread_rhs_chunk(const Geo& g, bool fp64) {
+    const int64_t cells = (int64_t)(g.TS[0] + 2 * g.m) * (g.d == 2 ? g.TS[1] + 2 * g.m : 1);
+    const int64_t per = cells * (fp64 ? 16 : 8);
+    int rc = (int)((48 * 1024) / per);
+    if (rc < 1) rc = 1;
+    if (rc > 16) rc = 16;
+    return rc;
+}
+
+template <typename R>
+void launch_spread(const Geo& g, NodesDev nd, const cx<R>* f, const cx<R>* B, cx<R>* grid, int64_t grs,
+                   cx<R>* h0, cx<R>* h1, cx<R>* h01, int64_t hrs0, int64_t hrs1, int64_t hrs01, int nrhs,
+                   int rchunk, hipStream_t s) {
+    const unsigned blocks = (unsigned)(g.ntile[0] * (g.d == 2 ? g.ntile[1] : 1));
+    const int64_t cells = (int64_t)(g.TS[0] + 2 * g.m) * (g.d == 2 ? g.TS[1] + 2 * g.m : 1);
+    const int rc = min(rchunk, nrhs);
+    const size_t shm = (size_t)rc * cells * sizeof(cx<R>);
+#define INFFT_SPREAD(D_, USEB_)                                                                   \
+    INFFT_DISPATCH_W(g.m, hipLaunchKernelGGL((k_spread<R, D_, W, USEB_>), dim3(blocks), dim3(256), shm, s, \
+                                             g, nd, f, B, grid, grs, h0, h1, h01, hrs0, hrs1, hrs01, nrhs, rc))
+    if (g.d == 1) {
+        if (B) { INFFT_SPREAD(1, true) } else { INFFT_SPREAD(1, false) }
+    } else {
+        if (B) { INFFT_SPREAD(2, true) } else { INFFT_SPREAD(2, false) }
+    }
+#undef INFFT_SPREAD
+}
+
+template <typename R>
+void launch_grad_x(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grs, const cx<R>* gradf,
+                   double* gradx, int nrhs, int accumulate, hipStream_t s) {
+    const unsigned blocks = (unsigned)((g.N + 255) / 256);
+    if (g.d == 1) {
+        INFFT_DISPATCH_W(g.m, hipLaunchKernelGGL((k_grad_x<R, 1, W>), dim3(blocks), dim3(256), 0, s, g, nd,
+                                                 grid, grs, gradf, gradx, nrhs, accumulate))
+    } else {
+        INFFT_DISPATCH_W(g.m, hipLaunchKernelGGL((k_grad_x<R, 2, W>), dim3(blocks), dim3(256), 0, s, g, nd,
+                                                 grid, grs, gradf, gradx, nrhs, accumulate))
+    }
+}
+
+#define INFFT_INST(R)                                                                                  \
+    template void launch_interp<R>(const Geo&, NodesDev, const cx<R>*, int64_t, cx<R>*, int, hipStream_t); \
+    template void launch_interp_B<R>(const Geo&, NodesDev, const cx<R>*, int64_t, const cx<R>*, cx<R>*, int, \
+                                     hipStream_t);                                                     \
+    template void launch_spread<R>(const Geo&, NodesDev, const cx<R>*, const cx<R>*, cx<R>*, int64_t, cx<R>*, \
+                                   cx<R>*, cx<R>*, int64_t, int64_t, int64_t, int, int, hipStream_t);  \
+    template void launch_grad_x<R>(const Geo&, NodesDev, const cx<R>*, int64_t, const cx<R>*, double*, int, \
+                                   int, hipStream_t);
+INFFT_INST(float)
+INFFT_INST(double)
+
+}  // namespace infft

@@ -1,0 +1,214 @@
+"""Python binding of the C ABI: argument marshalling only.  Every step of the transforms runs
+in the HIP library; torch supplies device memory and the stream."""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import Options, Status, check, load
+
+
+def _stream_handle() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: torch.Tensor) -> int:
+    return t.data_ptr()
+
+
+class NfftPlan:
+    """A plan of the direct inverse NFFT for fixed nodes (see include/infft.h).
+
+    M          coefficients per dimension (even), tuple of length d in {1, 2}
+    x          nodes, float64 tensor (N, d) on the GPU (wrapped onto the torus by the library)
+    sigma, m   oversampling factor and window cut-off
+    precision  "f32" (complex64 data, FP32 spreading/FFT) or "f64" (complex128)
+    rho        ridge of the local least-squares problems of the B optimisation
+    """
+
+    def __init__(self, M, x: torch.Tensor, sigma: float = 2.0, m: int = 4, precision: str = "f64",
+                 rho: float = 1e-8, max_rhs: int = 1, tile=None):
+        lib = load()
+        self.M = tuple(int(v) for v in (M if isinstance(M, (tuple, list)) else (M,)))
+        self.d = len(self.M)
+        x = self._nodes(x)
+        self.N = x.shape[0]
+        self.sigma, self.m = float(sigma), int(m)
+        self.precision = precision
+        self.ctype = torch.complex64 if precision == "f32" else torch.complex128
+        self.taps = (2 * self.m + 1) ** self.d
+        o = Options()
+        lib.infft_default_options(C.byref(o))
+        o.precision = _lib.INFFT_F32 if precision == "f32" else _lib.INFFT_F64
+        o.max_rhs = int(max_rhs)
+        o.rho = float(rho)
+        if tile is not None:
+            for t, v in enumerate(tile):
+                o.tile[t] = int(v)
+        Ms = (C.c_int64 * self.d)(*self.M)
+        h = C.c_void_p()
+        check(lib.nfft_plan(C.byref(h), self.d, Ms, self.N, self.sigma, self.m, C.c_void_p(_ptr(x)),
+                            C.byref(o), C.c_void_p(_stream_handle())))
+        self._h = h
+        self._x = x
+        self.device = x.device
+
+    # -------------------------------------------------------------- helpers
+    def _nodes(self, x: torch.Tensor) -> torch.Tensor:
+        if not x.is_cuda or x.dtype != torch.float64:
+            raise TypeError("x must be a float64 CUDA tensor")
+        if x.dim() == 1:
+            x = x[:, None]
+        if x.shape[1] != self.d:
+            raise ValueError(f"x must have shape (N, {self.d})")
+        return x.contiguous()
+
+    def _sync_stream(self):
+        check(load().nfft_set_stream(self._h, C.c_void_p(_stream_handle())))
+
+    def _coeffs(self, a: torch.Tensor):
+        if a.dtype != self.ctype or not a.is_cuda:
+            raise TypeError(f"expected a {self.ctype} CUDA tensor")
+        if tuple(a.shape[-self.d:]) != self.M:
+            raise ValueError(f"trailing shape must be {self.M}")
+        lead = a.shape[: a.dim() - self.d]
+        R = 1
+        for v in lead:
+            R *= int(v)
+        return a.contiguous(), lead, R
+
+    def _samples(self, a: torch.Tensor):
+        if a.dtype != self.ctype or not a.is_cuda:
+            raise TypeError(f"expected a {self.ctype} CUDA tensor")
+        if a.shape[-1] != self.N:
+            raise ValueError(f"last dimension must be N = {self.N}")
+        lead = a.shape[:-1]
+        R = 1
+        for v in lead:
+            R *= int(v)
+        return a.contiguous(), lead, R
+
+    # -------------------------------------------------------------- entry points
+    def set_nodes(self, x: torch.Tensor) -> None:
+        x = self._nodes(x)
+        if x.shape[0] != self.N:
+            raise ValueError("set_nodes keeps N fixed")
+        self._sync_stream()
+        check(load().nfft_set_nodes(self._h, C.c_void_p(_ptr(x))))
+        self._x = x
+
+    def trafo(self, fhat: torch.Tensor) -> torch.Tensor:
+        fh, lead, R = self._coeffs(fhat)
+        out = torch.empty(tuple(lead) + (self.N,), dtype=self.ctype, device=self.device)
+        self._sync_stream()
+        check(load().nfft_trafo(self._h, C.c_void_p(_ptr(fh)), C.c_void_p(_ptr(out)), R))
+        return out
+
+    def adjoint(self, f: torch.Tensor) -> torch.Tensor:
+        ff, lead, R = self._samples(f)
+        out = torch.empty(tuple(lead) + self.M, dtype=self.ctype, device=self.device)
+        self._sync_stream()
+        check(load().nfft_adjoint(self._h, C.c_void_p(_ptr(ff)), C.c_void_p(_ptr(out)), R))
+        return out
+
+    def precompute_B(self) -> None:
+        self._sync_stream()
+        check(load().infft_precompute_B(self._h))
+
+    def apply(self, f: torch.Tensor) -> torch.Tensor:
+        ff, lead, R = self._samples(f)
+        out = torch.empty(tuple(lead) + self.M, dtype=self.ctype, device=self.device)
+        self._sync_stream()
+        check(load().infft_apply(self._h, C.c_void_p(_ptr(ff)), C.c_void_p(_ptr(out)), R))
+        return out
+
+    def apply_adjoint(self, h: torch.Tensor) -> torch.Tensor:
+        hh, lead, R = self._coeffs(h)
+        out = torch.empty(tuple(lead) + (self.N,), dtype=self.ctype, device=self.device)
+        self._sync_stream()
+        check(load().infft_apply_adjoint(self._h, C.c_void_p(_ptr(hh)), C.c_void_p(_ptr(out)), R))
+        return out
+
+    def grad_x(self, fhat: torch.Tensor, gradf: torch.Tensor) -> torch.Tensor:
+        fh, lead, R = self._coeffs(fhat)
+        gf, lead2, R2 = self._samples(gradf)
+        if R2 != R:
+            raise ValueError("fhat and gradf need the same number of right-hand sides")
+        out = torch.empty((self.N, self.d), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        check(load().nfft_grad_x(self._h, C.c_void_p(_ptr(fh)), C.c_void_p(_ptr(gf)), C.c_void_p(_ptr(out)), R))
+        return out
+
+    def get_B(self) -> torch.Tensor:
+        out = torch.empty((self.N, self.taps), dtype=torch.complex128, device=self.device)
+        self._sync_stream()
+        check(load().infft_get_B(self._h, C.c_void_p(_ptr(out))))
+        return out
+
+    def status(self) -> dict:
+        st = Status()
+        code = load().nfft_plan_status(self._h, C.byref(st))
+        d = {name: getattr(st, name) for name, _ in Status._fields_}
+        d["code"] = code
+        return d
+
+    def device_bytes(self) -> int:
+        return int(load().nfft_plan_device_bytes(self._h))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().nfft_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# Function names of the C ABI, for callers who prefer them to the class.
+def nfft_plan(M, x, sigma=2.0, m=4, **kw) -> NfftPlan:
+    return NfftPlan(M, x, sigma, m, **kw)
+
+
+def nfft_set_nodes(plan: NfftPlan, x):
+    return plan.set_nodes(x)
+
+
+def nfft_trafo(plan: NfftPlan, fhat):
+    return plan.trafo(fhat)
+
+
+def nfft_adjoint(plan: NfftPlan, f):
+    return plan.adjoint(f)
+
+
+def infft_precompute_B(plan: NfftPlan):
+    return plan.precompute_B()
+
+
+def infft_apply(plan: NfftPlan, f):
+    return plan.apply(f)
+
+
+def infft_apply_adjoint(plan: NfftPlan, h):
+    return plan.apply_adjoint(h)
+
+
+def nfft_grad_x(plan: NfftPlan, fhat, gradf):
+    return plan.grad_x(fhat, gradf)
+
+
+def infft_get_B(plan: NfftPlan):
+    return plan.get_B()
+
+
+def nfft_plan_status(plan: NfftPlan):
+    return plan.status()
+
+
+def nfft_plan_destroy(plan: NfftPlan):
+    plan.close()

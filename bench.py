@@ -1,0 +1,305 @@
+"""Throughput of the direct inverse NFFT hot path on one MI355X.
+
+One step = one pass of the whole path over one node set and one coefficient batch:
+  node preprocessing (wrap, stencil, sort into tiles, I(l) lists)
+  NFFT                     f  = B F D fhat
+  adjoint NFFT             h  = D^* F^* B^* f
+  optimisation of B        Algorithm 3.17 (FP64 local least squares)
+  modified adjoint NFFT    fc = D^* F^* B_opt^* f        (the inverse NFFT, (3.32))
+  backward kernels         B_opt F D h (gradient of the modified adjoint) and the node gradient
+
+value = nodes * right-hand sides / step time, inputs resident on the GPU.  The same step runs in
+FP32 (complex64 spreading and FFT; the B solves stay FP64) and in FP64; the FP32 figure is the
+headline `value`.  The CPU baseline times the FP64 oracle on this host (the B optimisation on a
+sample of grid indices, scaled) and its outputs give the relative errors of the GPU results.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+WORKLOAD = dict(W.CONFIGS["c2"])
+WORKLOAD_NAME = "1-D jittered nodes, M=2^16, N=2^17, sigma=2, Kaiser-Bessel m=6"
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--rhs", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=192, help="grid indices of the sampled oracle B solve")
+    ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph replay")
+    ap.add_argument("--fp64", dest="fp64", action="store_true", default=True)
+    ap.add_argument("--no-fp64", dest="fp64", action="store_false")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+class Stage:
+    """Elapsed time of one library call, from events on the plan's (torch's current) stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = {}
+
+    def run(self, name, fn):
+        s = self.torch.cuda.Event(enable_timing=True)
+        e = self.torch.cuda.Event(enable_timing=True)
+        s.record()
+        out = fn()
+        e.record()
+        self.pairs.setdefault(name, []).append((s, e))
+        return out
+
+    def mean_ms(self):
+        return {k: float(np.mean([s.elapsed_time(e) for s, e in v])) for k, v in self.pairs.items()}
+
+
+def gpu_run(precision, x, fh, gf, steps, warmup, rho, m, sigma, M, use_graph=True):
+    import torch
+    from paper_1811_05335_amd import NfftPlan
+
+    ct = torch.complex64 if precision == "f32" else torch.complex128
+    xd = torch.from_numpy(x).cuda()
+    fhd = torch.from_numpy(fh).to(ct).cuda()
+    gfd = torch.from_numpy(gf).to(ct).cuda()
+    R = fh.shape[0]
+    P = NfftPlan(M, xd, sigma=sigma, m=m, precision=precision, rho=rho, max_rhs=R)
+
+    def step(stage=None):
+        run = (lambda n, f: stage.run(n, f)) if stage else (lambda n, f: f())
+        run("a1_nodes", lambda: P.set_nodes(xd))
+        f = run("a2-a4_trafo", lambda: P.trafo(fhd))
+        h = run("a5_adjoint", lambda: P.adjoint(f))
+        run("a6_precompute_B", lambda: P.precompute_B())
+        fc = run("a7_apply", lambda: P.apply(f))
+        fa = run("a8_apply_adjoint", lambda: P.apply_adjoint(fc))
+        gx = run("a8_grad_x", lambda: P.grad_x(fhd, gfd))
+        return f, h, fc, fa, gx
+
+    # eager launches
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        eager_outs = step()
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / steps
+    # per-call breakdown, eager, in a separately timed loop
+    st = Stage(torch)
+    for _ in range(max(3, min(steps, 20))):
+        step(st)
+    torch.cuda.synchronize()
+    eager_host = [o.cpu().numpy() for o in eager_outs]
+    ms_graph, graph_dev = None, None
+    if use_graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(2):
+                step()
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            gouts = step()
+        for _ in range(warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        ms_graph = (time.perf_counter() - t0) * 1e3 / steps
+        graph_host = [o.cpu().numpy() for o in gouts]
+        graph_dev = max(rel(a, b) for a, b in zip(graph_host, eager_host))
+    status = P.status()
+    rows = P.get_B().cpu().numpy()
+    torch.cuda.synchronize()
+    P.close()
+    return dict(ms_eager=ms_eager, ms_graph=ms_graph, breakdown=st.mean_ms(), status=status, outs=eager_host,
+                rows=rows, graph_vs_eager=graph_dev)
+
+
+def algorithmic_bytes(N, M, G, T, R, csize, wsize):
+    """Bytes each operation must move at least once (inputs, outputs, the oversampled grid written
+    and read once, stored weights once)."""
+    return {
+        "a2-a4_trafo": R * (M * csize + 2 * G * csize + N * csize) + N * 8,
+        "a5_adjoint": R * (N * csize + 2 * G * csize + M * csize) + N * 8,
+        "a7_apply": R * (N * csize + 2 * G * csize + M * csize) + N * (T * wsize + 4),
+        "a8_apply_adjoint": R * (M * csize + 2 * G * csize + N * csize) + N * (T * wsize + 4),
+    }
+
+
+def cpu_baseline(x, fh, gf, rho, m, sigma, M, sample):
+    from oracle import bopt, grad, nfft
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    p = nfft.Params(M, sigma, m)
+    t = {}
+    c0 = time.perf_counter()
+    f = nfft.trafo(x, fh, p)
+    t["trafo"] = time.perf_counter() - c0
+    c0 = time.perf_counter()
+    h = nfft.adjoint(x, f, p)
+    t["adjoint"] = time.perf_counter() - c0
+    mem = bopt.Members(x, p)
+    g = np.random.default_rng(1)
+    ls = np.sort(g.choice(mem.G, size=min(sample, mem.G), replace=False))
+    c0 = time.perf_counter()
+    rows, solved = bopt.bopt_rows(x, p, rho, route="R", ls=ls, members=mem)
+    t_s = time.perf_counter() - c0
+    t["precompute_B_sampled"] = t_s
+    t["precompute_B_scaled"] = t_s * mem.G / len(ls)
+    c0 = time.perf_counter()
+    fc = bopt.apply(x, f, rows, p)
+    t["apply"] = time.perf_counter() - c0
+    c0 = time.perf_counter()
+    fa = bopt.apply_adjoint(x, fc, rows, p)
+    t["apply_adjoint"] = time.perf_counter() - c0
+    c0 = time.perf_counter()
+    gx = grad.nfft_grad_x(x, fh, gf, p)
+    t["grad_x"] = time.perf_counter() - c0
+    total = t["trafo"] + t["adjoint"] + t["precompute_B_scaled"] + t["apply"] + t["apply_adjoint"] + t["grad_x"]
+    return dict(total_s=total, parts=t, threads=threads, sample=len(ls), f=f, h=h, ls=ls, solved=solved,
+                rows=rows, gx=gx, p=p)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    cfg = WORKLOAD
+    M, N, sigma, m, rho = cfg["M"], cfg["N"], cfg["sigma"], cfg["m"], cfg["rho"]
+    R = a.rhs
+    x, fh = W.make_problem(cfg, seed=0, rhs=R)
+    gf = W.complex_normal(W.rng(1), (R, N))
+    fh32 = W.round_to(fh, "f32")
+    gf32 = W.round_to(gf, "f32")
+    log(f"[bench] workload: {WORKLOAD_NAME}, rhs={R}; FP32 run")
+    r32 = gpu_run("f32", x, fh32, gf32, a.steps, a.warmup, rho, m, sigma, M, use_graph=not a.eager)
+    ms32 = r32["ms_graph"] if r32["ms_graph"] else r32["ms_eager"]
+    br32, st32, out32, rows32 = r32["breakdown"], r32["status"], r32["outs"], r32["rows"]
+    log(f"[bench] FP32 graph {r32['ms_graph']} ms/step, eager {r32['ms_eager']:.3f} ms/step {br32}")
+    res64 = None
+    if a.fp64:
+        log("[bench] FP64 run")
+        r64 = gpu_run("f64", x, fh, gf, a.steps, a.warmup, rho, m, sigma, M, use_graph=not a.eager)
+        ms64 = r64["ms_graph"] if r64["ms_graph"] else r64["ms_eager"]
+        out64, rows64 = r64["outs"], r64["rows"]
+        log(f"[bench] FP64 graph {r64['ms_graph']} ms/step, eager {r64['ms_eager']:.3f} ms/step {r64['breakdown']}")
+        res64 = dict(value=N * R / (ms64 * 1e-3), ms_per_step=ms64, eager_ms_per_step=r64["ms_eager"],
+                     breakdown_ms=r64["breakdown"], graph_vs_eager_rel=r64["graph_vs_eager"])
+
+    G = int(np.prod([int(round(sigma * v)) for v in M]))
+    P_ = int(np.prod(M))
+    T = 2 * m + 1
+    algo = algorithmic_bytes(N, P_, G, T, R, 8, 8)
+    stage_roof = {}
+    for k, b in algo.items():
+        if k in br32:
+            gbs = b / (br32[k] * 1e-3) / 1e9
+            stage_roof[k] = dict(bytes=b, ms=br32[k], GBps=gbs, frac=gbs / HBM_PEAK_GBS)
+
+    dom = max(br32, key=br32.get)
+    line = {
+        "metric": "nodes/sec for NFFT + modified adjoint iNFFT, FP32 vs FP64, at rel. error",
+        "value": N * R / (ms32 * 1e-3),
+        "unit": "nodes/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": WORKLOAD_NAME,
+            "M": M[0], "N": N, "sigma": sigma, "m": m, "rhs": R, "rho": rho,
+            "nodes": "x_j = (j - N/2)/N + U(-1/(4N), 1/(4N)), seed 0",
+            "step": "nodes + trafo + adjoint + B optimisation (FP64) + modified adjoint + both backward kernels",
+            "parallelism": "single GPU",
+        },
+        "precompute_dtype": "f64",
+        "timing": "hipGraph replay of the whole step" if r32["ms_graph"] else "eager launches",
+        "eager_ms_per_step": r32["ms_eager"],
+        "graph_vs_eager_rel": r32["graph_vs_eager"],
+        "breakdown_ms": br32,
+        "dominant_call": dom,
+        "stage_hbm": stage_roof,
+        "status": {k: st32[k] for k in ("failed_solves", "oversized", "min_members", "max_members", "empty_columns")},
+        "fp64": res64,
+        "fp32_over_fp64": (res64["ms_per_step"] / ms32) if res64 else None,
+    }
+    if not a.no_cpu_baseline:
+        log(f"[bench] CPU oracle baseline (B optimisation sampled on {a.cpu_sample} grid indices)")
+        cb = cpu_baseline(x, fh, gf, rho, m, sigma, M, a.cpu_sample)
+        f_o, h_o = cb["f"], cb["h"]
+        err = {
+            "f32_trafo": rel(out32[0], nfft_ref(cb, x, fh32)),
+            "f32_adjoint": rel(out32[1], adj_ref(cb, x, out32[0])),
+        }
+        if res64:
+            err["f64_trafo"] = rel(out64[0], f_o)
+            err["f64_adjoint"] = rel(out64[1], adj_ref(cb, x, out64[0]))
+            # B_opt on the sampled grid indices against the oracle's reduced route
+            mask = cb["solved"]
+            err["f64_bopt_sampled"] = rel(rows64[mask], cb["rows"][mask])
+            err["f32_bopt_sampled"] = rel(rows32[mask], cb["rows"][mask])
+        line["rel_err"] = err
+        line["cpu_baseline"] = {
+            "value": N * R / cb["total_s"],
+            "unit": "nodes/s",
+            "cores": cb["threads"],
+            "kind": "oracle",
+            "sample": (f"full NFFT, adjoint, modified adjoint, its adjoint and node gradient; B optimisation "
+                       f"on {cb['sample']} of {G} grid indices (route R), time scaled by {G / cb['sample']:.0f}"),
+            "parts_s": cb["parts"],
+        }
+        log(f"[bench] CPU oracle {cb['total_s']:.2f} s/step, errors {err}")
+    print(json.dumps(line))
+
+
+def nfft_ref(cb, x, fh32):
+    from oracle import nfft
+    return nfft.trafo(x, fh32, cb["p"])
+
+
+def adj_ref(cb, x, f):
+    from oracle import nfft
+    return nfft.adjoint(x, np.asarray(f, dtype=np.complex128), cb["p"])
+
+
+if __name__ == "__main__":
+    main()

@@ -96,6 +96,9 @@ struct infft_plan_s {
     float* D32[MAX_D] = {nullptr, nullptr};
     double2* Ktab[MAX_D] = {nullptr, nullptr};
     double2* Qtab[MAX_D] = {nullptr, nullptr};
+    double* Kstab = nullptr;   // 1-D symmetric (real) parts of K and Q
+    double* Qstab = nullptr;
+    double dM = 0.0;
     int qK = 0, qQ = 0;
     double lam = 0.0;
 
@@ -291,6 +294,8 @@ int set_nodes_impl(infft_plan_s* P, const double* x) {
     launch_prep_nodes(g, x, P->nd, P->counts, P->status, s);
     launch_exclusive_scan(P->counts, P->nd.start, g.G, P->bsum, s);
     launch_scatter_nodes(g, P->nd, P->fill, s);
+    launch_fill_i32(P->lcount, 4, 0, s);
+    launch_cell_sort(g, P->nd, P->lists, P->lcount + 2, s);
     LAUNCH_CHECK();
     P->bopt_ready = false;
     return INFFT_OK;
@@ -441,6 +446,13 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
         launch_taylor_table(g.M[t], g.Ms[t], P->D64[t], 2, P->qQ, P->Qtab[t], P->stream);
         if (hipGetLastError() != hipSuccess) TRY(fail(INFFT_EDEVICE, "table kernels failed to launch"));
     }
+    if (d == 1) {
+        TRY(P->alloc(&P->Kstab, (int64_t)(P->qK + 1) * TAY_NC));
+        TRY(P->alloc(&P->Qstab, (int64_t)(P->qQ + 1) * TAY_NC));
+        launch_taylor_table_sym(g.M[0], g.Ms[0], P->D64[0], 1, P->qK, P->Kstab, P->stream);
+        launch_taylor_table_sym(g.M[0], g.Ms[0], P->D64[0], 2, P->qQ, P->Qstab, P->stream);
+        if (hipGetLastError() != hipSuccess) TRY(fail(INFFT_EDEVICE, "table kernels failed to launch"));
+    }
     // FFT twiddles
     for (int t = 0; t < d; ++t) {
         if (g.Ms[t] <= cap) {
@@ -483,7 +495,7 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
     P->rchunk = spread_rhs_chunk(g, P->prec == INFFT_F64);
     TRY(P->alloc(&P->B64, (int64_t)T * N));
     if (P->prec == INFFT_F32) TRY(P->alloc(&P->B32, (int64_t)T * N));
-    TRY(P->alloc(&P->lists, g.G));
+    TRY(P->alloc(&P->lists, 2 * g.G));
     TRY(P->alloc(&P->lcount, 4));
     // ridge: lambda = rho * (diagonal of G_l) = rho * prod_t M_sigma_t Q_t(0)
     HIP_TRY(hipStreamSynchronize(P->stream));
@@ -495,6 +507,8 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
         q0 *= v.x * (double)g.Ms[t];
     }
     P->lam = P->rho * q0;
+    if (d == 1 && hipMemcpy(&P->dM, P->D64[0], sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        TRY(fail(INFFT_EDEVICE, "reading the deconvolution table failed"));
     TRY(set_nodes_impl(P, x));
     if (hipStreamSynchronize(P->stream) != hipSuccess) TRY(fail(INFFT_EDEVICE, "plan set-up failed on the device"));
 #undef TRY
@@ -578,6 +592,10 @@ int infft_precompute_B(infft_plan p) {
         kt.K[t] = p->Ktab[t];
         kt.Q[t] = p->Qtab[t];
     }
+    kt.Ks = p->Kstab;
+    kt.Qs = p->Qstab;
+    kt.dM = p->dM;
+    kt.inv_sigma = (double)g.M[0] / (double)g.Ms[0];
     kt.qK = p->qK;
     kt.qQ = p->qQ;
     kt.lam = p->lam;
@@ -586,14 +604,34 @@ int infft_precompute_B(infft_plan p) {
     a.B64 = p->B64;
     a.B32 = p->B32;
     a.status = p->status;
-    a.in_list = nullptr;
-    a.in_count = nullptr;
-    a.out_list = p->lists;
-    a.out_count = p->lcount;
-    launch_solve_tier(g, p->nd, kt, a, 16, p->stream);
-    LAUNCH_CHECK();
-    a.in_list = p->lists;
-    a.in_count = p->lcount;
+    int* listA = p->lists;
+    int* listB = p->lists + g.G;
+    if (g.d == 1) {
+        // one thread per problem for small I(l); the rest in groups of 16, then 32 lanes
+        a.in_list = nullptr;
+        a.in_count = nullptr;
+        a.out_list = listA;
+        a.out_count = p->lcount;
+        launch_solve_thread_1d(g, p->nd, kt, a, p->stream);
+        LAUNCH_CHECK();
+        a.in_list = listA;
+        a.in_count = p->lcount;
+        a.out_list = listB;
+        a.out_count = p->lcount + 1;
+        launch_solve_tier(g, p->nd, kt, a, 16, p->stream);
+        LAUNCH_CHECK();
+        a.in_list = listB;
+        a.in_count = p->lcount + 1;
+    } else {
+        a.in_list = nullptr;
+        a.in_count = nullptr;
+        a.out_list = listA;
+        a.out_count = p->lcount;
+        launch_solve_tier(g, p->nd, kt, a, 16, p->stream);
+        LAUNCH_CHECK();
+        a.in_list = listA;
+        a.in_count = p->lcount;
+    }
     a.out_list = nullptr;
     a.out_count = nullptr;
     launch_solve_tier(g, p->nd, kt, a, 32, p->stream);

@@ -99,6 +99,12 @@ constexpr int TAY_NC = 10;
 struct KTabDev {
     const double2* K[MAX_D];
     const double2* Q[MAX_D];
+    // 1-D split K = Ks + d e^{-i pi z / sigma}, Q = Qs + d^2 e^{-i pi z / sigma}: Ks, Qs are the
+    // real, even sums over the frequency pairs +-k; d = D_{-M/2} is the unpaired frequency
+    const double* Ks;
+    const double* Qs;
+    double dM;         // D_{-M/2}
+    double inv_sigma;  // M / M_sigma
     int qK, qQ;        // largest table index for K and Q
     double lam;        // ridge lambda (the same for every l: all diagonal entries of G_l agree)
     double scaleG;     // prod M_sigma
@@ -151,6 +157,7 @@ void launch_prep_nodes(const Geo& g, const double* x, NodesDev nd, int* counts, 
 void launch_exclusive_scan(const int* in, int* out, int64_t n, int* blocksums, hipStream_t s);
 int64_t scan_blocksum_len(int64_t n);
 void launch_scatter_nodes(const Geo& g, NodesDev nd, int* fill, hipStream_t s);
+void launch_cell_sort(const Geo& g, NodesDev nd, int* big_list, int* big_count, hipStream_t s);
 void launch_export_B(const Geo& g, const int* perm, const double2* B, double2* rows, hipStream_t s);
 void launch_status_init(long long* status, int keep_node_words, hipStream_t s);
 
@@ -161,6 +168,8 @@ void launch_twiddles_strided(int64_t N, int64_t count, int64_t step, double2* t6
                              hipStream_t s);
 void launch_taylor_table(int M, int Ms, const double* D, int power, int qmax, double2* tab,
                          hipStream_t s);
+void launch_taylor_table_sym(int M, int Ms, const double* D, int power, int qmax, double* tab,
+                             hipStream_t s);
 
 // fft.hip
 template <typename R>
@@ -192,8 +201,10 @@ struct SolveArgs {
     double2* B64;           // [T][N] sorted order
     float2* B32;            // [T][N] sorted order (nullptr for FP64 plans)
     long long* status;
+    int tables_in_lds;      // set by the launcher (1-D plans whose kernel tables fit in LDS)
 };
 void launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl, hipStream_t s);
+void launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s);
 int solve_max_supported();
 
 }  // namespace infft

@@ -114,6 +114,96 @@ void launch_scatter_nodes(const Geo& g, NodesDev nd, int* fill, hipStream_t s) {
         hipLaunchKernelGGL(k_scatter<2>, dim3(blocks), dim3(256), 0, s, g, nd, fill);
 }
 
+// ------------------------------------------------------------------ deterministic order in a cell
+// The scatter places the nodes of one cell in atomic order.  Sorting each cell's range by caller
+// index makes the sorted order, and with it every member order of the local problems, a function
+// of the input alone.  Cells of up to CELL_SORT_SMALL nodes are sorted by one thread in place;
+// larger cells (dense 2-D centres) by one workgroup with a bitonic sort in LDS.
+
+constexpr int CELL_SORT_SMALL = 32;
+constexpr int CELL_SORT_BIG = 4096;
+
+template <int D>
+__device__ inline void refresh_sorted(NodesDev& nd, int pos) {
+    const int j = nd.perm[pos];
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+        nd.l0s[(int64_t)pos * D + t] = nd.l0c[(int64_t)j * D + t];
+        nd.us[(int64_t)pos * D + t] = nd.uc[(int64_t)j * D + t];
+    }
+}
+
+template <int D>
+__global__ void k_cell_sort_small(Geo g, NodesDev nd, int* big_list, int* big_count) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= g.G) return;
+    const int s = nd.start[c], e = nd.start[c + 1];
+    const int cnt = e - s;
+    if (cnt <= 1) return;
+    if (cnt > CELL_SORT_SMALL) {
+        big_list[atomicAdd(big_count, 1)] = (int)c;
+        return;
+    }
+    for (int i = s + 1; i < e; ++i) {  // insertion sort of perm[s..e)
+        const int v = nd.perm[i];
+        int k = i - 1;
+        while (k >= s && nd.perm[k] > v) {
+            nd.perm[k + 1] = nd.perm[k];
+            --k;
+        }
+        nd.perm[k + 1] = v;
+    }
+    for (int i = s; i < e; ++i) refresh_sorted<D>(nd, i);
+}
+
+template <int D>
+__global__ void __launch_bounds__(1024) k_cell_sort_big(Geo g, NodesDev nd, const int* big_list,
+                                                        const int* big_count) {
+    __shared__ int buf[CELL_SORT_BIG];
+    const int nbig = *big_count;
+    for (int b = blockIdx.x; b < nbig; b += gridDim.x) {
+        const int c = big_list[b];
+        const int s = nd.start[c], e = nd.start[c + 1];
+        const int cnt = e - s;
+        if (cnt > CELL_SORT_BIG) continue;  // left in scatter order
+        int n2 = 1;
+        while (n2 < cnt) n2 <<= 1;
+        for (int i = threadIdx.x; i < n2; i += blockDim.x) buf[i] = (i < cnt) ? nd.perm[s + i] : INT_MAX;
+        __syncthreads();
+        for (int k = 2; k <= n2; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+                    const int ixj = i ^ j;
+                    if (ixj > i) {
+                        const int a = buf[i], bb = buf[ixj];
+                        const bool up = (i & k) == 0;
+                        if ((a > bb) == up) {
+                            buf[i] = bb;
+                            buf[ixj] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) nd.perm[s + i] = buf[i];
+        __syncthreads();
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) refresh_sorted<D>(nd, s + i);
+        __syncthreads();
+    }
+}
+
+void launch_cell_sort(const Geo& g, NodesDev nd, int* big_list, int* big_count, hipStream_t s) {
+    const unsigned blocks = (unsigned)((g.G + 255) / 256);
+    if (g.d == 1) {
+        hipLaunchKernelGGL(k_cell_sort_small<1>, dim3(blocks), dim3(256), 0, s, g, nd, big_list, big_count);
+        hipLaunchKernelGGL(k_cell_sort_big<1>, dim3(64), dim3(1024), 0, s, g, nd, big_list, big_count);
+    } else {
+        hipLaunchKernelGGL(k_cell_sort_small<2>, dim3(blocks), dim3(256), 0, s, g, nd, big_list, big_count);
+        hipLaunchKernelGGL(k_cell_sort_big<2>, dim3(64), dim3(1024), 0, s, g, nd, big_list, big_count);
+    }
+}
+
 // ------------------------------------------------------------------ exclusive scan
 // Three passes: per-block scan (256 threads x 8 items), scan of the block totals in one block,
 // then the block offsets are added.  out has n+1 entries (out[n] = total).

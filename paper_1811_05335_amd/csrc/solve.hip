@@ -14,7 +14,8 @@
 // Layout of the work: a group of NL lanes (NL = 16 or 32) owns one grid index at a time.  The
 // members of I(l) are gathered from the (2m+1)^d grid cells whose nodes reach l (the node CSR);
 // lane i owns member i and row i of the Hermitian system.  The Cholesky factorisation, forward
-// and backward substitution run across the group with register rows and cross-lane shuffles.
+// and backward substitution run across the group with register rows; each step's column or
+// partial sums pass through a small per-thread LDS slot, so all reads of a step issue together.
 // Problems with more than NL members are passed on to the next, wider group size.
 #include "internal.hpp"
 
@@ -39,70 +40,122 @@ __device__ inline double2 tay_eval(const double2* __restrict__ tab, int qmax, do
     return acc;
 }
 
-__device__ inline double2 shfl2(double2 v, int src) {
-    return make_double2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
+// Ordering point for the LDS exchange inside one wavefront: LDS operations of a wave execute
+// in program order, so only the compiler has to be kept from moving accesses across it.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Members of I(l) for d = 1.  Nodes are sorted by stencil base l0, so the cells l-2m+1 .. l
+// (every node of them reaches l) form at most two contiguous ranges of the sorted order (two when
+// the window wraps around the torus); the cell l-2m contributes only nodes with u = m exactly.
+__device__ inline void gather_1d(const Geo& g, const NodesDev& nd, int l, int lane, int NL, int gbase,
+                                 uint64_t gmask, int& n, int& my_p) {
+    const int w2 = 2 * g.m, Ms = g.Ms[0];
+    const int clo = l - w2 + 1;
+    int s0, e0, s1 = 0, e1 = 0;
+    if (clo >= 0) {
+        s0 = nd.start[clo];
+        e0 = nd.start[l + 1];
+    } else {
+        s0 = nd.start[clo + Ms];
+        e0 = nd.start[Ms];
+        s1 = nd.start[0];
+        e1 = nd.start[l + 1];
+    }
+    const int n0 = e0 - s0, n1 = e1 - s1;
+    if (lane < n0) my_p = s0 + lane;
+    else if (lane - n0 < n1) my_p = s1 + (lane - n0);
+    n = n0 + n1;
+    int ce = l - w2;
+    if (ce < 0) ce += Ms;
+    const int s = nd.start[ce], e = nd.start[ce + 1];
+    for (int base = s; base < e; base += NL) {
+        const int p = base + lane;
+        const bool mem = p < e && nd.us[p] == (double)g.m;
+        const uint64_t gm = (__ballot(mem) >> gbase) & gmask;
+        const int cnt = __popcll(gm);
+        const int k = lane - n;
+        if (k >= 0 && k < cnt) {
+            uint64_t mm = gm;
+            for (int i = 0; i < k; ++i) mm &= mm - 1ull;
+            my_p = base + (__ffsll((unsigned long long)mm) - 1);
+        }
+        n += cnt;
+    }
+}
+
+// Members of I(l) for d = 2: the (2m+1)^2 cells (l0 - tau0, l1 - tau1), cell by cell.
+__device__ inline void gather_2d(const Geo& g, const NodesDev& nd, int l, int lane, int NL, int gbase,
+                                 uint64_t gmask, int& n, int& my_p) {
+    const int W = 2 * g.m + 1, w2 = 2 * g.m;
+    const int lc0 = l / g.Ms[1], lc1 = l - lc0 * g.Ms[1];
+    n = 0;
+    for (int c = 0; c < W * W; ++c) {
+        const int tau0 = c / W, tau1 = c - tau0 * W;
+        int c0 = lc0 - tau0;
+        if (c0 < 0) c0 += g.Ms[0];
+        int c1 = lc1 - tau1;
+        if (c1 < 0) c1 += g.Ms[1];
+        const int64_t key = cell_key(g, c0, c1);
+        const int s = nd.start[key], e = nd.start[key + 1];
+        if (s == e) continue;
+        if (tau0 < w2 && tau1 < w2) {
+            const int k = lane - n;
+            if (k >= 0 && k < e - s) my_p = s + k;
+            n += e - s;
+        } else {
+            for (int base = s; base < e; base += NL) {
+                const int p = base + lane;
+                bool mem = p < e;
+                if (mem && tau0 == w2) mem = nd.us[(int64_t)p * 2] == (double)g.m;
+                if (mem && tau1 == w2) mem = nd.us[(int64_t)p * 2 + 1] == (double)g.m;
+                const uint64_t gm = (__ballot(mem) >> gbase) & gmask;
+                const int cnt = __popcll(gm);
+                const int k = lane - n;
+                if (k >= 0 && k < cnt) {
+                    uint64_t mm = gm;
+                    for (int i = 0; i < k; ++i) mm &= mm - 1ull;
+                    my_p = base + (__ffsll((unsigned long long)mm) - 1);
+                }
+                n += cnt;
+            }
+        }
+    }
 }
 
 template <int D, int NL>
 __global__ void __launch_bounds__(256) k_solve(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
+    __shared__ double2 s_col[256];   // per-thread exchange slot (column broadcasts, reductions)
+    __shared__ double2 s_z[256];     // z of each member (x: dimension 0, y: dimension 1)
+    extern __shared__ double2 s_tab[];
     const int lane = threadIdx.x & (NL - 1);
-    const int gbase = (threadIdx.x & 63) - lane;
+    const int sb = threadIdx.x - lane;               // first slot of this group
+    const int gbase = (threadIdx.x & 63) - lane;     // first lane of this group inside the wave
     const uint64_t gmask = (NL == 64) ? ~0ull : ((1ull << NL) - 1ull);
     const int64_t gid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / NL;
     const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / NL;
     const int64_t count = a.in_list ? (int64_t)(*a.in_count) : g.G;
-    const int m = g.m, W = 2 * g.m + 1, w2 = 2 * g.m;
-    const int ncell = (D == 2) ? W * W : W;
+    const int W = 2 * g.m + 1;
+
+    // 1-D plans keep the Q table (read n times per member) in LDS; K is read once per member.
+    const double2* tK0 = kt.K[0];
+    const double2* tQ0 = kt.Q[0];
+    if (D == 1 && a.tables_in_lds) {
+        const int nQ = (kt.qQ + 1) * TAY_NC;
+        for (int i = threadIdx.x; i < nQ; i += blockDim.x) s_tab[i] = kt.Q[0][i];
+        __syncthreads();
+        tQ0 = s_tab;
+    }
 
     unsigned long long st_min = ULLONG_MAX, st_max = 0, st_fail = 0, st_empty = 0, st_over = 0;
 
     for (int64_t qi = gid; qi < count; qi += ngroups) {
         const int l = a.in_list ? a.in_list[qi] : (int)qi;
-        const int lc0 = (D == 2) ? l / g.Ms[1] : l;
-        const int lc1 = (D == 2) ? l - lc0 * g.Ms[1] : 0;
-
-        // ---- members of I(l): nodes of the cells l - tau, tau in {0..2m}^d
-        int n = 0;
-        int my_p = 0, my_tau = 0;
-        for (int c = 0; c < ncell; ++c) {
-            const int tau0 = (D == 2) ? c / W : c;
-            const int tau1 = (D == 2) ? c - tau0 * W : 0;
-            int c0 = lc0 - tau0;
-            if (c0 < 0) c0 += g.Ms[0];
-            int c1 = lc1 - tau1;
-            if (c1 < 0) c1 += g.Ms[1];
-            const int64_t key = cell_key(g, c0, c1);
-            const int s = nd.start[key], e = nd.start[key + 1];
-            if (s == e) continue;
-            const bool edge = (tau0 == w2) || (D == 2 && tau1 == w2);
-            if (!edge) {
-                // tau < 2m in every dimension: |u - tau| <= m holds for every node of the cell
-                const int k = lane - n;
-                if (k >= 0 && k < e - s) {
-                    my_p = s + k;
-                    my_tau = c;
-                }
-                n += e - s;
-            } else {
-                // tau = 2m reaches l only when u = m exactly (node on a grid point)
-                for (int base = s; base < e; base += NL) {
-                    const int p = base + lane;
-                    bool mem = p < e;
-                    if (mem && tau0 == w2) mem = nd.us[(int64_t)p * D] == (double)m;
-                    if (mem && D == 2 && tau1 == w2) mem = nd.us[(int64_t)p * D + 1] == (double)m;
-                    const uint64_t gm = (__ballot(mem) >> gbase) & gmask;
-                    const int cnt = __popcll(gm);
-                    const int k = lane - n;
-                    if (k >= 0 && k < cnt) {
-                        uint64_t mm = gm;
-                        for (int i = 0; i < k; ++i) mm &= mm - 1ull;
-                        my_p = base + (__ffsll((unsigned long long)mm) - 1);
-                        my_tau = c;
-                    }
-                    n += cnt;
-                }
-            }
-        }
+        int n = 0, my_p = 0;
+        if (D == 1) gather_1d(g, nd, l, lane, NL, gbase, gmask, n, my_p);
+        else gather_2d(g, nd, l, lane, NL, gbase, gmask, n, my_p);
         if (n == 0) {
             if (lane == 0) ++st_empty;
             continue;
@@ -124,56 +177,73 @@ __global__ void __launch_bounds__(256) k_solve(Geo g, NodesDev nd, KTabDev kt, S
         }
         const bool act = lane < n;
 
-        // ---- z_i = tau_i - u_i per dimension; right-hand side r_i = conj K(z_i)
+        // ---- tap tau = (l - l0) mod M_sigma and z = tau - u per dimension; r = conj K(z)
         double z0 = 0.0, z1 = 0.0;
+        int my_tau = 0;
         double2 y = make_double2(0.0, 0.0);
         if (act) {
-            const int tau0 = (D == 2) ? my_tau / W : my_tau;
-            z0 = (double)tau0 - nd.us[(int64_t)my_p * D];
-            double2 kv = tay_eval(kt.K[0], kt.qK, z0);
-            if (D == 2) {
-                const int tau1 = my_tau - tau0 * W;
-                z1 = (double)tau1 - nd.us[(int64_t)my_p * D + 1];
-                kv = cmul(kv, tay_eval(kt.K[1], kt.qK, z1));
+            if (D == 1) {
+                int tau0 = l - nd.l0s[my_p];
+                if (tau0 < 0) tau0 += g.Ms[0];
+                z0 = (double)tau0 - nd.us[my_p];
+                my_tau = tau0;
+                y = cconj(tay_eval(tK0, kt.qK, z0));
+            } else {
+                const int lc0 = l / g.Ms[1], lc1 = l - lc0 * g.Ms[1];
+                int tau0 = lc0 - nd.l0s[(int64_t)my_p * 2];
+                if (tau0 < 0) tau0 += g.Ms[0];
+                int tau1 = lc1 - nd.l0s[(int64_t)my_p * 2 + 1];
+                if (tau1 < 0) tau1 += g.Ms[1];
+                z0 = (double)tau0 - nd.us[(int64_t)my_p * 2];
+                z1 = (double)tau1 - nd.us[(int64_t)my_p * 2 + 1];
+                my_tau = tau0 * W + tau1;
+                y = cconj(cmul(tay_eval(kt.K[0], kt.qK, z0), tay_eval(kt.K[1], kt.qK, z1)));
             }
-            y = cconj(kv);
         }
+        s_z[threadIdx.x] = make_double2(z0, z1);
+        wave_sync();
 
         // ---- row i of G + lambda I (lower triangle): G[i][j] = M_sigma^d Q(z_j - z_i)
         double2 A[NL];
 #pragma unroll
         for (int j = 0; j < NL; ++j) {
-            const double zj0 = __shfl(z0, gbase + j, 64);
-            const double zj1 = (D == 2) ? __shfl(z1, gbase + j, 64) : 0.0;
             A[j] = make_double2(0.0, 0.0);
-            if (act && j < n && j <= lane) {
-                double2 qv = tay_eval(kt.Q[0], kt.qQ, zj0 - z0);
-                if (D == 2) qv = cmul(qv, tay_eval(kt.Q[1], kt.qQ, zj1 - z1));
+            if (j < n) {
+                const double2 zj = s_z[sb + j];
+                double2 qv;
+                if (D == 1) qv = tay_eval(tQ0, kt.qQ, zj.x - z0);
+                else qv = cmul(tay_eval(kt.Q[0], kt.qQ, zj.x - z0), tay_eval(kt.Q[1], kt.qQ, zj.y - z1));
                 A[j] = cscale(qv, kt.scaleG);
                 if (j == lane) A[j] = make_double2(A[j].x + kt.lam, 0.0);
             }
         }
 
-        // ---- Cholesky G + lambda I = L L^*, lane i keeps row i of L
+        // ---- Cholesky G + lambda I = L L^*, lane i keeps row i of L.  Step k broadcasts the
+        // unscaled column k through LDS; with inv = 1/sqrt(pivot) the update of row i is
+        // A[i][j] -= (A[i][k] inv^2) conj(A[j][k]) for k < j <= i.
         bool ok = true;
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             if (k < n && ok) {
-                const double piv = __shfl(A[k].x, gbase + k, 64);
-                if (!(piv > 0.0)) {
-                    ok = false;
-                } else {
-                    const double sq = sqrt(piv), inv = 1.0 / sq;
-                    if (lane == k) A[k] = make_double2(sq, 0.0);
-                    else if (lane > k) A[k] = cscale(A[k], inv);
+                s_col[threadIdx.x] = A[k];
+                wave_sync();
+                const double piv = s_col[sb + k].x;
+                ok = piv > 0.0;
+                const double sq = sqrt(ok ? piv : 1.0), inv = 1.0 / sq;
+                const double2 Lk2 = cscale(A[k], inv * inv);
 #pragma unroll
-                    for (int j = k + 1; j < NL; ++j) {
-                        if (j < n) {
-                            const double2 Ljk = shfl2(A[k], gbase + j);
-                            if (lane >= j && act) A[j] = csub(A[j], cmulc(A[k], Ljk));
+                for (int j = k + 1; j < NL; ++j) {
+                    if (j < n) {
+                        const double2 raw = s_col[sb + j];
+                        if (lane >= j) {
+                            A[j].x -= Lk2.x * raw.x + Lk2.y * raw.y;
+                            A[j].y -= Lk2.y * raw.x - Lk2.x * raw.y;
                         }
                     }
                 }
+                if (lane == k) A[k] = make_double2(sq, 0.0);
+                else if (lane > k) A[k] = cscale(A[k], inv);
+                wave_sync();
             }
         }
         if (!ok) {
@@ -185,27 +255,28 @@ __global__ void __launch_bounds__(256) k_solve(Geo g, NodesDev nd, KTabDev kt, S
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             if (k < n) {
-                const double Lkk = __shfl(A[k].x, gbase + k, 64);
-                const double2 yk = cscale(shfl2(y, gbase + k), 1.0 / Lkk);
-                if (lane == k) y = yk;
-                else if (lane > k && act) y = csub(y, cmul(A[k], yk));
+                if (lane == k) y = cscale(y, 1.0 / A[k].x);
+                s_col[threadIdx.x] = y;
+                wave_sync();
+                const double2 yk = s_col[sb + k];
+                if (lane > k && act) y = csub(y, cmul(A[k], yk));
+                wave_sync();
             }
         }
-        // ---- backward substitution L^* b = y
+        // ---- backward substitution L^* b = y: b_k = (y_k - sum_{i>k} conj(L[i][k]) b_i) / L[k][k]
         double2 bsol = make_double2(0.0, 0.0);
 #pragma unroll
         for (int k = NL - 1; k >= 0; --k) {
             if (k < n) {
-                double2 c = make_double2(0.0, 0.0);
-                if (lane > k && act) c = cmul(cconj(A[k]), bsol);
+                s_col[threadIdx.x] = (lane > k && act) ? cmul(cconj(A[k]), bsol) : make_double2(0.0, 0.0);
+                wave_sync();
+                if (lane == k) {
+                    double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
-                for (int o = NL / 2; o >= 1; o >>= 1) {
-                    c.x += __shfl_xor(c.x, o, 64);
-                    c.y += __shfl_xor(c.y, o, 64);
+                    for (int j = k + 1; j < NL; ++j) sum = cadd(sum, s_col[sb + j]);
+                    bsol = cscale(csub(y, sum), 1.0 / A[k].x);
                 }
-                const double Lkk = __shfl(A[k].x, gbase + k, 64);
-                const double2 yk = shfl2(y, gbase + k);
-                if (lane == k) bsol = cscale(csub(yk, c), 1.0 / Lkk);
+                wave_sync();
             }
         }
 
@@ -215,6 +286,7 @@ __global__ void __launch_bounds__(256) k_solve(Geo g, NodesDev nd, KTabDev kt, S
             a.B64[idx] = bsol;
             if (a.B32) a.B32[idx] = make_float2((float)bsol.x, (float)bsol.y);
         }
+        wave_sync();
     }
 
     // ---- statistics: reduce over the wave, one set of atomics per wave
@@ -236,17 +308,412 @@ __global__ void __launch_bounds__(256) k_solve(Geo g, NodesDev nd, KTabDev kt, S
     }
 }
 
+// ------------------------------------------------------------------ 1-D: real solves + rank one
+// In one dimension the frequencies +-k pair up except k = -M/2, so with d = D_{-M/2},
+// w_i = e^{i pi z_i / sigma} and the real, even sums Ks, Qs over the pairs:
+//     G + lambda I = A0 + c w w^*,   A0 = M_sigma Qs(z_j - z_i) + lambda I (real SPD),  c = M_sigma d^2
+//     r            = Ks(z) + d w
+// and the Sherman-Morrison formula gives the solution from three real solves with A0,
+//     t = A0^{-1} Ks,  u = A0^{-1} w,  s = w^* u (real, >= 0),
+//     b = t + u (d - c w^* t) / (1 + c s),
+// whose denominator is at least one.
+
+__device__ inline double tay_eval_r(const double* __restrict__ tab, int qmax, double z) {
+    const double az = fabs(z);
+    int q = (int)rint(az * (double)TAY_S);
+    if (q > qmax) q = qmax;
+    const double e = az - (double)q * (1.0 / TAY_S);
+    const double* c = tab + (int64_t)q * TAY_NC;
+    double acc = c[TAY_NC - 1];
+#pragma unroll
+    for (int p = TAY_NC - 2; p >= 0; --p) acc = fma(acc, e, c[p]);
+    return acc;
+}
+
+template <int NL>
+__device__ inline double group_sum(double v) {
+#pragma unroll
+    for (int o = NL / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One group of NL lanes per grid index l; the group's (n x n, n <= NL) matrix lives in LDS,
+// lane i owns row i.  All loops run to the actual size n.
+template <int NL>
+__global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
+    constexpr int GPB = 128 / NL;   // groups per block
+    constexpr int LDA = NL + 1;
+    __shared__ double s_A[GPB * NL * LDA];
+    __shared__ double s_y[3][128];
+    __shared__ double s_z[128];
+    extern __shared__ double s_tabr[];
+    const int lane = threadIdx.x & (NL - 1);
+    const int sb = threadIdx.x - lane;
+    const int gbase = (threadIdx.x & 63) - lane;
+    const uint64_t gmask = (NL == 64) ? ~0ull : ((1ull << NL) - 1ull);
+    double* Ag = s_A + (threadIdx.x / NL) * NL * LDA;
+    double* Ai = Ag + lane * LDA;
+    const int64_t gid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / NL;
+    const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / NL;
+    const int64_t count = a.in_list ? (int64_t)(*a.in_count) : g.G;
+
+    {
+        const int nQ = (kt.qQ + 1) * TAY_NC;
+        for (int i = threadIdx.x; i < nQ; i += blockDim.x) s_tabr[i] = kt.Qs[i];
+        __syncthreads();
+    }
+    const double* tQ = s_tabr;
+    const double c1 = (double)g.Ms[0] * kt.dM * kt.dM;
+
+    unsigned long long st_min = ULLONG_MAX, st_max = 0, st_fail = 0, st_empty = 0, st_over = 0;
+
+    for (int64_t qi = gid; qi < count; qi += ngroups) {
+        const int l = a.in_list ? a.in_list[qi] : (int)qi;
+        int n = 0, my_p = 0;
+        gather_1d(g, nd, l, lane, NL, gbase, gmask, n, my_p);
+        if (n == 0) {
+            if (lane == 0) ++st_empty;
+            continue;
+        }
+        if (n > NL) {
+            if (lane == 0) {
+                if (a.out_list) {
+                    const int slot = atomicAdd(a.out_count, 1);
+                    a.out_list[slot] = l;
+                } else {
+                    ++st_over;
+                }
+            }
+            continue;
+        }
+        if (lane == 0) {
+            st_min = min(st_min, (unsigned long long)n);
+            st_max = max(st_max, (unsigned long long)n);
+        }
+        const bool act = lane < n;
+
+        double z = 0.0, t = 0.0, wr = 0.0, wi = 0.0;
+        int tau = 0;
+        if (act) {
+            tau = l - nd.l0s[my_p];
+            if (tau < 0) tau += g.Ms[0];
+            z = (double)tau - nd.us[my_p];
+            t = tay_eval_r(kt.Ks, kt.qK, z);
+            sincospi(z * kt.inv_sigma, &wi, &wr);
+        }
+        double ur = wr, ui = wi;
+        s_z[threadIdx.x] = z;
+        wave_sync();
+
+        // ---- lower triangle of A0 = M_sigma Qs(z_j - z_i) + lambda I, row i by lane i
+        if (act) {
+            for (int j = 0; j <= lane; ++j) Ai[j] = kt.scaleG * tay_eval_r(tQ, kt.qQ, s_z[sb + j] - z);
+            Ai[lane] += kt.lam;
+        }
+        wave_sync();
+
+        // ---- Cholesky A0 = L L^T in place (right-looking)
+        bool ok = true;
+        for (int k = 0; k < n; ++k) {
+            const double piv = Ag[k * LDA + k];
+            if (!(piv > 0.0)) {
+                ok = false;
+                break;
+            }
+            const double sq = sqrt(piv);
+            double lik = 0.0;
+            if (lane == k) Ai[k] = sq;
+            else if (lane > k && act) {
+                lik = Ai[k] / sq;
+                Ai[k] = lik;
+            }
+            wave_sync();
+            if (lane > k && act)
+                for (int j = k + 1; j <= lane; ++j) Ai[j] = fma(-lik, Ag[j * LDA + k], Ai[j]);
+            wave_sync();
+        }
+        if (!ok) {
+            if (lane == 0) ++st_fail;
+            wave_sync();
+            continue;
+        }
+
+        // ---- forward substitution L y = rhs (Ks, Re w, Im w)
+        for (int k = 0; k < n; ++k) {
+            if (lane == k) {
+                const double iv = 1.0 / Ai[k];
+                t *= iv;
+                ur *= iv;
+                ui *= iv;
+                s_y[0][threadIdx.x] = t;
+                s_y[1][threadIdx.x] = ur;
+                s_y[2][threadIdx.x] = ui;
+            }
+            wave_sync();
+            if (lane > k && act) {
+                const double lk = Ai[k];
+                t = fma(-lk, s_y[0][sb + k], t);
+                ur = fma(-lk, s_y[1][sb + k], ur);
+                ui = fma(-lk, s_y[2][sb + k], ui);
+            }
+        }
+        wave_sync();
+        // ---- backward substitution L^T x = y
+        for (int k = n - 1; k >= 0; --k) {
+            if (lane == k) {
+                const double iv = 1.0 / Ai[k];
+                t *= iv;
+                ur *= iv;
+                ui *= iv;
+                s_y[0][threadIdx.x] = t;
+                s_y[1][threadIdx.x] = ur;
+                s_y[2][threadIdx.x] = ui;
+            }
+            wave_sync();
+            if (lane < k) {
+                const double lk = Ag[k * LDA + lane];
+                t = fma(-lk, s_y[0][sb + k], t);
+                ur = fma(-lk, s_y[1][sb + k], ur);
+                ui = fma(-lk, s_y[2][sb + k], ui);
+            }
+        }
+
+        // ---- Sherman-Morrison combination
+        const double sdot = group_sum<NL>(act ? wr * ur + wi * ui : 0.0);        // w^* u
+        const double wtr = group_sum<NL>(act ? wr * t : 0.0);                     // Re w^* t
+        const double wti = group_sum<NL>(act ? -wi * t : 0.0);                    // Im w^* t
+        const double den = 1.0 + c1 * sdot;
+        const double cr = (kt.dM - c1 * wtr) / den, ci = (-c1 * wti) / den;
+        const double2 bsol = make_double2(t + ur * cr - ui * ci, ur * ci + ui * cr);
+
+        if (act) {
+            const int64_t idx = (int64_t)tau * g.N + my_p;
+            a.B64[idx] = bsol;
+            if (a.B32) a.B32[idx] = make_float2((float)bsol.x, (float)bsol.y);
+        }
+        wave_sync();
+    }
+
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        st_min = min(st_min, (unsigned long long)__shfl_xor((long long)st_min, o, 64));
+        st_max = max(st_max, (unsigned long long)__shfl_xor((long long)st_max, o, 64));
+        st_fail += (unsigned long long)__shfl_xor((long long)st_fail, o, 64);
+        st_empty += (unsigned long long)__shfl_xor((long long)st_empty, o, 64);
+        st_over += (unsigned long long)__shfl_xor((long long)st_over, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        unsigned long long* st = (unsigned long long*)a.status;
+        if (st_min != ULLONG_MAX) atomicMin(&st[ST_MIN_N], st_min);
+        if (st_max) atomicMax(&st[ST_MAX_N], st_max);
+        if (st_fail) atomicAdd(&st[ST_FAILED], st_fail);
+        if (st_empty) atomicAdd(&st[ST_EMPTY], st_empty);
+        if (st_over) atomicAdd(&st[ST_OVERSIZED], st_over);
+    }
+}
+
+// ------------------------------------------------------------------ 1-D: one thread per problem
+// For |I(l)| <= NMAX (the common case: about 2m members at one node per grid cell) a single thread
+// holds the whole real system of the Sherman-Morrison form in registers: the lower triangle of A0,
+// the three right-hand sides and the solution, with every loop unrolled.  Rows beyond n are padded
+// with an identity block and zero right-hand sides, which decouples them exactly.  Problems with
+// more members, or with a member exactly on the edge of its window (u = m), are appended to the
+// list of the group kernels.
+template <int NMAX>
+__global__ void __launch_bounds__(256) k_solve_t1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
+    extern __shared__ double s_tabq[];
+    {
+        const int nQ = (kt.qQ + 1) * TAY_NC;
+        for (int i = threadIdx.x; i < nQ; i += blockDim.x) s_tabq[i] = kt.Qs[i];
+        __syncthreads();
+    }
+    const int Ms = g.Ms[0], w2 = 2 * g.m;
+    const double c1 = (double)Ms * kt.dM * kt.dM;
+    unsigned long long st_min = ULLONG_MAX, st_max = 0, st_fail = 0, st_empty = 0;
+
+    for (int64_t li = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; li < g.G;
+         li += (int64_t)gridDim.x * blockDim.x) {
+        const int l = (int)li;
+        // members: cells l-2m+1 .. l (one or two contiguous ranges), edge cell l-2m
+        const int clo = l - w2 + 1;
+        int s0, e0, s1 = 0, e1 = 0;
+        if (clo >= 0) {
+            s0 = nd.start[clo];
+            e0 = nd.start[l + 1];
+        } else {
+            s0 = nd.start[clo + Ms];
+            e0 = nd.start[Ms];
+            s1 = nd.start[0];
+            e1 = nd.start[l + 1];
+        }
+        int ce = l - w2;
+        if (ce < 0) ce += Ms;
+        const int es = nd.start[ce], ee = nd.start[ce + 1];
+        bool edge = false;
+        for (int p = es; p < ee; ++p) edge |= nd.us[p] == (double)g.m;
+        const int n0 = e0 - s0, n = n0 + (e1 - s1);
+        if (n > NMAX || edge) {
+            const int slot = atomicAdd(a.out_count, 1);
+            a.out_list[slot] = l;
+            continue;
+        }
+        if (n == 0) {
+            ++st_empty;
+            continue;
+        }
+        st_min = min(st_min, (unsigned long long)n);
+        st_max = max(st_max, (unsigned long long)n);
+
+        int pm[NMAX], tau[NMAX];
+        double z[NMAX], t[NMAX], ur[NMAX], ui[NMAX];
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+            pm[i] = 0;
+            tau[i] = 0;
+            z[i] = 0.0;
+            t[i] = ur[i] = ui[i] = 0.0;
+            if (i < n) {
+                const int p = (i < n0) ? s0 + i : s1 + (i - n0);
+                pm[i] = p;
+                int tt = l - nd.l0s[p];
+                if (tt < 0) tt += Ms;
+                tau[i] = tt;
+                z[i] = (double)tt - nd.us[p];
+                t[i] = tay_eval_r(kt.Ks, kt.qK, z[i]);
+                sincospi(z[i] * kt.inv_sigma, &ui[i], &ur[i]);
+            }
+        }
+        double wr[NMAX], wi[NMAX];
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+            wr[i] = ur[i];
+            wi[i] = ui[i];
+        }
+        // lower triangle of A0 (padded rows: identity)
+        double A[NMAX * (NMAX + 1) / 2];
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+#pragma unroll
+            for (int j = 0; j <= i; ++j) {
+                double v = (i == j) ? 1.0 : 0.0;
+                if (i < n) {
+                    v = kt.scaleG * tay_eval_r(s_tabq, kt.qQ, z[j] - z[i]);
+                    if (i == j) v += kt.lam;
+                }
+                A[i * (i + 1) / 2 + j] = v;
+            }
+        }
+        // Cholesky in registers
+        bool ok = true;
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k) {
+            const double piv = A[k * (k + 1) / 2 + k];
+            ok = ok && piv > 0.0;
+            const double sq = sqrt(piv > 0.0 ? piv : 1.0), inv = 1.0 / sq;
+            A[k * (k + 1) / 2 + k] = sq;
+#pragma unroll
+            for (int i = k + 1; i < NMAX; ++i) A[i * (i + 1) / 2 + k] *= inv;
+#pragma unroll
+            for (int i = k + 1; i < NMAX; ++i) {
+                const double lik = A[i * (i + 1) / 2 + k];
+#pragma unroll
+                for (int j = k + 1; j <= i; ++j) A[i * (i + 1) / 2 + j] = fma(-lik, A[j * (j + 1) / 2 + k], A[i * (i + 1) / 2 + j]);
+            }
+        }
+        if (!ok) {
+            ++st_fail;
+            continue;
+        }
+        // L y = rhs, then L^T x = y, three right-hand sides
+#pragma unroll
+        for (int k = 0; k < NMAX; ++k) {
+            const double iv = 1.0 / A[k * (k + 1) / 2 + k];
+            t[k] *= iv;
+            ur[k] *= iv;
+            ui[k] *= iv;
+#pragma unroll
+            for (int i = k + 1; i < NMAX; ++i) {
+                const double lik = A[i * (i + 1) / 2 + k];
+                t[i] = fma(-lik, t[k], t[i]);
+                ur[i] = fma(-lik, ur[k], ur[i]);
+                ui[i] = fma(-lik, ui[k], ui[i]);
+            }
+        }
+#pragma unroll
+        for (int k = NMAX - 1; k >= 0; --k) {
+            const double iv = 1.0 / A[k * (k + 1) / 2 + k];
+            t[k] *= iv;
+            ur[k] *= iv;
+            ui[k] *= iv;
+#pragma unroll
+            for (int i = 0; i < k; ++i) {
+                const double lki = A[k * (k + 1) / 2 + i];
+                t[i] = fma(-lki, t[k], t[i]);
+                ur[i] = fma(-lki, ur[k], ur[i]);
+                ui[i] = fma(-lki, ui[k], ui[i]);
+            }
+        }
+        // Sherman-Morrison combination
+        double sdot = 0.0, wtr = 0.0, wti = 0.0;
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+            sdot = fma(wr[i], ur[i], fma(wi[i], ui[i], sdot));
+            wtr = fma(wr[i], t[i], wtr);
+            wti = fma(-wi[i], t[i], wti);
+        }
+        const double den = 1.0 + c1 * sdot;
+        const double cr = (kt.dM - c1 * wtr) / den, ci = (-c1 * wti) / den;
+#pragma unroll
+        for (int i = 0; i < NMAX; ++i) {
+            if (i < n) {
+                const double2 b = make_double2(t[i] + ur[i] * cr - ui[i] * ci, ur[i] * ci + ui[i] * cr);
+                const int64_t idx = (int64_t)tau[i] * g.N + pm[i];
+                a.B64[idx] = b;
+                if (a.B32) a.B32[idx] = make_float2((float)b.x, (float)b.y);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        st_min = min(st_min, (unsigned long long)__shfl_xor((long long)st_min, o, 64));
+        st_max = max(st_max, (unsigned long long)__shfl_xor((long long)st_max, o, 64));
+        st_fail += (unsigned long long)__shfl_xor((long long)st_fail, o, 64);
+        st_empty += (unsigned long long)__shfl_xor((long long)st_empty, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        unsigned long long* st = (unsigned long long*)a.status;
+        if (st_min != ULLONG_MAX) atomicMin(&st[ST_MIN_N], st_min);
+        if (st_max) atomicMax(&st[ST_MAX_N], st_max);
+        if (st_fail) atomicAdd(&st[ST_FAILED], st_fail);
+        if (st_empty) atomicAdd(&st[ST_EMPTY], st_empty);
+    }
+}
+
+void launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s) {
+    const size_t shm = (size_t)(kt.qQ + 1) * TAY_NC * sizeof(double);
+    int64_t blocks = (g.G + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL((k_solve_t1<13>), dim3((unsigned)blocks), dim3(256), shm, s, g, nd, kt, a);
+}
+
 int solve_max_supported() { return 32; }
 
 void launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl, hipStream_t s) {
     const int64_t groups_per_block = 256 / nl;
     int64_t blocks = (g.G + groups_per_block - 1) / groups_per_block;
-    const int64_t cap = a.in_list ? 1024 : 8192;
+    const int64_t cap = a.in_list ? 512 : 2048;
     if (blocks > cap) blocks = cap;
     if (g.d == 1) {
-        if (nl == 16) hipLaunchKernelGGL((k_solve<1, 16>), dim3((unsigned)blocks), dim3(256), 0, s, g, nd, kt, a);
-        else hipLaunchKernelGGL((k_solve<1, 32>), dim3((unsigned)blocks), dim3(256), 0, s, g, nd, kt, a);
+        // Q table of at most (2*8*TAY_S+2)*TAY_NC doubles (about 21 KB) in LDS
+        const size_t shm = (size_t)(kt.qQ + 1) * TAY_NC * sizeof(double);
+        a.tables_in_lds = 1;
+        int64_t b1 = (g.G + (128 / nl) - 1) / (128 / nl);
+        const int64_t cap1 = a.in_list ? 1024 : 4096;
+        if (b1 > cap1) b1 = cap1;
+        if (nl == 16) hipLaunchKernelGGL((k_solve_r1<16>), dim3((unsigned)b1), dim3(128), shm, s, g, nd, kt, a);
+        else hipLaunchKernelGGL((k_solve_r1<32>), dim3((unsigned)b1), dim3(128), shm, s, g, nd, kt, a);
     } else {
+        a.tables_in_lds = 0;
         if (nl == 16) hipLaunchKernelGGL((k_solve<2, 16>), dim3((unsigned)blocks), dim3(256), 0, s, g, nd, kt, a);
         else hipLaunchKernelGGL((k_solve<2, 32>), dim3((unsigned)blocks), dim3(256), 0, s, g, nd, kt, a);
     }

@@ -62,15 +62,17 @@ void launch_twiddles_strided(int64_t N, int64_t count, int64_t step, double2* t6
 }
 
 // One workgroup per table row q; threads split the frequency sum, then a tree reduction.
+// sym = 1 leaves out the unpaired frequency k = -M/2: the remaining sum pairs k with -k, is real
+// and even in z, and only the real parts are stored (table of doubles).
 __global__ void __launch_bounds__(256) k_taylor(int M, int Ms, const double* __restrict__ D, int power,
-                                                double2* __restrict__ tab) {
+                                                double2* __restrict__ tab, int sym) {
     __shared__ double red[256];
     const int q = blockIdx.x;
     const int64_t L = (int64_t)TAY_S * Ms;   // period of the phase index
     double ax[TAY_NC], ay[TAY_NC];
 #pragma unroll
     for (int p = 0; p < TAY_NC; ++p) ax[p] = ay[p] = 0.0;
-    for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    for (int i = threadIdx.x + (sym ? 1 : 0); i < M; i += blockDim.x) {
         const int64_t k = (int64_t)(i - M / 2);
         double c = D[i];
         if (power == 2) c = c * c;
@@ -92,6 +94,7 @@ __global__ void __launch_bounds__(256) k_taylor(int M, int Ms, const double* __r
     }
 #pragma unroll
     for (int p = 0; p < 2 * TAY_NC; ++p) {
+        if (sym && (p & 1)) continue;
         red[threadIdx.x] = (p & 1) ? ay[p >> 1] : ax[p >> 1];
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
@@ -99,16 +102,24 @@ __global__ void __launch_bounds__(256) k_taylor(int M, int Ms, const double* __r
             __syncthreads();
         }
         if (threadIdx.x == 0) {
-            double2* dst = &tab[(int64_t)q * TAY_NC + (p >> 1)];
-            if (p & 1) dst->y = red[0];
-            else dst->x = red[0];
+            if (sym) {
+                ((double*)tab)[(int64_t)q * TAY_NC + (p >> 1)] = red[0];
+            } else {
+                double2* dst = &tab[(int64_t)q * TAY_NC + (p >> 1)];
+                if (p & 1) dst->y = red[0];
+                else dst->x = red[0];
+            }
         }
         __syncthreads();
     }
 }
 
 void launch_taylor_table(int M, int Ms, const double* D, int power, int qmax, double2* tab, hipStream_t s) {
-    hipLaunchKernelGGL(k_taylor, dim3(qmax + 1), dim3(256), 0, s, M, Ms, D, power, tab);
+    hipLaunchKernelGGL(k_taylor, dim3(qmax + 1), dim3(256), 0, s, M, Ms, D, power, tab, 0);
+}
+
+void launch_taylor_table_sym(int M, int Ms, const double* D, int power, int qmax, double* tab, hipStream_t s) {
+    hipLaunchKernelGGL(k_taylor, dim3(qmax + 1), dim3(256), 0, s, M, Ms, D, power, (double2*)tab, 1);
 }
 
 }  // namespace infft

@@ -136,12 +136,23 @@ def gpu_run(precision, x, fh, gf, steps, warmup, rho, m, sigma, M, use_graph=Tru
         ms_graph = (time.perf_counter() - t0) * 1e3 / steps
         graph_host = [o.cpu().numpy() for o in gouts]
         graph_dev = max(rel(a, b) for a, b in zip(graph_host, eager_host))
+    # per kernel class: average launch duration from HIP events the library records around each
+    # launch on the plan's stream (eager launches, one class at a time)
+    kclass = {}
+    for cls in ("solve", "fft", "spread", "interp", "nodes"):
+        P.profile_begin(cls)
+        nsteps = max(3, min(steps, 20))
+        for _ in range(nsteps):
+            step()
+        tot_ms, nl = P.profile_end()
+        kclass[cls] = dict(ms_per_step=tot_ms / nsteps, launches_per_step=nl / nsteps,
+                           ms_per_launch=tot_ms / max(nl, 1))
     status = P.status()
     rows = P.get_B().cpu().numpy()
     torch.cuda.synchronize()
     P.close()
     return dict(ms_eager=ms_eager, ms_graph=ms_graph, breakdown=st.mean_ms(), status=status, outs=eager_host,
-                rows=rows, graph_vs_eager=graph_dev)
+                rows=rows, graph_vs_eager=graph_dev, kclass=kclass)
 
 
 def algorithmic_bytes(N, M, G, T, R, csize, wsize):
@@ -153,6 +164,31 @@ def algorithmic_bytes(N, M, G, T, R, csize, wsize):
         "a7_apply": R * (N * csize + 2 * G * csize + M * csize) + N * (T * wsize + 4),
         "a8_apply_adjoint": R * (M * csize + 2 * G * csize + N * csize) + N * (T * wsize + 4),
     }
+
+
+def member_counts(x, Ms, m):
+    """|I(l)| for every grid index l (1-D), from the stencil l0 = ceil(x M_sigma - m), u = x M_sigma - l0:
+    the cells l-2m+1..l contribute all their nodes, the cell l-2m those with u = m."""
+    xw = x[:, 0] - np.floor(x[:, 0] + 0.5)
+    t = xw * Ms
+    l0 = np.ceil(t - m)
+    u = t - l0
+    c = np.mod(l0.astype(np.int64), Ms)
+    cnt = np.bincount(c, minlength=Ms)
+    edge = np.bincount(c[u == m], minlength=Ms)
+    n = np.zeros(Ms, dtype=np.int64)
+    for tau in range(2 * m):
+        n += np.roll(cnt, tau)
+    n += np.roll(edge, 2 * m)
+    return n
+
+
+def solve_flops(n):
+    """FP64 flops of one local problem as the 1-D kernel computes it (real Sherman-Morrison form):
+    Gram entries n(n+1)/2 Taylor evaluations (10 fma), right-hand side n (10 fma), Cholesky n^3/3,
+    three right-hand sides forward and back 6 n^2, combination 10 n."""
+    n = np.asarray(n, dtype=np.float64)
+    return n * (n + 1) / 2 * 20 + n * 20 + n ** 3 / 3 + 6 * n ** 2 + 10 * n
 
 
 def cpu_baseline(x, fh, gf, rho, m, sigma, M, sample):
@@ -231,6 +267,30 @@ def main():
             stage_roof[k] = dict(bytes=b, ms=br32[k], GBps=gbs, frac=gbs / HBM_PEAK_GBS)
 
     dom = max(br32, key=br32.get)
+    kc = r32["kclass"]
+    dom_k = max(kc, key=lambda k: kc[k]["ms_per_step"])
+    Ms = int(round(sigma * M[0]))
+    nl = member_counts(x, Ms, m)
+    flops = float(np.sum(solve_flops(nl[nl > 0])))
+    ms_solve = kc["solve"]["ms_per_launch"]
+    roof_solve = {"bound": "alu", "kernel": "k_solve_t1 (B optimisation, FP64, one thread per grid index)",
+                  "achieved": flops / (ms_solve * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                  "frac": flops / (ms_solve * 1e-3) / 1e12 / 78.6, "traffic": None,
+                  "algorithmic_flops_per_launch": flops, "ms_per_launch": ms_solve,
+                  "units_per_launch": int(np.sum(nl > 0))}
+    # HBM view of the streaming kernels: bytes they must move at least once per launch
+    G_ = Ms
+    c8 = 8
+    kbytes = {
+        "fft": 2 * G_ * c8,                                   # one pass reads and writes the grid
+        "spread": N * (c8 + 4 + 8) + G_ * c8,                 # samples, stencil base, offset; grid once
+        "interp": G_ * c8 + N * (c8 + 4 + 8),
+    }
+    kroof = {}
+    for k, b in kbytes.items():
+        mpl = kc[k]["ms_per_launch"]
+        kroof[k] = dict(bytes_per_launch=b, ms_per_launch=mpl, GBps=b / (mpl * 1e-3) / 1e9,
+                        frac=b / (mpl * 1e-3) / 1e9 / HBM_PEAK_GBS)
     line = {
         "metric": "nodes/sec for NFFT + modified adjoint iNFFT, FP32 vs FP64, at rel. error",
         "value": N * R / (ms32 * 1e-3),
@@ -252,6 +312,10 @@ def main():
             "parallelism": "single GPU",
         },
         "precompute_dtype": "f64",
+        "roofline": roof_solve,
+        "kernel_classes": kc,
+        "dominant_kernel_class": dom_k,
+        "streaming_kernels_hbm": kroof,
         "timing": "hipGraph replay of the whole step" if r32["ms_graph"] else "eager launches",
         "eager_ms_per_step": r32["ms_eager"],
         "graph_vs_eager_rel": r32["graph_vs_eager"],

@@ -139,6 +139,22 @@ int64_t nfft_plan_device_bytes(infft_plan p);
 /* Releases the plan and its device workspace (waits for the plan's stream first). */
 void nfft_plan_destroy(infft_plan p);
 
+/* Kernel classes for infft_profile_begin. */
+#define INFFT_K_NODES 1    /* node preprocessing and sort */
+#define INFFT_K_FFT 2      /* FFT passes (with the fused deconvolution and halo fold-in) */
+#define INFFT_K_SPREAD 3   /* spreading with the window or with B_opt */
+#define INFFT_K_INTERP 4   /* interpolation with the window or with B_opt, node gradient */
+#define INFFT_K_SOLVE 5    /* local least-squares solves of the B optimisation */
+
+/* Starts timing the launches of one kernel class: each launch of that class is bracketed by a
+ * pair of HIP events recorded on the plan's stream (launch order is unchanged).  Not for use
+ * while the stream is being captured into a graph. */
+int infft_profile_begin(infft_plan p, int kernel_class);
+
+/* Synchronises the stream, stops timing and returns the summed event time in milliseconds and
+ * the number of timed launches. */
+int infft_profile_end(infft_plan p, double* total_ms, int64_t* launches);
+
 /* Thread-local description of the last error (empty string if none). */
 const char* infft_last_error(void);
 

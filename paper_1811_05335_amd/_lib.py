@@ -15,6 +15,7 @@ INFFT_ESINGULAR = -4
 INFFT_ESTATE = -5
 INFFT_F32 = 0
 INFFT_F64 = 1
+KERNEL_CLASSES = {"nodes": 1, "fft": 2, "spread": 3, "interp": 4, "solve": 5}
 
 ERROR_NAMES = {
     INFFT_EINVAL: "INFFT_EINVAL",
@@ -84,6 +85,8 @@ def load() -> C.CDLL:
         "nfft_plan_device_bytes": (i64, [vp]),
         "nfft_plan_destroy": (None, [vp]),
         "infft_last_error": (C.c_char_p, []),
+        "infft_profile_begin": (i32, [vp, i32]),
+        "infft_profile_end": (i32, [vp, C.POINTER(dbl), C.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

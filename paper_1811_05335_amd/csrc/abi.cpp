@@ -119,7 +119,14 @@ struct infft_plan_s {
     float2* B32 = nullptr;
     int* lists = nullptr;      // one list of grid indices for problems passed to the wider tier
     int* lcount = nullptr;
+    long long* stat_rec = nullptr;   // per-block statistics of the solve kernels
+    int stat_nrec = 0;
     bool bopt_ready = false;
+
+    // optional event timing of one kernel class
+    int prof_class = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
 
     size_t csize() const { return prec == INFFT_F32 ? sizeof(float2) : sizeof(double2); }
     int taps() const { return g.d == 1 ? 2 * g.m + 1 : (2 * g.m + 1) * (2 * g.m + 1); }
@@ -137,11 +144,36 @@ struct infft_plan_s {
     }
 
     ~infft_plan_s() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
     }
 };
 
 namespace {
+
+// Brackets the launches between construction and destruction with two events when the plan
+// times this kernel class.
+struct ProfScope {
+    infft_plan_s* P;
+    bool on;
+    ProfScope(infft_plan_s* p, int cls) : P(p), on(p->prof_class == cls) {
+        if (on) record();
+    }
+    ~ProfScope() {
+        if (on) record();
+    }
+    void record() {
+        if (P->ev_used == P->ev_pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) {
+                on = false;
+                return;
+            }
+            P->ev_pool.push_back(e);
+        }
+        (void)hipEventRecord(P->ev_pool[P->ev_used++], P->stream);
+    }
+};
 
 const TwTable* find_tw(const infft_plan_s* P, int64_t n) {
     for (const TwTable& t : P->tw)
@@ -204,7 +236,7 @@ int build_schedule(infft_plan_s* P, int nrhs, std::vector<FftStep>& to_grid, std
         FftStep a = s, b = s;
         a.pass.sign = +1; a.ld = LD_DECONV; a.st = ST_GRID; a.in_buf = 0; a.out_buf = 1;
         a.pass.in_rs = g.P; a.pass.out_rs = g.G;
-        b.pass.sign = -1; b.ld = LD_HALO; b.st = ST_DECONV; b.in_buf = 1; b.out_buf = 0;
+        b.pass.sign = -1; b.ld = LD_GRID; b.st = ST_DECONV; b.in_buf = 1; b.out_buf = 0;  // 1-D: gather, no halos
         b.pass.in_rs = g.G; b.pass.out_rs = g.P;
         to_grid.push_back(a);
         to_coeff.push_back(b);
@@ -223,7 +255,7 @@ int build_schedule(infft_plan_s* P, int nrhs, std::vector<FftStep>& to_grid, std
         FftStep a1 = A, a2 = B, b1 = A, b2 = B;
         a1.pass.sign = +1; a1.ld = LD_DECONV; a1.st = ST_TWIDDLE; a1.in_buf = 0; a1.out_buf = 2; a1.pass.in_rs = g.P;
         a2.pass.sign = +1; a2.ld = LD_GRID; a2.st = ST_GRID; a2.in_buf = 2; a2.out_buf = 1; a2.pass.out_rs = g.G;
-        b1.pass.sign = -1; b1.ld = LD_HALO; b1.st = ST_TWIDDLE; b1.in_buf = 1; b1.out_buf = 2; b1.pass.in_rs = g.G;
+        b1.pass.sign = -1; b1.ld = LD_GRID; b1.st = ST_TWIDDLE; b1.in_buf = 1; b1.out_buf = 2; b1.pass.in_rs = g.G;
         b2.pass.sign = -1; b2.ld = LD_GRID; b2.st = ST_DECONV; b2.in_buf = 2; b2.out_buf = 0; b2.pass.out_rs = g.P;
         to_grid.push_back(a1);
         to_grid.push_back(a2);
@@ -271,11 +303,60 @@ int run_fft(infft_plan_s* P, const std::vector<FftStep>& steps, const void* user
         io.halo_rs0 = P->hrs0;
         io.halo_rs1 = P->hrs1;
         io.halo_rs01 = P->hrs01;
+        ProfScope ps(P, INFFT_K_FFT);
         if (f32) launch_fft_pass<float>(s.pass, io, g, s.ld, s.st, P->stream);
         else launch_fft_pass<double>(s.pass, io, g, s.ld, s.st, P->stream);
         LAUNCH_CHECK();
     }
     return INFFT_OK;
+}
+
+// Kaiser-Bessel window in grid units (host, long double): sinh(b t) / (pi t), t = sqrt(m^2 - v^2).
+long double kb_window_host(long double v, int m, long double b) {
+    const long double t2 = ((long double)m - v) * ((long double)m + v);
+    if (t2 < 0) return 0.0L;
+    const long double t = sqrtl(t2);
+    const long double pi = 3.14159265358979323846264338327950288L;
+    return t > 0 ? sinhl(b * t) / (pi * t) : b / pi;
+}
+
+// Monomial coefficients (ascending powers of y in [-1, 1]) of the degree nc-1 polynomial that
+// interpolates w(m - 1 + (y + 1)/2 - tau) at the Chebyshev points, for taps tau = 0 .. 2m-1.
+std::vector<long double> window_poly_coeffs(int m, long double b, int nc) {
+    const int D = nc - 1;
+    const long double pi = 3.14159265358979323846264338327950288L;
+    std::vector<long double> out((size_t)2 * m * nc, 0.0L);
+    for (int tau = 0; tau < 2 * m; ++tau) {
+        std::vector<long double> f(nc), c(nc, 0.0L);
+        for (int j = 0; j < nc; ++j) {
+            const long double y = cosl(pi * (j + 0.5L) / nc);
+            f[j] = kb_window_host((long double)(m - 1) + (y + 1.0L) / 2.0L - tau, m, b);
+        }
+        for (int k = 0; k < nc; ++k) {
+            long double acc = 0.0L;
+            for (int j = 0; j < nc; ++j) acc += f[j] * cosl(pi * k * (j + 0.5L) / nc);
+            c[k] = acc * 2.0L / nc;
+        }
+        c[0] *= 0.5L;
+        // sum_k c_k T_k(y) -> monomials, with T_{k+1} = 2 y T_k - T_{k-1}
+        std::vector<long double> Tm(nc, 0.0L), T0(nc, 0.0L), T1(nc, 0.0L), mono(nc, 0.0L);
+        T0[0] = 1.0L;
+        if (D >= 1) T1[1] = 1.0L;
+        for (int i = 0; i < nc; ++i) mono[i] += c[0] * T0[i];
+        if (D >= 1)
+            for (int i = 0; i < nc; ++i) mono[i] += c[1] * T1[i];
+        for (int k = 2; k <= D; ++k) {
+            std::vector<long double> T2(nc, 0.0L);
+            for (int i = 0; i + 1 < nc; ++i) T2[i + 1] += 2.0L * T1[i];
+            for (int i = 0; i < nc; ++i) T2[i] -= T0[i];
+            for (int i = 0; i < nc; ++i) mono[i] += c[k] * T2[i];
+            T0 = T1;
+            T1 = T2;
+        }
+        (void)D;
+        for (int i = 0; i < nc; ++i) out[(size_t)tau * nc + i] = mono[i];
+    }
+    return out;
 }
 
 int auto_tile(int Ms, int m, int want) {
@@ -287,6 +368,7 @@ int auto_tile(int Ms, int m, int want) {
 int set_nodes_impl(infft_plan_s* P, const double* x) {
     const Geo& g = P->g;
     hipStream_t s = P->stream;
+    ProfScope ps(P, INFFT_K_NODES);
     launch_fill_bytes0(P->status, sizeof(long long) * STATUS_WORDS, s);
     launch_status_init(P->status, 0, s);
     launch_fill_i32(P->counts, g.G + 1, 0, s);
@@ -474,6 +556,26 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
             launch_twiddles_strided(g.Ms[t], nhi, Bsz, P->split_hi.t64, P->split_hi.t32, P->stream);
         }
     }
+    // window polynomials
+    {
+        const int nc = P->prec == INFFT_F32 ? WPoly<float>::NC : WPoly<double>::NC;
+        const std::vector<long double> cf = window_poly_coeffs(m, (long double)M_PI * (2.0L - 1.0L / sigma), nc);
+        if (P->prec == INFFT_F32) {
+            std::vector<float> h(cf.begin(), cf.end());
+            float* d = nullptr;
+            TRY(P->alloc(&d, (int64_t)h.size()));
+            if (hipMemcpy(d, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+                TRY(fail(INFFT_EDEVICE, "uploading the window polynomials failed"));
+            P->g.wpoly = d;
+        } else {
+            std::vector<double> h(cf.begin(), cf.end());
+            double* d = nullptr;
+            TRY(P->alloc(&d, (int64_t)h.size()));
+            if (hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+                TRY(fail(INFFT_EDEVICE, "uploading the window polynomials failed"));
+            P->g.wpoly = d;
+        }
+    }
     // grids, halos, B_opt, solver lists
     const size_t cs = P->csize();
     const int64_t ntiles = (int64_t)g.ntile[0] * g.ntile[1];
@@ -497,6 +599,8 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
     if (P->prec == INFFT_F32) TRY(P->alloc(&P->B32, (int64_t)T * N));
     TRY(P->alloc(&P->lists, 2 * g.G));
     TRY(P->alloc(&P->lcount, 4));
+    // records: one per block of each solve tier (first tier G/128 blocks at most, the others capped)
+    TRY(P->alloc(&P->stat_rec, (g.G / 64 + 8192) * 5));
     // ridge: lambda = rho * (diagonal of G_l) = rho * prod_t M_sigma_t Q_t(0)
     HIP_TRY(hipStreamSynchronize(P->stream));
     double q0 = 1.0;
@@ -542,6 +646,7 @@ int nfft_trafo(infft_plan p, const void* fhat, void* f, int nrhs) {
         if ((rc = schedule_for(p, c))) return rc;
         if ((rc = run_fft(p, p->to_grid, cptr(p, fhat, r0 * g.P), nullptr))) return rc;
         void* fo = (void*)cptr(p, f, r0 * g.N);
+        ProfScope ps(p, INFFT_K_INTERP);
         if (p->prec == INFFT_F32)
             launch_interp<float>(g, p->nd, (const float2*)p->grid, g.G, (float2*)fo, c, p->stream);
         else
@@ -558,6 +663,7 @@ static int spread_then_coeffs(infft_plan_s* p, const void* f, void* h, int nrhs,
         const int c = std::min(p->max_rhs, nrhs - r0);
         if ((rc = schedule_for(p, c))) return rc;
         const void* fi = cptr(p, f, r0 * g.N);
+        ProfScope ps(p, INFFT_K_SPREAD);
         if (p->prec == INFFT_F32)
             launch_spread<float>(g, p->nd, (const float2*)fi, useB ? p->B32 : nullptr, (float2*)p->grid, g.G,
                                  (float2*)p->h0, (float2*)p->h1, (float2*)p->h01, p->hrs0, p->hrs1, p->hrs01, c,
@@ -584,8 +690,11 @@ int infft_precompute_B(infft_plan p) {
     const Geo& g = p->g;
     const int64_t TN = (int64_t)p->taps() * g.N;
     launch_status_init(p->status, 1, p->stream);
-    launch_fill_bytes0(p->B64, TN * (int64_t)sizeof(double2), p->stream);
-    if (p->B32) launch_fill_bytes0(p->B32, TN * (int64_t)sizeof(float2), p->stream);
+    if (g.d == 2) {
+        // 1-D tiers write every entry of B_opt themselves (zeros where no problem reaches)
+        launch_fill_bytes0(p->B64, TN * (int64_t)sizeof(double2), p->stream);
+        if (p->B32) launch_fill_bytes0(p->B32, TN * (int64_t)sizeof(float2), p->stream);
+    }
     launch_fill_i32(p->lcount, 4, 0, p->stream);
     KTabDev kt{};
     for (int t = 0; t < MAX_D; ++t) {
@@ -604,6 +713,8 @@ int infft_precompute_B(infft_plan p) {
     a.B64 = p->B64;
     a.B32 = p->B32;
     a.status = p->status;
+    a.stat_rec = p->stat_rec;
+    a.stat_off = 0;
     int* listA = p->lists;
     int* listB = p->lists + g.G;
     if (g.d == 1) {
@@ -612,13 +723,16 @@ int infft_precompute_B(infft_plan p) {
         a.in_count = nullptr;
         a.out_list = listA;
         a.out_count = p->lcount;
-        launch_solve_thread_1d(g, p->nd, kt, a, p->stream);
+        {
+            ProfScope ps(p, INFFT_K_SOLVE);  // the first tier carries nearly all problems
+            a.stat_off += launch_solve_thread_1d(g, p->nd, kt, a, p->stream);
+        }
         LAUNCH_CHECK();
         a.in_list = listA;
         a.in_count = p->lcount;
         a.out_list = listB;
         a.out_count = p->lcount + 1;
-        launch_solve_tier(g, p->nd, kt, a, 16, p->stream);
+        a.stat_off += launch_solve_tier(g, p->nd, kt, a, 16, p->stream);
         LAUNCH_CHECK();
         a.in_list = listB;
         a.in_count = p->lcount + 1;
@@ -627,15 +741,19 @@ int infft_precompute_B(infft_plan p) {
         a.in_count = nullptr;
         a.out_list = listA;
         a.out_count = p->lcount;
-        launch_solve_tier(g, p->nd, kt, a, 16, p->stream);
+        {
+            ProfScope ps(p, INFFT_K_SOLVE);
+            a.stat_off += launch_solve_tier(g, p->nd, kt, a, 16, p->stream);
+        }
         LAUNCH_CHECK();
         a.in_list = listA;
         a.in_count = p->lcount;
     }
     a.out_list = nullptr;
     a.out_count = nullptr;
-    launch_solve_tier(g, p->nd, kt, a, 32, p->stream);
+    a.stat_off += launch_solve_tier(g, p->nd, kt, a, 32, p->stream);
     LAUNCH_CHECK();
+    p->stat_nrec = a.stat_off;   // folded into the status block by nfft_plan_status
     p->bopt_ready = true;
     return INFFT_OK;
 }
@@ -659,6 +777,7 @@ int infft_apply_adjoint(infft_plan p, const void* h, void* f, int nrhs) {
         if ((rc = schedule_for(p, c))) return rc;
         if ((rc = run_fft(p, p->to_grid, cptr(p, h, r0 * g.P), nullptr))) return rc;
         void* fo = (void*)cptr(p, f, r0 * g.N);
+        ProfScope ps(p, INFFT_K_INTERP);
         if (p->prec == INFFT_F32)
             launch_interp_B<float>(g, p->nd, (const float2*)p->grid, g.G, p->B32, (float2*)fo, c, p->stream);
         else
@@ -678,6 +797,7 @@ int nfft_grad_x(infft_plan p, const void* fhat, const void* gradf, double* gradx
         if ((rc = schedule_for(p, c))) return rc;
         if ((rc = run_fft(p, p->to_grid, cptr(p, fhat, r0 * g.P), nullptr))) return rc;
         const void* gf = cptr(p, gradf, r0 * g.N);
+        ProfScope ps(p, INFFT_K_INTERP);
         if (p->prec == INFFT_F32)
             launch_grad_x<float>(g, p->nd, (const float2*)p->grid, g.G, (const float2*)gf, gradx, c, r0 > 0,
                                  p->stream);
@@ -700,6 +820,10 @@ int infft_get_B(infft_plan p, void* rows) {
 
 int nfft_plan_status(infft_plan p, infft_status* out) {
     if (!p || !out) return fail(INFFT_EINVAL, "null argument");
+    if (p->bopt_ready && p->stat_nrec > 0) {
+        launch_solve_stats(p->stat_rec, p->stat_nrec, p->status, p->stream);
+        LAUNCH_CHECK();
+    }
     HIP_TRY(hipStreamSynchronize(p->stream));
     long long st[STATUS_WORDS];
     HIP_TRY(hipMemcpy(st, p->status, sizeof(st), hipMemcpyDeviceToHost));
@@ -718,6 +842,31 @@ int nfft_plan_status(infft_plan p, infft_status* out) {
 }
 
 int64_t nfft_plan_device_bytes(infft_plan p) { return p ? p->bytes : 0; }
+
+int infft_profile_begin(infft_plan p, int kernel_class) {
+    if (!p) return fail(INFFT_EINVAL, "null plan");
+    if (kernel_class < INFFT_K_NODES || kernel_class > INFFT_K_SOLVE) return fail(INFFT_EINVAL, "bad kernel class");
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    p->ev_used = 0;
+    p->prof_class = kernel_class;
+    return INFFT_OK;
+}
+
+int infft_profile_end(infft_plan p, double* total_ms, int64_t* launches) {
+    if (!p || !total_ms || !launches) return fail(INFFT_EINVAL, "null argument");
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < p->ev_used; i += 2) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, p->ev_pool[i], p->ev_pool[i + 1]));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)(p->ev_used / 2);
+    p->prof_class = 0;
+    p->ev_used = 0;
+    return INFFT_OK;
+}
 
 void nfft_plan_destroy(infft_plan p) {
     if (!p) return;

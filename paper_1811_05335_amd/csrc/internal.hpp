@@ -70,7 +70,14 @@ struct Geo {
     int64_t G;         // prod Ms
     int64_t P;         // prod M
     double b;          // Kaiser-Bessel shape pi (2 - 1/sigma)
+    // Window polynomials: for a node with offset u in (m-1, m], tap tau < 2m lies in one unit
+    // interval of the window, w(u - tau) = P_tau(y) with y = 2 (u - (m-1)) - 1 in [-1, 1];
+    // coefficients (plan precision) [tau][WPOLY_NC], ascending powers of y.
+    const void* wpoly;
 };
+template <typename R> struct WPoly;
+template <> struct WPoly<float> { static constexpr int NC = 11; };   // degree 10: ~2e-7 relative
+template <> struct WPoly<double> { static constexpr int NC = 17; };  // degree 16: ~2e-14 relative
 
 // Sort key of grid cell (c0, c1): tile-major, row-major inside a tile, so that the nodes of one
 // spreading tile form a contiguous range in sorted order.
@@ -201,10 +208,13 @@ struct SolveArgs {
     double2* B64;           // [T][N] sorted order
     float2* B32;            // [T][N] sorted order (nullptr for FP64 plans)
     long long* status;
+    long long* stat_rec;    // per-block statistics records [block][5]
+    int stat_off;           // first record of this launch
     int tables_in_lds;      // set by the launcher (1-D plans whose kernel tables fit in LDS)
 };
-void launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl, hipStream_t s);
-void launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s);
+int launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl, hipStream_t s);
+int launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s);
+void launch_solve_stats(const long long* rec, int nrec, long long* status, hipStream_t s);
 int solve_max_supported();
 
 }  // namespace infft

@@ -40,6 +40,105 @@ __device__ inline double2 tay_eval(const double2* __restrict__ tab, int qmax, do
     return acc;
 }
 
+// Copies n doubles from global memory to LDS with the whole workgroup, eight loads in flight per
+// thread before the first store.
+__device__ inline void stage_to_lds(double* dst, const double* __restrict__ src, int n) {
+    for (int i0 = threadIdx.x; i0 < n; i0 += 8 * blockDim.x) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = i0 + k * blockDim.x;
+            v[k] = (i < n) ? src[i] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int i = i0 + k * blockDim.x;
+            if (i < n) dst[i] = v[k];
+        }
+    }
+}
+
+
+// Per-block statistics of the solve kernels.  Each block reduces its waves' counters and writes
+// one record with plain stores (same-address global atomics from every wave would serialise in
+// the L2); k_solve_stats folds the records into the status block once all tiers have run.
+struct SolveStat {
+    unsigned long long mn, mx, fail, empty, over;
+};
+
+__device__ inline void write_block_stats(long long* rec, unsigned long long st_min, unsigned long long st_max,
+                                         unsigned long long st_fail, unsigned long long st_empty,
+                                         unsigned long long st_over) {
+    __shared__ SolveStat s_st[16];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        st_min = min(st_min, (unsigned long long)__shfl_xor((long long)st_min, o, 64));
+        st_max = max(st_max, (unsigned long long)__shfl_xor((long long)st_max, o, 64));
+        st_fail += (unsigned long long)__shfl_xor((long long)st_fail, o, 64);
+        st_empty += (unsigned long long)__shfl_xor((long long)st_empty, o, 64);
+        st_over += (unsigned long long)__shfl_xor((long long)st_over, o, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) s_st[w] = SolveStat{st_min, st_max, st_fail, st_empty, st_over};
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        SolveStat t = s_st[0];
+        for (int i = 1; i < (int)(blockDim.x + 63) / 64; ++i) {
+            t.mn = min(t.mn, s_st[i].mn);
+            t.mx = max(t.mx, s_st[i].mx);
+            t.fail += s_st[i].fail;
+            t.empty += s_st[i].empty;
+            t.over += s_st[i].over;
+        }
+        long long* r = rec + (int64_t)blockIdx.x * 5;
+        r[0] = (long long)t.mn;
+        r[1] = (long long)t.mx;
+        r[2] = (long long)t.fail;
+        r[3] = (long long)t.empty;
+        r[4] = (long long)t.over;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_solve_stats(const long long* rec, int nrec, long long* status) {
+    __shared__ unsigned long long sh[5][256];
+    unsigned long long mn = ULLONG_MAX, mx = 0, fail = 0, empty = 0, over = 0;
+    for (int i = threadIdx.x; i < nrec; i += blockDim.x) {
+        mn = min(mn, (unsigned long long)rec[i * 5 + 0]);
+        mx = max(mx, (unsigned long long)rec[i * 5 + 1]);
+        fail += rec[i * 5 + 2];
+        empty += rec[i * 5 + 3];
+        over += rec[i * 5 + 4];
+    }
+    sh[0][threadIdx.x] = mn;
+    sh[1][threadIdx.x] = mx;
+    sh[2][threadIdx.x] = fail;
+    sh[3][threadIdx.x] = empty;
+    sh[4][threadIdx.x] = over;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const int o = threadIdx.x + w;
+            sh[0][threadIdx.x] = min(sh[0][threadIdx.x], sh[0][o]);
+            sh[1][threadIdx.x] = max(sh[1][threadIdx.x], sh[1][o]);
+            sh[2][threadIdx.x] += sh[2][o];
+            sh[3][threadIdx.x] += sh[3][o];
+            sh[4][threadIdx.x] += sh[4][o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        status[ST_MIN_N] = (sh[0][0] == ULLONG_MAX) ? LLONG_MAX : (long long)sh[0][0];
+        status[ST_MAX_N] = (long long)sh[1][0];
+        status[ST_FAILED] = (long long)sh[2][0];
+        status[ST_EMPTY] = (long long)sh[3][0];
+        status[ST_OVERSIZED] = (long long)sh[4][0];
+    }
+}
+
+void launch_solve_stats(const long long* rec, int nrec, long long* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve_stats, dim3(1), dim3(256), 0, s, rec, nrec, status);
+}
+
 // Ordering point for the LDS exchange inside one wavefront: LDS operations of a wave execute
 // in program order, so only the compiler has to be kept from moving accesses across it.
 __device__ inline void wave_sync() {
@@ -290,22 +389,7 @@ __global__ void __launch_bounds__(256) k_solve(Geo g, NodesDev nd, KTabDev kt, S
     }
 
     // ---- statistics: reduce over the wave, one set of atomics per wave
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        st_min = min(st_min, (unsigned long long)__shfl_xor((long long)st_min, o, 64));
-        st_max = max(st_max, (unsigned long long)__shfl_xor((long long)st_max, o, 64));
-        st_fail += (unsigned long long)__shfl_xor((long long)st_fail, o, 64);
-        st_empty += (unsigned long long)__shfl_xor((long long)st_empty, o, 64);
-        st_over += (unsigned long long)__shfl_xor((long long)st_over, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        unsigned long long* st = (unsigned long long*)a.status;
-        if (st_min != ULLONG_MAX) atomicMin(&st[ST_MIN_N], st_min);
-        if (st_max) atomicMax(&st[ST_MAX_N], st_max);
-        if (st_fail) atomicAdd(&st[ST_FAILED], st_fail);
-        if (st_empty) atomicAdd(&st[ST_EMPTY], st_empty);
-        if (st_over) atomicAdd(&st[ST_OVERSIZED], st_over);
-    }
+    write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, st_min, st_max, st_fail, st_empty, st_over);
 }
 
 // ------------------------------------------------------------------ 1-D: real solves + rank one
@@ -328,6 +412,25 @@ __device__ inline double tay_eval_r(const double* __restrict__ tab, int qmax, do
 #pragma unroll
     for (int p = TAY_NC - 2; p >= 0; --p) acc = fma(acc, e, c[p]);
     return acc;
+}
+
+// Entries of B_opt belonging to a 1-D problem that no tier solves are set to zero.
+__device__ inline void zero_members_1d(const Geo& g, const NodesDev& nd, int l, int lane, int NL,
+                                       const SolveArgs& a) {
+    const int Ms = g.Ms[0], w2 = 2 * g.m;
+    int lo = l - w2;
+    if (lo < 0) lo += Ms;
+    for (int c = 0; c <= w2; ++c) {
+        int cell = lo + c;
+        if (cell >= Ms) cell -= Ms;
+        const int s = nd.start[cell], e = nd.start[cell + 1];
+        for (int p = s + lane; p < e; p += NL) {
+            int tau = l - nd.l0s[p];
+            if (tau < 0) tau += Ms;
+            a.B64[(int64_t)tau * g.N + p] = make_double2(0.0, 0.0);
+            if (a.B32) a.B32[(int64_t)tau * g.N + p] = make_float2(0.0f, 0.0f);
+        }
+    }
 }
 
 template <int NL>
@@ -357,11 +460,8 @@ __global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt
     const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / NL;
     const int64_t count = a.in_list ? (int64_t)(*a.in_count) : g.G;
 
-    {
-        const int nQ = (kt.qQ + 1) * TAY_NC;
-        for (int i = threadIdx.x; i < nQ; i += blockDim.x) s_tabr[i] = kt.Qs[i];
-        __syncthreads();
-    }
+    stage_to_lds(s_tabr, kt.Qs, (kt.qQ + 1) * TAY_NC);
+    __syncthreads();
     const double* tQ = s_tabr;
     const double c1 = (double)g.Ms[0] * kt.dM * kt.dM;
 
@@ -384,6 +484,7 @@ __global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt
                     ++st_over;
                 }
             }
+            if (!a.out_list) zero_members_1d(g, nd, l, lane, NL, a);
             continue;
         }
         if (lane == 0) {
@@ -494,215 +595,252 @@ __global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt
         wave_sync();
     }
 
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        st_min = min(st_min, (unsigned long long)__shfl_xor((long long)st_min, o, 64));
-        st_max = max(st_max, (unsigned long long)__shfl_xor((long long)st_max, o, 64));
-        st_fail += (unsigned long long)__shfl_xor((long long)st_fail, o, 64);
-        st_empty += (unsigned long long)__shfl_xor((long long)st_empty, o, 64);
-        st_over += (unsigned long long)__shfl_xor((long long)st_over, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        unsigned long long* st = (unsigned long long*)a.status;
-        if (st_min != ULLONG_MAX) atomicMin(&st[ST_MIN_N], st_min);
-        if (st_max) atomicMax(&st[ST_MAX_N], st_max);
-        if (st_fail) atomicAdd(&st[ST_FAILED], st_fail);
-        if (st_empty) atomicAdd(&st[ST_EMPTY], st_empty);
-        if (st_over) atomicAdd(&st[ST_OVERSIZED], st_over);
-    }
+    write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, st_min, st_max, st_fail, st_empty, st_over);
 }
 
 // ------------------------------------------------------------------ 1-D: one thread per problem
 // For |I(l)| <= NMAX (the common case: about 2m members at one node per grid cell) a single thread
 // holds the whole real system of the Sherman-Morrison form in registers: the lower triangle of A0,
 // the three right-hand sides and the solution, with every loop unrolled.  Rows beyond n are padded
-// with an identity block and zero right-hand sides, which decouples them exactly.  Problems with
-// more members, or with a member exactly on the edge of its window (u = m), are appended to the
-// list of the group kernels.
-template <int NMAX>
-__global__ void __launch_bounds__(256) k_solve_t1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
-    extern __shared__ double s_tabq[];
-    {
-        const int nQ = (kt.qQ + 1) * TAY_NC;
-        for (int i = threadIdx.x; i < nQ; i += blockDim.x) s_tabq[i] = kt.Qs[i];
-        __syncthreads();
-    }
-    const int Ms = g.Ms[0], w2 = 2 * g.m;
-    const double c1 = (double)Ms * kt.dM * kt.dM;
-    unsigned long long st_min = ULLONG_MAX, st_max = 0, st_fail = 0, st_empty = 0;
+// with an identity block and zero right-hand sides, which decouples them exactly.
+//
+// A workgroup takes TPB consecutive grid indices.  Their members are consecutive sorted nodes
+// p0(l) .. p0(l)+n-1, and (L_l^* L_l)[i][j] = M_sigma Qs(t_i - t_j) depends only on the node pair
+// (t = M_sigma x = l0 + u), so every local matrix is a principal submatrix of one banded matrix
+// over the workgroup's node range; the band (offsets 0 .. NMAX-1) is evaluated once in LDS.  The
+// phase w_i = e^{i pi z_i / sigma} factors into e^{i pi l / sigma} e^{-i pi t_p / sigma}, the second
+// factor per node.  Windows that wrap around the torus (the first 2m-1 grid indices) evaluate their
+// entries directly.  Problems with more members or with a member exactly on the window edge
+// (u = m) are appended to the list of the group kernels.
+constexpr int T1_TPB = 128;
+constexpr int T1_NODECAP = 320;   // staged nodes per workgroup (density up to ~2.4 per cell)
 
-    for (int64_t li = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; li < g.G;
-         li += (int64_t)gridDim.x * blockDim.x) {
-        const int l = (int)li;
-        // members: cells l-2m+1 .. l (one or two contiguous ranges), edge cell l-2m
+template <int NMAX>
+__global__ void __launch_bounds__(T1_TPB) k_solve_t1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
+    extern __shared__ double s_tabq[];                      // Qs, then Ks Taylor tables
+    __shared__ double s_band[T1_NODECAP * NMAX];       // band of the workgroup's nodes
+    __shared__ int s_l0[T1_NODECAP];                   // stencil base of the staged nodes
+    __shared__ double s_u[T1_NODECAP];                 // offsets: t_p = l0_p + u_p
+    __shared__ double2 s_phi[T1_NODECAP];              // e^{-i pi t_p / sigma}
+    __shared__ int s_range[2];
+    const int nQ = (kt.qQ + 1) * TAY_NC, nK = (kt.qK + 1) * TAY_NC;
+    stage_to_lds(s_tabq, kt.Qs, nQ);
+    stage_to_lds(s_tabq + nQ, kt.Ks, nK);
+    const double* s_tabk = s_tabq + nQ;
+
+    const int Ms = g.Ms[0], w2 = 2 * g.m;
+    const int L0 = blockIdx.x * T1_TPB;
+    const int l = L0 + threadIdx.x;
+    // node range of the workgroup: from the first member of problem L0 to the last of L0+TPB-1
+    if (threadIdx.x == 0) {
+        const int lo = max(L0 - w2 + 1, 0);
+        const int hi = min(L0 + T1_TPB, Ms);
+        s_range[0] = nd.start[lo];
+        s_range[1] = nd.start[hi];
+    }
+    __syncthreads();
+    const int P0 = s_range[0];
+    const int nnode = min(s_range[1] - P0, T1_NODECAP);
+    const bool staged = (s_range[1] - P0) <= T1_NODECAP;
+    for (int i = threadIdx.x; i < nnode; i += blockDim.x) {
+        const int p = P0 + i;
+        s_l0[i] = nd.l0s[p];
+        s_u[i] = nd.us[p];
+        // e^{-i pi t / sigma}, the integer part reduced exactly modulo 2 M_sigma
+        const int64_t lm = ((int64_t)nd.l0s[p] * g.M[0]) % (2 * (int64_t)Ms);
+        double sn, cs;
+        sincospi((double)lm / (double)Ms + nd.us[p] * kt.inv_sigma, &sn, &cs);
+        s_phi[i] = make_double2(cs, -sn);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nnode * NMAX; e += blockDim.x) {
+        const int i = e / NMAX, d = e - i * NMAX;
+        double v = 0.0;
+        // t_{i+d} - t_i with the integer parts subtracted exactly
+        if (i + d < nnode)
+            v = kt.scaleG * tay_eval_r(s_tabq, kt.qQ, (double)(s_l0[i + d] - s_l0[i]) + (s_u[i + d] - s_u[i]));
+        s_band[e] = v;
+    }
+    __syncthreads();
+
+    const double c1 = (double)Ms * kt.dM * kt.dM;
+    unsigned long long st_min = ULLONG_MAX, st_max = 0, st_fail = 0, st_empty = 0, st_over = 0;
+    if (l < Ms) {
+        // members: cells l-2m+1 .. l, one range, or two when the window wraps (l < 2m-1)
         const int clo = l - w2 + 1;
-        int s0, e0, s1 = 0, e1 = 0;
-        if (clo >= 0) {
+        const bool wrap = clo < 0;
+        int s0, n0, s1 = 0, n1 = 0;
+        if (!wrap) {
             s0 = nd.start[clo];
-            e0 = nd.start[l + 1];
+            n0 = nd.start[l + 1] - s0;
         } else {
             s0 = nd.start[clo + Ms];
-            e0 = nd.start[Ms];
+            n0 = nd.start[Ms] - s0;
             s1 = nd.start[0];
-            e1 = nd.start[l + 1];
+            n1 = nd.start[l + 1] - s1;
         }
-        int ce = l - w2;
-        if (ce < 0) ce += Ms;
-        const int es = nd.start[ce], ee = nd.start[ce + 1];
-        bool edge = false;
-        for (int p = es; p < ee; ++p) edge |= nd.us[p] == (double)g.m;
-        const int n0 = e0 - s0, n = n0 + (e1 - s1);
-        if (n > NMAX || edge) {
+        const int n = n0 + n1;
+        bool fallback = n > NMAX || (!wrap && !staged);
+        {
+            // the cell l-2m reaches l through its tap 2m only for nodes with u = m exactly; the tap
+            // 2m of every other node belongs to no problem and is zeroed here
+            int ce = l - w2;
+            if (ce < 0) ce += Ms;
+            const int es = nd.start[ce], ee = nd.start[ce + 1];
+            for (int p = es; p < ee; ++p) {
+                if (nd.us[p] == (double)g.m) {
+                    fallback = true;
+                } else {
+                    a.B64[(int64_t)w2 * g.N + p] = make_double2(0.0, 0.0);
+                    if (a.B32) a.B32[(int64_t)w2 * g.N + p] = make_float2(0.0f, 0.0f);
+                }
+            }
+        }
+        if (fallback) {
             const int slot = atomicAdd(a.out_count, 1);
             a.out_list[slot] = l;
-            continue;
-        }
-        if (n == 0) {
+        } else if (n == 0) {
             ++st_empty;
-            continue;
-        }
-        st_min = min(st_min, (unsigned long long)n);
-        st_max = max(st_max, (unsigned long long)n);
-
-        int pm[NMAX], tau[NMAX];
-        double z[NMAX], t[NMAX], ur[NMAX], ui[NMAX];
+        } else {
+            st_min = n;
+            st_max = n;
+            const int b0 = s0 - P0;   // first member in the staged node range (non-wrapping windows)
+            // e^{i pi l / sigma}, reduced exactly
+            double sl, cl;
+            sincospi((double)(((int64_t)l * g.M[0]) % (2 * (int64_t)Ms)) / (double)Ms, &sl, &cl);
+            int tau[NMAX], pm[NMAX];
+            double t[NMAX], ur[NMAX], ui[NMAX], wr[NMAX], wi[NMAX], zz[NMAX];
 #pragma unroll
-        for (int i = 0; i < NMAX; ++i) {
-            pm[i] = 0;
-            tau[i] = 0;
-            z[i] = 0.0;
-            t[i] = ur[i] = ui[i] = 0.0;
-            if (i < n) {
-                const int p = (i < n0) ? s0 + i : s1 + (i - n0);
-                pm[i] = p;
-                int tt = l - nd.l0s[p];
-                if (tt < 0) tt += Ms;
-                tau[i] = tt;
-                z[i] = (double)tt - nd.us[p];
-                t[i] = tay_eval_r(kt.Ks, kt.qK, z[i]);
-                sincospi(z[i] * kt.inv_sigma, &ui[i], &ur[i]);
-            }
-        }
-        double wr[NMAX], wi[NMAX];
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i) {
-            wr[i] = ur[i];
-            wi[i] = ui[i];
-        }
-        // lower triangle of A0 (padded rows: identity)
-        double A[NMAX * (NMAX + 1) / 2];
-#pragma unroll
-        for (int i = 0; i < NMAX; ++i) {
-#pragma unroll
-            for (int j = 0; j <= i; ++j) {
-                double v = (i == j) ? 1.0 : 0.0;
+            for (int i = 0; i < NMAX; ++i) {
+                tau[i] = 0;
+                pm[i] = 0;
+                zz[i] = 0.0;
+                t[i] = ur[i] = ui[i] = 0.0;
                 if (i < n) {
-                    v = kt.scaleG * tay_eval_r(s_tabq, kt.qQ, z[j] - z[i]);
-                    if (i == j) v += kt.lam;
+                    int p, l0;
+                    double u;
+                    if (!wrap) {
+                        p = s0 + i;
+                        l0 = s_l0[b0 + i];
+                        u = s_u[b0 + i];
+                    } else {
+                        p = (i < n0) ? s0 + i : s1 + (i - n0);
+                        l0 = nd.l0s[p];
+                        u = nd.us[p];
+                    }
+                    pm[i] = p;
+                    int tt = l - l0;
+                    if (tt < 0) tt += Ms;
+                    tau[i] = tt;
+                    zz[i] = (double)tt - u;
+                    t[i] = tay_eval_r(s_tabk, kt.qK, zz[i]);
+                    if (!wrap) {
+                        const double2 ph = s_phi[b0 + i];
+                        ur[i] = cl * ph.x - sl * ph.y;
+                        ui[i] = cl * ph.y + sl * ph.x;
+                    } else {
+                        sincospi(zz[i] * kt.inv_sigma, &ui[i], &ur[i]);
+                    }
                 }
-                A[i * (i + 1) / 2 + j] = v;
+                wr[i] = ur[i];
+                wi[i] = ui[i];
             }
-        }
-        // Cholesky in registers
-        bool ok = true;
+            double A[NMAX * (NMAX + 1) / 2];
 #pragma unroll
-        for (int k = 0; k < NMAX; ++k) {
-            const double piv = A[k * (k + 1) / 2 + k];
-            ok = ok && piv > 0.0;
-            const double sq = sqrt(piv > 0.0 ? piv : 1.0), inv = 1.0 / sq;
-            A[k * (k + 1) / 2 + k] = sq;
+            for (int i = 0; i < NMAX; ++i) {
 #pragma unroll
-            for (int i = k + 1; i < NMAX; ++i) A[i * (i + 1) / 2 + k] *= inv;
-#pragma unroll
-            for (int i = k + 1; i < NMAX; ++i) {
-                const double lik = A[i * (i + 1) / 2 + k];
-#pragma unroll
-                for (int j = k + 1; j <= i; ++j) A[i * (i + 1) / 2 + j] = fma(-lik, A[j * (j + 1) / 2 + k], A[i * (i + 1) / 2 + j]);
+                for (int j = 0; j <= i; ++j) {
+                    double v = (i == j) ? 1.0 : 0.0;
+                    if (i < n) {
+                        if (!wrap) v = s_band[(b0 + j) * NMAX + (i - j)];
+                        else v = kt.scaleG * tay_eval_r(s_tabq, kt.qQ, zz[j] - zz[i]);
+                        if (i == j) v += kt.lam;
+                    }
+                    A[i * (i + 1) / 2 + j] = v;
+                }
             }
-        }
-        if (!ok) {
-            ++st_fail;
-            continue;
-        }
-        // L y = rhs, then L^T x = y, three right-hand sides
+            bool ok = true;
 #pragma unroll
-        for (int k = 0; k < NMAX; ++k) {
-            const double iv = 1.0 / A[k * (k + 1) / 2 + k];
-            t[k] *= iv;
-            ur[k] *= iv;
-            ui[k] *= iv;
+            for (int k = 0; k < NMAX; ++k) {
+                const double piv = A[k * (k + 1) / 2 + k];
+                ok = ok && piv > 0.0;
+                const double sq = sqrt(piv > 0.0 ? piv : 1.0), inv = 1.0 / sq;
+                A[k * (k + 1) / 2 + k] = sq;
 #pragma unroll
-            for (int i = k + 1; i < NMAX; ++i) {
-                const double lik = A[i * (i + 1) / 2 + k];
-                t[i] = fma(-lik, t[k], t[i]);
-                ur[i] = fma(-lik, ur[k], ur[i]);
-                ui[i] = fma(-lik, ui[k], ui[i]);
+                for (int i = k + 1; i < NMAX; ++i) A[i * (i + 1) / 2 + k] *= inv;
+#pragma unroll
+                for (int i = k + 1; i < NMAX; ++i) {
+                    const double lik = A[i * (i + 1) / 2 + k];
+#pragma unroll
+                    for (int j = k + 1; j <= i; ++j)
+                        A[i * (i + 1) / 2 + j] = fma(-lik, A[j * (j + 1) / 2 + k], A[i * (i + 1) / 2 + j]);
+                }
             }
-        }
+            if (!ok) {
+                ++st_fail;
+            } else {
 #pragma unroll
-        for (int k = NMAX - 1; k >= 0; --k) {
-            const double iv = 1.0 / A[k * (k + 1) / 2 + k];
-            t[k] *= iv;
-            ur[k] *= iv;
-            ui[k] *= iv;
+                for (int k = 0; k < NMAX; ++k) {
+                    const double iv = 1.0 / A[k * (k + 1) / 2 + k];
+                    t[k] *= iv;
+                    ur[k] *= iv;
+                    ui[k] *= iv;
 #pragma unroll
-            for (int i = 0; i < k; ++i) {
-                const double lki = A[k * (k + 1) / 2 + i];
-                t[i] = fma(-lki, t[k], t[i]);
-                ur[i] = fma(-lki, ur[k], ur[i]);
-                ui[i] = fma(-lki, ui[k], ui[i]);
-            }
-        }
-        // Sherman-Morrison combination
-        double sdot = 0.0, wtr = 0.0, wti = 0.0;
+                    for (int i = k + 1; i < NMAX; ++i) {
+                        const double lik = A[i * (i + 1) / 2 + k];
+                        t[i] = fma(-lik, t[k], t[i]);
+                        ur[i] = fma(-lik, ur[k], ur[i]);
+                        ui[i] = fma(-lik, ui[k], ui[i]);
+                    }
+                }
 #pragma unroll
-        for (int i = 0; i < NMAX; ++i) {
-            sdot = fma(wr[i], ur[i], fma(wi[i], ui[i], sdot));
-            wtr = fma(wr[i], t[i], wtr);
-            wti = fma(-wi[i], t[i], wti);
-        }
-        const double den = 1.0 + c1 * sdot;
-        const double cr = (kt.dM - c1 * wtr) / den, ci = (-c1 * wti) / den;
+                for (int k = NMAX - 1; k >= 0; --k) {
+                    const double iv = 1.0 / A[k * (k + 1) / 2 + k];
+                    t[k] *= iv;
+                    ur[k] *= iv;
+                    ui[k] *= iv;
 #pragma unroll
-        for (int i = 0; i < NMAX; ++i) {
-            if (i < n) {
-                const double2 b = make_double2(t[i] + ur[i] * cr - ui[i] * ci, ur[i] * ci + ui[i] * cr);
-                const int64_t idx = (int64_t)tau[i] * g.N + pm[i];
-                a.B64[idx] = b;
-                if (a.B32) a.B32[idx] = make_float2((float)b.x, (float)b.y);
+                    for (int i = 0; i < k; ++i) {
+                        const double lki = A[k * (k + 1) / 2 + i];
+                        t[i] = fma(-lki, t[k], t[i]);
+                        ur[i] = fma(-lki, ur[k], ur[i]);
+                        ui[i] = fma(-lki, ui[k], ui[i]);
+                    }
+                }
+                double sdot = 0.0, wtr = 0.0, wti = 0.0;
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    sdot = fma(wr[i], ur[i], fma(wi[i], ui[i], sdot));
+                    wtr = fma(wr[i], t[i], wtr);
+                    wti = fma(-wi[i], t[i], wti);
+                }
+                const double den = 1.0 + c1 * sdot;
+                const double cr = (kt.dM - c1 * wtr) / den, ci = (-c1 * wti) / den;
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    if (i < n) {
+                        const double2 bb = make_double2(t[i] + ur[i] * cr - ui[i] * ci, ur[i] * ci + ui[i] * cr);
+                        const int64_t idx = (int64_t)tau[i] * g.N + pm[i];
+                        a.B64[idx] = bb;
+                        if (a.B32) a.B32[idx] = make_float2((float)bb.x, (float)bb.y);
+                    }
+                }
             }
         }
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        st_min = min(st_min, (unsigned long long)__shfl_xor((long long)st_min, o, 64));
-        st_max = max(st_max, (unsigned long long)__shfl_xor((long long)st_max, o, 64));
-        st_fail += (unsigned long long)__shfl_xor((long long)st_fail, o, 64);
-        st_empty += (unsigned long long)__shfl_xor((long long)st_empty, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        unsigned long long* st = (unsigned long long*)a.status;
-        if (st_min != ULLONG_MAX) atomicMin(&st[ST_MIN_N], st_min);
-        if (st_max) atomicMax(&st[ST_MAX_N], st_max);
-        if (st_fail) atomicAdd(&st[ST_FAILED], st_fail);
-        if (st_empty) atomicAdd(&st[ST_EMPTY], st_empty);
-    }
+    write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, st_min, st_max, st_fail, st_empty, st_over);
 }
 
-void launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s) {
-    const size_t shm = (size_t)(kt.qQ + 1) * TAY_NC * sizeof(double);
-    int64_t blocks = (g.G + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
-    hipLaunchKernelGGL((k_solve_t1<13>), dim3((unsigned)blocks), dim3(256), shm, s, g, nd, kt, a);
+int launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s) {
+    const size_t shm = (size_t)((kt.qQ + 1) + (kt.qK + 1)) * TAY_NC * sizeof(double);
+    const unsigned blocks = (unsigned)((g.Ms[0] + T1_TPB - 1) / T1_TPB);
+    hipLaunchKernelGGL((k_solve_t1<13>), dim3(blocks), dim3(T1_TPB), shm, s, g, nd, kt, a);
+    return (int)blocks;
 }
 
 int solve_max_supported() { return 32; }
 
-void launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl, hipStream_t s) {
-    const int64_t groups_per_block = 256 / nl;
-    int64_t blocks = (g.G + groups_per_block - 1) / groups_per_block;
-    const int64_t cap = a.in_list ? 512 : 2048;
-    if (blocks > cap) blocks = cap;
+int launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl, hipStream_t s) {
     if (g.d == 1) {
         // Q table of at most (2*8*TAY_S+2)*TAY_NC doubles (about 21 KB) in LDS
         const size_t shm = (size_t)(kt.qQ + 1) * TAY_NC * sizeof(double);
@@ -712,11 +850,16 @@ void launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int n
         if (b1 > cap1) b1 = cap1;
         if (nl == 16) hipLaunchKernelGGL((k_solve_r1<16>), dim3((unsigned)b1), dim3(128), shm, s, g, nd, kt, a);
         else hipLaunchKernelGGL((k_solve_r1<32>), dim3((unsigned)b1), dim3(128), shm, s, g, nd, kt, a);
-    } else {
-        a.tables_in_lds = 0;
-        if (nl == 16) hipLaunchKernelGGL((k_solve<2, 16>), dim3((unsigned)blocks), dim3(256), 0, s, g, nd, kt, a);
-        else hipLaunchKernelGGL((k_solve<2, 32>), dim3((unsigned)blocks), dim3(256), 0, s, g, nd, kt, a);
+        return (int)b1;
     }
+    const int64_t groups_per_block = 256 / nl;
+    int64_t blocks = (g.G + groups_per_block - 1) / groups_per_block;
+    const int64_t cap = a.in_list ? 512 : 2048;
+    if (blocks > cap) blocks = cap;
+    a.tables_in_lds = 0;
+    if (nl == 16) hipLaunchKernelGGL((k_solve<2, 16>), dim3((unsigned)blocks), dim3(256), 0, s, g, nd, kt, a);
+    else hipLaunchKernelGGL((k_solve<2, 32>), dim3((unsigned)blocks), dim3(256), 0, s, g, nd, kt, a);
+    return (int)blocks;
 }
 
 }  // namespace infft

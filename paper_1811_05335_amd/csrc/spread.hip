@@ -6,8 +6,9 @@
 //   grad_x     d/dx_j of the interpolation through the window derivative
 //
 // The Kaiser-Bessel window w(v) = sinh(b sqrt(m^2 - v^2)) / (pi sqrt(m^2 - v^2)) is evaluated in
-// registers; whether a tap lies in the closed support |v| <= m is decided in float64 from the
-// stored offsets for both precisions.
+// registers from per-tap polynomials fitted at plan time (w is an entire function of v, so each
+// unit interval needs degree 10 in FP32 and 16 in FP64); whether a tap lies in the closed support
+// |v| <= m is decided in float64 from the stored offsets for both precisions.
 //
 // Spreading runs one workgroup per grid tile (TS0 x TS1 cells).  The nodes of a tile are a
 // contiguous range of the sorted node order; their contributions are accumulated with LDS
@@ -18,53 +19,56 @@
 
 namespace infft {
 
-template <typename R> __device__ inline R kb_window(R v, int m, R b);
-
-template <> __device__ inline float kb_window<float>(float v, int m, float b) {
-    const float t2 = ((float)m - v) * ((float)m + v);
-    const float t = sqrtf(fmaxf(t2, 0.0f));
-    return t > 0.0f ? sinhf(b * t) / (3.14159265358979323846f * t) : b / 3.14159265358979323846f;
-}
-template <> __device__ inline double kb_window<double>(double v, int m, double b) {
-    const double t2 = ((double)m - v) * ((double)m + v);
-    const double t = sqrt(fmax(t2, 0.0));
-    return t > 0.0 ? sinh(b * t) / (M_PI * t) : b / M_PI;
-}
-
-// d w / d v inside the support: -v (x cosh x - sinh x) / (pi t^3) with x = b t, t = sqrt(m^2 - v^2),
-// written as
-// -v b^3 r(x) / pi, r(x) = (x cosh x - sinh x)/x^3 = sum_{n>=1} 2n x^(2n-2) / (2n+1)!.
-template <typename R> __device__ inline R kb_window_deriv(R v, int m, R b) {
-    const R t2 = ((R)m - v) * ((R)m + v);
-    const R t = sqrt(t2 > (R)0 ? t2 : (R)0);
-    const R x = b * t;
-    const R thr = (sizeof(R) == 8) ? (R)0.1 : (R)0.5;
-    R r;
-    if (x < thr) {
-        const R x2 = x * x;
-        r = (R)(1.0 / 3) + x2 * ((R)(1.0 / 30) + x2 * ((R)(1.0 / 840) + x2 * ((R)(1.0 / 45360) + x2 * (R)(1.0 / 3991680))));
-    } else {
-        r = (x * cosh(x) - sinh(x)) / (x * x * x);
-    }
-    return -v * b * b * b * r / (R)M_PI;
-}
-
+// Window values of the 2m+1 taps of one node.  Taps tau < 2m: Horner in y of the plan's polynomial
+// of that tap (membership |u - tau| <= m still decided in float64); tap 2m reaches the window only
+// when u = m exactly, where the window equals its edge value b/pi.
 template <typename R, int W>
-__device__ inline void window_row(double u, int m, R b, R* w) {
+__device__ inline void window_row(const Geo& g, double u, R* w) {
+    constexpr int NC = WPoly<R>::NC;
+    const R* cf = (const R*)g.wpoly;
+    const R y = (R)(2.0 * (u - (double)(g.m - 1)) - 1.0);
 #pragma unroll
-    for (int tau = 0; tau < W; ++tau) {
-        const double vd = u - (double)tau;
-        w[tau] = (fabs(vd) <= (double)m) ? kb_window<R>((R)vd, m, b) : (R)0;
+    for (int tau = 0; tau < W - 1; ++tau) {
+        R acc = cf[tau * NC + NC - 1];
+#pragma unroll
+        for (int k = NC - 2; k >= 0; --k) acc = acc * y + cf[tau * NC + k];
+        w[tau] = (fabs(u - (double)tau) <= (double)g.m) ? acc : (R)0;
     }
+    w[W - 1] = (u == (double)g.m) ? (R)(g.b / M_PI) : (R)0;
 }
 
+// Derivatives d w / d v of the same taps (times `scale`): d/dv = 2 d/dy; at the on-grid edge tap
+// the one-sided derivative inside the support, m b^3 / (3 pi).
 template <typename R, int W>
-__device__ inline void window_deriv_row(double u, int m, R b, R scale, R* dw) {
+__device__ inline void window_deriv_row(const Geo& g, double u, R scale, R* dw) {
+    constexpr int NC = WPoly<R>::NC;
+    const R* cf = (const R*)g.wpoly;
+    const R y = (R)(2.0 * (u - (double)(g.m - 1)) - 1.0);
 #pragma unroll
-    for (int tau = 0; tau < W; ++tau) {
-        const double vd = u - (double)tau;
-        dw[tau] = (fabs(vd) <= (double)m) ? scale * kb_window_deriv<R>((R)vd, m, b) : (R)0;
+    for (int tau = 0; tau < W - 1; ++tau) {
+        R p = cf[tau * NC + NC - 1], dp = (R)0;
+#pragma unroll
+        for (int k = NC - 2; k >= 0; --k) {
+            dp = dp * y + p;
+            p = p * y + cf[tau * NC + k];
+        }
+        dw[tau] = (fabs(u - (double)tau) <= (double)g.m) ? (R)2 * scale * dp : (R)0;
     }
+    dw[W - 1] = (u == (double)g.m) ? (R)(scale * (double)g.m * g.b * g.b * g.b / (3.0 * M_PI)) : (R)0;
+}
+
+// One tap with a tap index known only at run time (gather over the nodes reaching one cell).
+template <typename R>
+__device__ inline R window_tap(const Geo& g, double u, int tau) {
+    constexpr int NC = WPoly<R>::NC;
+    if (tau >= 2 * g.m) return (u == (double)g.m) ? (R)(g.b / M_PI) : (R)0;
+    if (fabs(u - (double)tau) > (double)g.m) return (R)0;
+    const R* cf = (const R*)g.wpoly + tau * NC;
+    const R y = (R)(2.0 * (u - (double)(g.m - 1)) - 1.0);
+    R acc = cf[NC - 1];
+#pragma unroll
+    for (int k = NC - 2; k >= 0; --k) acc = acc * y + cf[k];
+    return acc;
 }
 
 __device__ inline int wrap_add(int a, int t, int Ms) {
@@ -82,11 +86,11 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, NodesDev nd, const cx<R>*
     if (j >= g.N) return;
     const R b = (R)g.b;
     R w0[W], w1[W];
-    window_row<R, W>(nd.uc[j * D], g.m, b, w0);
+    window_row<R, W>(g, nd.uc[j * D], w0);
     const int a0 = nd.l0c[j * D];
     int a1 = 0;
     if (D == 2) {
-        window_row<R, W>(nd.uc[j * D + 1], g.m, b, w1);
+        window_row<R, W>(g, nd.uc[j * D + 1], w1);
         a1 = nd.l0c[j * D + 1];
     }
     for (int r = 0; r < nrhs; ++r) {
@@ -187,8 +191,8 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
             const int a1 = (D == 2) ? nd.l0s[(int64_t)p * D + 1] - base1 : 0;
             R w0[W], w1[W];
             if (!USEB) {
-                window_row<R, W>(nd.us[(int64_t)p * D], g.m, b, w0);
-                if (D == 2) window_row<R, W>(nd.us[(int64_t)p * D + 1], g.m, b, w1);
+                window_row<R, W>(g, nd.us[(int64_t)p * D], w0);
+                if (D == 2) window_row<R, W>(g, nd.us[(int64_t)p * D + 1], w1);
             }
             for (int rr = 0; rr < rc; ++rr) {
                 const C fv = f[(int64_t)(r0 + rr) * g.N + j];
@@ -240,6 +244,50 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
     }
 }
 
+// ------------------------------------------------------------------ 1-D spreading as a gather
+// In one dimension the nodes reaching grid cell l are those with stencil base l0 in
+// l-2m .. l (mod M_sigma), a contiguous range (two at the wrap) of the sorted order.  One thread
+// per cell sums them directly: no atomics, no halos, every (node, tap) pair evaluated once.
+
+template <typename R, bool USEB>
+__global__ void __launch_bounds__(256) k_gather1d(Geo g, NodesDev nd, const cx<R>* __restrict__ f,
+                                                  const cx<R>* __restrict__ B, cx<R>* __restrict__ grid,
+                                                  int64_t grs, int nrhs) {
+    using C = cx<R>;
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Ms = g.Ms[0], w2 = 2 * g.m;
+    if (l >= Ms) return;
+    const R b = (R)g.b;
+    int lo = l - w2;
+    int s0, e0, s1 = 0, e1 = 0;
+    if (lo >= 0) {
+        s0 = nd.start[lo];
+        e0 = nd.start[l + 1];
+    } else {
+        s0 = nd.start[lo + Ms];
+        e0 = nd.start[Ms];
+        s1 = nd.start[0];
+        e1 = nd.start[l + 1];
+    }
+    for (int r = 0; r < nrhs; ++r) {
+        C acc = cmake((R)0, (R)0);
+        for (int seg = 0; seg < 2; ++seg) {
+            const int s = seg ? s1 : s0, e = seg ? e1 : e0;
+            for (int p = s; p < e; ++p) {
+                int tau = l - nd.l0s[p];
+                if (tau < 0) tau += Ms;
+                const C fv = f[(int64_t)r * g.N + nd.perm[p]];
+                if (USEB) {
+                    acc = cadd(acc, cmulc(fv, B[(int64_t)tau * g.N + p]));
+                } else {
+                    acc = cadd(acc, cscale(fv, window_tap<R>(g, nd.us[p], tau)));
+                }
+            }
+        }
+        grid[(int64_t)r * grs + l] = acc;
+    }
+}
+
 // ------------------------------------------------------------------ gradient with respect to x
 
 template <typename R, int D, int W>
@@ -251,13 +299,13 @@ __global__ void __launch_bounds__(256) k_grad_x(Geo g, NodesDev nd, const cx<R>*
     if (j >= g.N) return;
     const R b = (R)g.b;
     R w0[W], w1[W], d0[W], d1[W];
-    window_row<R, W>(nd.uc[j * D], g.m, b, w0);
-    window_deriv_row<R, W>(nd.uc[j * D], g.m, b, (R)g.Ms[0], d0);
+    window_row<R, W>(g, nd.uc[j * D], w0);
+    window_deriv_row<R, W>(g, nd.uc[j * D], (R)g.Ms[0], d0);
     const int a0 = nd.l0c[j * D];
     int a1 = 0;
     if (D == 2) {
-        window_row<R, W>(nd.uc[j * D + 1], g.m, b, w1);
-        window_deriv_row<R, W>(nd.uc[j * D + 1], g.m, b, (R)g.Ms[1], d1);
+        window_row<R, W>(g, nd.uc[j * D + 1], w1);
+        window_deriv_row<R, W>(g, nd.uc[j * D + 1], (R)g.Ms[1], d1);
         a1 = nd.l0c[j * D + 1];
     }
     R gx0 = 0, gx1 = 0;
@@ -355,6 +403,12 @@ template <typename R>
 void launch_spread(const Geo& g, NodesDev nd, const cx<R>* f, const cx<R>* B, cx<R>* grid, int64_t grs,
                    cx<R>* h0, cx<R>* h1, cx<R>* h01, int64_t hrs0, int64_t hrs1, int64_t hrs01, int nrhs,
                    int rchunk, hipStream_t s) {
+    if (g.d == 1) {
+        const unsigned nb = (unsigned)((g.Ms[0] + 255) / 256);
+        if (B) hipLaunchKernelGGL((k_gather1d<R, true>), dim3(nb), dim3(256), 0, s, g, nd, f, B, grid, grs, nrhs);
+        else hipLaunchKernelGGL((k_gather1d<R, false>), dim3(nb), dim3(256), 0, s, g, nd, f, B, grid, grs, nrhs);
+        return;
+    }
     const unsigned blocks = (unsigned)(g.ntile[0] * (g.d == 2 ? g.ntile[1] : 1));
     const int64_t cells = (int64_t)(g.TS[0] + 2 * g.m) * (g.d == 2 ? g.TS[1] + 2 * g.m : 1);
     const int rc = min(rchunk, nrhs);

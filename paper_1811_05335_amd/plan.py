@@ -154,6 +154,18 @@ class NfftPlan:
         d["code"] = code
         return d
 
+    def profile_begin(self, kernel_class: str) -> None:
+        """Time every launch of one kernel class with HIP events on the plan's stream."""
+        self._sync_stream()
+        check(load().infft_profile_begin(self._h, _lib.KERNEL_CLASSES[kernel_class]))
+
+    def profile_end(self):
+        """(summed milliseconds, number of launches) since profile_begin."""
+        ms = C.c_double()
+        n = C.c_int64()
+        check(load().infft_profile_end(self._h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
+
     def device_bytes(self) -> int:
         return int(load().nfft_plan_device_bytes(self._h))
 

@@ -17,3 +17,4 @@ from .plan import (  # noqa: F401
     nfft_trafo,
 )
 from ._lib import InfftError  # noqa: F401
+from .autograd import NfftFunction, InfftApplyFunction, nfft, infft  # noqa: F401

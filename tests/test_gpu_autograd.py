@@ -1,0 +1,122 @@
+"""Gradients through the autograd wrappers: torch.autograd.gradcheck in FP64 (complex coefficients,
+real nodes) on tiny problems, and the loss ||iNFFT(NFFT(fhat)) - fhat||^2 against the FP64 oracle's
+analytic gradient and central finite differences of the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import bopt as obopt
+from oracle import grad as ograd
+from oracle import nfft as onfft
+
+from gpu_util import nodes_dev, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_gradcheck_nfft_fp64(d):
+    from paper_1811_05335_amd import NfftPlan, nfft
+    M = (8,) if d == 1 else (6, 4)
+    N = 9
+    g = W.rng(50 + d)
+    # nodes kept away from window-support edges so the finite differences stay inside one piece
+    x = W.uniform_nodes(g, N, d)
+    xd = nodes_dev(x).requires_grad_(True)
+    fh = torch.from_numpy(W.complex_normal(g, M)).cuda().requires_grad_(True)
+    P = NfftPlan(M, nodes_dev(x), sigma=2.0, m=2, precision="f64")
+    assert torch.autograd.gradcheck(lambda a: nfft(a, xd.detach(), P), (fh,), eps=1e-6, atol=1e-8)
+
+    def fx(xx):
+        return nfft(fh.detach(), xx, P)
+
+    assert torch.autograd.gradcheck(fx, (xd,), eps=1e-7, atol=1e-5, rtol=1e-4)
+
+
+def test_gradcheck_infft_apply_fp64():
+    from paper_1811_05335_amd import NfftPlan, infft
+    M, N = (8,), 20
+    x = W.uniform_nodes(W.rng(60), N, 1)
+    P = NfftPlan(M, nodes_dev(x), sigma=2.0, m=2, precision="f64", rho=1e-6)
+    P.precompute_B()
+    f = torch.from_numpy(W.complex_normal(W.rng(61), (N,))).cuda().requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda a: infft(a, P), (f,), eps=1e-6, atol=1e-8)
+
+
+def _setup(precision, d, seed):
+    from paper_1811_05335_amd import NfftPlan
+    M = (32,) if d == 1 else (12, 10)
+    N = 80 if d == 1 else 300
+    g = W.rng(seed)
+    x = W.jittered_nodes(g, N) if d == 1 else W.uniform_nodes(g, N, 2)
+    fh_np = W.complex_normal(g, (2,) + M)
+    y_np = W.complex_normal(g, (2,) + M)
+    if precision == "f32":
+        fh_np = W.round_to(fh_np, "f32")
+        y_np = W.round_to(y_np, "f32")
+    rho = 1e-10 if d == 1 else 1e-6
+    mm = 4 if d == 1 else 3
+    P = NfftPlan(M, nodes_dev(x), sigma=2.0, m=mm, precision=precision, max_rhs=2)        # follows x
+    Pi = NfftPlan(M, nodes_dev(x), sigma=2.0, m=mm, precision=precision, rho=rho, max_rhs=2)  # frozen B_opt
+    Pi.precompute_B()
+    rows = Pi.get_B().cpu().numpy()
+    if precision == "f32":
+        rows = rows.astype(np.complex64).astype(np.complex128)
+    return M, N, x, fh_np, y_np, P, Pi, rows, onfft.Params(M, 2.0, mm)
+
+
+def _oracle_grads(x, fh_np, target, rows, p):
+    """L = ||apply(trafo(fhat; x)) - target||^2 with target = fhat or an independent y.
+    PyTorch's gradient of a real loss is 2 dL/dconj(z)."""
+    f_o = onfft.trafo(x, fh_np, p)
+    r = obopt.apply(x, f_o, rows, p) - target
+    gC = obopt.apply_adjoint(x, 2 * r, rows, p)
+    g_fh = onfft.adjoint(x, gC, p)
+    return g_fh, ograd.nfft_grad_x(x, fh_np, gC, p), r
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 1e-4)])
+@pytest.mark.parametrize("d", [1, 2])
+def test_loss_gradients_through_nfft_and_inverse_match_oracle(precision, tol, d):
+    """L = ||iNFFT(NFFT(fhat; x)) - y|| ^2, y independent of fhat, B_opt frozen: gradients with
+    respect to fhat and x against the oracle's analytic gradient."""
+    from paper_1811_05335_amd import infft, nfft
+    M, N, x, fh_np, y_np, P, Pi, rows, p = _setup(precision, d, 70 + d)
+    ct = torch.complex64 if precision == "f32" else torch.complex128
+    fh = torch.from_numpy(fh_np).to(ct).cuda().requires_grad_(True)
+    y = torch.from_numpy(y_np).to(ct).cuda()
+    xd = nodes_dev(x).requires_grad_(True)
+    (infft(nfft(fh, xd, P), Pi) - y).abs().pow(2).sum().backward()
+    g_fh, g_x, _ = _oracle_grads(x, fh_np, y_np, rows, p)
+    assert rel(fh.grad.detach().cpu().numpy(), g_fh) <= tol
+    assert rel(xd.grad.detach().cpu().numpy(), g_x) <= tol
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_reconstruction_loss_gradients_fp64(d):
+    """The reconstruction loss L = ||iNFFT(NFFT(fhat; x)) - fhat||^2.  Its residual is a difference of
+    nearly equal vectors (the inversion is accurate), so agreement is judged against the size of
+    the terms: |grad - ref| <= 1e-10 (|ref| + 2 ||C^* C fhat|| eps-scale), with the oracle's
+    x-gradient also checked against central differences of the oracle loss."""
+    from paper_1811_05335_amd import infft, nfft
+    M, N, x, fh_np, _, P, Pi, rows, p = _setup("f64", d, 80 + d)
+    fh = torch.from_numpy(fh_np).cuda().requires_grad_(True)
+    xd = nodes_dev(x).requires_grad_(True)
+    (infft(nfft(fh, xd, P), Pi) - fh).abs().pow(2).sum().backward()
+    g_fh, g_x, r = _oracle_grads(x, fh_np, fh_np, rows, p)
+    g_fh = g_fh - 2 * r          # the target is fhat itself: dL/dconj(fhat) gains -r
+    scale = 1e-12 * np.linalg.norm(fh_np)
+    assert np.linalg.norm(fh.grad.detach().cpu().numpy() - g_fh) <= 1e-6 * np.linalg.norm(g_fh) + scale
+    gxs = np.linalg.norm(g_x)
+    assert np.linalg.norm(xd.grad.detach().cpu().numpy() - g_x) <= 1e-6 * gxs + 1e-12 * np.abs(fh_np).sum() * N
+
+    def L(xx):
+        return float(np.sum(np.abs(obopt.apply(x, onfft.trafo(xx, fh_np, p), rows, p) - fh_np) ** 2))
+    h = 1e-7
+    for j in [0, N // 3, N - 1]:
+        for t in range(d):
+            xp = x.copy(); xp[j, t] += h
+            xm = x.copy(); xm[j, t] -= h
+            fd = (L(xp) - L(xm)) / (2 * h)
+            assert abs(fd - g_x[j, t]) <= 1e-4 * max(abs(g_x[j, t]), 1e-6)

@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=192, help="grid indices of the sampled oracle B solve")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph replay")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="run one device-to-device copy of this size first (counter calibration under a profiler)")
     ap.add_argument("--fp64", dest="fp64", action="store_true", default=True)
     ap.add_argument("--no-fp64", dest="fp64", action="store_false")
     return ap.parse_args()
@@ -183,6 +185,25 @@ def member_counts(x, Ms, m):
     return n
 
 
+def solve_traffic(precision):
+    """Measured HBM bytes per launch of the solve kernel, from the committed counter summary, or None
+    once the kernel source differs from the one the counters were taken on."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_solve_t1_c2_hbm.md")
+    src = os.path.join(ROOT, "paper_1811_05335_amd", "csrc", "solve.hip")
+    try:
+        text = open(path).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    mh = re.search(r"source_sha256: ([0-9a-f]{64})", text)
+    mt = re.search(r"traffic_bytes_per_launch_%s: ([0-9]+)" % precision, text)
+    if not mh or not mt or mh.group(1) != digest:
+        return None
+    return int(mt.group(1))
+
+
 def solve_flops(n):
     """FP64 flops of one local problem as the 1-D kernel computes it (real Sherman-Morrison form):
     Gram entries n(n+1)/2 Taylor evaluations (10 fma), right-hand side n (10 fma), Cholesky n^3/3,
@@ -234,6 +255,13 @@ def main():
     if a.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if a.copy_calibration_mb:
+        import torch
+        src = torch.ones(a.copy_calibration_mb * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg = WORKLOAD
     M, N, sigma, m, rho = cfg["M"], cfg["N"], cfg["sigma"], cfg["m"], cfg["rho"]
     R = a.rhs
@@ -275,7 +303,7 @@ def main():
     ms_solve = kc["solve"]["ms_per_launch"]
     roof_solve = {"bound": "alu", "kernel": "k_solve_t1 (B optimisation, FP64, one thread per grid index)",
                   "achieved": flops / (ms_solve * 1e-3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
-                  "frac": flops / (ms_solve * 1e-3) / 1e12 / 78.6, "traffic": None,
+                  "frac": flops / (ms_solve * 1e-3) / 1e12 / 78.6, "traffic": solve_traffic("f32"),
                   "algorithmic_flops_per_launch": flops, "ms_per_launch": ms_solve,
                   "units_per_launch": int(np.sum(nl > 0))}
     # HBM view of the streaming kernels: bytes they must move at least once per launch

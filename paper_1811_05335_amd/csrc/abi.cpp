@@ -123,6 +123,23 @@ struct infft_plan_s {
     int stat_nrec = 0;
     bool bopt_ready = false;
 
+    // large local problems: sizes, failure flags and one batch of matrices and members,
+    // allocated when first needed and grown on demand
+    int* big_n = nullptr;
+    int* big_fail = nullptr;
+    int64_t big_fail_cap = 0;
+    double2* big_A = nullptr;
+    int64_t big_A_cap = 0;
+    int* big_midx = nullptr;
+    int* big_mtap = nullptr;
+    double2* big_mz = nullptr;
+    double2* big_mr = nullptr;
+    int64_t big_m_cap = 0;
+    BigProb* big_probs = nullptr;
+    int64_t big_probs_cap = 0;
+    int4* big_tasks = nullptr;
+    int64_t big_tasks_cap = 0;
+
     // optional event timing of one kernel class
     int prof_class = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -140,6 +157,25 @@ struct infft_plan_s {
         allocs.push_back(q);
         bytes += (int64_t)nb;
         *p = (T*)q;
+        return INFFT_OK;
+    }
+
+    // Replaces *p by an allocation of at least `need` elements when it holds fewer.
+    template <typename T>
+    int grow(T** p, int64_t& cap, int64_t need) {
+        if (need <= cap) return INFFT_OK;
+        if (*p) {
+            auto it = std::find(allocs.begin(), allocs.end(), (void*)*p);
+            if (it != allocs.end()) allocs.erase(it);
+            (void)hipFree(*p);
+            bytes -= cap * (int64_t)sizeof(T);
+            *p = nullptr;
+            cap = 0;
+        }
+        const int64_t n = need + need / 4;
+        int rc = alloc(p, n);
+        if (rc) return rc;
+        cap = n;
         return INFFT_OK;
     }
 
@@ -392,6 +428,124 @@ int check_rhs(infft_plan_s* P, int nrhs) {
 // Schedules are built per chunk size (the number of sequences enters the pass descriptors).
 int schedule_for(infft_plan_s* P, int rc) {
     return build_schedule(P, rc, P->to_grid, P->to_coeff);
+}
+
+// Local problems with more members than the register tiers hold (list of grid indices and its
+// device count from the last tier).  Reads the count and the sizes back to the host, sorts the
+// problems by size, packs them into batches whose matrices fit the workspace and runs the
+// blocked Cholesky pipeline on each batch; adds one statistics record.
+int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* count_dev, int& stat_off) {
+    const Geo& g = p->g;
+    hipStream_t st = p->stream;
+    int count = 0;
+    HIP_TRY(hipMemcpyAsync(&count, count_dev, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (count <= 0) return INFFT_OK;
+    int rc;
+    if (!p->big_n && (rc = p->alloc(&p->big_n, g.G))) return rc;
+    launch_big_count(g, p->nd, list, count, p->big_n, st);
+    LAUNCH_CHECK();
+    std::vector<int> ls(count), ns(count);
+    HIP_TRY(hipMemcpyAsync(ls.data(), list, sizeof(int) * count, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(ns.data(), p->big_n, sizeof(int) * count, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    std::vector<int> order(count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+        return ns[a] != ns[b] ? ns[a] > ns[b] : ls[a] < ls[b];
+    });
+    const int nmax = ns[order.front()], nmin = ns[order.back()];
+    if ((rc = p->grow(&p->big_fail, p->big_fail_cap, count))) return rc;
+    launch_fill_i32(p->big_fail, count, 0, st);
+    // workspace of one batch: matrices plus member data (40 bytes per member)
+    constexpr int64_t kBudget = (int64_t)1 << 30;
+    const int64_t cap_bytes = std::max<int64_t>(kBudget, (int64_t)nmax * nmax * 16 + (int64_t)nmax * 40 + 4096);
+    std::vector<BigProb> probs;
+    std::vector<int4> tasks;
+    size_t pos = 0;
+    while (pos < order.size()) {
+        probs.clear();
+        int64_t ent = 0, mem = 0;
+        while (pos < order.size()) {
+            const int q = order[pos];
+            const int64_t n = ns[q];
+            const int64_t e = (n * n + 31) / 32 * 32;
+            if (!probs.empty() && (ent + e) * 16 + (mem + n) * 40 > cap_bytes) break;
+            BigProb b{};
+            b.l = ls[q];
+            b.n = (int)n;
+            b.nblk = (int)((n + BIG_NB - 1) / BIG_NB);
+            b.id = q;
+            b.off = ent;
+            b.moff = mem;
+            probs.push_back(b);
+            ent += e;
+            mem += n;
+            ++pos;
+        }
+        const int np = (int)probs.size();
+        const int T0 = probs.front().nblk;
+        // task lists: Gram tiles, then per block column k the panel and trailing tiles
+        tasks.clear();
+        std::vector<int64_t> seg;   // [gram, trsm_0, herk_0, trsm_1, herk_1, ...] starts
+        seg.push_back(0);
+        for (int i = 0; i < np; ++i)
+            for (int I = 0; I < probs[i].nblk; ++I)
+                for (int J = 0; J <= I; ++J) tasks.push_back(make_int4(i, I, J, 0));
+        for (int k = 0; k < T0; ++k) {
+            seg.push_back((int64_t)tasks.size());
+            for (int i = 0; i < np && probs[i].nblk > k; ++i)
+                for (int I = k + 1; I < probs[i].nblk; ++I) tasks.push_back(make_int4(i, I, 0, 0));
+            seg.push_back((int64_t)tasks.size());
+            for (int i = 0; i < np && probs[i].nblk > k; ++i)
+                for (int I = k + 1; I < probs[i].nblk; ++I)
+                    for (int J = k + 1; J <= I; ++J) tasks.push_back(make_int4(i, I, J, 0));
+        }
+        seg.push_back((int64_t)tasks.size());
+        if ((rc = p->grow(&p->big_A, p->big_A_cap, std::max<int64_t>(ent, 1)))) return rc;
+        if (mem > p->big_m_cap) {
+            int64_t c1 = p->big_m_cap, c2 = p->big_m_cap, c3 = p->big_m_cap, c4 = p->big_m_cap;
+            if ((rc = p->grow(&p->big_midx, c1, mem)) || (rc = p->grow(&p->big_mtap, c2, mem)) ||
+                (rc = p->grow(&p->big_mz, c3, mem)) || (rc = p->grow(&p->big_mr, c4, mem)))
+                return rc;
+            p->big_m_cap = c1;
+        }
+        if ((rc = p->grow(&p->big_probs, p->big_probs_cap, np))) return rc;
+        if ((rc = p->grow(&p->big_tasks, p->big_tasks_cap, std::max<int64_t>((int64_t)tasks.size(), 1)))) return rc;
+        HIP_TRY(hipMemcpyAsync(p->big_probs, probs.data(), sizeof(BigProb) * np, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(p->big_tasks, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice, st));
+        BigArgs a{};
+        a.probs = p->big_probs;
+        a.A = p->big_A;
+        a.midx = p->big_midx;
+        a.mtap = p->big_mtap;
+        a.mz = p->big_mz;
+        a.mr = p->big_mr;
+        a.fail = p->big_fail;
+        launch_big_setup(g, p->nd, kt, a, np, st);
+        LAUNCH_CHECK();
+        launch_big_gram(g, kt, a, p->big_tasks + seg[0], (int)(seg[1] - seg[0]), st);
+        LAUNCH_CHECK();
+        int active = np;
+        for (int k = 0; k < T0; ++k) {
+            while (active > 0 && probs[active - 1].nblk <= k) --active;
+            launch_big_potrf(a, active, k, st);
+            LAUNCH_CHECK();
+            const int64_t t0 = seg[1 + 2 * k], t1 = seg[2 + 2 * k], t2 = seg[3 + 2 * k];
+            launch_big_trsm(a, p->big_tasks + t0, (int)(t1 - t0), k, st);
+            LAUNCH_CHECK();
+            launch_big_herk(a, p->big_tasks + t1, (int)(t2 - t1), k, st);
+            LAUNCH_CHECK();
+        }
+        launch_big_solve(g, a, np, p->B64, p->B32, st);
+        LAUNCH_CHECK();
+        // the host task arrays are reused by the next batch
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    launch_big_stats(p->big_fail, count, nmin, nmax, p->stat_rec + (int64_t)stat_off * 5, st);
+    LAUNCH_CHECK();
+    stat_off += 1;
+    return INFFT_OK;
 }
 
 }  // namespace
@@ -687,8 +841,14 @@ int nfft_adjoint(infft_plan p, const void* f, void* h, int nrhs) {
 
 int infft_precompute_B(infft_plan p) {
     if (!p) return fail(INFFT_EINVAL, "null plan");
+    // The pass for problems beyond the register tiers reads their sizes back to the host; under
+    // graph capture it cannot run, and such problems are counted as oversized (zero columns).
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(p->stream, &cs));
+    const bool capturing = cs != hipStreamCaptureStatusNone;
     const Geo& g = p->g;
     const int64_t TN = (int64_t)p->taps() * g.N;
+    p->bopt_ready = false;
     launch_status_init(p->status, 1, p->stream);
     if (g.d == 2) {
         // 1-D tiers write every entry of B_opt themselves (zeros where no problem reaches)
@@ -717,8 +877,11 @@ int infft_precompute_B(infft_plan p) {
     a.stat_off = 0;
     int* listA = p->lists;
     int* listB = p->lists + g.G;
+    const int* last_list;
+    const int* last_count;
     if (g.d == 1) {
-        // one thread per problem for small I(l); the rest in groups of 16, then 32 lanes
+        // one thread per problem for small I(l); the rest in groups of 16, then 32 lanes, then
+        // the blocked pass
         a.in_list = nullptr;
         a.in_count = nullptr;
         a.out_list = listA;
@@ -736,6 +899,10 @@ int infft_precompute_B(infft_plan p) {
         LAUNCH_CHECK();
         a.in_list = listB;
         a.in_count = p->lcount + 1;
+        a.out_list = listA;
+        a.out_count = p->lcount + 2;
+        last_list = listA;
+        last_count = p->lcount + 2;
     } else {
         a.in_list = nullptr;
         a.in_count = nullptr;
@@ -748,12 +915,23 @@ int infft_precompute_B(infft_plan p) {
         LAUNCH_CHECK();
         a.in_list = listA;
         a.in_count = p->lcount;
+        a.out_list = listB;
+        a.out_count = p->lcount + 1;
+        last_list = listB;
+        last_count = p->lcount + 1;
     }
-    a.out_list = nullptr;
-    a.out_count = nullptr;
+    if (capturing) {
+        a.out_list = nullptr;
+        a.out_count = nullptr;
+    }
     a.stat_off += launch_solve_tier(g, p->nd, kt, a, 32, p->stream);
     LAUNCH_CHECK();
-    p->stat_nrec = a.stat_off;   // folded into the status block by nfft_plan_status
+    int stat_off = a.stat_off;
+    if (!capturing) {
+        int rc = solve_large(p, kt, last_list, last_count, stat_off);
+        if (rc) return rc;
+    }
+    p->stat_nrec = stat_off;   // folded into the status block by nfft_plan_status
     p->bopt_ready = true;
     return INFFT_OK;
 }
@@ -835,7 +1013,7 @@ int nfft_plan_status(infft_plan p, infft_status* out) {
     out->min_members = st[ST_MIN_N] == LLONG_MAX ? 0 : st[ST_MIN_N];
     out->max_members = st[ST_MAX_N];
     out->bopt_ready = p->bopt_ready ? 1 : 0;
-    out->max_supported = solve_max_supported();
+    out->max_supported = INT32_MAX;   // limited only by device memory (16 n^2 bytes)
     if (p->bopt_ready && st[ST_FAILED] > 0)
         return fail(INFFT_ESINGULAR, "%lld local solves met a non-positive pivot", st[ST_FAILED]);
     return INFFT_OK;

@@ -117,6 +117,49 @@ struct KTabDev {
     double scaleG;     // prod M_sigma
 };
 
+// Taylor evaluation of a complex kernel table at z (grid units); the tables hold z >= 0 and
+// F(-z) = conj F(z) because the coefficients D_k are real.
+__device__ inline double2 tay_eval(const double2* __restrict__ tab, int qmax, double z) {
+    const double az = fabs(z);
+    int q = (int)rint(az * (double)TAY_S);
+    if (q > qmax) q = qmax;
+    const double e = az - (double)q * (1.0 / TAY_S);
+    const double2* c = tab + (int64_t)q * TAY_NC;
+    double2 acc = c[TAY_NC - 1];
+#pragma unroll
+    for (int p = TAY_NC - 2; p >= 0; --p) {
+        const double2 cp = c[p];
+        acc.x = fma(acc.x, e, cp.x);
+        acc.y = fma(acc.y, e, cp.y);
+    }
+    if (z < 0.0) acc.y = -acc.y;
+    return acc;
+}
+
+// ------------------------------------------------------------------ large local problems
+
+constexpr int BIG_NB = 64;   // block size of the blocked Cholesky
+
+struct BigProb {
+    int l;         // grid index
+    int n;         // members |I(l)|
+    int nblk;      // ceil(n / BIG_NB)
+    int id;        // index of the problem's failure flag
+    int64_t off;   // first entry of its n x n matrix (row-major) in the workspace
+    int64_t moff;  // first member slot
+};
+
+struct BigArgs {
+    const BigProb* probs;
+    double2* A;    // Gram matrices, then their Cholesky factors (lower triangle; the strictly
+                   // upper part of each diagonal block holds its inverse, conjugate-transposed)
+    int* midx;     // member -> sorted node position
+    int* mtap;     // member -> tap index (row of B_opt)
+    double2* mz;   // member -> z = tau - u per dimension
+    double2* mr;   // member -> right-hand side, then solution
+    int* fail;     // per problem id: non-positive pivot
+};
+
 // ------------------------------------------------------------------ FFT pass description
 
 constexpr int FFT_THREADS = 256;
@@ -215,6 +258,15 @@ struct SolveArgs {
 int launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl, hipStream_t s);
 int launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s);
 void launch_solve_stats(const long long* rec, int nrec, long long* status, hipStream_t s);
-int solve_max_supported();
+
+// solve_big.hip
+void launch_big_count(const Geo& g, NodesDev nd, const int* list, int count, int* nout, hipStream_t s);
+void launch_big_setup(const Geo& g, NodesDev nd, KTabDev kt, BigArgs a, int nprob, hipStream_t s);
+void launch_big_gram(const Geo& g, KTabDev kt, BigArgs a, const int4* tasks, int ntask, hipStream_t s);
+void launch_big_potrf(BigArgs a, int nprob, int k, hipStream_t s);
+void launch_big_trsm(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t s);
+void launch_big_herk(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t s);
+void launch_big_solve(const Geo& g, BigArgs a, int nprob, double2* B64, float2* B32, hipStream_t s);
+void launch_big_stats(const int* fail, int n, int nmin, int nmax, long long* rec, hipStream_t s);
 
 }  // namespace infft

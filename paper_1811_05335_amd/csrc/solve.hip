@@ -23,23 +23,6 @@
 
 namespace infft {
 
-__device__ inline double2 tay_eval(const double2* __restrict__ tab, int qmax, double z) {
-    const double az = fabs(z);
-    int q = (int)rint(az * (double)TAY_S);
-    if (q > qmax) q = qmax;
-    const double e = az - (double)q * (1.0 / TAY_S);
-    const double2* c = tab + (int64_t)q * TAY_NC;
-    double2 acc = c[TAY_NC - 1];
-#pragma unroll
-    for (int p = TAY_NC - 2; p >= 0; --p) {
-        const double2 cp = c[p];
-        acc.x = fma(acc.x, e, cp.x);
-        acc.y = fma(acc.y, e, cp.y);
-    }
-    if (z < 0.0) acc.y = -acc.y;
-    return acc;
-}
-
 // Copies n doubles from global memory to LDS with the whole workgroup, eight loads in flight per
 // thread before the first store.
 __device__ inline void stage_to_lds(double* dst, const double* __restrict__ src, int n) {
@@ -838,7 +821,6 @@ int launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, h
     return (int)blocks;
 }
 
-int solve_max_supported() { return 32; }
 
 int launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl, hipStream_t s) {
     if (g.d == 1) {

@@ -1,0 +1,496 @@
+// Local least-squares problems of Algorithm 3.17 with more members than one lane group holds
+// (FP64): the dense centre of polar and spiral trajectories gives |I(l)| in the thousands.
+//
+// The system is the same as in the register tiers: (G + lambda I) b = r with
+// G[i][j] = M_sigma^d Q(z_j - z_i) and r_i = conj K(z_i), z = tau - u per dimension.  Here G is
+// formed in device memory (row-major, lower triangle) and factorised by a blocked right-looking
+// Cholesky with 64 x 64 blocks.  The host has read the problem sizes back, sorted the problems
+// by size (largest first) and packed them into batches whose matrices fit the workspace.  Per
+// batch:
+//   k_big_setup   one workgroup per problem: members of I(l), z, r and the tap of each member
+//   k_big_gram    one workgroup per 64 x 64 tile of the lower triangle
+//   for each block column k:
+//     k_big_potrf   factor the diagonal block in LDS and invert the factor (lower triangular)
+//     k_big_trsm    panel below it: L[i][k] = A[i][k] L_kk^{-*} (a product with the inverse)
+//     k_big_herk    trailing tiles: A[i][j] -= L[i][k] L[j][k]^*, k < j <= i
+//   k_big_solve   L y = r and L^* b = y with the inverse diagonal blocks, b written to B_opt
+// The inverse X = L_kk^{-1} needs no storage of its own: its strictly lower part, conjugated and
+// transposed, fills the unused strictly upper part of the diagonal block, and X[i][i] = 1/L[i][i].
+// Problems sorted largest first make "problems with more than k block columns" a prefix of the
+// batch, so k_big_potrf needs no task list.
+#include "internal.hpp"
+
+namespace infft {
+
+constexpr int BIG_TPB = 256;
+constexpr int CELL_TPB = 128;
+constexpr int MAX_CELLS = (2 * MAX_M_CUT + 1) * (2 * MAX_M_CUT + 1);
+
+// Cell c of the (2m+1)^d cells whose nodes may reach grid index l: the CSR range of its nodes
+// and whether it sits at tap 2m in a dimension (there only nodes with u = m exactly reach l).
+__device__ inline void big_cell(const Geo& g, const NodesDev& nd, int l, int c, int& s, int& e, bool& edge0,
+                                bool& edge1) {
+    const int W = 2 * g.m + 1, w2 = 2 * g.m;
+    if (g.d == 1) {
+        int c0 = l - c;
+        if (c0 < 0) c0 += g.Ms[0];
+        s = nd.start[c0];
+        e = nd.start[c0 + 1];
+        edge0 = c == w2;
+        edge1 = false;
+    } else {
+        const int lc0 = l / g.Ms[1], lc1 = l - lc0 * g.Ms[1];
+        const int tau0 = c / W, tau1 = c - tau0 * W;
+        int c0 = lc0 - tau0;
+        if (c0 < 0) c0 += g.Ms[0];
+        int c1 = lc1 - tau1;
+        if (c1 < 0) c1 += g.Ms[1];
+        const int64_t key = cell_key(g, c0, c1);
+        s = nd.start[key];
+        e = nd.start[key + 1];
+        edge0 = tau0 == w2;
+        edge1 = tau1 == w2;
+    }
+}
+
+__device__ inline bool big_member(const Geo& g, const NodesDev& nd, int p, bool edge0, bool edge1) {
+    const double um = (double)g.m;
+    if (edge0 && nd.us[(int64_t)p * g.d] != um) return false;
+    if (edge1 && nd.us[(int64_t)p * g.d + 1] != um) return false;
+    return true;
+}
+
+__device__ inline int big_cell_count(const Geo& g, const NodesDev& nd, int l, int c) {
+    int s, e;
+    bool e0, e1;
+    big_cell(g, nd, l, c, s, e, e0, e1);
+    if (!e0 && !e1) return e - s;
+    int n = 0;
+    for (int p = s; p < e; ++p) n += big_member(g, nd, p, e0, e1) ? 1 : 0;
+    return n;
+}
+
+__device__ inline int num_cells(const Geo& g) {
+    const int W = 2 * g.m + 1;
+    return g.d == 1 ? W : W * W;
+}
+
+// |I(l)| for each listed grid index.
+__global__ void __launch_bounds__(CELL_TPB) k_big_count(Geo g, NodesDev nd, const int* __restrict__ list,
+                                                        int* __restrict__ nout) {
+    __shared__ int s_sum[CELL_TPB];
+    const int l = list[blockIdx.x];
+    int n = 0;
+    for (int c = threadIdx.x; c < num_cells(g); c += CELL_TPB) n += big_cell_count(g, nd, l, c);
+    s_sum[threadIdx.x] = n;
+    __syncthreads();
+    for (int w = CELL_TPB / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s_sum[threadIdx.x] += s_sum[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) nout[blockIdx.x] = s_sum[0];
+}
+
+void launch_big_count(const Geo& g, NodesDev nd, const int* list, int count, int* nout, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_big_count, dim3(count), dim3(CELL_TPB), 0, s, g, nd, list, nout);
+}
+
+// Members of one problem (cells in order, nodes of a cell in sorted order), then per member the
+// tap index, z = tau - u per dimension and r = conj K(z).
+__global__ void __launch_bounds__(CELL_TPB) k_big_setup(Geo g, NodesDev nd, KTabDev kt, BigArgs a) {
+    __shared__ int s_base[MAX_CELLS + 1];
+    const BigProb P = a.probs[blockIdx.x];
+    const int ncell = num_cells(g);
+    for (int c = threadIdx.x; c < ncell; c += CELL_TPB) s_base[c + 1] = big_cell_count(g, nd, P.l, c);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_base[0] = 0;
+        for (int c = 0; c < ncell; ++c) s_base[c + 1] += s_base[c];
+        if (s_base[ncell] != P.n) a.fail[P.id] = 2;   // cannot happen: the count uses the same test
+    }
+    __syncthreads();
+    if (s_base[ncell] != P.n) return;
+    int* midx = a.midx + P.moff;
+    for (int c = threadIdx.x; c < ncell; c += CELL_TPB) {
+        int s, e;
+        bool e0, e1;
+        big_cell(g, nd, P.l, c, s, e, e0, e1);
+        int pos = s_base[c];
+        for (int p = s; p < e && pos < P.n; ++p)
+            if (big_member(g, nd, p, e0, e1)) midx[pos++] = p;
+    }
+    __syncthreads();
+    const int W = 2 * g.m + 1;
+    int lc0 = P.l, lc1 = 0;
+    if (g.d == 2) {
+        lc0 = P.l / g.Ms[1];
+        lc1 = P.l - lc0 * g.Ms[1];
+    }
+    for (int i = threadIdx.x; i < P.n; i += CELL_TPB) {
+        const int p = midx[i];
+        int tau0 = lc0 - nd.l0s[(int64_t)p * g.d];
+        if (tau0 < 0) tau0 += g.Ms[0];
+        double2 z = make_double2((double)tau0 - nd.us[(int64_t)p * g.d], 0.0);
+        double2 K = tay_eval(kt.K[0], kt.qK, z.x);
+        int tap = tau0;
+        if (g.d == 2) {
+            int tau1 = lc1 - nd.l0s[(int64_t)p * 2 + 1];
+            if (tau1 < 0) tau1 += g.Ms[1];
+            z.y = (double)tau1 - nd.us[(int64_t)p * 2 + 1];
+            K = cmul(K, tay_eval(kt.K[1], kt.qK, z.y));
+            tap = tau0 * W + tau1;
+        }
+        a.mtap[P.moff + i] = tap;
+        a.mz[P.moff + i] = z;
+        a.mr[P.moff + i] = cconj(K);
+    }
+}
+
+void launch_big_setup(const Geo& g, NodesDev nd, KTabDev kt, BigArgs a, int nprob, hipStream_t s) {
+    if (nprob <= 0) return;
+    hipLaunchKernelGGL(k_big_setup, dim3(nprob), dim3(CELL_TPB), 0, s, g, nd, kt, a);
+}
+
+// Tile (I, J), J <= I, of the lower triangle of G + lambda I.
+__global__ void __launch_bounds__(BIG_TPB) k_big_gram(Geo g, KTabDev kt, BigArgs a, const int4* __restrict__ tasks) {
+    __shared__ double2 s_zi[BIG_NB];
+    const int4 t = tasks[blockIdx.x];
+    const BigProb P = a.probs[t.x];
+    const int i0 = t.y * BIG_NB, j0 = t.z * BIG_NB;
+    if (threadIdx.x < BIG_NB) {
+        const int i = i0 + threadIdx.x;
+        s_zi[threadIdx.x] = i < P.n ? a.mz[P.moff + i] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int j = j0 + (threadIdx.x & (BIG_NB - 1));
+    if (j >= P.n) return;
+    const double2 zj = a.mz[P.moff + j];
+    double2* A = a.A + P.off;
+    for (int rr = threadIdx.x / BIG_NB; rr < BIG_NB; rr += BIG_TPB / BIG_NB) {
+        const int i = i0 + rr;
+        if (i >= P.n || j > i) continue;
+        const double2 zi = s_zi[rr];
+        double2 v = tay_eval(kt.Q[0], kt.qQ, zj.x - zi.x);
+        if (g.d == 2) v = cmul(v, tay_eval(kt.Q[1], kt.qQ, zj.y - zi.y));
+        v = cscale(v, kt.scaleG);
+        if (i == j) v = make_double2(v.x + kt.lam, 0.0);
+        A[(int64_t)i * P.n + j] = v;
+    }
+}
+
+void launch_big_gram(const Geo& g, KTabDev kt, BigArgs a, const int4* tasks, int ntask, hipStream_t s) {
+    if (ntask <= 0) return;
+    hipLaunchKernelGGL(k_big_gram, dim3(ntask), dim3(BIG_TPB), 0, s, g, kt, a, tasks);
+}
+
+// Diagonal block k of problem blockIdx.x: Cholesky in LDS, then X = L_kk^{-1} row by row
+// (X[i][j] = (delta_ij - sum_{j<=q<i} L[i][q] X[q][j]) / L[i][i]).  A non-positive pivot marks
+// the problem failed (its later steps run on zeros and its solution is not written).
+__global__ void __launch_bounds__(BIG_TPB) k_big_potrf(BigArgs a, int k) {
+    __shared__ double2 T[BIG_NB][BIG_NB + 1];
+    __shared__ double2 X[BIG_NB][BIG_NB + 1];
+    __shared__ double2 red[BIG_TPB / BIG_NB][BIG_NB];
+    const BigProb P = a.probs[blockIdx.x];
+    const int r0 = k * BIG_NB, nk = min(BIG_NB, P.n - r0);
+    double2* D = a.A + P.off + (int64_t)r0 * P.n + r0;   // the diagonal block
+    const int64_t ld = P.n;
+    for (int e = threadIdx.x; e < BIG_NB * BIG_NB; e += BIG_TPB) {
+        const int i = e / BIG_NB, j = e % BIG_NB;
+        T[i][j] = (i < nk && j <= i) ? D[(int64_t)i * ld + j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    bool ok = true;
+    for (int c = 0; c < nk; ++c) {
+        const double piv = T[c][c].x;   // the same value in every thread: the exit is uniform
+        if (!(piv > 0.0) || !isfinite(piv)) {
+            ok = false;
+            break;
+        }
+        const double sq = sqrt(piv), inv = 1.0 / sq;
+        __syncthreads();
+        if (threadIdx.x == 0) T[c][c] = make_double2(sq, 0.0);
+        for (int i = c + 1 + threadIdx.x; i < nk; i += BIG_TPB) T[i][c] = cscale(T[i][c], inv);
+        __syncthreads();
+        const int w = nk - c - 1;
+        for (int e = threadIdx.x; e < w * w; e += BIG_TPB) {
+            const int i = c + 1 + e / w, j = c + 1 + e % w;
+            if (j <= i) T[i][j] = csub(T[i][j], cmulc(T[i][c], T[j][c]));
+        }
+        __syncthreads();
+    }
+    if (ok) {
+        const int j = threadIdx.x % BIG_NB, part = threadIdx.x / BIG_NB;
+        constexpr int NP = BIG_TPB / BIG_NB;
+        for (int i = 0; i < nk; ++i) {
+            double2 acc = make_double2(0.0, 0.0);
+            for (int q = j + part; q < i; q += NP) acc = cadd(acc, cmul(T[i][q], X[q][j]));
+            red[part][j] = acc;
+            __syncthreads();
+            if (part == 0) {
+                double2 v = make_double2(0.0, 0.0);
+                if (j <= i) {
+                    double2 s = red[0][j];
+                    for (int pp = 1; pp < NP; ++pp) s = cadd(s, red[pp][j]);
+                    v = cscale(make_double2((i == j ? 1.0 : 0.0) - s.x, -s.y), 1.0 / T[i][i].x);
+                }
+                X[i][j] = v;
+            }
+            __syncthreads();
+        }
+    }
+    for (int e = threadIdx.x; e < BIG_NB * BIG_NB; e += BIG_TPB) {
+        const int i = e / BIG_NB, j = e % BIG_NB;
+        if (i >= nk || j >= nk) continue;
+        if (j <= i) D[(int64_t)i * ld + j] = T[i][j];
+        else D[(int64_t)i * ld + j] = ok ? cconj(X[j][i]) : make_double2(0.0, 0.0);
+    }
+    if (!ok && threadIdx.x == 0) a.fail[P.id] = 1;
+}
+
+// X[c][q] = (L_kk^{-1})[c][q] from the diagonal block D of the factor.
+__device__ inline double2 inv_entry(const double2* D, int64_t ld, int c, int q) {
+    if (q < c) return cconj(D[(int64_t)q * ld + c]);
+    if (q == c) return make_double2(1.0 / D[(int64_t)c * ld + c].x, 0.0);
+    return make_double2(0.0, 0.0);
+}
+
+void launch_big_potrf(BigArgs a, int nprob, int k, hipStream_t s) {
+    if (nprob <= 0) return;
+    hipLaunchKernelGGL(k_big_potrf, dim3(nprob), dim3(BIG_TPB), 0, s, a, k);
+}
+
+// Register tile of a 64 x 64 complex product: thread (tr, tc) owns rows 4 tr .. 4 tr + 3 and
+// columns 4 tc .. 4 tc + 3.
+struct Tile4 {
+    double2 v[4][4];
+    __device__ void zero() {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) v[a][b] = make_double2(0.0, 0.0);
+    }
+    // v += x y^*
+    __device__ void acc(const double2 (&x)[4], const double2 (&y)[4]) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                v[a][b].x = fma(x[a].x, y[b].x, fma(x[a].y, y[b].y, v[a][b].x));
+                v[a][b].y = fma(x[a].y, y[b].x, fma(-x[a].x, y[b].y, v[a][b].y));
+            }
+    }
+};
+
+// Panel block (I, k): A[I][k] <- A[I][k] X^*, X = L_kk^{-1}.
+__global__ void __launch_bounds__(BIG_TPB) k_big_trsm(BigArgs a, const int4* __restrict__ tasks, int k) {
+    constexpr int KC = 16;
+    __shared__ double2 sA[KC][BIG_NB + 1];   // [q][row]
+    __shared__ double2 sX[KC][BIG_NB + 1];   // [q][col]
+    const int4 t = tasks[blockIdx.x];
+    const BigProb P = a.probs[t.x];
+    const int r0 = t.y * BIG_NB, c0 = k * BIG_NB;
+    const int nr = min(BIG_NB, P.n - r0), nk = min(BIG_NB, P.n - c0);
+    double2* A = a.A + P.off;
+    const int64_t ld = P.n;
+    const double2* D = A + (int64_t)c0 * ld + c0;
+    const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+    Tile4 acc;
+    acc.zero();
+    for (int q0 = 0; q0 < nk; q0 += KC) {
+#pragma unroll
+        for (int s = 0; s < BIG_NB * KC / BIG_TPB; ++s) {
+            const int e = threadIdx.x + s * BIG_TPB;
+            const int r = e / KC, qq = e % KC, q = q0 + qq;
+            sA[qq][r] = (r < nr && q < nk) ? A[(int64_t)(r0 + r) * ld + c0 + q] : make_double2(0.0, 0.0);
+            sX[qq][r] = (r < nk && q < nk) ? inv_entry(D, ld, r, q) : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int qq = 0; qq < KC; ++qq) {
+            double2 x[4], y[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                x[u] = sA[qq][tr * 4 + u];
+                y[u] = sX[qq][tc * 4 + u];
+            }
+            acc.acc(x, y);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = tr * 4 + u, c = tc * 4 + v;
+            if (r < nr && c < nk) A[(int64_t)(r0 + r) * ld + c0 + c] = acc.v[u][v];
+        }
+}
+
+void launch_big_trsm(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t s) {
+    if (ntask <= 0) return;
+    hipLaunchKernelGGL(k_big_trsm, dim3(ntask), dim3(BIG_TPB), 0, s, a, tasks, k);
+}
+
+// Trailing tile (I, J), k < J <= I: A[I][J] -= L[I][k] L[J][k]^* (lower part only when I == J).
+__global__ void __launch_bounds__(BIG_TPB) k_big_herk(BigArgs a, const int4* __restrict__ tasks, int k) {
+    constexpr int KC = 16;
+    __shared__ double2 sI[KC][BIG_NB + 1];
+    __shared__ double2 sJ[KC][BIG_NB + 1];
+    const int4 t = tasks[blockIdx.x];
+    const BigProb P = a.probs[t.x];
+    const int rI = t.y * BIG_NB, rJ = t.z * BIG_NB, c0 = k * BIG_NB;
+    const int nI = min(BIG_NB, P.n - rI), nJ = min(BIG_NB, P.n - rJ), nk = min(BIG_NB, P.n - c0);
+    double2* A = a.A + P.off;
+    const int64_t ld = P.n;
+    const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+    Tile4 acc;
+    acc.zero();
+    for (int q0 = 0; q0 < nk; q0 += KC) {
+#pragma unroll
+        for (int s = 0; s < BIG_NB * KC / BIG_TPB; ++s) {
+            const int e = threadIdx.x + s * BIG_TPB;
+            const int r = e / KC, qq = e % KC, q = q0 + qq;
+            sI[qq][r] = (r < nI && q < nk) ? A[(int64_t)(rI + r) * ld + c0 + q] : make_double2(0.0, 0.0);
+            sJ[qq][r] = (r < nJ && q < nk) ? A[(int64_t)(rJ + r) * ld + c0 + q] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int qq = 0; qq < KC; ++qq) {
+            double2 x[4], y[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                x[u] = sI[qq][tr * 4 + u];
+                y[u] = sJ[qq][tc * 4 + u];
+            }
+            acc.acc(x, y);
+        }
+        __syncthreads();
+    }
+    const bool diag = t.y == t.z;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = tr * 4 + u, c = tc * 4 + v;
+            if (r < nI && c < nJ && (!diag || c <= r)) {
+                double2* dst = &A[(int64_t)(rI + r) * ld + rJ + c];
+                *dst = csub(*dst, acc.v[u][v]);
+            }
+        }
+}
+
+void launch_big_herk(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t s) {
+    if (ntask <= 0) return;
+    hipLaunchKernelGGL(k_big_herk, dim3(ntask), dim3(BIG_TPB), 0, s, a, tasks, k);
+}
+
+// Forward and backward substitution for one problem, then its column of B_opt.  The right-hand
+// side vector is overwritten by y and then by b; the workgroup's own global writes are visible
+// to its threads after each barrier.
+__global__ void __launch_bounds__(BIG_TPB) k_big_solve(Geo g, BigArgs a, double2* __restrict__ B64,
+                                                       float2* __restrict__ B32) {
+    constexpr int NP = BIG_TPB / BIG_NB;
+    __shared__ double2 s_t[BIG_NB];
+    __shared__ double2 red[NP][BIG_NB];
+    const BigProb P = a.probs[blockIdx.x];
+    const int fl = a.fail[P.id];   // 1: non-positive pivot (zero column written), 2: no members known
+    if (fl == 2) return;
+    const double2* A = a.A + P.off;
+    const int64_t ld = P.n;
+    double2* y = a.mr + P.moff;
+    const int col = threadIdx.x % BIG_NB, part = threadIdx.x / BIG_NB;
+    const int nblk = fl ? 0 : P.nblk;
+    // ---- L y = r: y_k = X_k (r_k - sum_{c < r0} L[r0 + i][c] y_c)
+    for (int k = 0; k < nblk; ++k) {
+        const int r0 = k * BIG_NB, nk = min(BIG_NB, P.n - r0);
+        const int i = threadIdx.x / NP, p4 = threadIdx.x % NP;   // NP threads per row
+        double2 acc = make_double2(0.0, 0.0);
+        if (i < nk) {
+            const double2* row = A + (int64_t)(r0 + i) * ld;
+            for (int c = p4; c < r0; c += NP) acc = cadd(acc, cmul(row[c], y[c]));
+        }
+#pragma unroll
+        for (int o = 1; o < NP; o <<= 1) {
+            acc.x += __shfl_xor(acc.x, o, 64);
+            acc.y += __shfl_xor(acc.y, o, 64);
+        }
+        if (p4 == 0 && i < nk) s_t[i] = csub(y[r0 + i], acc);
+        __syncthreads();
+        const double2* D = A + (int64_t)r0 * ld + r0;
+        double2 v = make_double2(0.0, 0.0);
+        if (i < nk)
+            for (int c = p4; c <= i; c += NP) v = cadd(v, cmul(inv_entry(D, ld, i, c), s_t[c]));
+#pragma unroll
+        for (int o = 1; o < NP; o <<= 1) {
+            v.x += __shfl_xor(v.x, o, 64);
+            v.y += __shfl_xor(v.y, o, 64);
+        }
+        if (p4 == 0 && i < nk) y[r0 + i] = v;
+        __syncthreads();
+    }
+    // ---- L^* b = y: b_k = X_k^* (y_k - sum_{i >= r0 + nk} conj(L[i][r0 + c]) b_i)
+    for (int k = nblk - 1; k >= 0; --k) {
+        const int r0 = k * BIG_NB, nk = min(BIG_NB, P.n - r0);
+        double2 acc = make_double2(0.0, 0.0);
+        if (col < nk)
+            for (int i = r0 + nk + part; i < P.n; i += NP) acc = cadd(acc, cmul(cconj(A[(int64_t)i * ld + r0 + col]), y[i]));
+        red[part][col] = acc;
+        __syncthreads();
+        if (part == 0 && col < nk) {
+            double2 s = red[0][col];
+            for (int pp = 1; pp < NP; ++pp) s = cadd(s, red[pp][col]);
+            s_t[col] = csub(y[r0 + col], s);
+        }
+        __syncthreads();
+        const double2* D = A + (int64_t)r0 * ld + r0;
+        double2 v = make_double2(0.0, 0.0);
+        if (col < nk)
+            for (int r = col + part; r < nk; r += NP) v = cadd(v, cmul(cconj(inv_entry(D, ld, r, col)), s_t[r]));
+        red[part][col] = v;
+        __syncthreads();
+        if (part == 0 && col < nk) {
+            double2 s = red[0][col];
+            for (int pp = 1; pp < NP; ++pp) s = cadd(s, red[pp][col]);
+            y[r0 + col] = s;
+        }
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < P.n; i += BIG_TPB) {
+        const int64_t idx = (int64_t)a.mtap[P.moff + i] * g.N + a.midx[P.moff + i];
+        const double2 b = fl ? make_double2(0.0, 0.0) : y[i];
+        B64[idx] = b;
+        if (B32) B32[idx] = make_float2((float)b.x, (float)b.y);
+    }
+}
+
+void launch_big_solve(const Geo& g, BigArgs a, int nprob, double2* B64, float2* B32, hipStream_t s) {
+    if (nprob <= 0) return;
+    hipLaunchKernelGGL(k_big_solve, dim3(nprob), dim3(BIG_TPB), 0, s, g, a, B64, B32);
+}
+
+// One statistics record for the whole pass: sizes known on the host, failures counted here.
+__global__ void __launch_bounds__(256) k_big_stats(const int* fail, int n, int nmin, int nmax, long long* rec) {
+    __shared__ int sh[256];
+    int f = 0;
+    for (int i = threadIdx.x; i < n; i += 256) f += fail[i] ? 1 : 0;
+    sh[threadIdx.x] = f;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        rec[0] = nmin;
+        rec[1] = nmax;
+        rec[2] = sh[0];
+        rec[3] = 0;
+        rec[4] = 0;
+    }
+}
+
+void launch_big_stats(const int* fail, int n, int nmin, int nmax, long long* rec, hipStream_t s) {
+    hipLaunchKernelGGL(k_big_stats, dim3(1), dim3(256), 0, s, fail, n, nmin, nmax, rec);
+}
+
+}  // namespace infft

@@ -1,0 +1,114 @@
+"""Local problems of Algorithm 3.17 with more members than the register tiers hold (|I(l)| > 32):
+the blocked Cholesky pass, against the oracle's Gram route on every such grid index, with
+sizes spanning one block, several blocks and a ragged last block; in one and two dimensions."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import bopt as obopt
+from oracle import nfft as onfft
+
+from gpu_util import dev, host, nodes_dev, rel
+
+pytestmark = pytest.mark.gpu
+
+# M, N, d, m, nodes in the dense spot, half-width of the spot in grid cells, rho
+CASES = [
+    ((32, 32), 700, 2, 3, 300, 2.5, 1e-8),
+    ((24, 20), 400, 2, 2, 150, 1.5, 1e-8),
+    ((64,), 600, 1, 4, 200, 2.0, 1e-8),
+    ((48,), 300, 1, 3, 80, 1.0, 1e-10),
+]
+
+
+def check_columns(x, p, rho, mem, ls, rows_gpu):
+    """Per grid index: the column itself where cond(G + lambda I) <= 1e6, else the excess of
+    the least-squares objective, (b - b*)^* (G + lambda I) (b - b*), against the optimum
+    J* = 1 - r^* b*: the error measure that conditioning does not inflate."""
+    nobj = 0
+    for l in ls:
+        js, ts, _ = mem.of(int(l))
+        G, r = obopt.gram_system(x, int(l), js, p)
+        n = len(js)
+        A = G + rho * np.real(np.trace(G)) / n * np.eye(n)
+        b_o = obopt.solve_G(x, int(l), js, p, rho)
+        b_g = rows_gpu[js, ts]
+        ev = np.linalg.eigvalsh(A)
+        if ev[-1] / ev[0] <= 1e6:
+            assert rel(b_g, b_o) <= 1e-9, int(l)
+        else:
+            d = b_g - b_o
+            excess = float(np.real(np.vdot(d, A @ d)))
+            J = 1.0 - float(np.real(np.vdot(r, b_o)))
+            assert excess <= 1e-10 * J, (int(l), n, excess, J)
+            nobj += 1
+    return nobj
+
+
+def clustered(M, N, d, m, ncl, half_cells, seed):
+    g = W.rng(seed)
+    x = W.clustered_nodes(g, N, d, ncl, half_cells / (2 * M[0]))
+    p = onfft.Params(M, 2.0, m)
+    return x, p
+
+
+@pytest.mark.parametrize("M,N,d,m,ncl,half,rho", CASES)
+def test_large_problems_match_oracle(M, N, d, m, ncl, half, rho):
+    from paper_1811_05335_amd import NfftPlan
+    x, p = clustered(M, N, d, m, ncl, half, seed=11)
+    mem = obopt.Members(x, p)
+    sizes = mem.sizes()
+    assert sizes.max() > 64          # the multi-block path runs
+    P = NfftPlan(M, nodes_dev(x), sigma=2.0, m=m, precision="f64", rho=rho)
+    P.precompute_B()
+    st = P.status()
+    assert st["failed_solves"] == 0 and st["oversized"] == 0
+    assert st["max_members"] == sizes.max()
+    assert st["min_members"] == sizes[sizes > 0].min()
+    assert st["empty_columns"] == int(np.sum(sizes == 0))
+    rows_gpu = host(P.get_B())
+    big = np.nonzero(sizes > 32)[0]
+    g = W.rng(3)
+    small = g.choice(np.nonzero((sizes > 0) & (sizes <= 32))[0], size=32, replace=False)
+    ls = np.sort(np.concatenate([big, small]))
+    check_columns(x, p, rho, mem, ls, rows_gpu)
+    P.close()
+
+
+def test_large_problems_under_graph_capture_are_counted_not_solved():
+    """Under graph capture the large-problem pass cannot read sizes back: its problems are
+    reported as oversized and their columns are zero, while the captured small ones match."""
+    from paper_1811_05335_amd import NfftPlan
+    M, N, d, m = (32, 32), 700, 2, 3
+    x, p = clustered(M, N, d, m, 300, 2.5, seed=12)
+    sizes = obopt.Members(x, p).sizes()
+    xd = nodes_dev(x)
+    P = NfftPlan(M, xd, sigma=2.0, m=m, precision="f64", rho=1e-8)
+    P.precompute_B()
+    eager = host(P.get_B())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        P.precompute_B()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        P.precompute_B()
+    graph.replay()
+    torch.cuda.synchronize()
+    st = P.status()
+    assert st["oversized"] == int(np.sum(sizes > 32))
+    captured = host(P.get_B())
+    mem = obopt.Members(x, p)
+    big_mask = np.zeros(captured.shape, dtype=bool)
+    small_mask = np.zeros(captured.shape, dtype=bool)
+    for l in range(mem.G):
+        js, ts, _ = mem.of(l)
+        if len(js) > 32:
+            big_mask[js, ts] = True
+        elif len(js) > 0:
+            small_mask[js, ts] = True
+    assert np.all(captured[big_mask] == 0)
+    assert rel(captured[small_mask], eager[small_mask]) <= 1e-14
+    P.close()

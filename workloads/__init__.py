@@ -31,6 +31,16 @@ def uniform_nodes(g: np.random.Generator, N: int, d: int = 1) -> np.ndarray:
     return g.uniform(-0.5, 0.5, size=(N, d))
 
 
+def clustered_nodes(g: np.random.Generator, N: int, d: int, ncluster: int, radius: float,
+                    centre: float = 0.1) -> np.ndarray:
+    """N - ncluster uniform nodes plus ncluster nodes uniform in the box of half-width `radius`
+    (x units) around (centre, ..., centre): a dense spot like the centre of a polar or spiral
+    trajectory, which makes some |I(l)| far larger than the mean."""
+    x = g.uniform(-0.5, 0.5, size=(N, d))
+    x[:ncluster] = centre + g.uniform(-radius, radius, size=(ncluster, d))
+    return x
+
+
 def jittered_nodes(g: np.random.Generator, N: int) -> np.ndarray:
     """x_j = (j - N/2)/N + U(-1/(4N), 1/(4N)), j = 0..N-1 (may leave [-1/2,1/2) at j = 0)."""
     j = np.arange(N, dtype=np.float64)

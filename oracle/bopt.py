@@ -102,6 +102,16 @@ def kernel_Q_1d(y, Mt: int, Ms_t: int, m: int, b: float) -> np.ndarray:
     return phase_matrix(y, k, +1) @ coef
 
 
+def gram_Q_1d(xt, Mt: int, Ms_t: int, m: int, b: float) -> np.ndarray:
+    """Q(x_i - x_j) for all pairs of one coordinate: e^{2 pi i k (x_i - x_j)} factors into
+    e^{2 pi i k x_i} conj(e^{2 pi i k x_j}), so the matrix is E diag(c) E^* with
+    E[i, k] = e^{2 pi i k x_i} and c_k = 1/(M_sigma w_hat(k))^2 (the same sum as kernel_Q_1d)."""
+    k = centred(Mt)
+    coef = 1.0 / (Ms_t * kb.window_hat(k, Ms_t, m, b)) ** 2
+    E = phase_matrix(np.asarray(xt, dtype=np.float64).ravel(), k, +1)
+    return (E * coef[None, :]) @ E.conj().T
+
+
 def kernel_K(Y, p: Params) -> np.ndarray:
     """Tensor-product K for arguments Y (n, d) in x units."""
     Y = np.atleast_2d(Y)
@@ -193,8 +203,9 @@ def gram_system(x, l: int, js, p: Params):
     xw, _, _ = prepare_nodes(x, p)
     X = xw[np.asarray(js)]
     n = len(js)
-    Y = (X[:, None, :] - X[None, :, :]).reshape(-1, p.d)
-    G = float(np.prod(p.Ms)) * kernel_Q(Y, p).reshape(n, n)
+    G = np.full((n, n), float(np.prod(p.Ms)), dtype=np.complex128)
+    for t in range(p.d):
+        G *= gram_Q_1d(X[:, t], p.M[t], p.Ms[t], p.m, p.b)
     lv = grid_multi_index(l, p) / np.array(p.Ms, dtype=np.float64)
     r = np.conj(kernel_K(lv[None, :] - X, p))
     return G, r

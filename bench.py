@@ -170,14 +170,14 @@ def algorithmic_bytes(N, M, G, T, R, csize, wsize):
 
 def member_counts(x, Ms, m):
     """|I(l)| for every grid index l (1-D), from the stencil l0 = ceil(x M_sigma - m), u = x M_sigma - l0:
-    the cells l-2m+1..l contribute all their nodes, the cell l-2m those with u = m."""
+    the cells l-2m+1..l contribute all their nodes, the cell l-2m those with |u - 2m| <= m."""
     xw = x[:, 0] - np.floor(x[:, 0] + 0.5)
     t = xw * Ms
     l0 = np.ceil(t - m)
     u = t - l0
     c = np.mod(l0.astype(np.int64), Ms)
     cnt = np.bincount(c, minlength=Ms)
-    edge = np.bincount(c[u == m], minlength=Ms)
+    edge = np.bincount(c[np.abs(u - 2 * m) <= m], minlength=Ms)
     n = np.zeros(Ms, dtype=np.int64)
     for tau in range(2 * m):
         n += np.roll(cnt, tau)

@@ -88,6 +88,13 @@ __host__ __device__ inline int64_t cell_key(const Geo& g, int c0, int c1) {
     return ((int64_t)t0 * g.ntile[1] + t1) * ((int64_t)g.TS[0] * g.TS[1]) + (int64_t)o0 * g.TS[1] + o1;
 }
 
+// Tap 2m of a node with offset u in (m-1, m] is inside the closed window support when
+// |u - 2m| <= m in FP64: at u = m exactly, and also when u lies within rounding of m (the
+// difference then rounds to -m).  Every kernel takes this decision in this one way.
+__host__ __device__ inline bool edge_tap_member(double u, int m) {
+    return fabs(u - 2.0 * (double)m) <= (double)m;
+}
+
 struct NodesDev {
     const double* xw;  // [N][d] wrapped nodes, caller order
     int* l0c;          // [N][d] stencil base mod M_sigma, caller order

@@ -131,7 +131,7 @@ __device__ inline void wave_sync() {
 
 // Members of I(l) for d = 1.  Nodes are sorted by stencil base l0, so the cells l-2m+1 .. l
 // (every node of them reaches l) form at most two contiguous ranges of the sorted order (two when
-// the window wraps around the torus); the cell l-2m contributes only nodes with u = m exactly.
+// the window wraps around the torus); the cell l-2m contributes only nodes whose tap 2m is a member.
 __device__ inline void gather_1d(const Geo& g, const NodesDev& nd, int l, int lane, int NL, int gbase,
                                  uint64_t gmask, int& n, int& my_p) {
     const int w2 = 2 * g.m, Ms = g.Ms[0];
@@ -155,7 +155,7 @@ __device__ inline void gather_1d(const Geo& g, const NodesDev& nd, int l, int la
     const int s = nd.start[ce], e = nd.start[ce + 1];
     for (int base = s; base < e; base += NL) {
         const int p = base + lane;
-        const bool mem = p < e && nd.us[p] == (double)g.m;
+        const bool mem = p < e && edge_tap_member(nd.us[p], g.m);
         const uint64_t gm = (__ballot(mem) >> gbase) & gmask;
         const int cnt = __popcll(gm);
         const int k = lane - n;
@@ -191,8 +191,8 @@ __device__ inline void gather_2d(const Geo& g, const NodesDev& nd, int l, int la
             for (int base = s; base < e; base += NL) {
                 const int p = base + lane;
                 bool mem = p < e;
-                if (mem && tau0 == w2) mem = nd.us[(int64_t)p * 2] == (double)g.m;
-                if (mem && tau1 == w2) mem = nd.us[(int64_t)p * 2 + 1] == (double)g.m;
+                if (mem && tau0 == w2) mem = edge_tap_member(nd.us[(int64_t)p * 2], g.m);
+                if (mem && tau1 == w2) mem = edge_tap_member(nd.us[(int64_t)p * 2 + 1], g.m);
                 const uint64_t gm = (__ballot(mem) >> gbase) & gmask;
                 const int cnt = __popcll(gm);
                 const int k = lane - n;
@@ -593,8 +593,8 @@ __global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt
 // over the workgroup's node range; the band (offsets 0 .. NMAX-1) is evaluated once in LDS.  The
 // phase w_i = e^{i pi z_i / sigma} factors into e^{i pi l / sigma} e^{-i pi t_p / sigma}, the second
 // factor per node.  Windows that wrap around the torus (the first 2m-1 grid indices) evaluate their
-// entries directly.  Problems with more members or with a member exactly on the window edge
-// (u = m) are appended to the list of the group kernels.
+// entries directly.  Problems with more members or with a member on the window edge (tap 2m
+// inside the support) are appended to the list of the group kernels.
 constexpr int T1_TPB = 128;
 constexpr int T1_NODECAP = 320;   // staged nodes per workgroup (density up to ~2.4 per cell)
 
@@ -665,13 +665,13 @@ __global__ void __launch_bounds__(T1_TPB) k_solve_t1(Geo g, NodesDev nd, KTabDev
         const int n = n0 + n1;
         bool fallback = n > NMAX || (!wrap && !staged);
         {
-            // the cell l-2m reaches l through its tap 2m only for nodes with u = m exactly; the tap
+            // the cell l-2m reaches l through its tap 2m only for nodes with u at m; the tap
             // 2m of every other node belongs to no problem and is zeroed here
             int ce = l - w2;
             if (ce < 0) ce += Ms;
             const int es = nd.start[ce], ee = nd.start[ce + 1];
             for (int p = es; p < ee; ++p) {
-                if (nd.us[p] == (double)g.m) {
+                if (edge_tap_member(nd.us[p], g.m)) {
                     fallback = true;
                 } else {
                     a.B64[(int64_t)w2 * g.N + p] = make_double2(0.0, 0.0);

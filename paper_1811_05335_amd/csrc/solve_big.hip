@@ -27,7 +27,7 @@ constexpr int CELL_TPB = 128;
 constexpr int MAX_CELLS = (2 * MAX_M_CUT + 1) * (2 * MAX_M_CUT + 1);
 
 // Cell c of the (2m+1)^d cells whose nodes may reach grid index l: the CSR range of its nodes
-// and whether it sits at tap 2m in a dimension (there only nodes with u = m exactly reach l).
+// and whether it sits at tap 2m in a dimension (there only nodes with u at m reach l).
 __device__ inline void big_cell(const Geo& g, const NodesDev& nd, int l, int c, int& s, int& e, bool& edge0,
                                 bool& edge1) {
     const int W = 2 * g.m + 1, w2 = 2 * g.m;
@@ -54,9 +54,8 @@ __device__ inline void big_cell(const Geo& g, const NodesDev& nd, int l, int c, 
 }
 
 __device__ inline bool big_member(const Geo& g, const NodesDev& nd, int p, bool edge0, bool edge1) {
-    const double um = (double)g.m;
-    if (edge0 && nd.us[(int64_t)p * g.d] != um) return false;
-    if (edge1 && nd.us[(int64_t)p * g.d + 1] != um) return false;
+    if (edge0 && !edge_tap_member(nd.us[(int64_t)p * g.d], g.m)) return false;
+    if (edge1 && !edge_tap_member(nd.us[(int64_t)p * g.d + 1], g.m)) return false;
     return true;
 }
 

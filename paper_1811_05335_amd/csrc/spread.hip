@@ -21,7 +21,7 @@ namespace infft {
 
 // Window values of the 2m+1 taps of one node.  Taps tau < 2m: Horner in y of the plan's polynomial
 // of that tap (membership |u - tau| <= m still decided in float64); tap 2m reaches the window only
-// when u = m exactly, where the window equals its edge value b/pi.
+// when u - 2m rounds to -m (u at m), where the window equals its edge value b/pi.
 template <typename R, int W>
 __device__ inline void window_row(const Geo& g, double u, R* w) {
     constexpr int NC = WPoly<R>::NC;
@@ -34,7 +34,7 @@ __device__ inline void window_row(const Geo& g, double u, R* w) {
         for (int k = NC - 2; k >= 0; --k) acc = acc * y + cf[tau * NC + k];
         w[tau] = (fabs(u - (double)tau) <= (double)g.m) ? acc : (R)0;
     }
-    w[W - 1] = (u == (double)g.m) ? (R)(g.b / M_PI) : (R)0;
+    w[W - 1] = edge_tap_member(u, g.m) ? (R)(g.b / M_PI) : (R)0;
 }
 
 // Derivatives d w / d v of the same taps (times `scale`): d/dv = 2 d/dy; at the on-grid edge tap
@@ -54,14 +54,14 @@ __device__ inline void window_deriv_row(const Geo& g, double u, R scale, R* dw) 
         }
         dw[tau] = (fabs(u - (double)tau) <= (double)g.m) ? (R)2 * scale * dp : (R)0;
     }
-    dw[W - 1] = (u == (double)g.m) ? (R)(scale * (double)g.m * g.b * g.b * g.b / (3.0 * M_PI)) : (R)0;
+    dw[W - 1] = edge_tap_member(u, g.m) ? (R)(scale * (double)g.m * g.b * g.b * g.b / (3.0 * M_PI)) : (R)0;
 }
 
 // One tap with a tap index known only at run time (gather over the nodes reaching one cell).
 template <typename R>
 __device__ inline R window_tap(const Geo& g, double u, int tau) {
     constexpr int NC = WPoly<R>::NC;
-    if (tau >= 2 * g.m) return (u == (double)g.m) ? (R)(g.b / M_PI) : (R)0;
+    if (tau >= 2 * g.m) return edge_tap_member(u, g.m) ? (R)(g.b / M_PI) : (R)0;
     if (fabs(u - (double)tau) > (double)g.m) return (R)0;
     const R* cf = (const R*)g.wpoly + tau * NC;
     const R y = (R)(2.0 * (u - (double)(g.m - 1)) - 1.0);

@@ -3,6 +3,7 @@ import numpy as np
 import torch
 
 import workloads as W
+from oracle import bopt as obopt
 from oracle import nfft as onfft
 
 CT = {"f32": torch.complex64, "f64": torch.complex128}
@@ -40,3 +41,27 @@ def problem(M, N, d=1, nodes="uniform", seed=0, rhs=1, sigma=2.0, m=4):
     f = W.complex_normal(g, (rhs, N))
     p = onfft.Params(M, sigma, m)
     return x, fh, f, p
+
+
+def check_columns(x, p, rho, mem, ls, rows_gpu):
+    """Per grid index: the column itself where cond(G + lambda I) <= 1e6, else the excess of
+    the least-squares objective, (b - b*)^* (G + lambda I) (b - b*), against the optimum
+    J* = 1 - r^* b*: the error measure that conditioning does not inflate."""
+    nobj = 0
+    for l in ls:
+        js, ts, _ = mem.of(int(l))
+        G, r = obopt.gram_system(x, int(l), js, p)
+        n = len(js)
+        A = G + rho * np.real(np.trace(G)) / n * np.eye(n)
+        b_o = obopt.solve_G(x, int(l), js, p, rho)
+        b_g = rows_gpu[js, ts]
+        ev = np.linalg.eigvalsh(A)
+        if ev[-1] / ev[0] <= 1e6:
+            assert rel(b_g, b_o) <= 1e-9, int(l)
+        else:
+            d = b_g - b_o
+            excess = float(np.real(np.vdot(d, A @ d)))
+            J = 1.0 - float(np.real(np.vdot(r, b_o)))
+            assert excess <= 1e-10 * J, (int(l), n, excess, J)
+            nobj += 1
+    return nobj

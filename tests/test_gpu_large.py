@@ -9,7 +9,7 @@ import workloads as W
 from oracle import bopt as obopt
 from oracle import nfft as onfft
 
-from gpu_util import dev, host, nodes_dev, rel
+from gpu_util import check_columns, host, nodes_dev, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -20,30 +20,6 @@ CASES = [
     ((64,), 600, 1, 4, 200, 2.0, 1e-8),
     ((48,), 300, 1, 3, 80, 1.0, 1e-10),
 ]
-
-
-def check_columns(x, p, rho, mem, ls, rows_gpu):
-    """Per grid index: the column itself where cond(G + lambda I) <= 1e6, else the excess of
-    the least-squares objective, (b - b*)^* (G + lambda I) (b - b*), against the optimum
-    J* = 1 - r^* b*: the error measure that conditioning does not inflate."""
-    nobj = 0
-    for l in ls:
-        js, ts, _ = mem.of(int(l))
-        G, r = obopt.gram_system(x, int(l), js, p)
-        n = len(js)
-        A = G + rho * np.real(np.trace(G)) / n * np.eye(n)
-        b_o = obopt.solve_G(x, int(l), js, p, rho)
-        b_g = rows_gpu[js, ts]
-        ev = np.linalg.eigvalsh(A)
-        if ev[-1] / ev[0] <= 1e6:
-            assert rel(b_g, b_o) <= 1e-9, int(l)
-        else:
-            d = b_g - b_o
-            excess = float(np.real(np.vdot(d, A @ d)))
-            J = 1.0 - float(np.real(np.vdot(r, b_o)))
-            assert excess <= 1e-10 * J, (int(l), n, excess, J)
-            nobj += 1
-    return nobj
 
 
 def clustered(M, N, d, m, ncl, half_cells, seed):

@@ -74,11 +74,13 @@ typedef struct {
     int64_t nonfinite_nodes;  /* nodes rejected as NaN/Inf (their samples are set to 0) */
     int64_t failed_solves;    /* local problems whose Cholesky met a pivot <= 0 */
     int64_t empty_columns;    /* grid indices l with empty I(l): zero column of B_opt */
-    int64_t oversized;        /* local problems with |I(l)| above the supported size */
+    int64_t oversized;        /* local problems not solved because the precompute ran under
+                                 graph capture and |I(l)| exceeds 32 (their columns are zero) */
     int64_t min_members;      /* min |I(l)| over non-empty l of the last precompute */
     int64_t max_members;      /* max |I(l)| */
     int32_t bopt_ready;       /* 1 after a successful infft_precompute_B for the current nodes */
-    int32_t max_supported;    /* largest |I(l)| the local solver handles */
+    int32_t max_supported;    /* largest |I(l)| the local solver handles (INT32_MAX: limited
+                                 only by device memory, 16 |I(l)|^2 bytes for the largest) */
 } infft_status;
 
 /* Fills *o with the defaults listed above. */
@@ -108,7 +110,10 @@ int nfft_adjoint(infft_plan p, const void* f, void* h, int nrhs);
 
 /* Algorithm 3.17: optimises the nonzero entries of B, one regularised least-squares problem
  * per oversampled grid index l over the nodes I(l) of (3.29), solved through its normal
- * equations in FP64 on the GPU (whatever the plan precision).  Stores B_opt in the plan. */
+ * equations in FP64 on the GPU (whatever the plan precision).  Stores B_opt in the plan.
+ * Problems with more than 32 members are solved by a blocked Cholesky pass whose sizes are read
+ * back to the host, so the call synchronises the stream when such problems exist; under HIP
+ * graph capture that pass is skipped and the problems are counted in infft_status.oversized. */
 int infft_precompute_B(infft_plan p);
 
 /* Modified adjoint NFFT (3.32): fcheck = D^* F^* B_opt^* f ~ fhat.  f [nrhs][N],
@@ -138,6 +143,21 @@ int64_t nfft_plan_device_bytes(infft_plan p);
 
 /* Releases the plan and its device workspace (waits for the plan's stream first). */
 void nfft_plan_destroy(infft_plan p);
+
+/* A batch of nprob independent one-dimensional problems of uneven sizes in one plan (the
+ * setting of many small inverse NFFTs): problem i has M[i] coefficients (even) and N[i] nodes;
+ * sigma, m and the options are shared.  M and N are host arrays; x (device, float64) holds the
+ * nodes of all problems one after the other (sum N[i] values).  Every entry point above accepts
+ * the batch plan and runs each stage for all problems in one kernel launch (per stage: FFT
+ * passes grouped by pass type, spreading, interpolation, the local solves), so a whole step is
+ * a handful of launches that a HIP graph can capture.  Caller arrays are problem-major:
+ *   fhat, fcheck, h: [problem][nrhs][M_i]   f, gradf: [problem][nrhs][N_i]
+ *   gradx: float64 [sum N_i]                 rows of infft_get_B: [sum N_i][2m+1]
+ * with nrhs <= opts->max_rhs (INFFT_ESTATE otherwise).  nfft_set_nodes runs the node
+ * preprocessing problem by problem; nfft_plan_status reports sums (and the extremes of
+ * |I(l)|) over the problems.  On failure *out is NULL and the message names the problem. */
+int nfft_plan_batched(infft_plan* out, int nprob, const int64_t* M, const int64_t* N, double sigma, int m,
+                      const double* x, const infft_options* opts, void* stream);
 
 /* Kernel classes for infft_profile_begin. */
 #define INFFT_K_NODES 1    /* node preprocessing and sort */

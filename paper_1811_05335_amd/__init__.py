@@ -3,6 +3,7 @@ matrix B (Algorithm 3.17) and the modified adjoint NFFT (3.32), as hand-written 
 behind a C ABI (include/infft.h).  This package is the thin Python binding plus the
 torch.autograd wrappers."""
 from .plan import (  # noqa: F401
+    NfftBatchPlan,
     NfftPlan,
     infft_apply,
     infft_apply_adjoint,
@@ -11,6 +12,7 @@ from .plan import (  # noqa: F401
     nfft_adjoint,
     nfft_grad_x,
     nfft_plan,
+    nfft_plan_batched,
     nfft_plan_destroy,
     nfft_plan_status,
     nfft_set_nodes,

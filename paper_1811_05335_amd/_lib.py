@@ -72,6 +72,8 @@ def load() -> C.CDLL:
     sig = {
         "infft_default_options": (None, [C.POINTER(Options)]),
         "nfft_plan": (i32, [C.POINTER(vp), i32, C.POINTER(i64), i64, dbl, i32, vp, C.POINTER(Options), vp]),
+        "nfft_plan_batched": (i32, [C.POINTER(vp), i32, C.POINTER(i64), C.POINTER(i64), dbl, i32, vp,
+                                    C.POINTER(Options), vp]),
         "nfft_set_nodes": (i32, [vp, vp]),
         "nfft_set_stream": (i32, [vp, vp]),
         "nfft_trafo": (i32, [vp, vp, vp, i32]),

@@ -10,6 +10,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -76,6 +78,9 @@ struct FftStep {
 
 }  // namespace
 
+struct BatchState;
+void batch_free(BatchState* b);
+
 struct infft_plan_s {
     Geo g{};
     int prec = INFFT_F64;
@@ -122,6 +127,9 @@ struct infft_plan_s {
     long long* stat_rec = nullptr;   // per-block statistics of the solve kernels
     int stat_nrec = 0;
     bool bopt_ready = false;
+
+    // many 1-D problems in one plan (nullptr for a single problem)
+    struct BatchState* batch = nullptr;
 
     // large local problems: sizes, failure flags and one batch of matrices and members,
     // allocated when first needed and grown on demand
@@ -180,6 +188,7 @@ struct infft_plan_s {
     }
 
     ~infft_plan_s() {
+        if (batch) batch_free(batch);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
     }
@@ -430,6 +439,24 @@ int schedule_for(infft_plan_s* P, int rc) {
     return build_schedule(P, rc, P->to_grid, P->to_coeff);
 }
 
+KTabDev plan_ktab(const infft_plan_s* p) {
+    const Geo& g = p->g;
+    KTabDev kt{};
+    for (int t = 0; t < MAX_D; ++t) {
+        kt.K[t] = p->Ktab[t];
+        kt.Q[t] = p->Qtab[t];
+    }
+    kt.Ks = p->Kstab;
+    kt.Qs = p->Qstab;
+    kt.dM = p->dM;
+    kt.inv_sigma = (double)g.M[0] / (double)g.Ms[0];
+    kt.qK = p->qK;
+    kt.qQ = p->qQ;
+    kt.lam = p->lam;
+    kt.scaleG = (double)g.G;
+    return kt;
+}
+
 // Local problems with more members than the register tiers hold (list of grid indices and its
 // device count from the last tier).  Reads the count and the sizes back to the host, sorts the
 // problems by size, packs them into batches whose matrices fit the workspace and runs the
@@ -549,6 +576,259 @@ int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* 
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ many 1-D problems in one plan
+// A batch plan owns one ordinary plan per problem (its nodes, grid, tables, B_opt, lists) and
+// launch tables that let every stage run for all problems in one launch: per launch an array of
+// per-problem arguments ("jobs") and a map workgroup -> (job, block of that job).  Caller arrays
+// are problem-major: coefficients [problem][nrhs][M_i], samples [problem][nrhs][N_i].
+
+struct BatchLaunch {
+    int ld = 0, st = 0;
+    int64_t map_off = 0;
+    int nblocks = 0;
+    size_t shm = 0;
+};
+
+struct BatchState {
+    std::vector<infft_plan_s*> subs;
+    std::vector<int64_t> Poff, Noff;
+    int64_t Ptot = 0, Ntot = 0;
+    FftJob* fft_jobs = nullptr;
+    int2* fft_map = nullptr;
+    std::vector<BatchLaunch> to_grid, to_coeff;
+    NodeJob* node_jobs = nullptr;
+    int2* node_map = nullptr;
+    int node_blocks = 0;
+    int2* cell_map = nullptr;
+    int cell_blocks = 0;
+    SolveJob* solve_jobs = nullptr;   // [4][nprob]: thread tier, 16 lanes, 32 lanes, 32 lanes under capture
+    int2* t1_map = nullptr;
+    int t1_blocks = 0;
+    std::vector<int> t1_per_prob;
+    int tier_blocks = 1024;
+    int* counts = nullptr;
+};
+
+void batch_free(BatchState* b) {
+    for (infft_plan_s* s : b->subs) {
+        if (s) {
+            (void)hipStreamSynchronize(s->stream);
+            delete s;
+        }
+    }
+    delete b;
+}
+
+namespace {
+
+template <typename T>
+int upload(infft_plan_s* P, T** dst, const std::vector<T>& v) {
+    int rc = P->alloc(dst, (int64_t)std::max<size_t>(v.size(), 1));
+    if (rc) return rc;
+    if (!v.empty()) HIP_TRY(hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return INFFT_OK;
+}
+
+// Launch tables of the batch plan P from its per-problem plans.
+int batch_build(infft_plan_s* P) {
+    BatchState& B = *P->batch;
+    const int np = (int)B.subs.size();
+    const size_t cs = P->csize();
+    // ---- FFT passes, grouped by (step index, load mode, store mode)
+    std::vector<FftJob> jobs;
+    std::vector<int2> map;
+    for (int dir = 0; dir < 2; ++dir) {
+        std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+        for (int i = 0; i < np; ++i) {
+            infft_plan_s* sub = B.subs[i];
+            std::vector<FftStep> tg, tc;
+            int rc = build_schedule(sub, sub->max_rhs, tg, tc);
+            if (rc) return rc;
+            const std::vector<FftStep>& steps = dir == 0 ? tg : tc;
+            for (size_t k = 0; k < steps.size(); ++k) {
+                const FftStep& st = steps[k];
+                FftJob J{};
+                J.pass = st.pass;
+                J.g = sub->g;
+                const bool f32 = sub->prec == INFFT_F32;
+                J.io.in = st.in_buf == 1 ? sub->grid : st.in_buf == 2 ? sub->grid2 : nullptr;
+                J.io.out = st.out_buf == 1 ? sub->grid : st.out_buf == 2 ? sub->grid2 : nullptr;
+                J.io.D0 = f32 ? (const void*)sub->D32[0] : (const void*)sub->D64[0];
+                J.io.D1 = nullptr;
+                J.user_in = st.in_buf == 0;
+                J.user_out = st.out_buf == 0;
+                J.user_off = B.Poff[i];
+                groups[std::make_tuple((int)k, st.ld, st.st)].push_back((int)jobs.size());
+                jobs.push_back(J);
+            }
+        }
+        std::vector<BatchLaunch>& launches = dir == 0 ? B.to_grid : B.to_coeff;
+        launches.clear();
+        for (auto& kv : groups) {
+            BatchLaunch L;
+            L.ld = std::get<1>(kv.first);
+            L.st = std::get<2>(kv.first);
+            L.map_off = (int64_t)map.size();
+            for (int ji : kv.second) {
+                const FftPass& ps = jobs[ji].pass;
+                const int64_t nb = (ps.nseq + ps.rows - 1) / ps.rows;
+                for (int64_t b = 0; b < nb; ++b) map.push_back(make_int2(ji, (int)b));
+                L.shm = std::max(L.shm, (size_t)ps.rows * (ps.n + 1) * cs);
+            }
+            L.nblocks = (int)((int64_t)map.size() - L.map_off);
+            launches.push_back(L);
+        }
+    }
+    int rc;
+    if ((rc = upload(P, &B.fft_jobs, jobs)) || (rc = upload(P, &B.fft_map, map))) return rc;
+    // ---- per-node and per-cell kernels
+    std::vector<NodeJob> nj(np);
+    std::vector<int2> nmap, cmap, tmap;
+    B.t1_per_prob.assign(np, 0);
+    for (int i = 0; i < np; ++i) {
+        infft_plan_s* sub = B.subs[i];
+        NodeJob& J = nj[i];
+        J.g = sub->g;
+        J.nd = sub->nd;
+        J.B = sub->prec == INFFT_F32 ? (const void*)sub->B32 : (const void*)sub->B64;
+        J.grid = sub->grid;
+        J.grs = sub->g.G;
+        J.noff = B.Noff[i];
+        for (int64_t b = 0; b < (sub->g.N + 255) / 256; ++b) nmap.push_back(make_int2(i, (int)b));
+        for (int64_t b = 0; b < (sub->g.G + 255) / 256; ++b) cmap.push_back(make_int2(i, (int)b));
+        const int nt = (int)((sub->g.G + T1_CELLS - 1) / T1_CELLS);
+        B.t1_per_prob[i] = nt;
+        for (int b = 0; b < nt; ++b) tmap.push_back(make_int2(i, b));
+    }
+    B.node_blocks = (int)nmap.size();
+    B.cell_blocks = (int)cmap.size();
+    B.t1_blocks = (int)tmap.size();
+    if ((rc = upload(P, &B.node_jobs, nj)) || (rc = upload(P, &B.node_map, nmap)) ||
+        (rc = upload(P, &B.cell_map, cmap)) || (rc = upload(P, &B.t1_map, tmap)))
+        return rc;
+    // ---- solver tiers: thread per problem, then 16- and 32-lane groups over each problem's lists
+    std::vector<SolveJob> sj(4 * (size_t)np);
+    for (int i = 0; i < np; ++i) {
+        infft_plan_s* sub = B.subs[i];
+        SolveJob base{};
+        base.g = sub->g;
+        base.nd = sub->nd;
+        base.kt = plan_ktab(sub);
+        base.a.B64 = sub->B64;
+        base.a.B32 = sub->B32;
+        base.a.status = sub->status;
+        base.a.stat_rec = sub->stat_rec;
+        int* listA = sub->lists;
+        int* listB = sub->lists + sub->g.G;
+        SolveJob t0 = base, t1 = base, t2 = base, t3 = base;
+        t0.a.out_list = listA;
+        t0.a.out_count = sub->lcount;
+        t0.a.stat_off = 0;
+        t1.a.in_list = listA;
+        t1.a.in_count = sub->lcount;
+        t1.a.out_list = listB;
+        t1.a.out_count = sub->lcount + 1;
+        t1.a.stat_off = B.t1_per_prob[i];
+        t2.a.in_list = listB;
+        t2.a.in_count = sub->lcount + 1;
+        t2.a.out_list = listA;
+        t2.a.out_count = sub->lcount + 2;
+        t2.a.stat_off = B.t1_per_prob[i] + B.tier_blocks;
+        t3 = t2;
+        t3.a.out_list = nullptr;
+        t3.a.out_count = nullptr;
+        sj[i] = t0;
+        sj[np + i] = t1;
+        sj[2 * (size_t)np + i] = t2;
+        sj[3 * (size_t)np + i] = t3;
+    }
+    if ((rc = upload(P, &B.solve_jobs, sj))) return rc;
+    if ((rc = P->alloc(&B.counts, np))) return rc;
+    return INFFT_OK;
+}
+
+int run_fft_batched(infft_plan_s* P, const std::vector<BatchLaunch>& launches, const void* user_in,
+                    void* user_out, int nrhs) {
+    BatchState& B = *P->batch;
+    for (const BatchLaunch& L : launches) {
+        ProfScope ps(P, INFFT_K_FFT);
+        if (P->prec == INFFT_F32)
+            launch_fft_batched<float>(B.fft_jobs, B.fft_map + L.map_off, L.nblocks, L.shm, L.ld, L.st, user_in,
+                                      user_out, nrhs, P->stream);
+        else
+            launch_fft_batched<double>(B.fft_jobs, B.fft_map + L.map_off, L.nblocks, L.shm, L.ld, L.st, user_in,
+                                       user_out, nrhs, P->stream);
+        LAUNCH_CHECK();
+    }
+    return INFFT_OK;
+}
+
+int node_batched(infft_plan_s* P, int kind, const void* in, void* out, double* gradx, int nrhs) {
+    BatchState& B = *P->batch;
+    const bool cells = kind == NB_GATHER || kind == NB_GATHER_B;
+    const int2* map = cells ? B.cell_map : B.node_map;
+    const int nb = cells ? B.cell_blocks : B.node_blocks;
+    ProfScope ps(P, cells ? INFFT_K_SPREAD : INFFT_K_INTERP);
+    if (P->prec == INFFT_F32)
+        launch_node_batched<float>(kind, P->g.m, B.node_jobs, map, nb, (const float2*)in, (float2*)out, gradx, nrhs,
+                                   0, P->stream);
+    else
+        launch_node_batched<double>(kind, P->g.m, B.node_jobs, map, nb, (const double2*)in, (double2*)out, gradx,
+                                    nrhs, 0, P->stream);
+    LAUNCH_CHECK();
+    return INFFT_OK;
+}
+
+int batch_check_rhs(infft_plan_s* P, int nrhs) {
+    if (nrhs < 1) return fail(INFFT_EINVAL, "nrhs must be positive");
+    if (nrhs > P->max_rhs) return fail(INFFT_ESTATE, "a batch plan takes at most max_rhs = %d right-hand sides", P->max_rhs);
+    return INFFT_OK;
+}
+
+int batch_precompute(infft_plan_s* P) {
+    BatchState& B = *P->batch;
+    const int np = (int)B.subs.size();
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(P->stream, &cs));
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    P->bopt_ready = false;
+    launch_batch_solve_reset(B.solve_jobs, np, P->stream);
+    LAUNCH_CHECK();
+    {
+        ProfScope ps(P, INFFT_K_SOLVE);
+        launch_solve_t1_batched(B.solve_jobs, B.t1_map, B.t1_blocks, B.subs[0]->qQ, B.subs[0]->qK, P->stream);
+    }
+    LAUNCH_CHECK();
+    launch_solve_tier_batched(B.solve_jobs + np, np, 16, B.tier_blocks, P->stream);
+    LAUNCH_CHECK();
+    launch_solve_tier_batched(B.solve_jobs + (capturing ? 3 : 2) * (size_t)np, np, 32, B.tier_blocks, P->stream);
+    LAUNCH_CHECK();
+    for (int i = 0; i < np; ++i) {
+        B.subs[i]->stat_nrec = B.t1_per_prob[i] + 2 * B.tier_blocks;
+        B.subs[i]->bopt_ready = true;
+    }
+    if (!capturing) {
+        launch_batch_counts(B.solve_jobs + 2 * (size_t)np, np, B.counts, P->stream);
+        LAUNCH_CHECK();
+        std::vector<int> cnt(np);
+        HIP_TRY(hipMemcpyAsync(cnt.data(), B.counts, sizeof(int) * np, hipMemcpyDeviceToHost, P->stream));
+        HIP_TRY(hipStreamSynchronize(P->stream));
+        for (int i = 0; i < np; ++i) {
+            if (cnt[i] == 0) continue;
+            infft_plan_s* sub = B.subs[i];
+            int off = sub->stat_nrec;
+            int rc = solve_large(sub, plan_ktab(sub), sub->lists, sub->lcount + 2, off);
+            if (rc) return rc;
+            sub->stat_nrec = off;
+        }
+    }
+    P->bopt_ready = true;
+    return INFFT_OK;
+}
+
+}  // namespace
+
 
 // =====================================================================================  C ABI
 
@@ -777,12 +1057,23 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
 int nfft_set_nodes(infft_plan p, const double* x) {
     if (!p) return fail(INFFT_EINVAL, "null plan");
     if (!x) return fail(INFFT_EINVAL, "x is null");
+    if (p->batch) {
+        BatchState& B = *p->batch;
+        p->bopt_ready = false;
+        for (size_t i = 0; i < B.subs.size(); ++i) {
+            int rc = set_nodes_impl(B.subs[i], x + B.Noff[i] * p->g.d);
+            if (rc) return rc;
+        }
+        return INFFT_OK;
+    }
     return set_nodes_impl(p, x);
 }
 
 int nfft_set_stream(infft_plan p, void* stream) {
     if (!p) return fail(INFFT_EINVAL, "null plan");
     p->stream = (hipStream_t)stream;
+    if (p->batch)
+        for (infft_plan_s* s : p->batch->subs) s->stream = (hipStream_t)stream;
     return INFFT_OK;
 }
 
@@ -794,6 +1085,11 @@ int nfft_trafo(infft_plan p, const void* fhat, void* f, int nrhs) {
     int rc = check_rhs(p, nrhs);
     if (rc) return rc;
     if (!fhat || !f) return fail(INFFT_EINVAL, "null data pointer");
+    if (p->batch) {
+        if ((rc = batch_check_rhs(p, nrhs)) || (rc = run_fft_batched(p, p->batch->to_grid, fhat, nullptr, nrhs)))
+            return rc;
+        return node_batched(p, NB_INTERP, nullptr, f, nullptr, nrhs);
+    }
     const Geo& g = p->g;
     for (int r0 = 0; r0 < nrhs; r0 += p->max_rhs) {
         const int c = std::min(p->max_rhs, nrhs - r0);
@@ -836,11 +1132,17 @@ int nfft_adjoint(infft_plan p, const void* f, void* h, int nrhs) {
     int rc = check_rhs(p, nrhs);
     if (rc) return rc;
     if (!f || !h) return fail(INFFT_EINVAL, "null data pointer");
+    if (p->batch) {
+        if ((rc = batch_check_rhs(p, nrhs)) || (rc = node_batched(p, NB_GATHER, f, nullptr, nullptr, nrhs)))
+            return rc;
+        return run_fft_batched(p, p->batch->to_coeff, nullptr, h, nrhs);
+    }
     return spread_then_coeffs(p, f, h, nrhs, false);
 }
 
 int infft_precompute_B(infft_plan p) {
     if (!p) return fail(INFFT_EINVAL, "null plan");
+    if (p->batch) return batch_precompute(p);
     // The pass for problems beyond the register tiers reads their sizes back to the host; under
     // graph capture it cannot run, and such problems are counted as oversized (zero columns).
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -856,19 +1158,7 @@ int infft_precompute_B(infft_plan p) {
         if (p->B32) launch_fill_bytes0(p->B32, TN * (int64_t)sizeof(float2), p->stream);
     }
     launch_fill_i32(p->lcount, 4, 0, p->stream);
-    KTabDev kt{};
-    for (int t = 0; t < MAX_D; ++t) {
-        kt.K[t] = p->Ktab[t];
-        kt.Q[t] = p->Qtab[t];
-    }
-    kt.Ks = p->Kstab;
-    kt.Qs = p->Qstab;
-    kt.dM = p->dM;
-    kt.inv_sigma = (double)g.M[0] / (double)g.Ms[0];
-    kt.qK = p->qK;
-    kt.qQ = p->qQ;
-    kt.lam = p->lam;
-    kt.scaleG = (double)g.G;
+    const KTabDev kt = plan_ktab(p);
     SolveArgs a{};
     a.B64 = p->B64;
     a.B32 = p->B32;
@@ -941,6 +1231,11 @@ int infft_apply(infft_plan p, const void* f, void* fcheck, int nrhs) {
     if (rc) return rc;
     if (!f || !fcheck) return fail(INFFT_EINVAL, "null data pointer");
     if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_apply before infft_precompute_B");
+    if (p->batch) {
+        if ((rc = batch_check_rhs(p, nrhs)) || (rc = node_batched(p, NB_GATHER_B, f, nullptr, nullptr, nrhs)))
+            return rc;
+        return run_fft_batched(p, p->batch->to_coeff, nullptr, fcheck, nrhs);
+    }
     return spread_then_coeffs(p, f, fcheck, nrhs, true);
 }
 
@@ -949,6 +1244,11 @@ int infft_apply_adjoint(infft_plan p, const void* h, void* f, int nrhs) {
     if (rc) return rc;
     if (!h || !f) return fail(INFFT_EINVAL, "null data pointer");
     if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_apply_adjoint before infft_precompute_B");
+    if (p->batch) {
+        if ((rc = batch_check_rhs(p, nrhs)) || (rc = run_fft_batched(p, p->batch->to_grid, h, nullptr, nrhs)))
+            return rc;
+        return node_batched(p, NB_INTERP_B, nullptr, f, nullptr, nrhs);
+    }
     const Geo& g = p->g;
     for (int r0 = 0; r0 < nrhs; r0 += p->max_rhs) {
         const int c = std::min(p->max_rhs, nrhs - r0);
@@ -969,6 +1269,11 @@ int nfft_grad_x(infft_plan p, const void* fhat, const void* gradf, double* gradx
     int rc = check_rhs(p, nrhs);
     if (rc) return rc;
     if (!fhat || !gradf || !gradx) return fail(INFFT_EINVAL, "null data pointer");
+    if (p->batch) {
+        if ((rc = batch_check_rhs(p, nrhs)) || (rc = run_fft_batched(p, p->batch->to_grid, fhat, nullptr, nrhs)))
+            return rc;
+        return node_batched(p, NB_GRAD, gradf, nullptr, gradx, nrhs);
+    }
     const Geo& g = p->g;
     for (int r0 = 0; r0 < nrhs; r0 += p->max_rhs) {
         const int c = std::min(p->max_rhs, nrhs - r0);
@@ -991,6 +1296,15 @@ int infft_get_B(infft_plan p, void* rows) {
     if (!p) return fail(INFFT_EINVAL, "null plan");
     if (!rows) return fail(INFFT_EINVAL, "rows is null");
     if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_get_B before infft_precompute_B");
+    if (p->batch) {
+        const BatchState& B = *p->batch;
+        for (size_t i = 0; i < B.subs.size(); ++i) {
+            const infft_plan_s* s = B.subs[i];
+            launch_export_B(s->g, s->nd.perm, s->B64, (double2*)rows + B.Noff[i] * p->taps(), p->stream);
+            LAUNCH_CHECK();
+        }
+        return INFFT_OK;
+    }
     launch_export_B(p->g, p->nd.perm, p->B64, (double2*)rows, p->stream);
     LAUNCH_CHECK();
     return INFFT_OK;
@@ -998,6 +1312,28 @@ int infft_get_B(infft_plan p, void* rows) {
 
 int nfft_plan_status(infft_plan p, infft_status* out) {
     if (!p || !out) return fail(INFFT_EINVAL, "null argument");
+    if (p->batch) {
+        // sums and extremes over the problems of the batch
+        std::memset(out, 0, sizeof(*out));
+        int64_t mn = INT64_MAX;
+        for (infft_plan_s* s : p->batch->subs) {
+            infft_status o{};
+            int rc = nfft_plan_status(s, &o);
+            if (rc && rc != INFFT_ESINGULAR) return rc;
+            out->nonfinite_nodes += o.nonfinite_nodes;
+            out->failed_solves += o.failed_solves;
+            out->empty_columns += o.empty_columns;
+            out->oversized += o.oversized;
+            if (o.max_members > 0) mn = std::min<int64_t>(mn, o.min_members);
+            out->max_members = std::max(out->max_members, o.max_members);
+        }
+        out->min_members = mn == INT64_MAX ? 0 : mn;
+        out->bopt_ready = p->bopt_ready ? 1 : 0;
+        out->max_supported = INT32_MAX;
+        if (p->bopt_ready && out->failed_solves > 0)
+            return fail(INFFT_ESINGULAR, "%lld local solves met a non-positive pivot", (long long)out->failed_solves);
+        return INFFT_OK;
+    }
     if (p->bopt_ready && p->stat_nrec > 0) {
         launch_solve_stats(p->stat_rec, p->stat_nrec, p->status, p->stream);
         LAUNCH_CHECK();
@@ -1019,7 +1355,62 @@ int nfft_plan_status(infft_plan p, infft_status* out) {
     return INFFT_OK;
 }
 
-int64_t nfft_plan_device_bytes(infft_plan p) { return p ? p->bytes : 0; }
+int64_t nfft_plan_device_bytes(infft_plan p) {
+    if (!p) return 0;
+    int64_t b = p->bytes;
+    if (p->batch)
+        for (const infft_plan_s* s : p->batch->subs) b += s->bytes;
+    return b;
+}
+
+int nfft_plan_batched(infft_plan* out, int nprob, const int64_t* M, const int64_t* N, double sigma, int m,
+                      const double* x, const infft_options* opts, void* stream) {
+    if (!out) return fail(INFFT_EINVAL, "out is null");
+    *out = nullptr;
+    if (nprob < 1) return fail(INFFT_EINVAL, "nprob must be positive");
+    if (!M || !N || !x) return fail(INFFT_EINVAL, "null size or node pointer");
+    infft_options o;
+    if (opts) o = *opts;
+    else infft_default_options(&o);
+    auto* P = new infft_plan_s();
+    P->batch = new BatchState();
+    P->prec = o.precision;
+    P->max_rhs = o.max_rhs;
+    P->rho = o.rho;
+    P->sigma = sigma;
+    P->stream = (hipStream_t)stream;
+    BatchState& B = *P->batch;
+    int64_t poff = 0, noff = 0, goff = 0;
+    for (int i = 0; i < nprob; ++i) {
+        infft_plan sub = nullptr;
+        int rc = nfft_plan(&sub, 1, &M[i], N[i], sigma, m, x + noff, &o, stream);
+        if (rc) {
+            const std::string msg = "problem " + std::to_string(i) + ": " + g_err;
+            delete P;
+            g_err = msg;
+            return rc;
+        }
+        B.subs.push_back(sub);
+        B.Poff.push_back(poff);
+        B.Noff.push_back(noff);
+        poff += M[i];
+        noff += N[i];
+        goff += sub->g.G;
+    }
+    B.Ptot = poff;
+    B.Ntot = noff;
+    P->g = B.subs[0]->g;
+    P->g.N = noff;
+    P->g.P = poff;
+    P->g.G = goff;
+    int rc = batch_build(P);
+    if (rc) {
+        delete P;
+        return rc;
+    }
+    *out = P;
+    return INFFT_OK;
+}
 
 int infft_profile_begin(infft_plan p, int kernel_class) {
     if (!p) return fail(INFFT_EINVAL, "null plan");

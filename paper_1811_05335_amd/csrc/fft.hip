@@ -268,12 +268,14 @@ __device__ inline void store_elem(const FftIO& io, const FftPass& P, const Geo& 
     }
 }
 
+// One workgroup's share of a pass: sub-transforms blk * rows .. of the pass.
 template <typename R, int E, int LD, int ST>
-__global__ void __launch_bounds__(FFT_THREADS) k_fft(FftPass P, FftIO io, Geo g) {
+__device__ inline void fft_block(const FftPass& P, const FftIO& io, const Geo& g, int64_t blk) {
     extern __shared__ char smem_raw[];
     cx<R>* lds = (cx<R>*)smem_raw;
     const int ld = P.n + 1;
-    const int64_t seq0 = blockIdx.x * (int64_t)P.rows;
+    const int64_t seq0 = blk * (int64_t)P.rows;
+    if (seq0 >= P.nseq) return;
     const int rows = (int)min((int64_t)P.rows, P.nseq - seq0);
     const int tot = rows * P.n;
     for (int L = threadIdx.x; L < tot; L += FFT_THREADS) {
@@ -294,6 +296,29 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft(FftPass P, FftIO io, Geo g)
         const int64_t r = s / P.nq, q = s - r * P.nq;
         store_elem<R, ST>(io, P, g, r, q * P.out_qs + (int64_t)k * P.out_ks, q, k, lds[row * ld + k]);
     }
+}
+
+template <typename R, int E, int LD, int ST>
+__global__ void __launch_bounds__(FFT_THREADS) k_fft(FftPass P, FftIO io, Geo g) {
+    fft_block<R, E, LD, ST>(P, io, g, blockIdx.x);
+}
+
+// Passes of many problems in one launch: workgroup -> (job, block of that job's pass).  A job's
+// caller-side array is the batch array plus nrhs times the job's offset (problem-major layout);
+// its sub-transform count follows the call's nrhs, so blocks planned for more right-hand sides
+// find no work and return.
+template <typename R, int E, int LD, int ST>
+__global__ void __launch_bounds__(FFT_THREADS) k_fft_batched(const FftJob* __restrict__ jobs,
+                                                             const int2* __restrict__ bmap, const void* user_in,
+                                                             void* user_out, int nrhs) {
+    const int2 b = bmap[blockIdx.x];
+    const FftJob& J = jobs[b.x];
+    FftPass P = J.pass;
+    P.nseq = P.nq * nrhs;
+    FftIO io = J.io;
+    if (J.user_in) io.in = (const cx<R>*)user_in + (int64_t)nrhs * J.user_off;
+    if (J.user_out) io.out = (cx<R>*)user_out + (int64_t)nrhs * J.user_off;
+    fft_block<R, E, LD, ST>(P, io, J.g, b.y);
 }
 
 template <typename R>
@@ -320,5 +345,29 @@ void launch_fft_pass(const FftPass& p, const FftIO& io, const Geo& g, int ld, in
 
 template void launch_fft_pass<float>(const FftPass&, const FftIO&, const Geo&, int, int, hipStream_t);
 template void launch_fft_pass<double>(const FftPass&, const FftIO&, const Geo&, int, int, hipStream_t);
+
+template <typename R>
+void launch_fft_batched(const FftJob* jobs, const int2* bmap, int nblocks, size_t shm, int ld, int st,
+                        const void* user_in, void* user_out, int nrhs, hipStream_t s) {
+    if (nblocks <= 0) return;
+    constexpr int E = (sizeof(R) == 8) ? FFT_E64 : FFT_E32;
+#define INFFT_FFTB_CASE(L_, S_)                                                                       \
+    if (ld == L_ && st == S_) {                                                                       \
+        hipLaunchKernelGGL((k_fft_batched<R, E, L_, S_>), dim3(nblocks), dim3(FFT_THREADS), shm, s, jobs, \
+                           bmap, user_in, user_out, nrhs);                                            \
+        return;                                                                                       \
+    }
+    INFFT_FFTB_CASE(LD_DECONV, ST_GRID)
+    INFFT_FFTB_CASE(LD_DECONV, ST_TWIDDLE)
+    INFFT_FFTB_CASE(LD_GRID, ST_GRID)
+    INFFT_FFTB_CASE(LD_GRID, ST_TWIDDLE)
+    INFFT_FFTB_CASE(LD_GRID, ST_DECONV)
+#undef INFFT_FFTB_CASE
+}
+
+template void launch_fft_batched<float>(const FftJob*, const int2*, int, size_t, int, int, const void*, void*, int,
+                                        hipStream_t);
+template void launch_fft_batched<double>(const FftJob*, const int2*, int, size_t, int, int, const void*, void*,
+                                         int, hipStream_t);
 
 }  // namespace infft

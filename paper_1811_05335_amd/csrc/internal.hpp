@@ -204,6 +204,27 @@ struct FftIO {
     int64_t halo_rs0, halo_rs1, halo_rs01;  // per right-hand side strides of the halos
 };
 
+// One problem's share of a batched launch: the pass (or kernel arguments) of that problem, and
+// where its caller-side array starts inside the batch array (problem-major: nrhs * user_off).
+struct FftJob {
+    FftPass pass;
+    FftIO io;
+    Geo g;
+    int user_in, user_out;   // the pass reads / writes the caller's array
+    int64_t user_off;        // the problem's first element (per right-hand side) in the batch
+};
+
+// Per-node and per-cell kernels of one 1-D problem inside a batch.
+struct NodeJob {
+    Geo g;
+    NodesDev nd;
+    const void* B;      // B_opt of the problem ([tap][N_i], sorted order, plan precision)
+    void* grid;         // the problem's oversampled grid, [rhs][M_sigma_i]
+    int64_t grs;        // grid stride per right-hand side
+    int64_t noff;       // first node of the problem in the batch
+};
+enum NodeBatchKind { NB_INTERP = 0, NB_INTERP_B = 1, NB_GATHER = 2, NB_GATHER_B = 3, NB_GRAD = 4 };
+
 // ------------------------------------------------------------------ launchers (per .hip file)
 
 // nodes.hip
@@ -232,6 +253,9 @@ void launch_taylor_table_sym(int M, int Ms, const double* D, int power, int qmax
 template <typename R>
 void launch_fft_pass(const FftPass& p, const FftIO& io, const Geo& g, int ld, int st, hipStream_t s);
 int fft_capacity(bool fp64);   // elements of one workgroup's LDS transform buffer
+template <typename R>
+void launch_fft_batched(const FftJob* jobs, const int2* bmap, int nblocks, size_t shm, int ld, int st,
+                        const void* user_in, void* user_out, int nrhs, hipStream_t s);
 
 // spread.hip
 template <typename R>
@@ -248,6 +272,11 @@ template <typename R>
 void launch_grad_x(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grid_rs, const cx<R>* gradf,
                    double* gradx, int nrhs, int accumulate, hipStream_t s);
 int spread_rhs_chunk(const Geo& g, bool fp64);
+// kind NB_*: interpolation reads the grid and writes `out`; gathers read `in` and write the grid;
+// the gradient reads `in` (gradient of f) and writes `gradx`
+template <typename R>
+void launch_node_batched(int kind, int m, const NodeJob* jobs, const int2* bmap, int nblocks, const cx<R>* in,
+                         cx<R>* out, double* gradx, int nrhs, int accumulate, hipStream_t s);
 
 // solve.hip
 struct SolveArgs {
@@ -263,6 +292,21 @@ struct SolveArgs {
     int tables_in_lds;      // set by the launcher (1-D plans whose kernel tables fit in LDS)
 };
 int launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl, hipStream_t s);
+// One 1-D problem of a batch for the solve kernels (its own tables, lists and statistics slots).
+struct SolveJob {
+    Geo g;
+    NodesDev nd;
+    KTabDev kt;
+    SolveArgs a;
+};
+// Thread-per-problem tier over all problems of a batch (workgroup -> (job, block of 128 cells)).
+void launch_solve_t1_batched(const SolveJob* jobs, const int2* t1_map, int t1_blocks, int qQ, int qK,
+                             hipStream_t s);
+void launch_batch_solve_reset(const SolveJob* jobs, int njobs, hipStream_t s);
+void launch_batch_counts(const SolveJob* jobs, int njobs, int* out, hipStream_t s);
+constexpr int T1_CELLS = 128;   // cells per workgroup of the thread-per-problem tier
+// Group tier (nl = 16 or 32) over the lists of all problems; each workgroup visits every list.
+void launch_solve_tier_batched(const SolveJob* jobs, int njobs, int nl, int blocks, hipStream_t s);
 int launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s);
 void launch_solve_stats(const long long* rec, int nrec, long long* status, hipStream_t s);
 

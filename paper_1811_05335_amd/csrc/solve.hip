@@ -49,7 +49,7 @@ struct SolveStat {
     unsigned long long mn, mx, fail, empty, over;
 };
 
-__device__ inline void write_block_stats(long long* rec, unsigned long long st_min, unsigned long long st_max,
+__device__ inline void write_block_stats(long long* rec, int64_t blk, unsigned long long st_min, unsigned long long st_max,
                                          unsigned long long st_fail, unsigned long long st_empty,
                                          unsigned long long st_over) {
     __shared__ SolveStat s_st[16];
@@ -73,7 +73,7 @@ __device__ inline void write_block_stats(long long* rec, unsigned long long st_m
             t.empty += s_st[i].empty;
             t.over += s_st[i].over;
         }
-        long long* r = rec + (int64_t)blockIdx.x * 5;
+        long long* r = rec + blk * 5;
         r[0] = (long long)t.mn;
         r[1] = (long long)t.mx;
         r[2] = (long long)t.fail;
@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(256) k_solve(Geo g, NodesDev nd, KTabDev kt, S
     }
 
     // ---- statistics: reduce over the wave, one set of atomics per wave
-    write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, st_min, st_max, st_fail, st_empty, st_over);
+    write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, blockIdx.x, st_min, st_max, st_fail, st_empty, st_over);
 }
 
 // ------------------------------------------------------------------ 1-D: real solves + rank one
@@ -425,8 +425,12 @@ __device__ inline double group_sum(double v) {
 
 // One group of NL lanes per grid index l; the group's (n x n, n <= NL) matrix lives in LDS,
 // lane i owns row i.  All loops run to the actual size n.
-template <int NL>
-__global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
+// blk / nblk: this workgroup's index and the number of workgroups sharing the problem list.
+// TAB_LDS: the Q table is staged in LDS (one problem per launch) or read through the caches
+// (a batch, where every workgroup visits every problem's list).
+template <int NL, bool TAB_LDS>
+__device__ inline void solve_r1_body(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a,
+                                     int64_t blk, int64_t nblk) {
     constexpr int GPB = 128 / NL;   // groups per block
     constexpr int LDA = NL + 1;
     __shared__ double s_A[GPB * NL * LDA];
@@ -439,13 +443,16 @@ __global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt
     const uint64_t gmask = (NL == 64) ? ~0ull : ((1ull << NL) - 1ull);
     double* Ag = s_A + (threadIdx.x / NL) * NL * LDA;
     double* Ai = Ag + lane * LDA;
-    const int64_t gid = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / NL;
-    const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / NL;
+    const int64_t gid = (blk * (int64_t)blockDim.x + threadIdx.x) / NL;
+    const int64_t ngroups = nblk * blockDim.x / NL;
     const int64_t count = a.in_list ? (int64_t)(*a.in_count) : g.G;
 
-    stage_to_lds(s_tabr, kt.Qs, (kt.qQ + 1) * TAY_NC);
-    __syncthreads();
-    const double* tQ = s_tabr;
+    const double* tQ = kt.Qs;
+    if (TAB_LDS) {
+        stage_to_lds(s_tabr, kt.Qs, (kt.qQ + 1) * TAY_NC);
+        __syncthreads();
+        tQ = s_tabr;
+    }
     const double c1 = (double)g.Ms[0] * kt.dM * kt.dM;
 
     unsigned long long st_min = ULLONG_MAX, st_max = 0, st_fail = 0, st_empty = 0, st_over = 0;
@@ -578,7 +585,22 @@ __global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt
         wave_sync();
     }
 
-    write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, st_min, st_max, st_fail, st_empty, st_over);
+    write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, blk, st_min, st_max, st_fail, st_empty, st_over);
+}
+
+template <int NL>
+__global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
+    solve_r1_body<NL, true>(g, nd, kt, a, blockIdx.x, gridDim.x);
+}
+
+// Every workgroup walks the lists of all problems of a batch in turn.
+template <int NL>
+__global__ void __launch_bounds__(128) k_solve_r1_batched(const SolveJob* __restrict__ jobs, int njobs) {
+    for (int j = 0; j < njobs; ++j) {
+        const SolveJob& J = jobs[j];
+        solve_r1_body<NL, false>(J.g, J.nd, J.kt, J.a, blockIdx.x, gridDim.x);
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------------ 1-D: one thread per problem
@@ -595,11 +617,12 @@ __global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt
 // factor per node.  Windows that wrap around the torus (the first 2m-1 grid indices) evaluate their
 // entries directly.  Problems with more members or with a member on the window edge (tap 2m
 // inside the support) are appended to the list of the group kernels.
-constexpr int T1_TPB = 128;
+constexpr int T1_TPB = T1_CELLS;
 constexpr int T1_NODECAP = 320;   // staged nodes per workgroup (density up to ~2.4 per cell)
 
 template <int NMAX>
-__global__ void __launch_bounds__(T1_TPB) k_solve_t1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
+__device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a,
+                                     int blk) {
     extern __shared__ double s_tabq[];                      // Qs, then Ks Taylor tables
     __shared__ double s_band[T1_NODECAP * NMAX];       // band of the workgroup's nodes
     __shared__ int s_l0[T1_NODECAP];                   // stencil base of the staged nodes
@@ -612,7 +635,7 @@ __global__ void __launch_bounds__(T1_TPB) k_solve_t1(Geo g, NodesDev nd, KTabDev
     const double* s_tabk = s_tabq + nQ;
 
     const int Ms = g.Ms[0], w2 = 2 * g.m;
-    const int L0 = blockIdx.x * T1_TPB;
+    const int L0 = blk * T1_TPB;
     const int l = L0 + threadIdx.x;
     // node range of the workgroup: from the first member of problem L0 to the last of L0+TPB-1
     if (threadIdx.x == 0) {
@@ -811,7 +834,59 @@ __global__ void __launch_bounds__(T1_TPB) k_solve_t1(Geo g, NodesDev nd, KTabDev
             }
         }
     }
-    write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, st_min, st_max, st_fail, st_empty, st_over);
+    write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, blk, st_min, st_max, st_fail, st_empty, st_over);
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(T1_TPB) k_solve_t1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
+    solve_t1_body<NMAX>(g, nd, kt, a, blockIdx.x);
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(T1_TPB) k_solve_t1_batched(const SolveJob* __restrict__ jobs,
+                                                             const int2* __restrict__ bmap) {
+    const int2 b = bmap[blockIdx.x];
+    const SolveJob& J = jobs[b.x];
+    solve_t1_body<NMAX>(J.g, J.nd, J.kt, J.a, b.y);
+}
+
+void launch_solve_t1_batched(const SolveJob* jobs, const int2* t1_map, int t1_blocks, int qQ, int qK,
+                             hipStream_t s) {
+    const size_t shm = (size_t)((qQ + 1) + (qK + 1)) * TAY_NC * sizeof(double);
+    if (t1_blocks > 0)
+        hipLaunchKernelGGL((k_solve_t1_batched<13>), dim3(t1_blocks), dim3(T1_TPB), shm, s, jobs, t1_map);
+}
+
+// Per problem of a batch: reset the solver's status words (the node word stays) and the four
+// list counters (jobs of the thread tier, whose out_count is the first counter).
+__global__ void k_batch_solve_reset(const SolveJob* __restrict__ jobs, int njobs) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= njobs) return;
+    long long* st = jobs[j].a.status;
+    for (int w = 0; w < STATUS_WORDS; ++w)
+        if (w != ST_NONFINITE) st[w] = (w == ST_MIN_N) ? LLONG_MAX : 0;
+    int* c = jobs[j].a.out_count;
+    for (int i = 0; i < 4; ++i) c[i] = 0;
+}
+
+// out[j] = the count of the list the job's tier wrote.
+__global__ void k_batch_counts(const SolveJob* __restrict__ jobs, int njobs, int* __restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < njobs) out[j] = *jobs[j].a.out_count;
+}
+
+void launch_batch_solve_reset(const SolveJob* jobs, int njobs, hipStream_t s) {
+    if (njobs > 0) hipLaunchKernelGGL(k_batch_solve_reset, dim3((njobs + 255) / 256), dim3(256), 0, s, jobs, njobs);
+}
+
+void launch_batch_counts(const SolveJob* jobs, int njobs, int* out, hipStream_t s) {
+    if (njobs > 0) hipLaunchKernelGGL(k_batch_counts, dim3((njobs + 255) / 256), dim3(256), 0, s, jobs, njobs, out);
+}
+
+void launch_solve_tier_batched(const SolveJob* jobs, int njobs, int nl, int blocks, hipStream_t s) {
+    if (njobs <= 0 || blocks <= 0) return;
+    if (nl == 16) hipLaunchKernelGGL((k_solve_r1_batched<16>), dim3(blocks), dim3(128), 0, s, jobs, njobs);
+    else hipLaunchKernelGGL((k_solve_r1_batched<32>), dim3(blocks), dim3(128), 0, s, jobs, njobs);
 }
 
 int launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s) {

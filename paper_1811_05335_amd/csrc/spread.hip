@@ -79,10 +79,9 @@ __device__ inline int wrap_add(int a, int t, int Ms) {
 // ------------------------------------------------------------------ interpolation (trafo)
 
 template <typename R, int D, int W>
-__global__ void __launch_bounds__(256) k_interp(Geo g, NodesDev nd, const cx<R>* __restrict__ grid,
-                                                int64_t grs, cx<R>* __restrict__ f, int nrhs) {
+__device__ inline void interp_item(const Geo& g, const NodesDev& nd, const cx<R>* __restrict__ grid, int64_t grs,
+                                   cx<R>* __restrict__ f, int nrhs, int64_t j) {
     using C = cx<R>;
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= g.N) return;
     const R b = (R)g.b;
     R w0[W], w1[W];
@@ -122,14 +121,18 @@ __global__ void __launch_bounds__(256) k_interp(Geo g, NodesDev nd, const cx<R>*
     }
 }
 
+template <typename R, int D, int W>
+__global__ void __launch_bounds__(256) k_interp(Geo g, NodesDev nd, const cx<R>* __restrict__ grid,
+                                                int64_t grs, cx<R>* __restrict__ f, int nrhs) {
+    interp_item<R, D, W>(g, nd, grid, grs, f, nrhs, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+
 // ------------------------------------------------------------------ interpolation with B_opt
 
 template <typename R, int D, int W>
-__global__ void __launch_bounds__(256) k_interp_B(Geo g, NodesDev nd, const cx<R>* __restrict__ grid,
-                                                  int64_t grs, const cx<R>* __restrict__ B,
-                                                  cx<R>* __restrict__ f, int nrhs) {
+__device__ inline void interp_B_item(const Geo& g, const NodesDev& nd, const cx<R>* __restrict__ grid, int64_t grs,
+                                     const cx<R>* __restrict__ B, cx<R>* __restrict__ f, int nrhs, int64_t p) {
     using C = cx<R>;
-    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= g.N) return;
     const int j = nd.perm[p];
     const int a0 = nd.l0s[p * D];
@@ -154,6 +157,13 @@ __global__ void __launch_bounds__(256) k_interp_B(Geo g, NodesDev nd, const cx<R
         }
         f[r * g.N + j] = acc;
     }
+}
+
+template <typename R, int D, int W>
+__global__ void __launch_bounds__(256) k_interp_B(Geo g, NodesDev nd, const cx<R>* __restrict__ grid,
+                                                  int64_t grs, const cx<R>* __restrict__ B,
+                                                  cx<R>* __restrict__ f, int nrhs) {
+    interp_B_item<R, D, W>(g, nd, grid, grs, B, f, nrhs, blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
 }
 
 // ------------------------------------------------------------------ tiled spreading
@@ -250,11 +260,10 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
 // per cell sums them directly: no atomics, no halos, every (node, tap) pair evaluated once.
 
 template <typename R, bool USEB>
-__global__ void __launch_bounds__(256) k_gather1d(Geo g, NodesDev nd, const cx<R>* __restrict__ f,
-                                                  const cx<R>* __restrict__ B, cx<R>* __restrict__ grid,
-                                                  int64_t grs, int nrhs) {
+__device__ inline void gather1d_item(const Geo& g, const NodesDev& nd, const cx<R>* __restrict__ f,
+                                     const cx<R>* __restrict__ B, cx<R>* __restrict__ grid, int64_t grs, int nrhs,
+                                     int l) {
     using C = cx<R>;
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
     const int Ms = g.Ms[0], w2 = 2 * g.m;
     if (l >= Ms) return;
     const R b = (R)g.b;
@@ -288,14 +297,20 @@ __global__ void __launch_bounds__(256) k_gather1d(Geo g, NodesDev nd, const cx<R
     }
 }
 
+template <typename R, bool USEB>
+__global__ void __launch_bounds__(256) k_gather1d(Geo g, NodesDev nd, const cx<R>* __restrict__ f,
+                                                  const cx<R>* __restrict__ B, cx<R>* __restrict__ grid,
+                                                  int64_t grs, int nrhs) {
+    gather1d_item<R, USEB>(g, nd, f, B, grid, grs, nrhs, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 // ------------------------------------------------------------------ gradient with respect to x
 
 template <typename R, int D, int W>
-__global__ void __launch_bounds__(256) k_grad_x(Geo g, NodesDev nd, const cx<R>* __restrict__ grid,
-                                                int64_t grs, const cx<R>* __restrict__ gradf,
-                                                double* __restrict__ gradx, int nrhs, int accumulate) {
+__device__ inline void grad_x_item(const Geo& g, const NodesDev& nd, const cx<R>* __restrict__ grid, int64_t grs,
+                                   const cx<R>* __restrict__ gradf, double* __restrict__ gradx, int nrhs,
+                                   int accumulate, int64_t j) {
     using C = cx<R>;
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= g.N) return;
     const R b = (R)g.b;
     R w0[W], w1[W], d0[W], d1[W];
@@ -349,6 +364,55 @@ __global__ void __launch_bounds__(256) k_grad_x(Geo g, NodesDev nd, const cx<R>*
         gradx[j * D] = (double)gx0;
         if (D == 2) gradx[j * D + 1] = (double)gx1;
     }
+}
+
+template <typename R, int D, int W>
+__global__ void __launch_bounds__(256) k_grad_x(Geo g, NodesDev nd, const cx<R>* __restrict__ grid,
+                                                int64_t grs, const cx<R>* __restrict__ gradf,
+                                                double* __restrict__ gradx, int nrhs, int accumulate) {
+    grad_x_item<R, D, W>(g, nd, grid, grs, gradf, gradx, nrhs, accumulate,
+                         blockIdx.x * (int64_t)blockDim.x + threadIdx.x);
+}
+
+// ------------------------------------------------------------------ many 1-D problems in one launch
+// Workgroup -> (job, block of that job's items).  A job's caller-side arrays are the batch arrays
+// plus nrhs times its node offset (problem-major layout).
+
+template <typename R, int W>
+__global__ void __launch_bounds__(256) k_interp_batched(const NodeJob* __restrict__ jobs, const int2* __restrict__ bmap,
+                                                        cx<R>* f, int nrhs) {
+    const int2 b = bmap[blockIdx.x];
+    const NodeJob& J = jobs[b.x];
+    interp_item<R, 1, W>(J.g, J.nd, (const cx<R>*)J.grid, J.grs, f + (int64_t)nrhs * J.noff, nrhs,
+                         (int64_t)b.y * 256 + threadIdx.x);
+}
+
+template <typename R, int W>
+__global__ void __launch_bounds__(256) k_interp_B_batched(const NodeJob* __restrict__ jobs,
+                                                          const int2* __restrict__ bmap, cx<R>* f, int nrhs) {
+    const int2 b = bmap[blockIdx.x];
+    const NodeJob& J = jobs[b.x];
+    interp_B_item<R, 1, W>(J.g, J.nd, (const cx<R>*)J.grid, J.grs, (const cx<R>*)J.B, f + (int64_t)nrhs * J.noff,
+                           nrhs, (int64_t)b.y * 256 + threadIdx.x);
+}
+
+template <typename R, bool USEB>
+__global__ void __launch_bounds__(256) k_gather1d_batched(const NodeJob* __restrict__ jobs,
+                                                          const int2* __restrict__ bmap, const cx<R>* f, int nrhs) {
+    const int2 b = bmap[blockIdx.x];
+    const NodeJob& J = jobs[b.x];
+    gather1d_item<R, USEB>(J.g, J.nd, f + (int64_t)nrhs * J.noff, (const cx<R>*)J.B, (cx<R>*)J.grid, J.grs, nrhs,
+                           b.y * 256 + threadIdx.x);
+}
+
+template <typename R, int W>
+__global__ void __launch_bounds__(256) k_grad_x_batched(const NodeJob* __restrict__ jobs,
+                                                        const int2* __restrict__ bmap, const cx<R>* gradf,
+                                                        double* gradx, int nrhs, int accumulate) {
+    const int2 b = bmap[blockIdx.x];
+    const NodeJob& J = jobs[b.x];
+    grad_x_item<R, 1, W>(J.g, J.nd, (const cx<R>*)J.grid, J.grs, gradf + (int64_t)nrhs * J.noff, gradx + J.noff,
+                         nrhs, accumulate, (int64_t)b.y * 256 + threadIdx.x);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -437,6 +501,31 @@ void launch_grad_x(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grs, co
     }
 }
 
+template <typename R>
+void launch_node_batched(int kind, int m, const NodeJob* jobs, const int2* bmap, int nblocks, const cx<R>* in,
+                         cx<R>* out, double* gradx, int nrhs, int accumulate, hipStream_t s) {
+    if (nblocks <= 0) return;
+    const dim3 gr(nblocks), bl(256);
+    switch (kind) {
+        case NB_INTERP:
+            INFFT_DISPATCH_W(m, hipLaunchKernelGGL((k_interp_batched<R, W>), gr, bl, 0, s, jobs, bmap, out, nrhs))
+            break;
+        case NB_INTERP_B:
+            INFFT_DISPATCH_W(m, hipLaunchKernelGGL((k_interp_B_batched<R, W>), gr, bl, 0, s, jobs, bmap, out, nrhs))
+            break;
+        case NB_GATHER:
+            hipLaunchKernelGGL((k_gather1d_batched<R, false>), gr, bl, 0, s, jobs, bmap, in, nrhs);
+            break;
+        case NB_GATHER_B:
+            hipLaunchKernelGGL((k_gather1d_batched<R, true>), gr, bl, 0, s, jobs, bmap, in, nrhs);
+            break;
+        default:
+            INFFT_DISPATCH_W(m, hipLaunchKernelGGL((k_grad_x_batched<R, W>), gr, bl, 0, s, jobs, bmap, in, gradx,
+                                                   nrhs, accumulate))
+            break;
+    }
+}
+
 #define INFFT_INST(R)                                                                                  \
     template void launch_interp<R>(const Geo&, NodesDev, const cx<R>*, int64_t, cx<R>*, int, hipStream_t); \
     template void launch_interp_B<R>(const Geo&, NodesDev, const cx<R>*, int64_t, const cx<R>*, cx<R>*, int, \
@@ -444,7 +533,9 @@ void launch_grad_x(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grs, co
     template void launch_spread<R>(const Geo&, NodesDev, const cx<R>*, const cx<R>*, cx<R>*, int64_t, cx<R>*, \
                                    cx<R>*, cx<R>*, int64_t, int64_t, int64_t, int, int, hipStream_t);  \
     template void launch_grad_x<R>(const Geo&, NodesDev, const cx<R>*, int64_t, const cx<R>*, double*, int, \
-                                   int, hipStream_t);
+                                   int, hipStream_t);                                                  \
+    template void launch_node_batched<R>(int, int, const NodeJob*, const int2*, int, const cx<R>*, cx<R>*,    \
+                                         double*, int, int, hipStream_t);
 INFFT_INST(float)
 INFFT_INST(double)
 

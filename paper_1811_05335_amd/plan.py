@@ -181,7 +181,128 @@ class NfftPlan:
             pass
 
 
+class NfftBatchPlan(NfftPlan):
+    """Many independent one-dimensional problems of uneven sizes in one plan (nfft_plan_batched):
+    every stage runs for all problems in one kernel launch.
+
+    Ms, Ns     coefficients (even) and nodes of each problem
+    x          float64 CUDA tensor with the nodes of all problems one after the other
+    Data are flat, problem-major tensors: coefficients [problem][R][M_i] (length R * sum Ms),
+    samples [problem][R][N_i] (length R * sum Ns), with R <= max_rhs given to each call;
+    `pack` and `unpack` convert from and to lists of per-problem (R, M_i) / (R, N_i) tensors.
+    """
+
+    def __init__(self, Ms, Ns, x: torch.Tensor, sigma: float = 2.0, m: int = 4, precision: str = "f64",
+                 rho: float = 1e-8, max_rhs: int = 1):
+        lib = load()
+        self.Ms = [int(v) for v in Ms]
+        self.Ns = [int(v) for v in Ns]
+        if len(self.Ms) != len(self.Ns) or not self.Ms:
+            raise ValueError("Ms and Ns must be non-empty and of equal length")
+        self.d = 1
+        self.M = (sum(self.Ms),)
+        self.N = sum(self.Ns)
+        x = self._nodes(x)
+        if x.shape[0] != self.N:
+            raise ValueError("x must hold sum(Ns) nodes")
+        self.sigma, self.m = float(sigma), int(m)
+        self.precision = precision
+        self.ctype = torch.complex64 if precision == "f32" else torch.complex128
+        self.taps = 2 * self.m + 1
+        self.max_rhs = int(max_rhs)
+        o = Options()
+        lib.infft_default_options(C.byref(o))
+        o.precision = _lib.INFFT_F32 if precision == "f32" else _lib.INFFT_F64
+        o.max_rhs = self.max_rhs
+        o.rho = float(rho)
+        n = len(self.Ms)
+        Mv = (C.c_int64 * n)(*self.Ms)
+        Nv = (C.c_int64 * n)(*self.Ns)
+        h = C.c_void_p()
+        check(lib.nfft_plan_batched(C.byref(h), n, Mv, Nv, self.sigma, self.m, C.c_void_p(_ptr(x)), C.byref(o),
+                                    C.c_void_p(_stream_handle())))
+        self._h = h
+        self._x = x
+        self.device = x.device
+
+    def _flat(self, a: torch.Tensor, per: int):
+        if a.dtype != self.ctype or not a.is_cuda:
+            raise TypeError(f"expected a {self.ctype} CUDA tensor")
+        a = a.reshape(-1).contiguous()
+        if a.numel() % per:
+            raise ValueError(f"length must be a multiple of {per}")
+        R = a.numel() // per
+        if R < 1 or R > self.max_rhs:
+            raise ValueError(f"1 <= R <= max_rhs = {self.max_rhs}")
+        return a, R
+
+    def _coeffs(self, a):
+        a, R = self._flat(a, self.M[0])
+        return a, (R * self.M[0],), R
+
+    def _samples(self, a):
+        a, R = self._flat(a, self.N)
+        return a, (R * self.N,), R
+
+    def _out(self, n):
+        return torch.empty(n, dtype=self.ctype, device=self.device)
+
+    def trafo(self, fhat):
+        fh, _, R = self._coeffs(fhat)
+        out = self._out(R * self.N)
+        self._sync_stream()
+        check(load().nfft_trafo(self._h, C.c_void_p(_ptr(fh)), C.c_void_p(_ptr(out)), R))
+        return out
+
+    def adjoint(self, f):
+        ff, _, R = self._samples(f)
+        out = self._out(R * self.M[0])
+        self._sync_stream()
+        check(load().nfft_adjoint(self._h, C.c_void_p(_ptr(ff)), C.c_void_p(_ptr(out)), R))
+        return out
+
+    def apply(self, f):
+        ff, _, R = self._samples(f)
+        out = self._out(R * self.M[0])
+        self._sync_stream()
+        check(load().infft_apply(self._h, C.c_void_p(_ptr(ff)), C.c_void_p(_ptr(out)), R))
+        return out
+
+    def apply_adjoint(self, h):
+        hh, _, R = self._coeffs(h)
+        out = self._out(R * self.N)
+        self._sync_stream()
+        check(load().infft_apply_adjoint(self._h, C.c_void_p(_ptr(hh)), C.c_void_p(_ptr(out)), R))
+        return out
+
+    def grad_x(self, fhat, gradf):
+        fh, _, R = self._coeffs(fhat)
+        gf, _, R2 = self._samples(gradf)
+        if R2 != R:
+            raise ValueError("fhat and gradf need the same number of right-hand sides")
+        out = torch.empty((self.N, 1), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        check(load().nfft_grad_x(self._h, C.c_void_p(_ptr(fh)), C.c_void_p(_ptr(gf)), C.c_void_p(_ptr(out)), R))
+        return out
+
+    def pack(self, arrays, kind: str) -> torch.Tensor:
+        """Per-problem tensors of shape (R, M_i) ("coeffs") or (R, N_i) ("samples") -> flat tensor."""
+        return torch.cat([a.reshape(-1) for a in arrays]).contiguous()
+
+    def unpack(self, flat: torch.Tensor, kind: str, R: int):
+        sizes = self.Ms if kind == "coeffs" else self.Ns
+        out, o = [], 0
+        for n in sizes:
+            out.append(flat[o:o + R * n].reshape(R, n))
+            o += R * n
+        return out
+
+
 # Function names of the C ABI, for callers who prefer them to the class.
+def nfft_plan_batched(Ms, Ns, x, sigma=2.0, m=4, **kw) -> NfftBatchPlan:
+    return NfftBatchPlan(Ms, Ns, x, sigma=sigma, m=m, **kw)
+
+
 def nfft_plan(M, x, sigma=2.0, m=4, **kw) -> NfftPlan:
     return NfftPlan(M, x, sigma, m, **kw)
 

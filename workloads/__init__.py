@@ -151,6 +151,8 @@ CONFIGS = {
     # 2-D polar trajectory
     "c3": dict(d=2, M=(512, 512), N=524288, sigma=2.0, m=4, nodes="polar", rho=1e-8, rhs=1),
     # 2-D spiral trajectory, 16 right-hand sides
+    # batched uneven 1-D problems (M_i, N_i from batched_sizes), 8 right-hand sides each
+    "c4": dict(d=1, nprob=256, lo=1024, hi=16384, sigma=2.0, m=4, nodes="uniform", rho=1e-8, rhs=8),
     "c5": dict(d=2, M=(256, 256), N=65536, sigma=2.0, m=4, nodes="spiral", rho=1e-8, rhs=16),
 }
 
@@ -182,3 +184,16 @@ def make_problem(cfg: dict, seed: int = 0, rhs: int | None = None):
     R = cfg.get("rhs", 1) if rhs is None else rhs
     fhat = complex_normal(g, (R,) + tuple(cfg["M"]))
     return x, fhat
+
+
+def make_batch(cfg: dict, seed: int = 0, rhs: int | None = None):
+    """Uneven batch: sizes first (M_i, then r_i), then per problem its nodes and its R
+    right-hand sides of coefficients.  Returns Ms, Ns, list of x_i (N_i, 1), list of fhat_i (R, M_i)."""
+    g = rng(seed)
+    Ms, Ns = batched_sizes(g, cfg["nprob"], cfg["lo"], cfg["hi"])
+    R = cfg.get("rhs", 1) if rhs is None else rhs
+    xs, fhs = [], []
+    for M, N in zip(Ms, Ns):
+        xs.append(uniform_nodes(g, int(N), 1))
+        fhs.append(complex_normal(g, (R, int(M))))
+    return Ms, Ns, xs, fhs

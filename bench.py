@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph replay")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration under a profiler)")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the batched and polar workloads reported beside the headline")
     ap.add_argument("--fp64", dest="fp64", action="store_true", default=True)
     ap.add_argument("--no-fp64", dest="fp64", action="store_false")
     return ap.parse_args()
@@ -212,6 +214,118 @@ def solve_flops(n):
     return n * (n + 1) / 2 * 20 + n * 20 + n ** 3 / 3 + 6 * n ** 2 + 10 * n
 
 
+def timed_graph(torch, fn, steps, warmup):
+    """Milliseconds per call of fn replayed from a HIP graph (fn captured once)."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fn()
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def class_ms(P, cls, fn, reps):
+    """Average launch time of one kernel class inside fn (HIP events on the plan's stream)."""
+    P.profile_begin(cls)
+    for _ in range(reps):
+        fn()
+    tot, n = P.profile_end()
+    return tot / max(n, 1), n / reps
+
+
+def secondary_batched(steps, warmup):
+    """The batched workload: 256 uneven 1-D problems, 8 right-hand sides, FP32 transforms."""
+    import torch
+    from paper_1811_05335_amd import NfftBatchPlan
+    cfg = W.CONFIGS["c4"]
+    R, m = cfg["rhs"], cfg["m"]
+    Ms, Ns, xs, fhs = W.make_batch(cfg, seed=0)
+    P_, N_ = int(Ms.sum()), int(Ns.sum())
+    G_ = 2 * P_
+    xd = torch.from_numpy(np.concatenate(xs)).cuda()
+    fh = torch.from_numpy(np.concatenate([W.round_to(a, "f32").reshape(-1) for a in fhs])).to(torch.complex64).cuda()
+    B = NfftBatchPlan(Ms, Ns, xd, sigma=cfg["sigma"], m=m, precision="f32", rho=cfg["rho"], max_rhs=R)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.precompute_B()
+    torch.cuda.synchronize()
+    t_pre = (time.perf_counter() - t0) * 1e3
+    f = B.trafo(fh)
+    out = {}
+    out["ms_trafo"] = timed_graph(torch, lambda: B.trafo(fh), steps, warmup)
+    out["ms_adjoint"] = timed_graph(torch, lambda: B.adjoint(f), steps, warmup)
+    out["ms_apply"] = timed_graph(torch, lambda: B.apply(f), steps, warmup)
+    out["ms_apply_adjoint"] = timed_graph(torch, lambda: B.apply_adjoint(fh), steps, warmup)
+    out["ms_precompute_graph"] = timed_graph(torch, lambda: B.precompute_B(), max(3, steps // 4), 1)
+    out["ms_precompute_eager_first"] = t_pre
+    T, c, wB = 2 * m + 1, 8, 8
+    # bytes each call must move at least once (the oversampled grid written and read once)
+    alg = {
+        "trafo": R * (P_ * c + 2 * G_ * c + N_ * c) + N_ * 12,
+        "adjoint": R * (N_ * c + 2 * G_ * c + P_ * c) + N_ * 12,
+        "apply": R * (N_ * c + 2 * G_ * c + P_ * c) + N_ * (T * wB + 4),
+        "apply_adjoint": R * (P_ * c + 2 * G_ * c + N_ * c) + N_ * (T * wB + 4),
+    }
+    for k, b in alg.items():
+        ms = out["ms_" + k]
+        out["hbm_frac_" + k] = b / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+    # the spreading kernel of the modified adjoint: samples and B_opt read once, grid written once
+    ms_sp, _ = class_ms(B, "spread", lambda: B.apply(f), 5)
+    sp_bytes = R * N_ * c + N_ * (T * wB + 8) + R * G_ * c
+    out["spread_apply_kernel"] = dict(ms=ms_sp, bytes=sp_bytes, GBps=sp_bytes / (ms_sp * 1e-3) / 1e9,
+                                      frac=sp_bytes / (ms_sp * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    ms_ad, _ = class_ms(B, "spread", lambda: B.adjoint(f), 5)
+    ad_bytes = R * N_ * c + N_ * 16 + R * G_ * c
+    out["spread_adjoint_kernel"] = dict(ms=ms_ad, bytes=ad_bytes, GBps=ad_bytes / (ms_ad * 1e-3) / 1e9,
+                                        frac=ad_bytes / (ms_ad * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    st = B.status()
+    out["status"] = {k: st[k] for k in ("failed_solves", "oversized", "min_members", "max_members")}
+    out["nodes_per_s_trafo_plus_apply"] = N_ * R / ((out["ms_trafo"] + out["ms_apply"]) * 1e-3)
+    out["config"] = dict(problems=len(Ms), sum_M=P_, sum_N=N_, rhs=R, m=m, sigma=cfg["sigma"], dtype="f32")
+    B.close()
+    return out
+
+
+def secondary_polar(steps, warmup):
+    """The polar trajectory: M = 512 x 512, N = 524288, FP32 transforms, FP64 B optimisation."""
+    import torch
+    from paper_1811_05335_amd import NfftPlan
+    cfg = W.CONFIGS["c3"]
+    x, fh = W.make_problem(cfg, seed=0, rhs=1)
+    xd = torch.from_numpy(x).cuda()
+    fhd = torch.from_numpy(W.round_to(fh, "f32")).to(torch.complex64).cuda()
+    P = NfftPlan(cfg["M"], xd, sigma=cfg["sigma"], m=cfg["m"], precision="f32", rho=cfg["rho"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.precompute_B()
+    torch.cuda.synchronize()
+    out = {"ms_precompute": (time.perf_counter() - t0) * 1e3}
+    f = P.trafo(fhd)
+    out["ms_trafo"] = timed_graph(torch, lambda: P.trafo(fhd), steps, warmup)
+    out["ms_adjoint"] = timed_graph(torch, lambda: P.adjoint(f), steps, warmup)
+    out["ms_apply"] = timed_graph(torch, lambda: P.apply(f), steps, warmup)
+    N, G, Pc, T = cfg["N"], 1024 * 1024, 512 * 512, 81
+    ms_sp, _ = class_ms(P, "spread", lambda: P.apply(f), 5)
+    sp_bytes = N * 8 + N * (T * 8 + 8) + G * 8
+    out["spread_apply_kernel"] = dict(ms=ms_sp, bytes=sp_bytes, GBps=sp_bytes / (ms_sp * 1e-3) / 1e9,
+                                      frac=sp_bytes / (ms_sp * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    st = P.status()
+    out["status"] = {k: st[k] for k in ("failed_solves", "oversized", "min_members", "max_members")}
+    out["nodes_per_s_trafo_plus_apply"] = N / ((out["ms_trafo"] + out["ms_apply"]) * 1e-3)
+    P.close()
+    return out
+
+
 def cpu_baseline(x, fh, gf, rho, m, sigma, M, sample):
     from oracle import bopt, grad, nfft
 
@@ -354,6 +468,13 @@ def main():
         "fp64": res64,
         "fp32_over_fp64": (res64["ms_per_step"] / ms32) if res64 else None,
     }
+    if not a.no_secondary:
+        log("[bench] batched workload (256 uneven 1-D problems, 8 right-hand sides)")
+        line["secondary"] = {"batched_1d": secondary_batched(max(5, a.steps // 2), 2)}
+        log(f"[bench] batched: {line['secondary']['batched_1d']}")
+        log("[bench] polar workload (512 x 512, N = 524288)")
+        line["secondary"]["polar_2d"] = secondary_polar(max(5, a.steps // 2), 2)
+        log(f"[bench] polar: {line['secondary']['polar_2d']}")
     if not a.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline (B optimisation sampled on {a.cpu_sample} grid indices)")
         cb = cpu_baseline(x, fh, gf, rho, m, sigma, M, a.cpu_sample)

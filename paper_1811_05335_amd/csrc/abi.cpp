@@ -119,6 +119,9 @@ struct infft_plan_s {
     void* h01 = nullptr;
     int64_t hrs0 = 0, hrs1 = 0, hrs01 = 0;
     int rchunk = 1;
+    // FFT workgroups a pass should at least have before sub-transforms are packed together
+    // (a batch plan's problems share their launches, so they pack as many as fit)
+    int64_t fft_min_blocks = 1024;
 
     double2* B64 = nullptr;
     float2* B32 = nullptr;
@@ -243,8 +246,8 @@ const void* tw_ptr(const infft_plan_s* P, int64_t n) {
     return P->prec == INFFT_F32 ? (const void*)t->t32 : (const void*)t->t64;
 }
 
-int choose_rows(int64_t n, int64_t nseq, int cap) {
-    int64_t rows = std::max<int64_t>(1, nseq / 1024);
+int choose_rows(int64_t n, int64_t nseq, int cap, int64_t min_blocks) {
+    int64_t rows = std::max<int64_t>(1, nseq / min_blocks);
     rows = std::min<int64_t>(rows, cap / n);
     rows = std::min<int64_t>(rows, 16);
     return (int)std::max<int64_t>(rows, 1);
@@ -269,7 +272,7 @@ int build_schedule(infft_plan_s* P, int nrhs, std::vector<FftStep>& to_grid, std
         s.pass.n = (int)n;
         s.pass.nq = nq;
         s.pass.nseq = nq * nrhs;
-        s.pass.rows = choose_rows(n, s.pass.nseq, cap);
+        s.pass.rows = choose_rows(n, s.pass.nseq, cap, P->fft_min_blocks);
         s.pass.tw = tw_ptr(P, n);
         fill_radices(s.pass);
         return s;
@@ -600,7 +603,7 @@ struct BatchState {
     NodeJob* node_jobs = nullptr;
     int2* node_map = nullptr;
     int node_blocks = 0;
-    int2* cell_map = nullptr;
+    int2* cell_map = nullptr;   // tiles of the 1-D spreading
     int cell_blocks = 0;
     SolveJob* solve_jobs = nullptr;   // [4][nprob]: thread tier, 16 lanes, 32 lanes, 32 lanes under capture
     int2* t1_map = nullptr;
@@ -643,7 +646,9 @@ int batch_build(infft_plan_s* P) {
         for (int i = 0; i < np; ++i) {
             infft_plan_s* sub = B.subs[i];
             std::vector<FftStep> tg, tc;
+            sub->fft_min_blocks = 1;
             int rc = build_schedule(sub, sub->max_rhs, tg, tc);
+            sub->fft_min_blocks = 1024;
             if (rc) return rc;
             const std::vector<FftStep>& steps = dir == 0 ? tg : tc;
             for (size_t k = 0; k < steps.size(); ++k) {
@@ -674,7 +679,7 @@ int batch_build(infft_plan_s* P) {
                 const FftPass& ps = jobs[ji].pass;
                 const int64_t nb = (ps.nseq + ps.rows - 1) / ps.rows;
                 for (int64_t b = 0; b < nb; ++b) map.push_back(make_int2(ji, (int)b));
-                L.shm = std::max(L.shm, (size_t)ps.rows * (ps.n + 1) * cs);
+                L.shm = std::max(L.shm, fft_lds_bytes(ps, cs));
             }
             L.nblocks = (int)((int64_t)map.size() - L.map_off);
             launches.push_back(L);
@@ -696,7 +701,7 @@ int batch_build(infft_plan_s* P) {
         J.grs = sub->g.G;
         J.noff = B.Noff[i];
         for (int64_t b = 0; b < (sub->g.N + 255) / 256; ++b) nmap.push_back(make_int2(i, (int)b));
-        for (int64_t b = 0; b < (sub->g.G + 255) / 256; ++b) cmap.push_back(make_int2(i, (int)b));
+        for (int b = 0; b < spread1d_tiles(sub->g); ++b) cmap.push_back(make_int2(i, b));
         const int nt = (int)((sub->g.G + T1_CELLS - 1) / T1_CELLS);
         B.t1_per_prob[i] = nt;
         for (int b = 0; b < nt; ++b) tmap.push_back(make_int2(i, b));
@@ -1113,15 +1118,17 @@ static int spread_then_coeffs(infft_plan_s* p, const void* f, void* h, int nrhs,
         const int c = std::min(p->max_rhs, nrhs - r0);
         if ((rc = schedule_for(p, c))) return rc;
         const void* fi = cptr(p, f, r0 * g.N);
-        ProfScope ps(p, INFFT_K_SPREAD);
-        if (p->prec == INFFT_F32)
-            launch_spread<float>(g, p->nd, (const float2*)fi, useB ? p->B32 : nullptr, (float2*)p->grid, g.G,
-                                 (float2*)p->h0, (float2*)p->h1, (float2*)p->h01, p->hrs0, p->hrs1, p->hrs01, c,
-                                 p->rchunk, p->stream);
-        else
-            launch_spread<double>(g, p->nd, (const double2*)fi, useB ? p->B64 : nullptr, (double2*)p->grid, g.G,
-                                  (double2*)p->h0, (double2*)p->h1, (double2*)p->h01, p->hrs0, p->hrs1,
-                                  p->hrs01, c, p->rchunk, p->stream);
+        {
+            ProfScope ps(p, INFFT_K_SPREAD);
+            if (p->prec == INFFT_F32)
+                launch_spread<float>(g, p->nd, (const float2*)fi, useB ? p->B32 : nullptr, (float2*)p->grid, g.G,
+                                     (float2*)p->h0, (float2*)p->h1, (float2*)p->h01, p->hrs0, p->hrs1, p->hrs01, c,
+                                     p->rchunk, p->stream);
+            else
+                launch_spread<double>(g, p->nd, (const double2*)fi, useB ? p->B64 : nullptr, (double2*)p->grid, g.G,
+                                      (double2*)p->h0, (double2*)p->h1, (double2*)p->h01, p->hrs0, p->hrs1,
+                                      p->hrs01, c, p->rchunk, p->stream);
+        }
         LAUNCH_CHECK();
         if ((rc = run_fft(p, p->to_coeff, nullptr, (void*)cptr(p, h, r0 * g.P)))) return rc;
     }

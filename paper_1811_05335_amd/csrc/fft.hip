@@ -15,6 +15,10 @@ namespace infft {
 constexpr int FFT_E32 = 16;  // complex elements per thread (LDS buffer = 256 * E elements)
 constexpr int FFT_E64 = 8;
 
+size_t fft_lds_bytes(const FftPass& p, size_t csize) {
+    return ((size_t)p.rows * (p.n + 1) + (size_t)p.n) * csize;
+}
+
 int fft_capacity(bool fp64) { return FFT_THREADS * (fp64 ? FFT_E64 : FFT_E32); }
 
 // ------------------------------------------------------------------ radix-r DFT, sign -1
@@ -176,8 +180,7 @@ __device__ inline void stage(cx<R>* lds, int ld, int rows, int n, int Ns, int si
 }
 
 template <typename R, int E>
-__device__ inline void lds_fft(cx<R>* lds, int ld, int rows, const FftPass& P) {
-    const cx<R>* tw = (const cx<R>*)P.tw;
+__device__ inline void lds_fft(cx<R>* lds, int ld, int rows, const FftPass& P, const cx<R>* tw) {
     int Ns = 1;
     for (int s = 0; s < P.nst; ++s) {
         const int r = P.rad[s];
@@ -278,6 +281,11 @@ __device__ inline void fft_block(const FftPass& P, const FftIO& io, const Geo& g
     if (seq0 >= P.nseq) return;
     const int rows = (int)min((int64_t)P.rows, P.nseq - seq0);
     const int tot = rows * P.n;
+    // the twiddle table follows the data in LDS, loaded together with it (one wait on memory
+    // instead of one per stage)
+    cx<R>* s_tw = lds + (int64_t)P.rows * ld;
+    const cx<R>* gtw = (const cx<R>*)P.tw;
+    for (int i = threadIdx.x; i < P.n; i += FFT_THREADS) s_tw[i] = gtw[i];
     for (int L = threadIdx.x; L < tot; L += FFT_THREADS) {
         int row, i;
         if (P.in_rowfast) { row = L % rows; i = L / rows; }
@@ -287,7 +295,7 @@ __device__ inline void fft_block(const FftPass& P, const FftIO& io, const Geo& g
         lds[row * ld + i] = load_elem<R, LD>(io, P, g, r, q * P.in_qs + (int64_t)i * P.in_is);
     }
     __syncthreads();
-    lds_fft<R, E>(lds, ld, rows, P);
+    lds_fft<R, E>(lds, ld, rows, P, s_tw);
     for (int L = threadIdx.x; L < tot; L += FFT_THREADS) {
         int row, k;
         if (P.out_rowfast) { row = L % rows; k = L / rows; }
@@ -325,7 +333,7 @@ template <typename R>
 void launch_fft_pass(const FftPass& p, const FftIO& io, const Geo& g, int ld, int st, hipStream_t s) {
     constexpr int E = (sizeof(R) == 8) ? FFT_E64 : FFT_E32;
     const unsigned blocks = (unsigned)((p.nseq + p.rows - 1) / p.rows);
-    const size_t shm = (size_t)p.rows * (p.n + 1) * sizeof(cx<R>);
+    const size_t shm = fft_lds_bytes(p, sizeof(cx<R>));
 #define INFFT_FFT_CASE(L_, S_)                                                                  \
     if (ld == L_ && st == S_) {                                                                 \
         hipLaunchKernelGGL((k_fft<R, E, L_, S_>), dim3(blocks), dim3(FFT_THREADS), shm, s, p, io, g); \

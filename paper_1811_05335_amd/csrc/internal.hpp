@@ -253,6 +253,7 @@ void launch_taylor_table_sym(int M, int Ms, const double* D, int power, int qmax
 template <typename R>
 void launch_fft_pass(const FftPass& p, const FftIO& io, const Geo& g, int ld, int st, hipStream_t s);
 int fft_capacity(bool fp64);   // elements of one workgroup's LDS transform buffer
+size_t fft_lds_bytes(const FftPass& p, size_t csize);   // LDS of one pass's workgroup (data + twiddles)
 template <typename R>
 void launch_fft_batched(const FftJob* jobs, const int2* bmap, int nblocks, size_t shm, int ld, int st,
                         const void* user_in, void* user_out, int nrhs, hipStream_t s);
@@ -272,6 +273,7 @@ template <typename R>
 void launch_grad_x(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grid_rs, const cx<R>* gradf,
                    double* gradx, int nrhs, int accumulate, hipStream_t s);
 int spread_rhs_chunk(const Geo& g, bool fp64);
+int spread1d_tiles(const Geo& g);   // workgroups of the tiled 1-D spreading
 // kind NB_*: interpolation reads the grid and writes `out`; gathers read `in` and write the grid;
 // the gradient reads `in` (gradient of f) and writes `gradx`
 template <typename R>

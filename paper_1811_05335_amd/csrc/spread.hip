@@ -17,6 +17,9 @@
 // pass of the following FFT adds in (no global atomics, no zero-fill of the grid).
 #include "internal.hpp"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace infft {
 
 // Window values of the 2m+1 taps of one node.  Taps tau < 2m: Horner in y of the plan's polynomial
@@ -254,54 +257,133 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
     }
 }
 
-// ------------------------------------------------------------------ 1-D spreading as a gather
-// In one dimension the nodes reaching grid cell l are those with stencil base l0 in
-// l-2m .. l (mod M_sigma), a contiguous range (two at the wrap) of the sorted order.  One thread
-// per cell sums them directly: no atomics, no halos, every (node, tap) pair evaluated once.
+// ------------------------------------------------------------------ 1-D spreading, tiled
+// One workgroup per tile of TS consecutive cells.  The nodes reaching the tile (stencil base in
+// c0-2m .. c0+TS-1, a contiguous range of the sorted order, two at the wrap) are staged in LDS in
+// chunks: per node its 2m+1 weights (window taps or B_opt entries, the latter read coalesced
+// from the [tap][node] layout) and its samples for RC right-hand sides (gathered from the
+// caller's order, all loads of a chunk in flight together).  Then thread t sums for cell c0+t
+// over the nodes of cells c0+t-2m .. c0+t, a contiguous range of the staged nodes.
 
-template <typename R, bool USEB>
-__device__ inline void gather1d_item(const Geo& g, const NodesDev& nd, const cx<R>* __restrict__ f,
-                                     const cx<R>* __restrict__ B, cx<R>* __restrict__ grid, int64_t grs, int nrhs,
-                                     int l) {
-    using C = cx<R>;
-    const int Ms = g.Ms[0], w2 = 2 * g.m;
-    if (l >= Ms) return;
-    const R b = (R)g.b;
-    int lo = l - w2;
-    int s0, e0, s1 = 0, e1 = 0;
-    if (lo >= 0) {
-        s0 = nd.start[lo];
-        e0 = nd.start[l + 1];
-    } else {
-        s0 = nd.start[lo + Ms];
-        e0 = nd.start[Ms];
-        s1 = nd.start[0];
-        e1 = nd.start[l + 1];
+constexpr int SP1_TS = 256;     // cells per tile (threads per workgroup)
+constexpr int SP1_CAP = 256;    // staged nodes per chunk
+
+// Position of the first node of tile-relative cell `rel` in the tile's node sequence, and the
+// sorted position of sequence index i.  lo = c0 - 2m may be negative (the window wraps).
+struct Tile1 {
+    int lo, Ms;
+    int sA, nA, sB;   // segment A: cells Ms+lo .. Ms-1 (only when lo < 0); segment B from cell max(lo, 0)
+    __device__ Tile1(const NodesDev& nd, int c0, int m2, int Ms_) : Ms(Ms_) {
+        lo = c0 - m2;
+        if (lo < 0) {
+            sA = nd.start[Ms + lo];
+            nA = nd.start[Ms] - sA;
+            sB = nd.start[0];
+        } else {
+            sA = nA = 0;
+            sB = nd.start[lo];
+        }
     }
-    for (int r = 0; r < nrhs; ++r) {
-        C acc = cmake((R)0, (R)0);
-        for (int seg = 0; seg < 2; ++seg) {
-            const int s = seg ? s1 : s0, e = seg ? e1 : e0;
-            for (int p = s; p < e; ++p) {
-                int tau = l - nd.l0s[p];
-                if (tau < 0) tau += Ms;
-                const C fv = f[(int64_t)r * g.N + nd.perm[p]];
-                if (USEB) {
-                    acc = cadd(acc, cmulc(fv, B[(int64_t)tau * g.N + p]));
+    __device__ int pos(const NodesDev& nd, int rel) const {
+        if (lo < 0 && rel <= -lo) return nd.start[Ms + lo + rel] - sA;
+        return nA + nd.start[lo + rel] - sB;
+    }
+    __device__ int sorted(int i) const { return i < nA ? sA + i : sB + (i - nA); }
+};
+
+template <typename R, int W, bool USEB, int RC>
+__device__ inline void spread1d_tile(const Geo& g, const NodesDev& nd, const cx<R>* __restrict__ f,
+                                     const cx<R>* __restrict__ B, cx<R>* __restrict__ grid, int64_t grs,
+                                     int nrhs, int tile) {
+    using C = cx<R>;
+    using Wt = typename std::conditional<USEB, C, R>::type;
+    __shared__ Wt s_w[SP1_CAP][W];
+    __shared__ C s_f[SP1_CAP][RC];
+    __shared__ int s_rel[SP1_CAP];
+    __shared__ int s_pos[SP1_TS + 2 * MAX_M_CUT + 1];
+    const int Ms = g.Ms[0], m2 = 2 * g.m;
+    const int TS = min(SP1_TS, Ms - m2);          // the window c0-2m .. c0+TS-1 never wraps onto itself
+    const int c0 = tile * TS;
+    if (c0 >= Ms) return;
+    const int hi = min(c0 + TS, Ms);
+    const int nrel = hi - c0 + m2;                  // relative cells 0 .. nrel-1
+    const Tile1 T(nd, c0, m2, Ms);
+    for (int r = threadIdx.x; r <= nrel; r += blockDim.x) s_pos[r] = T.pos(nd, r);
+    __syncthreads();
+    const int ntot = s_pos[nrel];
+    const int t = threadIdx.x;
+    const bool own = t < hi - c0;
+    const int a = own ? s_pos[t] : 0, b = own ? s_pos[t + m2 + 1] : 0;   // this cell's node range
+    for (int r0 = 0; r0 < nrhs; r0 += RC) {
+        const int rc = min(RC, nrhs - r0);
+        C acc[RC];
+#pragma unroll
+        for (int q = 0; q < RC; ++q) acc[q] = cmake((R)0, (R)0);
+        for (int k0 = 0; k0 < ntot; k0 += SP1_CAP) {
+            const int nk = min(SP1_CAP, ntot - k0);
+            __syncthreads();   // the previous chunk is consumed
+            for (int i = threadIdx.x; i < nk; i += blockDim.x) {
+                const int p = T.sorted(k0 + i);
+                int rel = nd.l0s[p] - T.lo;
+                if (rel >= Ms) rel -= Ms;
+                if (rel < 0) rel += Ms;
+                s_rel[i] = rel;
+                const int j = nd.perm[p];
+#pragma unroll
+                for (int q = 0; q < RC; ++q)
+                    if (q < rc) s_f[i][q] = f[(int64_t)(r0 + q) * g.N + j];
+                if constexpr (USEB) {
+#pragma unroll
+                    for (int tau = 0; tau < W; ++tau) s_w[i][tau] = B[(int64_t)tau * g.N + p];
                 } else {
-                    acc = cadd(acc, cscale(fv, window_tap<R>(g, nd.us[p], tau)));
+                    R wv[W];
+                    window_row<R, W>(g, nd.us[p], wv);
+#pragma unroll
+                    for (int tau = 0; tau < W; ++tau) s_w[i][tau] = wv[tau];
+                }
+            }
+            __syncthreads();
+            if (own) {
+                const int ia = max(a - k0, 0), ib = min(b - k0, nk);
+                for (int i = ia; i < ib; ++i) {
+                    const int tau = t + m2 - s_rel[i];
+                    const Wt w = s_w[i][tau];
+#pragma unroll
+                    for (int q = 0; q < RC; ++q) {
+                        if constexpr (USEB) acc[q] = cadd(acc[q], cmulc(s_f[i][q], w));
+                        else acc[q] = cadd(acc[q], cscale(s_f[i][q], w));
+                    }
                 }
             }
         }
-        grid[(int64_t)r * grs + l] = acc;
+        if (own) {
+#pragma unroll
+            for (int q = 0; q < RC; ++q)
+                if (q < rc) grid[(int64_t)(r0 + q) * grs + c0 + t] = acc[q];
+        }
     }
 }
 
-template <typename R, bool USEB>
-__global__ void __launch_bounds__(256) k_gather1d(Geo g, NodesDev nd, const cx<R>* __restrict__ f,
-                                                  const cx<R>* __restrict__ B, cx<R>* __restrict__ grid,
-                                                  int64_t grs, int nrhs) {
-    gather1d_item<R, USEB>(g, nd, f, B, grid, grs, nrhs, blockIdx.x * blockDim.x + threadIdx.x);
+template <typename R, int W, bool USEB, int RC>
+__global__ void __launch_bounds__(SP1_TS) k_spread1d(Geo g, NodesDev nd, const cx<R>* __restrict__ f,
+                                                     const cx<R>* __restrict__ B, cx<R>* __restrict__ grid,
+                                                     int64_t grs, int nrhs) {
+    spread1d_tile<R, W, USEB, RC>(g, nd, f, B, grid, grs, nrhs, blockIdx.x);
+}
+
+template <typename R, int W, bool USEB, int RC>
+__global__ void __launch_bounds__(SP1_TS) k_spread1d_batched(const NodeJob* __restrict__ jobs,
+                                                             const int2* __restrict__ bmap, const cx<R>* f,
+                                                             int nrhs) {
+    const int2 bm = bmap[blockIdx.x];
+    const NodeJob& J = jobs[bm.x];
+    spread1d_tile<R, W, USEB, RC>(J.g, J.nd, f + (int64_t)nrhs * J.noff, (const cx<R>*)J.B, (cx<R>*)J.grid, J.grs,
+                                  nrhs, bm.y);
+}
+
+int spread1d_tiles(const Geo& g) {
+    const int TS = std::min(SP1_TS, g.Ms[0] - 2 * g.m);
+    return (g.Ms[0] + TS - 1) / TS;
 }
 
 // ------------------------------------------------------------------ gradient with respect to x
@@ -396,15 +478,6 @@ __global__ void __launch_bounds__(256) k_interp_B_batched(const NodeJob* __restr
                            nrhs, (int64_t)b.y * 256 + threadIdx.x);
 }
 
-template <typename R, bool USEB>
-__global__ void __launch_bounds__(256) k_gather1d_batched(const NodeJob* __restrict__ jobs,
-                                                          const int2* __restrict__ bmap, const cx<R>* f, int nrhs) {
-    const int2 b = bmap[blockIdx.x];
-    const NodeJob& J = jobs[b.x];
-    gather1d_item<R, USEB>(J.g, J.nd, f + (int64_t)nrhs * J.noff, (const cx<R>*)J.B, (cx<R>*)J.grid, J.grs, nrhs,
-                           b.y * 256 + threadIdx.x);
-}
-
 template <typename R, int W>
 __global__ void __launch_bounds__(256) k_grad_x_batched(const NodeJob* __restrict__ jobs,
                                                         const int2* __restrict__ bmap, const cx<R>* gradf,
@@ -427,6 +500,16 @@ __global__ void __launch_bounds__(256) k_grad_x_batched(const NodeJob* __restric
         case 7: { constexpr int W = 15; __VA_ARGS__; } break; \
         default: { constexpr int W = 17; __VA_ARGS__; } break; \
     }
+
+// right-hand sides per pass of the tiled 1-D spreading (1, 2, 4 or 8), window or B_opt weights
+#define INFFT_SPREAD1D_RC(useb, nrhs, ...)                                              \
+    if (nrhs >= 8) { constexpr int RC = 8; constexpr bool USEB = useb; __VA_ARGS__; }   \
+    else if (nrhs >= 4) { constexpr int RC = 4; constexpr bool USEB = useb; __VA_ARGS__; } \
+    else if (nrhs >= 2) { constexpr int RC = 2; constexpr bool USEB = useb; __VA_ARGS__; } \
+    else { constexpr int RC = 1; constexpr bool USEB = useb; __VA_ARGS__; }
+#define INFFT_SPREAD1D_DISPATCH(nrhs, m, useB, ...)                                  \
+    if (useB) { INFFT_DISPATCH_W(m, INFFT_SPREAD1D_RC(true, nrhs, __VA_ARGS__)) }      \
+    else { INFFT_DISPATCH_W(m, INFFT_SPREAD1D_RC(false, nrhs, __VA_ARGS__)) }
 
 template <typename R>
 void launch_interp(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grs, cx<R>* f, int nrhs,
@@ -468,9 +551,10 @@ void launch_spread(const Geo& g, NodesDev nd, const cx<R>* f, const cx<R>* B, cx
                    cx<R>* h0, cx<R>* h1, cx<R>* h01, int64_t hrs0, int64_t hrs1, int64_t hrs01, int nrhs,
                    int rchunk, hipStream_t s) {
     if (g.d == 1) {
-        const unsigned nb = (unsigned)((g.Ms[0] + 255) / 256);
-        if (B) hipLaunchKernelGGL((k_gather1d<R, true>), dim3(nb), dim3(256), 0, s, g, nd, f, B, grid, grs, nrhs);
-        else hipLaunchKernelGGL((k_gather1d<R, false>), dim3(nb), dim3(256), 0, s, g, nd, f, B, grid, grs, nrhs);
+        const dim3 nb(spread1d_tiles(g)), bl(SP1_TS);
+        INFFT_SPREAD1D_DISPATCH(nrhs, g.m, B != nullptr,
+                                hipLaunchKernelGGL((k_spread1d<R, W, USEB, RC>), nb, bl, 0, s, g, nd, f, B, grid, grs,
+                                                   nrhs))
         return;
     }
     const unsigned blocks = (unsigned)(g.ntile[0] * (g.d == 2 ? g.ntile[1] : 1));
@@ -514,11 +598,13 @@ void launch_node_batched(int kind, int m, const NodeJob* jobs, const int2* bmap,
             INFFT_DISPATCH_W(m, hipLaunchKernelGGL((k_interp_B_batched<R, W>), gr, bl, 0, s, jobs, bmap, out, nrhs))
             break;
         case NB_GATHER:
-            hipLaunchKernelGGL((k_gather1d_batched<R, false>), gr, bl, 0, s, jobs, bmap, in, nrhs);
+        case NB_GATHER_B: {
+            const dim3 sb(SP1_TS);
+            INFFT_SPREAD1D_DISPATCH(nrhs, m, kind == NB_GATHER_B,
+                                    hipLaunchKernelGGL((k_spread1d_batched<R, W, USEB, RC>), gr, sb, 0, s, jobs, bmap,
+                                                       in, nrhs))
             break;
-        case NB_GATHER_B:
-            hipLaunchKernelGGL((k_gather1d_batched<R, true>), gr, bl, 0, s, jobs, bmap, in, nrhs);
-            break;
+        }
         default:
             INFFT_DISPATCH_W(m, hipLaunchKernelGGL((k_grad_x_batched<R, W>), gr, bl, 0, s, jobs, bmap, in, gradx,
                                                    nrhs, accumulate))

@@ -144,6 +144,18 @@ int64_t nfft_plan_device_bytes(infft_plan p);
 /* Releases the plan and its device workspace (waits for the plan's stream first). */
 void nfft_plan_destroy(infft_plan p);
 
+/* Autotuner: times every FFT pass of the plan's two schedules (coefficients -> grid and back)
+ * with 1, 2, 4, 8 and 16 sub-transforms per workgroup (as far as LDS holds them), `reps` launches
+ * each on the plan's buffers, and keeps the fastest for later calls.  Synchronous; allocates a
+ * temporary buffer of max_rhs x prod(M) coefficients for the duration of the call; not under graph
+ * capture (INFFT_ESTATE).  A no-op for batch plans, whose launches pack workgroups as full as LDS
+ * allows. */
+int infft_autotune(infft_plan p, int reps);
+
+/* Sub-transforms per workgroup the autotuner chose for step `step` (0 or 1) of direction `dir`
+ * (0: coefficients -> grid, 1: grid -> coefficients); 0 when not tuned, -1 for bad arguments. */
+int infft_autotune_rows(infft_plan p, int dir, int step);
+
 /* A batch of nprob independent one-dimensional problems of uneven sizes in one plan (the
  * setting of many small inverse NFFTs): problem i has M[i] coefficients (even) and N[i] nodes;
  * sigma, m and the options are shared.  M and N are host arrays; x (device, float64) holds the

@@ -88,6 +88,8 @@ def load() -> C.CDLL:
         "nfft_plan_destroy": (None, [vp]),
         "infft_last_error": (C.c_char_p, []),
         "infft_profile_begin": (i32, [vp, i32]),
+        "infft_autotune": (i32, [vp, i32]),
+        "infft_autotune_rows": (i32, [vp, i32, i32]),
         "infft_profile_end": (i32, [vp, C.POINTER(dbl), C.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():

@@ -122,6 +122,8 @@ struct infft_plan_s {
     // FFT workgroups a pass should at least have before sub-transforms are packed together
     // (a batch plan's problems share their launches, so they pack as many as fit)
     int64_t fft_min_blocks = 1024;
+    // rows per FFT workgroup chosen by infft_autotune, per step of each direction (0: default)
+    int fft_rows[2][2] = {{0, 0}, {0, 0}};
 
     double2* B64 = nullptr;
     float2* B32 = nullptr;
@@ -296,6 +298,8 @@ int build_schedule(infft_plan_s* P, int nrhs, std::vector<FftStep>& to_grid, std
         A.pass.in_qs = 1; A.pass.in_is = n2; A.pass.in_rowfast = 1;
         A.pass.out_qs = 1; A.pass.out_ks = n2; A.pass.out_rowfast = 1; A.pass.out_rs = g.G;
         A.pass.twN = g.Ms[0]; A.pass.twB = (int)P->split_lo.n;
+        A.pass.twShift = 0;
+        while ((1 << A.pass.twShift) < A.pass.twB) ++A.pass.twShift;
         A.pass.twLo = P->prec == INFFT_F32 ? (const void*)P->split_lo.t32 : (const void*)P->split_lo.t64;
         A.pass.twHi = P->prec == INFFT_F32 ? (const void*)P->split_hi.t32 : (const void*)P->split_hi.t64;
         B.pass.in_qs = n2; B.pass.in_is = 1; B.pass.in_rowfast = 0; B.pass.in_rs = g.G;
@@ -328,6 +332,14 @@ int build_schedule(infft_plan_s* P, int nrhs, std::vector<FftStep>& to_grid, std
         to_grid.push_back(a2);
         to_coeff.push_back(b1);
         to_coeff.push_back(b2);
+    }
+    // rows per workgroup found by the autotuner
+    for (int dir = 0; dir < 2; ++dir) {
+        std::vector<FftStep>& v = dir == 0 ? to_grid : to_coeff;
+        for (size_t k = 0; k < v.size() && k < 2; ++k) {
+            const int want = P->fft_rows[dir][k];
+            if (want > 0) v[k].pass.rows = std::max(1, std::min<int>(want, cap / v[k].pass.n));
+        }
     }
     return INFFT_OK;
 }
@@ -981,7 +993,8 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
         } else {
             TRY(ensure_tw(P, n1_split));
             TRY(ensure_tw(P, g.Ms[t] / n1_split));
-            const int64_t Bsz = (int64_t)std::ceil(std::sqrt((double)g.Ms[t]));
+            int64_t Bsz = 1;   // power of two near sqrt(M_sigma): the split of a twiddle exponent is a shift
+            while (Bsz * Bsz < g.Ms[t]) Bsz *= 2;
             P->split_lo.n = Bsz;
             P->split_hi.n = n1_split;  // remembered sub-length of the first pass
             const int64_t nhi = (g.Ms[t] + Bsz - 1) / Bsz;
@@ -1368,6 +1381,85 @@ int64_t nfft_plan_device_bytes(infft_plan p) {
     if (p->batch)
         for (const infft_plan_s* s : p->batch->subs) b += s->bytes;
     return b;
+}
+
+int infft_autotune(infft_plan p, int reps) {
+    if (!p) return fail(INFFT_EINVAL, "null plan");
+    if (p->batch) return INFFT_OK;   // batch launches already pack FFT workgroups as LDS allows
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(p->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone) return fail(INFFT_ESTATE, "infft_autotune cannot run under graph capture");
+    if (reps < 1) reps = 10;
+    const Geo& g = p->g;
+    const int cap = fft_capacity(p->prec == INFFT_F64);
+    const int R = p->max_rhs;
+    void* tmp = nullptr;
+    const size_t tbytes = (size_t)R * (size_t)g.P * p->csize();
+    HIP_TRY(hipMalloc(&tmp, tbytes));
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipFree(tmp);
+        return fail(INFFT_EDEVICE, "hipEventCreate failed");
+    }
+    int rc = INFFT_OK;
+    if (hipMemsetAsync(tmp, 0, tbytes, p->stream) != hipSuccess) rc = fail(INFFT_EDEVICE, "hipMemsetAsync failed");
+    for (int dir = 0; dir < 2 && rc == INFFT_OK; ++dir) {
+        for (int k = 0; k < 2 && rc == INFFT_OK; ++k) {
+            float best = 1e30f;
+            int best_rows = 0;
+            for (int rows = 1; rows <= 16 && rc == INFFT_OK; rows *= 2) {
+                p->fft_rows[dir][k] = rows;
+                if ((rc = build_schedule(p, R, p->to_grid, p->to_coeff))) break;
+                const std::vector<FftStep>& v = dir == 0 ? p->to_grid : p->to_coeff;
+                if ((int)v.size() <= k) break;
+                const FftStep& st = v[k];
+                if (st.pass.rows != rows) continue;   // beyond the LDS capacity for this length
+                if (rows > 1 && rows > st.pass.nseq) break;
+                FftIO io{};
+                io.in = st.in_buf == 0 ? tmp : st.in_buf == 1 ? p->grid : p->grid2;
+                io.out = st.out_buf == 0 ? tmp : st.out_buf == 1 ? p->grid : p->grid2;
+                const bool f32 = p->prec == INFFT_F32;
+                io.D0 = f32 ? (const void*)p->D32[0] : (const void*)p->D64[0];
+                io.D1 = f32 ? (const void*)p->D32[1] : (const void*)p->D64[1];
+                io.h0 = p->h0;
+                io.h1 = p->h1;
+                io.h01 = p->h01;
+                io.halo_rs0 = p->hrs0;
+                io.halo_rs1 = p->hrs1;
+                io.halo_rs01 = p->hrs01;
+                auto launch = [&]() {
+                    if (f32) launch_fft_pass<float>(st.pass, io, g, st.ld, st.st, p->stream);
+                    else launch_fft_pass<double>(st.pass, io, g, st.ld, st.st, p->stream);
+                };
+                launch();   // warm-up
+                (void)hipEventRecord(e0, p->stream);
+                for (int i = 0; i < reps; ++i) launch();
+                (void)hipEventRecord(e1, p->stream);
+                if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    rc = fail(INFFT_EDEVICE, "autotune launch failed");
+                    break;
+                }
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best) {
+                    best = ms;
+                    best_rows = rows;
+                }
+            }
+            p->fft_rows[dir][k] = best_rows;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(p->stream);
+    (void)hipFree(tmp);
+    if (rc == INFFT_OK) rc = build_schedule(p, R, p->to_grid, p->to_coeff);
+    return rc;
+}
+
+int infft_autotune_rows(infft_plan p, int dir, int step) {
+    if (!p || dir < 0 || dir > 1 || step < 0 || step > 1) return -1;
+    return p->fft_rows[dir][step];
 }
 
 int nfft_plan_batched(infft_plan* out, int nprob, const int64_t* M, const int64_t* N, double sigma, int m,

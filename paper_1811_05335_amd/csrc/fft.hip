@@ -253,8 +253,9 @@ __device__ inline void store_elem(const FftIO& io, const FftPass& P, const Geo& 
     if (ST == ST_GRID) {
         ((C*)io.out)[r * P.out_rs + pos] = v;
     } else if (ST == ST_TWIDDLE) {
-        const int64_t e = (q * (int64_t)k) % P.twN;
-        const int64_t hi = e / P.twB, lo = e - hi * P.twB;
+        // q < n2 and k < n1, so e = q k < N: no reduction; twB is a power of two
+        const uint32_t e = (uint32_t)q * (uint32_t)k;
+        const uint32_t hi = e >> P.twShift, lo = e & (uint32_t)(P.twB - 1);
         C w = cmul(((const C*)P.twHi)[hi], ((const C*)P.twLo)[lo]);
         if (P.sign > 0) w.y = -w.y;
         ((C*)io.out)[r * P.out_rs + pos] = cmul(v, w);
@@ -290,9 +291,9 @@ __device__ inline void fft_block(const FftPass& P, const FftIO& io, const Geo& g
         int row, i;
         if (P.in_rowfast) { row = L % rows; i = L / rows; }
         else { row = L / P.n; i = L - row * P.n; }
-        const int64_t s = seq0 + row;
-        const int64_t r = s / P.nq, q = s - r * P.nq;
-        lds[row * ld + i] = load_elem<R, LD>(io, P, g, r, q * P.in_qs + (int64_t)i * P.in_is);
+        const uint32_t s = (uint32_t)(seq0 + row);
+        const uint32_t r = s / (uint32_t)P.nq, q = s - r * (uint32_t)P.nq;
+        lds[row * ld + i] = load_elem<R, LD>(io, P, g, r, (int64_t)q * P.in_qs + (int64_t)i * P.in_is);
     }
     __syncthreads();
     lds_fft<R, E>(lds, ld, rows, P, s_tw);
@@ -300,9 +301,9 @@ __device__ inline void fft_block(const FftPass& P, const FftIO& io, const Geo& g
         int row, k;
         if (P.out_rowfast) { row = L % rows; k = L / rows; }
         else { row = L / P.n; k = L - row * P.n; }
-        const int64_t s = seq0 + row;
-        const int64_t r = s / P.nq, q = s - r * P.nq;
-        store_elem<R, ST>(io, P, g, r, q * P.out_qs + (int64_t)k * P.out_ks, q, k, lds[row * ld + k]);
+        const uint32_t s = (uint32_t)(seq0 + row);
+        const uint32_t r = s / (uint32_t)P.nq, q = s - r * (uint32_t)P.nq;
+        store_elem<R, ST>(io, P, g, r, (int64_t)q * P.out_qs + (int64_t)k * P.out_ks, q, k, lds[row * ld + k]);
     }
 }
 

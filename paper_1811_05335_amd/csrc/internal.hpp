@@ -188,7 +188,8 @@ struct FftPass {
     const void* tw;    // e^{-2 pi i e / n}, e = 0..n-1
     // inter-pass twiddle omega_N^{sign * q * k}, from two tables: e = hi * twB + lo
     int64_t twN;
-    int twB;
+    int twB;           // a power of two, 1 << twShift
+    int twShift;
     const void* twLo;  // e^{-2 pi i lo / N}, lo < twB
     const void* twHi;  // e^{-2 pi i hi twB / N}
 };

@@ -686,7 +686,9 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
             n1 = nd.start[l + 1] - s1;
         }
         const int n = n0 + n1;
-        bool fallback = n > NMAX || (!wrap && !staged);
+        // windows that wrap around the torus, unstaged node ranges and oversized problems go to
+        // the group kernels
+        bool fallback = wrap || n > NMAX || !staged;
         {
             // the cell l-2m reaches l through its tap 2m only for nodes with u at m; the tap
             // 2m of every other node belongs to no problem and is zeroed here
@@ -710,47 +712,13 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
         } else {
             st_min = n;
             st_max = n;
-            const int b0 = s0 - P0;   // first member in the staged node range (non-wrapping windows)
-            // e^{i pi l / sigma}, reduced exactly
+            const int b0 = s0 - P0;   // first member in the staged node range
+            // e^{i pi l / sigma}, reduced exactly; w_i = e^{i pi (l - t_i) / sigma} from the staged
+            // phases e^{-i pi t_i / sigma}
             double sl, cl;
             sincospi((double)(((int64_t)l * g.M[0]) % (2 * (int64_t)Ms)) / (double)Ms, &sl, &cl);
-            int tau[NMAX], pm[NMAX];
-            double t[NMAX], ur[NMAX], ui[NMAX], wr[NMAX], wi[NMAX], zz[NMAX];
-#pragma unroll
-            for (int i = 0; i < NMAX; ++i) {
-                tau[i] = 0;
-                pm[i] = 0;
-                zz[i] = 0.0;
-                t[i] = ur[i] = ui[i] = 0.0;
-                if (i < n) {
-                    int p, l0;
-                    double u;
-                    if (!wrap) {
-                        p = s0 + i;
-                        l0 = s_l0[b0 + i];
-                        u = s_u[b0 + i];
-                    } else {
-                        p = (i < n0) ? s0 + i : s1 + (i - n0);
-                        l0 = nd.l0s[p];
-                        u = nd.us[p];
-                    }
-                    pm[i] = p;
-                    int tt = l - l0;
-                    if (tt < 0) tt += Ms;
-                    tau[i] = tt;
-                    zz[i] = (double)tt - u;
-                    t[i] = tay_eval_r(s_tabk, kt.qK, zz[i]);
-                    if (!wrap) {
-                        const double2 ph = s_phi[b0 + i];
-                        ur[i] = cl * ph.x - sl * ph.y;
-                        ui[i] = cl * ph.y + sl * ph.x;
-                    } else {
-                        sincospi(zz[i] * kt.inv_sigma, &ui[i], &ur[i]);
-                    }
-                }
-                wr[i] = ur[i];
-                wi[i] = ui[i];
-            }
+            // ---- A0 = M_sigma Qs(z_j - z_i) + lambda I from the band, Cholesky A0 = L L^T; the
+            // diagonal keeps 1 / L[k][k]
             double A[NMAX * (NMAX + 1) / 2];
 #pragma unroll
             for (int i = 0; i < NMAX; ++i) {
@@ -758,8 +726,7 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
                 for (int j = 0; j <= i; ++j) {
                     double v = (i == j) ? 1.0 : 0.0;
                     if (i < n) {
-                        if (!wrap) v = s_band[(b0 + j) * NMAX + (i - j)];
-                        else v = kt.scaleG * tay_eval_r(s_tabq, kt.qQ, zz[j] - zz[i]);
+                        v = s_band[(b0 + j) * NMAX + (i - j)];
                         if (i == j) v += kt.lam;
                     }
                     A[i * (i + 1) / 2 + j] = v;
@@ -770,8 +737,8 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
             for (int k = 0; k < NMAX; ++k) {
                 const double piv = A[k * (k + 1) / 2 + k];
                 ok = ok && piv > 0.0;
-                const double sq = sqrt(piv > 0.0 ? piv : 1.0), inv = 1.0 / sq;
-                A[k * (k + 1) / 2 + k] = sq;
+                const double inv = 1.0 / sqrt(piv > 0.0 ? piv : 1.0);
+                A[k * (k + 1) / 2 + k] = inv;
 #pragma unroll
                 for (int i = k + 1; i < NMAX; ++i) A[i * (i + 1) / 2 + k] *= inv;
 #pragma unroll
@@ -785,48 +752,81 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
             if (!ok) {
                 ++st_fail;
             } else {
+                // two real right-hand sides x, y through L L^T
+                auto solve2 = [&](double (&x)[NMAX], double (&y)[NMAX]) {
 #pragma unroll
-                for (int k = 0; k < NMAX; ++k) {
-                    const double iv = 1.0 / A[k * (k + 1) / 2 + k];
-                    t[k] *= iv;
-                    ur[k] *= iv;
-                    ui[k] *= iv;
+                    for (int k = 0; k < NMAX; ++k) {
+                        const double iv = A[k * (k + 1) / 2 + k];
+                        x[k] *= iv;
+                        y[k] *= iv;
 #pragma unroll
-                    for (int i = k + 1; i < NMAX; ++i) {
-                        const double lik = A[i * (i + 1) / 2 + k];
-                        t[i] = fma(-lik, t[k], t[i]);
-                        ur[i] = fma(-lik, ur[k], ur[i]);
-                        ui[i] = fma(-lik, ui[k], ui[i]);
+                        for (int i = k + 1; i < NMAX; ++i) {
+                            const double lik = A[i * (i + 1) / 2 + k];
+                            x[i] = fma(-lik, x[k], x[i]);
+                            y[i] = fma(-lik, y[k], y[i]);
+                        }
                     }
-                }
 #pragma unroll
-                for (int k = NMAX - 1; k >= 0; --k) {
-                    const double iv = 1.0 / A[k * (k + 1) / 2 + k];
-                    t[k] *= iv;
-                    ur[k] *= iv;
-                    ui[k] *= iv;
+                    for (int k = NMAX - 1; k >= 0; --k) {
+                        const double iv = A[k * (k + 1) / 2 + k];
+                        x[k] *= iv;
+                        y[k] *= iv;
 #pragma unroll
-                    for (int i = 0; i < k; ++i) {
-                        const double lki = A[k * (k + 1) / 2 + i];
-                        t[i] = fma(-lki, t[k], t[i]);
-                        ur[i] = fma(-lki, ur[k], ur[i]);
-                        ui[i] = fma(-lki, ui[k], ui[i]);
+                        for (int i = 0; i < k; ++i) {
+                            const double lki = A[k * (k + 1) / 2 + i];
+                            x[i] = fma(-lki, x[k], x[i]);
+                            y[i] = fma(-lki, y[k], y[i]);
+                        }
                     }
+                };
+                auto phase = [&](int i, double& wr, double& wi) {
+                    const double2 ph = s_phi[b0 + i];
+                    wr = cl * ph.x - sl * ph.y;
+                    wi = cl * ph.y + sl * ph.x;
+                };
+                auto ks = [&](int i) {
+                    return tay_eval_r(s_tabk, kt.qK, (double)(l - s_l0[b0 + i]) - s_u[b0 + i]);
+                };
+                // ---- u = A0^{-1} w
+                double xr[NMAX], xi[NMAX];
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    xr[i] = xi[i] = 0.0;
+                    if (i < n) phase(i, xr[i], xi[i]);
                 }
+                solve2(xr, xi);
+                // ---- s = w^* u (real), u^* Ks = w^* A0^{-1} Ks
                 double sdot = 0.0, wtr = 0.0, wti = 0.0;
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
-                    sdot = fma(wr[i], ur[i], fma(wi[i], ui[i], sdot));
-                    wtr = fma(wr[i], t[i], wtr);
-                    wti = fma(-wi[i], t[i], wti);
+                    if (i < n) {
+                        double wr, wi;
+                        phase(i, wr, wi);
+                        const double k_i = ks(i);
+                        sdot = fma(wr, xr[i], fma(wi, xi[i], sdot));
+                        wtr = fma(xr[i], k_i, wtr);
+                        wti = fma(-xi[i], k_i, wti);
+                    }
                 }
                 const double den = 1.0 + c1 * sdot;
                 const double cr = (kt.dM - c1 * wtr) / den, ci = (-c1 * wti) / den;
+                // ---- b = A0^{-1} (Ks + c' w), c' = (d - c u^* Ks) / (1 + c s)
+#pragma unroll
+                for (int i = 0; i < NMAX; ++i) {
+                    xr[i] = xi[i] = 0.0;
+                    if (i < n) {
+                        double wr, wi;
+                        phase(i, wr, wi);
+                        xr[i] = ks(i) + cr * wr - ci * wi;
+                        xi[i] = cr * wi + ci * wr;
+                    }
+                }
+                solve2(xr, xi);
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
                     if (i < n) {
-                        const double2 bb = make_double2(t[i] + ur[i] * cr - ui[i] * ci, ur[i] * ci + ui[i] * cr);
-                        const int64_t idx = (int64_t)tau[i] * g.N + pm[i];
+                        const double2 bb = make_double2(xr[i], xi[i]);
+                        const int64_t idx = (int64_t)(l - s_l0[b0 + i]) * g.N + (s0 + i);
                         a.B64[idx] = bb;
                         if (a.B32) a.B32[idx] = make_float2((float)bb.x, (float)bb.y);
                     }

@@ -166,6 +166,15 @@ class NfftPlan:
         check(load().infft_profile_end(self._h, C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
+    def autotune(self, reps: int = 10) -> dict:
+        """Times the FFT passes with 1..16 sub-transforms per workgroup and keeps the fastest;
+        returns the choice per direction and step."""
+        self._sync_stream()
+        check(load().infft_autotune(self._h, int(reps)))
+        lib = load()
+        return {f"{'to_grid' if d == 0 else 'to_coeff'}_{k}": lib.infft_autotune_rows(self._h, d, k)
+                for d in (0, 1) for k in (0, 1)}
+
     def device_bytes(self) -> int:
         return int(load().nfft_plan_device_bytes(self._h))
 

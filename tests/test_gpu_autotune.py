@@ -1,0 +1,31 @@
+"""The autotuner changes only how FFT sub-transforms are grouped into workgroups: results before
+and after tuning agree to rounding, in one dimension (one pass and two passes) and two."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+from gpu_util import dev, host, nodes_dev, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("M,d,precision", [((5000,), 1, "f32"), ((5000,), 1, "f64"), ((96,), 1, "f64"),
+                                           ((48, 40), 2, "f32")])
+def test_autotuned_plan_matches_untuned(M, d, precision):
+    from paper_1811_05335_amd import NfftPlan
+    g = W.rng(41)
+    N = 3 * int(np.prod(M)) // 2
+    x = W.uniform_nodes(g, N, d)
+    fh = dev(W.complex_normal(g, (2,) + M), precision)
+    f = dev(W.complex_normal(g, (2, N)), precision)
+    P = NfftPlan(M, nodes_dev(x), sigma=2.0, m=4, precision=precision, rho=1e-8, max_rhs=2)
+    before = [host(P.trafo(fh)), host(P.adjoint(f))]
+    rows = P.autotune(reps=3)
+    assert all(v in (0, 1, 2, 4, 8, 16) for v in rows.values())
+    assert rows["to_grid_0"] > 0 and rows["to_coeff_0"] > 0
+    after = [host(P.trafo(fh)), host(P.adjoint(f))]
+    tol = 1e-14 if precision == "f64" else 1e-6
+    for a, b in zip(after, before):
+        assert rel(a, b) <= tol
+    P.close()

@@ -118,6 +118,9 @@ struct infft_plan_s {
     void* h1 = nullptr;
     void* h01 = nullptr;
     int64_t hrs0 = 0, hrs1 = 0, hrs01 = 0;
+    SpreadWork spwork{};            // 2-D: work list of the tiled spreading (rebuilt by set_nodes)
+    int* sp_offs = nullptr;
+    int* sp_bsum = nullptr;
     int rchunk = 1;
     // FFT workgroups a pass should at least have before sub-transforms are packed together
     // (a batch plan's problems share their launches, so they pack as many as fit)
@@ -438,6 +441,7 @@ int set_nodes_impl(infft_plan_s* P, const double* x) {
     launch_scatter_nodes(g, P->nd, P->fill, s);
     launch_fill_i32(P->lcount, 4, 0, s);
     launch_cell_sort(g, P->nd, P->lists, P->lcount + 2, s);
+    if (g.d == 2) launch_spread_worklist(g, P->nd, P->spwork, P->sp_offs, P->sp_bsum, s);
     LAUNCH_CHECK();
     P->bopt_ready = false;
     return INFFT_OK;
@@ -1046,6 +1050,16 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
     P->h1 = tmp;
     TRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs01, 1) * P->max_rhs));
     P->h01 = tmp;
+    if (d == 2) {
+        const int nt = g.ntile[0] * g.ntile[1];
+        P->spwork.chunk = 1024;
+        P->spwork.cap = (int)(nt + N / P->spwork.chunk + 1);
+        TRY(P->alloc(&P->spwork.nchunk, nt));
+        TRY(P->alloc(&P->spwork.items, P->spwork.cap));
+        TRY(P->alloc(&P->spwork.total, 1));
+        TRY(P->alloc(&P->sp_offs, nt));
+        TRY(P->alloc(&P->sp_bsum, scan_blocksum_len(nt)));
+    }
     P->rchunk = spread_rhs_chunk(g, P->prec == INFFT_F64);
     TRY(P->alloc(&P->B64, (int64_t)T * N));
     if (P->prec == INFFT_F32) TRY(P->alloc(&P->B32, (int64_t)T * N));
@@ -1136,11 +1150,11 @@ static int spread_then_coeffs(infft_plan_s* p, const void* f, void* h, int nrhs,
             if (p->prec == INFFT_F32)
                 launch_spread<float>(g, p->nd, (const float2*)fi, useB ? p->B32 : nullptr, (float2*)p->grid, g.G,
                                      (float2*)p->h0, (float2*)p->h1, (float2*)p->h01, p->hrs0, p->hrs1, p->hrs01, c,
-                                     p->rchunk, p->stream);
+                                     p->rchunk, p->spwork, p->stream);
             else
                 launch_spread<double>(g, p->nd, (const double2*)fi, useB ? p->B64 : nullptr, (double2*)p->grid, g.G,
                                       (double2*)p->h0, (double2*)p->h1, (double2*)p->h01, p->hrs0, p->hrs1,
-                                      p->hrs01, c, p->rchunk, p->stream);
+                                      p->hrs01, c, p->rchunk, p->spwork, p->stream);
         }
         LAUNCH_CHECK();
         if ((rc = run_fft(p, p->to_coeff, nullptr, (void*)cptr(p, h, r0 * g.P)))) return rc;

@@ -263,10 +263,20 @@ void launch_fft_batched(const FftJob* jobs, const int2* bmap, int nblocks, size_
 template <typename R>
 void launch_interp(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grid_rs, cx<R>* f,
                    int nrhs, hipStream_t s);
+// Work list of the 2-D tiled spreading (built at node preprocessing): items (tile, chunk) with at
+// most `chunk` nodes each; tiles split into several chunks flush with atomics.
+struct SpreadWork {
+    int chunk;       // nodes per work item
+    int cap;         // capacity of items (launch size; items beyond *total exit)
+    int* nchunk;     // [ntiles]
+    int2* items;     // [cap]
+    int* total;      // number of items
+};
+void launch_spread_worklist(const Geo& g, NodesDev nd, SpreadWork wk, int* offs, int* bsum, hipStream_t s);
 template <typename R>
 void launch_spread(const Geo& g, NodesDev nd, const cx<R>* f, const cx<R>* B, cx<R>* grid,
                    int64_t grid_rs, cx<R>* h0, cx<R>* h1, cx<R>* h01, int64_t hrs0, int64_t hrs1,
-                   int64_t hrs01, int nrhs, int rchunk, hipStream_t s);
+                   int64_t hrs01, int nrhs, int rchunk, SpreadWork wk, hipStream_t s);
 template <typename R>
 void launch_interp_B(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grid_rs, const cx<R>* B,
                      cx<R>* f, int nrhs, hipStream_t s);

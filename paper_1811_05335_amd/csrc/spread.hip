@@ -173,17 +173,22 @@ __global__ void __launch_bounds__(256) k_interp_B(Geo g, NodesDev nd, const cx<R
 
 template <typename R> __device__ inline void lds_add(R* p, R v) { atomicAdd(p, v); }
 
+template <typename T> __device__ inline void gadd(T* p, T v) { unsafeAtomicAdd(p, v); }
+
 template <typename R, int D, int W, bool USEB>
 __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>* __restrict__ f,
                                                 const cx<R>* __restrict__ B, cx<R>* __restrict__ grid,
                                                 int64_t grs, cx<R>* __restrict__ h0, cx<R>* __restrict__ h1,
                                                 cx<R>* __restrict__ h01, int64_t hrs0, int64_t hrs1,
-                                                int64_t hrs01, int nrhs, int rchunk) {
+                                                int64_t hrs01, int nrhs, int rchunk, SpreadWork wk) {
     using C = cx<R>;
     extern __shared__ char smem_raw[];
     R* acc = (R*)smem_raw;  // [rc][E0][E1][2]
     const int w2 = 2 * g.m;
-    const int tile = blockIdx.x;
+    if ((int)blockIdx.x >= *wk.total) return;
+    const int2 item = wk.items[blockIdx.x];
+    const int tile = item.x;
+    const int nch = wk.nchunk[tile];   // chunks of the tile: more than one -> atomic flush
     const int t0 = (D == 2) ? tile / g.ntile[1] : tile;
     const int t1 = (D == 2) ? tile - t0 * g.ntile[1] : 0;
     const int TS0 = g.TS[0], TS1 = (D == 2) ? g.TS[1] : 1;
@@ -191,45 +196,73 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
     const int cells = E0 * E1;
     const int base0 = t0 * TS0, base1 = t1 * TS1;
     const int64_t kbeg = (int64_t)tile * TS0 * TS1;
-    const int pbeg = nd.start[kbeg], pend = nd.start[kbeg + (int64_t)TS0 * TS1];
+    const int tbeg = nd.start[kbeg], tend = nd.start[kbeg + (int64_t)TS0 * TS1];
+    const int pbeg = min(tbeg + item.y * wk.chunk, tend), pend = min(pbeg + wk.chunk, tend);
     const R b = (R)g.b;
 
     for (int r0 = 0; r0 < nrhs; r0 += rchunk) {
         const int rc = min(rchunk, nrhs - r0);
         for (int c = threadIdx.x; c < 2 * rc * cells; c += blockDim.x) acc[c] = (R)0;
         __syncthreads();
-        for (int p = pbeg + threadIdx.x; p < pend; p += blockDim.x) {
-            const int j = nd.perm[p];
-            const int a0 = nd.l0s[(int64_t)p * D] - base0;
-            const int a1 = (D == 2) ? nd.l0s[(int64_t)p * D + 1] - base1 : 0;
+        // Nodes are sorted by cell, so the lanes of a wave holding nodes of one cell form
+        // contiguous segments whose taps hit the same LDS words.  When a wave has few segments
+        // (a dense spot: hundreds of nodes per cell) each tap's contributions are first summed
+        // along the segment with shuffles and only the segment's first lane adds them to LDS;
+        // otherwise every lane adds its own.
+        const int lane = threadIdx.x & 63;
+        for (int base = pbeg; base < pend; base += blockDim.x) {
+            const int p = base + threadIdx.x;
+            const bool valid = p < pend;
+            int j = 0, a0 = 0, a1 = 0;
             R w0[W], w1[W];
-            if (!USEB) {
-                window_row<R, W>(g, nd.us[(int64_t)p * D], w0);
-                if (D == 2) window_row<R, W>(g, nd.us[(int64_t)p * D + 1], w1);
+#pragma unroll
+            for (int t = 0; t < W; ++t) w0[t] = w1[t] = (R)0;
+            if (valid) {
+                j = nd.perm[p];
+                a0 = nd.l0s[(int64_t)p * D] - base0;
+                a1 = (D == 2) ? nd.l0s[(int64_t)p * D + 1] - base1 : 0;
+                if (!USEB) {
+                    window_row<R, W>(g, nd.us[(int64_t)p * D], w0);
+                    if (D == 2) window_row<R, W>(g, nd.us[(int64_t)p * D + 1], w1);
+                }
             }
+            const int cid = valid ? a0 * E1 + a1 : -1 - lane;
+            const int prev = __shfl_up(cid, 1, 64);
+            const bool head = lane == 0 || prev != cid;
+            const uint64_t hm = __ballot(head);
+            const bool reduce = __popcll(hm) <= 16;   // the same in every lane of the wave
+            const uint64_t above = hm & ~((2ull << lane) - 1ull);
+            const int seg_end = above ? __ffsll((unsigned long long)above) - 1 : 64;
             for (int rr = 0; rr < rc; ++rr) {
-                const C fv = f[(int64_t)(r0 + rr) * g.N + j];
+                const C fv = valid ? f[(int64_t)(r0 + rr) * g.N + j] : cmake((R)0, (R)0);
                 R* a = acc + (int64_t)rr * cells * 2;
-                if (D == 1) {
 #pragma unroll
-                    for (int t = 0; t < W; ++t) {
-                        C v;
-                        if (USEB) v = cmulc(fv, B[(int64_t)t * g.N + p]);
-                        else v = cscale(fv, w0[t]);
-                        lds_add(&a[2 * (a0 + t)], v.x);
-                        lds_add(&a[2 * (a0 + t) + 1], v.y);
-                    }
-                } else {
+                for (int s0 = 0; s0 < W; ++s0) {
+                    C fs;
+                    if (!USEB) fs = cscale(fv, w0[s0]);
 #pragma unroll
-                    for (int s0 = 0; s0 < W; ++s0) {
-                        C fs;
-                        if (!USEB) fs = cscale(fv, w0[s0]);
+                    for (int s1 = 0; s1 < W; ++s1) {
+                        C v = cmake((R)0, (R)0);
+                        if (USEB) {
+                            if (valid) v = cmulc(fv, B[(int64_t)(s0 * W + s1) * g.N + p]);
+                        } else {
+                            v = cscale(fs, w1[s1]);
+                        }
+                        const int cidx = (a0 + s0) * E1 + (a1 + s1);
+                        if (reduce) {
 #pragma unroll
-                        for (int s1 = 0; s1 < W; ++s1) {
-                            C v;
-                            if (USEB) v = cmulc(fv, B[(int64_t)(s0 * W + s1) * g.N + p]);
-                            else v = cscale(fs, w1[s1]);
-                            const int cidx = (a0 + s0) * E1 + (a1 + s1);
+                            for (int o = 1; o < 64; o <<= 1) {
+                                const R x2 = __shfl_down(v.x, o, 64), y2 = __shfl_down(v.y, o, 64);
+                                if (lane + o < seg_end) {
+                                    v.x += x2;
+                                    v.y += y2;
+                                }
+                            }
+                            if (head && valid) {
+                                lds_add(&a[2 * cidx], v.x);
+                                lds_add(&a[2 * cidx + 1], v.y);
+                            }
+                        } else if (valid) {
                             lds_add(&a[2 * cidx], v.x);
                             lds_add(&a[2 * cidx + 1], v.y);
                         }
@@ -243,17 +276,75 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
             const int e0 = cc / E1, e1 = cc - e0 * E1;
             const C v = cmake(acc[2 * c], acc[2 * c + 1]);
             const int64_t r = r0 + rr;
+            C* dst;
             if (e0 < TS0 && e1 < TS1) {
-                grid[r * grs + (int64_t)(base0 + e0) * g.Ms[1] + (base1 + e1)] = v;
+                dst = &grid[r * grs + (int64_t)(base0 + e0) * g.Ms[1] + (base1 + e1)];
             } else if (e0 >= TS0 && e1 < TS1) {
-                h0[r * hrs0 + ((int64_t)tile * w2 + (e0 - TS0)) * TS1 + e1] = v;
+                dst = &h0[r * hrs0 + ((int64_t)tile * w2 + (e0 - TS0)) * TS1 + e1];
             } else if (e0 < TS0) {
-                h1[r * hrs1 + ((int64_t)tile * TS0 + e0) * w2 + (e1 - TS1)] = v;
+                dst = &h1[r * hrs1 + ((int64_t)tile * TS0 + e0) * w2 + (e1 - TS1)];
             } else {
-                h01[r * hrs01 + ((int64_t)tile * w2 + (e0 - TS0)) * w2 + (e1 - TS1)] = v;
+                dst = &h01[r * hrs01 + ((int64_t)tile * w2 + (e0 - TS0)) * w2 + (e1 - TS1)];
+            }
+            if (nch == 1) {
+                *dst = v;
+            } else {
+                gadd(&dst->x, v.x);
+                gadd(&dst->y, v.y);
             }
         }
         __syncthreads();
+    }
+}
+
+// Work list of the tiled spreading: a tile with more nodes than one chunk (the dense centre of a
+// polar or spiral trajectory) is split into chunks, each a workgroup, whose partial tiles are added
+// with global atomics into the tile's (zeroed) cells and halo strips.
+__global__ void k_spread_chunks(Geo g, NodesDev nd, int chunk, int* __restrict__ nchunk) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ntiles = g.ntile[0] * g.ntile[1];
+    if (t >= ntiles) return;
+    const int64_t per = (int64_t)g.TS[0] * g.TS[1];
+    const int cnt = nd.start[(t + 1) * per] - nd.start[t * per];
+    nchunk[t] = max(1, (cnt + chunk - 1) / chunk);
+}
+
+__global__ void k_spread_items(Geo g, const int* __restrict__ nchunk, const int* __restrict__ offs,
+                               int2* __restrict__ items, int* __restrict__ total) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ntiles = g.ntile[0] * g.ntile[1];
+    if (t >= ntiles) return;
+    for (int c = 0; c < nchunk[t]; ++c) items[offs[t] + c] = make_int2(t, c);
+    if (t == ntiles - 1) *total = offs[t] + nchunk[t];
+}
+
+void launch_spread_worklist(const Geo& g, NodesDev nd, SpreadWork wk, int* offs, int* bsum, hipStream_t s) {
+    const int ntiles = g.ntile[0] * g.ntile[1];
+    const unsigned nb = (unsigned)((ntiles + 255) / 256);
+    hipLaunchKernelGGL(k_spread_chunks, dim3(nb), dim3(256), 0, s, g, nd, wk.chunk, wk.nchunk);
+    launch_exclusive_scan(wk.nchunk, offs, ntiles, bsum, s);
+    hipLaunchKernelGGL(k_spread_items, dim3(nb), dim3(256), 0, s, g, (const int*)wk.nchunk, (const int*)offs,
+                       wk.items, wk.total);
+}
+
+// Zeroes the cells and halo strips of split tiles for all right-hand sides.
+template <typename R>
+__global__ void __launch_bounds__(256) k_spread_zero_split(Geo g, SpreadWork wk, cx<R>* grid, int64_t grs,
+                                                           cx<R>* h0, cx<R>* h1, cx<R>* h01, int64_t hrs0,
+                                                           int64_t hrs1, int64_t hrs01, int nrhs) {
+    const int tile = blockIdx.x;
+    if (wk.nchunk[tile] == 1) return;
+    const int w2 = 2 * g.m, TS0 = g.TS[0], TS1 = g.TS[1];
+    const int t0 = tile / g.ntile[1], t1 = tile - t0 * g.ntile[1];
+    const int E0 = TS0 + w2, E1 = TS1 + w2, cells = E0 * E1;
+    const cx<R> z = cmake((R)0, (R)0);
+    for (int c = threadIdx.x; c < nrhs * cells; c += blockDim.x) {
+        const int r = c / cells, cc = c - r * cells;
+        const int e0 = cc / E1, e1 = cc - e0 * E1;
+        if (e0 < TS0 && e1 < TS1) grid[r * grs + (int64_t)(t0 * TS0 + e0) * g.Ms[1] + (t1 * TS1 + e1)] = z;
+        else if (e0 >= TS0 && e1 < TS1) h0[r * hrs0 + ((int64_t)tile * w2 + (e0 - TS0)) * TS1 + e1] = z;
+        else if (e0 < TS0) h1[r * hrs1 + ((int64_t)tile * TS0 + e0) * w2 + (e1 - TS1)] = z;
+        else h01[r * hrs01 + ((int64_t)tile * w2 + (e0 - TS0)) * w2 + (e1 - TS1)] = z;
     }
 }
 
@@ -549,7 +640,7 @@ int spread_rhs_chunk(const Geo& g, bool fp64) {
 template <typename R>
 void launch_spread(const Geo& g, NodesDev nd, const cx<R>* f, const cx<R>* B, cx<R>* grid, int64_t grs,
                    cx<R>* h0, cx<R>* h1, cx<R>* h01, int64_t hrs0, int64_t hrs1, int64_t hrs01, int nrhs,
-                   int rchunk, hipStream_t s) {
+                   int rchunk, SpreadWork wk, hipStream_t s) {
     if (g.d == 1) {
         const dim3 nb(spread1d_tiles(g)), bl(SP1_TS);
         INFFT_SPREAD1D_DISPATCH(nrhs, g.m, B != nullptr,
@@ -557,18 +648,17 @@ void launch_spread(const Geo& g, NodesDev nd, const cx<R>* f, const cx<R>* B, cx
                                                    nrhs))
         return;
     }
-    const unsigned blocks = (unsigned)(g.ntile[0] * (g.d == 2 ? g.ntile[1] : 1));
+    const unsigned ntiles = (unsigned)(g.ntile[0] * g.ntile[1]);
+    hipLaunchKernelGGL(k_spread_zero_split<R>, dim3(ntiles), dim3(256), 0, s, g, wk, grid, grs, h0, h1, h01, hrs0,
+                       hrs1, hrs01, nrhs);
+    const unsigned blocks = (unsigned)wk.cap;
     const int64_t cells = (int64_t)(g.TS[0] + 2 * g.m) * (g.d == 2 ? g.TS[1] + 2 * g.m : 1);
     const int rc = min(rchunk, nrhs);
     const size_t shm = (size_t)rc * cells * sizeof(cx<R>);
 #define INFFT_SPREAD(D_, USEB_)                                                                   \
     INFFT_DISPATCH_W(g.m, hipLaunchKernelGGL((k_spread<R, D_, W, USEB_>), dim3(blocks), dim3(256), shm, s, \
-                                             g, nd, f, B, grid, grs, h0, h1, h01, hrs0, hrs1, hrs01, nrhs, rc))
-    if (g.d == 1) {
-        if (B) { INFFT_SPREAD(1, true) } else { INFFT_SPREAD(1, false) }
-    } else {
-        if (B) { INFFT_SPREAD(2, true) } else { INFFT_SPREAD(2, false) }
-    }
+                                             g, nd, f, B, grid, grs, h0, h1, h01, hrs0, hrs1, hrs01, nrhs, rc, wk))
+    if (B) { INFFT_SPREAD(2, true) } else { INFFT_SPREAD(2, false) }
 #undef INFFT_SPREAD
 }
 
@@ -617,7 +707,8 @@ void launch_node_batched(int kind, int m, const NodeJob* jobs, const int2* bmap,
     template void launch_interp_B<R>(const Geo&, NodesDev, const cx<R>*, int64_t, const cx<R>*, cx<R>*, int, \
                                      hipStream_t);                                                     \
     template void launch_spread<R>(const Geo&, NodesDev, const cx<R>*, const cx<R>*, cx<R>*, int64_t, cx<R>*, \
-                                   cx<R>*, cx<R>*, int64_t, int64_t, int64_t, int, int, hipStream_t);  \
+                                   cx<R>*, cx<R>*, int64_t, int64_t, int64_t, int, int, SpreadWork,    \
+                                   hipStream_t);                                                       \
     template void launch_grad_x<R>(const Geo&, NodesDev, const cx<R>*, int64_t, const cx<R>*, double*, int, \
                                    int, hipStream_t);                                                  \
     template void launch_node_batched<R>(int, int, const NodeJob*, const int2*, int, const cx<R>*, cx<R>*,    \

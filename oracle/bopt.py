@@ -84,30 +84,31 @@ def grid_multi_index(l: int, p: Params):
 
 # ---------------------------------------------------------------- kernels K, Q (direct sums)
 
-def kernel_K_1d(y, Mt: int, Ms_t: int, m: int, b: float) -> np.ndarray:
-    """(3.15) K(y) = (1/M_sigma) sum_{k=-M/2}^{M/2-1} e^{2 pi i k y} / w_hat(-k)."""
-    k = centred(Mt)
-    coef = 1.0 / (Ms_t * kb.window_hat(-k, Ms_t, m, b))
+def kernel_K_1d(y, p: Params, t: int) -> np.ndarray:
+    """(3.15) K(y) = (1/M_sigma) sum_{k=-M/2}^{M/2-1} e^{2 pi i k y} / w_hat(-k) in dimension t,
+    i.e. sum_k D_k e^{2 pi i k y} with the inverse's D (w_hat is even)."""
+    k = centred(p.M[t])
+    coef = p.deconv_inv(t)
     y = np.asarray(y, dtype=np.float64).ravel()
     y = y - np.floor(y + 0.5)
     return phase_matrix(y, k, +1) @ coef
 
 
-def kernel_Q_1d(y, Mt: int, Ms_t: int, m: int, b: float) -> np.ndarray:
-    """Q(y) = sum_k e^{2 pi i k y} / (M_sigma w_hat(k))^2."""
-    k = centred(Mt)
-    coef = 1.0 / (Ms_t * kb.window_hat(k, Ms_t, m, b)) ** 2
+def kernel_Q_1d(y, p: Params, t: int) -> np.ndarray:
+    """Q(y) = sum_k D_k^2 e^{2 pi i k y} in dimension t."""
+    k = centred(p.M[t])
+    coef = p.deconv_inv(t) ** 2
     y = np.asarray(y, dtype=np.float64).ravel()
     y = y - np.floor(y + 0.5)
     return phase_matrix(y, k, +1) @ coef
 
 
-def gram_Q_1d(xt, Mt: int, Ms_t: int, m: int, b: float) -> np.ndarray:
+def gram_Q_1d(xt, p: Params, t: int) -> np.ndarray:
     """Q(x_i - x_j) for all pairs of one coordinate: e^{2 pi i k (x_i - x_j)} factors into
     e^{2 pi i k x_i} conj(e^{2 pi i k x_j}), so the matrix is E diag(c) E^* with
-    E[i, k] = e^{2 pi i k x_i} and c_k = 1/(M_sigma w_hat(k))^2 (the same sum as kernel_Q_1d)."""
-    k = centred(Mt)
-    coef = 1.0 / (Ms_t * kb.window_hat(k, Ms_t, m, b)) ** 2
+    E[i, k] = e^{2 pi i k x_i} and c_k = D_k^2 (the same sum as kernel_Q_1d)."""
+    k = centred(p.M[t])
+    coef = p.deconv_inv(t) ** 2
     E = phase_matrix(np.asarray(xt, dtype=np.float64).ravel(), k, +1)
     return (E * coef[None, :]) @ E.conj().T
 
@@ -117,7 +118,7 @@ def kernel_K(Y, p: Params) -> np.ndarray:
     Y = np.atleast_2d(Y)
     out = np.ones(Y.shape[0], dtype=np.complex128)
     for t in range(p.d):
-        out = out * kernel_K_1d(Y[:, t], p.M[t], p.Ms[t], p.m, p.b)
+        out = out * kernel_K_1d(Y[:, t], p, t)
     return out
 
 
@@ -125,7 +126,7 @@ def kernel_Q(Y, p: Params) -> np.ndarray:
     Y = np.atleast_2d(Y)
     out = np.ones(Y.shape[0], dtype=np.complex128)
     for t in range(p.d):
-        out = out * kernel_Q_1d(Y[:, t], p.M[t], p.Ms[t], p.m, p.b)
+        out = out * kernel_Q_1d(Y[:, t], p, t)
     return out
 
 
@@ -182,7 +183,7 @@ def solve_R(x, l: int, js, p: Params, rho: float) -> np.ndarray:
     if n == 0:
         return np.zeros(0, dtype=np.complex128)
     xw, _, _ = prepare_nodes(x, p)
-    DH = p.deconv_full().ravel()[:, None] * _H(xw[np.asarray(js)], p)
+    DH = p.deconv_inv_full().ravel()[:, None] * _H(xw[np.asarray(js)], p)
     lv = grid_multi_index(l, p)
     q = np.ones(1, dtype=np.complex128)
     for t in range(p.d):
@@ -205,7 +206,7 @@ def gram_system(x, l: int, js, p: Params):
     n = len(js)
     G = np.full((n, n), float(np.prod(p.Ms)), dtype=np.complex128)
     for t in range(p.d):
-        G *= gram_Q_1d(X[:, t], p.M[t], p.Ms[t], p.m, p.b)
+        G *= gram_Q_1d(X[:, t], p, t)
     lv = grid_multi_index(l, p) / np.array(p.Ms, dtype=np.float64)
     r = np.conj(kernel_K(lv[None, :] - X, p))
     return G, r
@@ -262,14 +263,14 @@ def apply(x, f, rows, p: Params) -> np.ndarray:
     gt = np.zeros((f.shape[0], G), dtype=np.complex128)
     for r in range(f.shape[0]):
         np.add.at(gt[r], idx.ravel(), (np.conj(rows) * f[r][:, None]).ravel())
-    h = grid_to_coeffs(gt.reshape((f.shape[0],) + p.Ms), p)
+    h = grid_to_coeffs(gt.reshape((f.shape[0],) + p.Ms), p, inverse=True)
     return h[0] if single else h
 
 
 def apply_adjoint(x, h, rows, p: Params) -> np.ndarray:
     """Remark 3.24: f = B_opt F D h; h (R, *M) or (*M) -> (R, N) or (N,)."""
     single = np.asarray(h).ndim == p.d
-    g = trafo_grid(h, p).reshape(-1, int(np.prod(p.Ms)))
+    g = trafo_grid(h, p, inverse=True).reshape(-1, int(np.prod(p.Ms)))
     idx = _tap_grid_index(x, p)
     f = np.einsum("rnt,nt->rn", g[:, idx], rows)
     return f[0] if single else f

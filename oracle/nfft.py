@@ -26,7 +26,12 @@ from .direct import centred
 
 
 class Params:
-    def __init__(self, M, sigma: float = 2.0, m: int = 4):
+    """kernel: what the inverse (Algorithm 3.17 and the modified adjoint (3.32)) uses as D:
+    "window" the NFFT's D, or "dirichlet" (Remark 3.19): w_hat(k) = 1 for |k| < M/2 and the entry
+    of k = -M/2 set to zero, i.e. D_k = 1/M_sigma, D_{-M/2} = 0, so that K = D_{M/2-1}/M_sigma (3.23).
+    The NFFT and its adjoint always use the window."""
+
+    def __init__(self, M, sigma: float = 2.0, m: int = 4, kernel: str = "window"):
         self.M = tuple(int(v) for v in np.atleast_1d(M))
         self.d = len(self.M)
         self.sigma = float(sigma)
@@ -45,6 +50,9 @@ class Params:
         if any(2 * self.m + 2 > v for v in self.Ms) or self.m < 1:
             raise ValueError("need 1 <= m and 2m+2 <= M_sigma")
         self.b = kb.shape_b(self.sigma)
+        if kernel not in ("window", "dirichlet"):
+            raise ValueError("kernel must be 'window' or 'dirichlet'")
+        self.kernel = kernel
 
     @property
     def taps(self) -> int:
@@ -58,6 +66,20 @@ class Params:
         D = self.deconv(0)
         for t in range(1, self.d):
             D = np.multiply.outer(D, self.deconv(t))
+        return D
+
+    def deconv_inv(self, t: int) -> np.ndarray:
+        """D of the inverse for dimension t (the window's, or the Dirichlet kernel's)."""
+        if self.kernel == "window":
+            return self.deconv(t)
+        D = np.full(self.M[t], 1.0 / self.Ms[t])
+        D[0] = 0.0   # k = -M/2
+        return D
+
+    def deconv_inv_full(self) -> np.ndarray:
+        D = self.deconv_inv(0)
+        for t in range(1, self.d):
+            D = np.multiply.outer(D, self.deconv_inv(t))
         return D
 
 
@@ -116,10 +138,10 @@ def _axes(p):
     return tuple(range(1, p.d + 1))
 
 
-def trafo_grid(fhat, p: Params) -> np.ndarray:
-    """g = F D fhat on the oversampled grid, (R, *M_sigma)."""
+def trafo_grid(fhat, p: Params, inverse: bool = False) -> np.ndarray:
+    """g = F D fhat on the oversampled grid, (R, *M_sigma); D of the inverse when `inverse`."""
     fh = np.asarray(fhat, dtype=np.complex128).reshape((-1,) + p.M)
-    ghat = _place(fh * p.deconv_full(), p)
+    ghat = _place(fh * (p.deconv_inv_full() if inverse else p.deconv_full()), p)
     # sum_k ghat_k e^{+2 pi i k l / M_sigma}: numpy's ifftn carries 1/prod(M_sigma)
     return np.fft.ifftn(ghat, axes=_axes(p)) * float(np.prod(p.Ms))
 
@@ -144,10 +166,10 @@ def adjoint_grid(x, f, p: Params) -> np.ndarray:
     return out.reshape((f.shape[0],) + p.Ms)
 
 
-def grid_to_coeffs(gt, p: Params) -> np.ndarray:
-    """h~ = D^* F^* g~ restricted to the centred M range, (R, *M)."""
+def grid_to_coeffs(gt, p: Params, inverse: bool = False) -> np.ndarray:
+    """h~ = D^* F^* g~ restricted to the centred M range, (R, *M); D of the inverse when `inverse`."""
     H = np.fft.fftn(gt, axes=_axes(p))     # sum_l g~_l e^{-2 pi i k l / M_sigma}
-    return _extract(H, p) * p.deconv_full()
+    return _extract(H, p) * (p.deconv_inv_full() if inverse else p.deconv_full())
 
 
 def adjoint(x, f, p: Params) -> np.ndarray:

@@ -392,3 +392,53 @@ def test_node_gradient_matches_finite_differences(d):
     # and the NFFT derivative approximates the exact derivative of the trigonometric sum
     exact = np.sum(np.real(np.conj(gf)[:, :, None] * direct.ndft_grad_x(x, fh)), axis=0)
     assert np.max(np.abs(exact - an)) < 1e-4 * np.max(np.abs(exact))
+
+
+# ------------------------------------------------------------------ Dirichlet kernel (Remark 3.19)
+
+def test_dirichlet_kernel_closed_form():
+    """With w_hat = 1 for |k| < M/2 and the k = -M/2 entry zeroed, K(y) = D_{M/2-1}(y) / M_sigma,
+    D_{M/2-1}(y) = sin((M-1) pi y) / sin(pi y) (3.23); its value at 0 is (M-1)/M_sigma."""
+    M, Ms = 20, 40
+    p = nfft.Params((M,), 2.0, 3, kernel="dirichlet")
+    y = np.linspace(-0.49, 0.49, 97) + 1e-3
+    K = bopt.kernel_K(y[:, None], p)
+    closed = np.sin((M - 1) * np.pi * y) / np.sin(np.pi * y) / Ms
+    assert np.max(np.abs(K - closed)) <= 1e-14 * np.max(np.abs(closed))
+    assert abs(bopt.kernel_K(np.zeros((1, 1)), p)[0] - (M - 1) / Ms) < 1e-15
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_dirichlet_routes_agree_and_b_opt_is_real(d):
+    """The three routes solve the same Dirichlet problem; the kernel is real and even, so the
+    Gram matrix and right-hand side are real and so is B_opt (the real B of (3.27))."""
+    g = W.rng(50 + d)
+    if d == 1:
+        p = nfft.Params((16,), 2.0, 3, kernel="dirichlet")
+        x = W.jittered_nodes(g, 48)
+    else:
+        p = nfft.Params((6, 8), 2.0, 2, kernel="dirichlet")
+        x = W.uniform_nodes(g, 60, 2)
+    mem = bopt.Members(x, p)
+    rE, _ = bopt.bopt_rows(x, p, 1e-6, "E", members=mem)
+    rR, _ = bopt.bopt_rows(x, p, 1e-6, "R", members=mem)
+    rG, _ = bopt.bopt_rows(x, p, 1e-6, "G", members=mem)
+    tol = 100 * 2.2e-16 / 1e-6
+    assert rel(rR, rE) < tol and rel(rG, rE) < tol
+    assert np.max(np.abs(rE.imag)) <= tol * np.max(np.abs(rE))
+
+
+def test_dirichlet_apply_zeroes_the_unpaired_frequency_and_reconstructs():
+    """The zeroed entry of D^* makes the estimate at k = -M/2 vanish; for jittered nodes with
+    N = 4M (Example 3.23's setting) the other coefficients are reconstructed closely (the paper's
+    figure carries no numbers: the bound is a loose check, the size is reported in the design)."""
+    g = W.rng(60)
+    M = 32
+    p = nfft.Params((M,), 2.0, 4, kernel="dirichlet")
+    x = W.jittered_nodes(g, 4 * M)
+    fh = W.complex_normal(g, (M,))
+    f = direct.ndft(x, fh)
+    rows, _ = bopt.bopt_rows(x, p, 1e-12, "G")
+    fc = bopt.apply(x, f, rows, p)
+    assert fc[0] == 0
+    assert rel(fc[1:], fh[1:]) < 1e-5

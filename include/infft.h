@@ -67,8 +67,16 @@ typedef struct {
                         minimises ||L_l b - e_l||^2 + lambda ||b||^2 with
                         lambda = rho * trace(L_l^* L_l) / |I(l)| */
     int tile[2];     /* spreading tile in grid cells per dimension (0 = automatic) */
-    int reserved[6];
+    int inverse_kernel; /* kernel of the inverse (B optimisation, infft_apply, infft_apply_adjoint):
+                           INFFT_KERNEL_WINDOW (default): D of the window, as in the NFFT;
+                           INFFT_KERNEL_DIRICHLET: Remark 3.19, w_hat = 1 for |k| < M/2 and the
+                           entry of k = -M/2 set to zero, so K is the Dirichlet kernel (3.23)
+                           divided by M_sigma (the NFFT and its adjoint keep the window) */
+    int reserved[5];
 } infft_options;
+
+#define INFFT_KERNEL_WINDOW 0
+#define INFFT_KERNEL_DIRICHLET 1
 
 typedef struct {
     int64_t nonfinite_nodes;  /* nodes rejected as NaN/Inf (their samples are set to 0) */

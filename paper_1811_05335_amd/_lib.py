@@ -26,13 +26,19 @@ ERROR_NAMES = {
 }
 
 
+INFFT_KERNEL_WINDOW = 0
+INFFT_KERNEL_DIRICHLET = 1
+KERNELS = {"window": INFFT_KERNEL_WINDOW, "dirichlet": INFFT_KERNEL_DIRICHLET}
+
+
 class Options(C.Structure):
     _fields_ = [
         ("precision", C.c_int),
         ("max_rhs", C.c_int),
         ("rho", C.c_double),
         ("tile", C.c_int * 2),
-        ("reserved", C.c_int * 6),
+        ("inverse_kernel", C.c_int),
+        ("reserved", C.c_int * 5),
     ]
 
 

@@ -99,6 +99,11 @@ struct infft_plan_s {
 
     double* D64[MAX_D] = {nullptr, nullptr};
     float* D32[MAX_D] = {nullptr, nullptr};
+    // factors of the inverse (B optimisation, modified adjoint and its adjoint): the same as D,
+    // or for the Dirichlet kernel of Remark 3.19 1/M_sigma with the entry of k = -M/2 zero
+    int inv_kernel = INFFT_KERNEL_WINDOW;
+    double* Di64[MAX_D] = {nullptr, nullptr};
+    float* Di32[MAX_D] = {nullptr, nullptr};
     double2* Ktab[MAX_D] = {nullptr, nullptr};
     double2* Qtab[MAX_D] = {nullptr, nullptr};
     double* Kstab = nullptr;   // 1-D symmetric (real) parts of K and Q
@@ -347,7 +352,8 @@ int build_schedule(infft_plan_s* P, int nrhs, std::vector<FftStep>& to_grid, std
     return INFFT_OK;
 }
 
-int run_fft(infft_plan_s* P, const std::vector<FftStep>& steps, const void* user_in, void* user_out) {
+int run_fft(infft_plan_s* P, const std::vector<FftStep>& steps, const void* user_in, void* user_out,
+            bool inv = false) {
     const Geo& g = P->g;
     for (const FftStep& s : steps) {
         FftIO io{};
@@ -358,8 +364,10 @@ int run_fft(infft_plan_s* P, const std::vector<FftStep>& steps, const void* user
         io.in = buf(s.in_buf, true);
         io.out = buf(s.out_buf, false);
         const bool f32 = P->prec == INFFT_F32;
-        io.D0 = f32 ? (const void*)P->D32[0] : (const void*)P->D64[0];
-        io.D1 = f32 ? (const void*)P->D32[1] : (const void*)P->D64[1];
+        float* const* D32 = inv ? P->Di32 : P->D32;
+        double* const* D64 = inv ? P->Di64 : P->D64;
+        io.D0 = f32 ? (const void*)D32[0] : (const void*)D64[0];
+        io.D1 = f32 ? (const void*)D32[1] : (const void*)D64[1];
         io.h0 = P->h0;
         io.h1 = P->h1;
         io.h01 = P->h01;
@@ -614,6 +622,7 @@ struct BatchState {
     std::vector<int64_t> Poff, Noff;
     int64_t Ptot = 0, Ntot = 0;
     FftJob* fft_jobs = nullptr;
+    FftJob* fft_jobs_inv = nullptr;   // the same passes with the inverse's factors
     int2* fft_map = nullptr;
     std::vector<BatchLaunch> to_grid, to_coeff;
     NodeJob* node_jobs = nullptr;
@@ -655,7 +664,7 @@ int batch_build(infft_plan_s* P) {
     const int np = (int)B.subs.size();
     const size_t cs = P->csize();
     // ---- FFT passes, grouped by (step index, load mode, store mode)
-    std::vector<FftJob> jobs;
+    std::vector<FftJob> jobs, jobs_inv;
     std::vector<int2> map;
     for (int dir = 0; dir < 2; ++dir) {
         std::map<std::tuple<int, int, int>, std::vector<int>> groups;
@@ -682,6 +691,8 @@ int batch_build(infft_plan_s* P) {
                 J.user_off = B.Poff[i];
                 groups[std::make_tuple((int)k, st.ld, st.st)].push_back((int)jobs.size());
                 jobs.push_back(J);
+                J.io.D0 = f32 ? (const void*)sub->Di32[0] : (const void*)sub->Di64[0];
+                jobs_inv.push_back(J);
             }
         }
         std::vector<BatchLaunch>& launches = dir == 0 ? B.to_grid : B.to_coeff;
@@ -703,6 +714,8 @@ int batch_build(infft_plan_s* P) {
     }
     int rc;
     if ((rc = upload(P, &B.fft_jobs, jobs)) || (rc = upload(P, &B.fft_map, map))) return rc;
+    if (B.subs[0]->inv_kernel == INFFT_KERNEL_WINDOW) B.fft_jobs_inv = B.fft_jobs;
+    else if ((rc = upload(P, &B.fft_jobs_inv, jobs_inv))) return rc;
     // ---- per-node and per-cell kernels
     std::vector<NodeJob> nj(np);
     std::vector<int2> nmap, cmap, tmap;
@@ -770,15 +783,16 @@ int batch_build(infft_plan_s* P) {
 }
 
 int run_fft_batched(infft_plan_s* P, const std::vector<BatchLaunch>& launches, const void* user_in,
-                    void* user_out, int nrhs) {
+                    void* user_out, int nrhs, bool inv = false) {
     BatchState& B = *P->batch;
+    const FftJob* jobs = inv ? B.fft_jobs_inv : B.fft_jobs;
     for (const BatchLaunch& L : launches) {
         ProfScope ps(P, INFFT_K_FFT);
         if (P->prec == INFFT_F32)
-            launch_fft_batched<float>(B.fft_jobs, B.fft_map + L.map_off, L.nblocks, L.shm, L.ld, L.st, user_in,
+            launch_fft_batched<float>(jobs, B.fft_map + L.map_off, L.nblocks, L.shm, L.ld, L.st, user_in,
                                       user_out, nrhs, P->stream);
         else
-            launch_fft_batched<double>(B.fft_jobs, B.fft_map + L.map_off, L.nblocks, L.shm, L.ld, L.st, user_in,
+            launch_fft_batched<double>(jobs, B.fft_map + L.map_off, L.nblocks, L.shm, L.ld, L.st, user_in,
                                        user_out, nrhs, P->stream);
         LAUNCH_CHECK();
     }
@@ -880,6 +894,8 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
     infft_default_options(&o);
     if (opts) o = *opts;
     if (o.precision != INFFT_F32 && o.precision != INFFT_F64) return fail(INFFT_EINVAL, "bad precision");
+    if (o.inverse_kernel != INFFT_KERNEL_WINDOW && o.inverse_kernel != INFFT_KERNEL_DIRICHLET)
+        return fail(INFFT_EINVAL, "bad inverse_kernel");
     if (o.max_rhs < 1 || o.max_rhs > 64) return fail(INFFT_EINVAL, "max_rhs must be in 1..64");
     if (!(o.rho >= 0.0) || !std::isfinite(o.rho)) return fail(INFFT_EINVAL, "rho must be finite and >= 0");
 
@@ -946,6 +962,7 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
     P->rho = o.rho;
     P->sigma = sigma;
     P->stream = (hipStream_t)stream;
+    P->inv_kernel = o.inverse_kernel;
     int rc = INFFT_OK;
 #define TRY(e)                     \
     do {                           \
@@ -979,15 +996,29 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
         TRY(P->alloc(&P->Ktab[t], (int64_t)(P->qK + 1) * TAY_NC));
         TRY(P->alloc(&P->Qtab[t], (int64_t)(P->qQ + 1) * TAY_NC));
         launch_deconv_table(g.M[t], g.Ms[t], m, g.b, P->D64[t], P->D32[t], P->stream);
-        launch_taylor_table(g.M[t], g.Ms[t], P->D64[t], 1, P->qK, P->Ktab[t], P->stream);
-        launch_taylor_table(g.M[t], g.Ms[t], P->D64[t], 2, P->qQ, P->Qtab[t], P->stream);
+        if (P->inv_kernel == INFFT_KERNEL_DIRICHLET) {
+            std::vector<double> h64(g.M[t], 1.0 / (double)g.Ms[t]);
+            h64[0] = 0.0;   // k = -M/2
+            std::vector<float> h32(h64.begin(), h64.end());
+            TRY(P->alloc(&P->Di64[t], g.M[t]));
+            HIP_TRY(hipMemcpy(P->Di64[t], h64.data(), sizeof(double) * g.M[t], hipMemcpyHostToDevice));
+            if (P->prec == INFFT_F32) {
+                TRY(P->alloc(&P->Di32[t], g.M[t]));
+                HIP_TRY(hipMemcpy(P->Di32[t], h32.data(), sizeof(float) * g.M[t], hipMemcpyHostToDevice));
+            }
+        } else {
+            P->Di64[t] = P->D64[t];
+            P->Di32[t] = P->D32[t];
+        }
+        launch_taylor_table(g.M[t], g.Ms[t], P->Di64[t], 1, P->qK, P->Ktab[t], P->stream);
+        launch_taylor_table(g.M[t], g.Ms[t], P->Di64[t], 2, P->qQ, P->Qtab[t], P->stream);
         if (hipGetLastError() != hipSuccess) TRY(fail(INFFT_EDEVICE, "table kernels failed to launch"));
     }
     if (d == 1) {
         TRY(P->alloc(&P->Kstab, (int64_t)(P->qK + 1) * TAY_NC));
         TRY(P->alloc(&P->Qstab, (int64_t)(P->qQ + 1) * TAY_NC));
-        launch_taylor_table_sym(g.M[0], g.Ms[0], P->D64[0], 1, P->qK, P->Kstab, P->stream);
-        launch_taylor_table_sym(g.M[0], g.Ms[0], P->D64[0], 2, P->qQ, P->Qstab, P->stream);
+        launch_taylor_table_sym(g.M[0], g.Ms[0], P->Di64[0], 1, P->qK, P->Kstab, P->stream);
+        launch_taylor_table_sym(g.M[0], g.Ms[0], P->Di64[0], 2, P->qQ, P->Qstab, P->stream);
         if (hipGetLastError() != hipSuccess) TRY(fail(INFFT_EDEVICE, "table kernels failed to launch"));
     }
     // FFT twiddles
@@ -1077,7 +1108,7 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
         q0 *= v.x * (double)g.Ms[t];
     }
     P->lam = P->rho * q0;
-    if (d == 1 && hipMemcpy(&P->dM, P->D64[0], sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+    if (d == 1 && hipMemcpy(&P->dM, P->Di64[0], sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
         TRY(fail(INFFT_EDEVICE, "reading the deconvolution table failed"));
     TRY(set_nodes_impl(P, x));
     if (hipStreamSynchronize(P->stream) != hipSuccess) TRY(fail(INFFT_EDEVICE, "plan set-up failed on the device"));
@@ -1157,7 +1188,7 @@ static int spread_then_coeffs(infft_plan_s* p, const void* f, void* h, int nrhs,
                                       p->hrs01, c, p->rchunk, p->spwork, p->stream);
         }
         LAUNCH_CHECK();
-        if ((rc = run_fft(p, p->to_coeff, nullptr, (void*)cptr(p, h, r0 * g.P)))) return rc;
+        if ((rc = run_fft(p, p->to_coeff, nullptr, (void*)cptr(p, h, r0 * g.P), useB))) return rc;
     }
     return INFFT_OK;
 }
@@ -1268,7 +1299,7 @@ int infft_apply(infft_plan p, const void* f, void* fcheck, int nrhs) {
     if (p->batch) {
         if ((rc = batch_check_rhs(p, nrhs)) || (rc = node_batched(p, NB_GATHER_B, f, nullptr, nullptr, nrhs)))
             return rc;
-        return run_fft_batched(p, p->batch->to_coeff, nullptr, fcheck, nrhs);
+        return run_fft_batched(p, p->batch->to_coeff, nullptr, fcheck, nrhs, true);
     }
     return spread_then_coeffs(p, f, fcheck, nrhs, true);
 }
@@ -1279,7 +1310,7 @@ int infft_apply_adjoint(infft_plan p, const void* h, void* f, int nrhs) {
     if (!h || !f) return fail(INFFT_EINVAL, "null data pointer");
     if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_apply_adjoint before infft_precompute_B");
     if (p->batch) {
-        if ((rc = batch_check_rhs(p, nrhs)) || (rc = run_fft_batched(p, p->batch->to_grid, h, nullptr, nrhs)))
+        if ((rc = batch_check_rhs(p, nrhs)) || (rc = run_fft_batched(p, p->batch->to_grid, h, nullptr, nrhs, true)))
             return rc;
         return node_batched(p, NB_INTERP_B, nullptr, f, nullptr, nrhs);
     }
@@ -1287,7 +1318,7 @@ int infft_apply_adjoint(infft_plan p, const void* h, void* f, int nrhs) {
     for (int r0 = 0; r0 < nrhs; r0 += p->max_rhs) {
         const int c = std::min(p->max_rhs, nrhs - r0);
         if ((rc = schedule_for(p, c))) return rc;
-        if ((rc = run_fft(p, p->to_grid, cptr(p, h, r0 * g.P), nullptr))) return rc;
+        if ((rc = run_fft(p, p->to_grid, cptr(p, h, r0 * g.P), nullptr, true))) return rc;
         void* fo = (void*)cptr(p, f, r0 * g.N);
         ProfScope ps(p, INFFT_K_INTERP);
         if (p->prec == INFFT_F32)

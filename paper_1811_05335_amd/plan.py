@@ -26,10 +26,11 @@ class NfftPlan:
     sigma, m   oversampling factor and window cut-off
     precision  "f32" (complex64 data, FP32 spreading/FFT) or "f64" (complex128)
     rho        ridge of the local least-squares problems of the B optimisation
+    kernel     kernel of the inverse: "window" (the NFFT's window) or "dirichlet" (Remark 3.19)
     """
 
     def __init__(self, M, x: torch.Tensor, sigma: float = 2.0, m: int = 4, precision: str = "f64",
-                 rho: float = 1e-8, max_rhs: int = 1, tile=None):
+                 rho: float = 1e-8, max_rhs: int = 1, tile=None, kernel: str = "window"):
         lib = load()
         self.M = tuple(int(v) for v in (M if isinstance(M, (tuple, list)) else (M,)))
         self.d = len(self.M)
@@ -44,6 +45,7 @@ class NfftPlan:
         o.precision = _lib.INFFT_F32 if precision == "f32" else _lib.INFFT_F64
         o.max_rhs = int(max_rhs)
         o.rho = float(rho)
+        o.inverse_kernel = _lib.KERNELS[kernel]
         if tile is not None:
             for t, v in enumerate(tile):
                 o.tile[t] = int(v)
@@ -202,7 +204,7 @@ class NfftBatchPlan(NfftPlan):
     """
 
     def __init__(self, Ms, Ns, x: torch.Tensor, sigma: float = 2.0, m: int = 4, precision: str = "f64",
-                 rho: float = 1e-8, max_rhs: int = 1):
+                 rho: float = 1e-8, max_rhs: int = 1, kernel: str = "window"):
         lib = load()
         self.Ms = [int(v) for v in Ms]
         self.Ns = [int(v) for v in Ns]
@@ -224,6 +226,7 @@ class NfftBatchPlan(NfftPlan):
         o.precision = _lib.INFFT_F32 if precision == "f32" else _lib.INFFT_F64
         o.max_rhs = self.max_rhs
         o.rho = float(rho)
+        o.inverse_kernel = _lib.KERNELS[kernel]
         n = len(self.Ms)
         Mv = (C.c_int64 * n)(*self.Ms)
         Nv = (C.c_int64 * n)(*self.Ns)

@@ -343,6 +343,75 @@ def secondary_polar(steps, warmup):
     return out
 
 
+def secondary_spiral(steps, warmup):
+    """The differentiable spiral: M = 256 x 256, N = 65536 on a 32-interleave spiral, 16 right-hand
+    sides (FP32), loss ||infft(nfft(fhat, x)) - fhat||^2 with gradients for fhat and x."""
+    import torch
+    from paper_1811_05335_amd import NfftPlan, infft, nfft
+    cfg = W.CONFIGS["c5"]
+    R = cfg["rhs"]
+    x, fh = W.make_problem(cfg, seed=0, rhs=R)
+    xd = torch.from_numpy(x).cuda()
+    fhd = torch.from_numpy(W.round_to(fh, "f32")).to(torch.complex64).cuda()
+    P = NfftPlan(cfg["M"], xd, sigma=cfg["sigma"], m=cfg["m"], precision="f32", rho=cfg["rho"], max_rhs=R)
+    Pi = NfftPlan(cfg["M"], xd, sigma=cfg["sigma"], m=cfg["m"], precision="f32", rho=cfg["rho"], max_rhs=R)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Pi.precompute_B()
+    torch.cuda.synchronize()
+    out = {"ms_precompute": (time.perf_counter() - t0) * 1e3}
+
+    def it():
+        a = fhd.clone().requires_grad_(True)
+        xx = xd.clone().requires_grad_(True)
+        loss = (infft(nfft(a, xx, P), Pi) - a).abs().pow(2).sum()
+        loss.backward()
+        return loss, a.grad, xx.grad
+
+    for _ in range(warmup):
+        it()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        loss, ga, gx = it()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    st = Pi.status()
+    out.update(ms_loss_and_gradients=ms, node_rhs_per_s=cfg["N"] * R / (ms * 1e-3),
+               relative_residual=float(loss.item()) ** 0.5 / float(fhd.abs().pow(2).sum().item()) ** 0.5,
+               timing="eager autograd (forward NFFT and modified adjoint, backward adjoint NFFT, node "
+                      "gradient and inverse adjoint)",
+               status={k: st[k] for k in ("failed_solves", "oversized", "min_members", "max_members")})
+    P.close()
+    Pi.close()
+    return out
+
+
+def secondary_small(steps, warmup):
+    """The small 1-D uniform workload (M = 256, N = 512, m = 4, FP64): the whole path per step."""
+    import torch
+    from paper_1811_05335_amd import NfftPlan
+    cfg = W.CONFIGS["c1"]
+    x, fh = W.make_problem(cfg, seed=0, rhs=1)
+    xd = torch.from_numpy(x).cuda()
+    fhd = torch.from_numpy(fh).cuda()
+    P = NfftPlan(cfg["M"], xd, sigma=cfg["sigma"], m=cfg["m"], precision="f64", rho=cfg["rho"])
+
+    def step():
+        P.set_nodes(xd)
+        f = P.trafo(fhd)
+        P.adjoint(f)
+        P.precompute_B()
+        fc = P.apply(f)
+        P.apply_adjoint(fc)
+        P.grad_x(fhd, f)
+
+    ms = timed_graph(torch, step, steps, warmup)
+    P.close()
+    return {"ms_per_step": ms, "nodes_per_s": cfg["N"] / (ms * 1e-3), "dtype": "f64",
+            "timing": "hipGraph replay of the whole path (launch-latency bound at this size)"}
+
+
 def cpu_baseline(x, fh, gf, rho, m, sigma, M, sample):
     from oracle import bopt, grad, nfft
 
@@ -496,6 +565,11 @@ def main():
         log("[bench] polar workload (512 x 512, N = 524288)")
         line["secondary"]["polar_2d"] = secondary_polar(max(5, a.steps // 2), 2)
         log(f"[bench] polar: {line['secondary']['polar_2d']}")
+        log("[bench] spiral workload (256 x 256, N = 65536, 16 RHS, loss and gradients)")
+        line["secondary"]["spiral_2d_autograd"] = secondary_spiral(5, 1)
+        log(f"[bench] spiral: {line['secondary']['spiral_2d_autograd']}")
+        line["secondary"]["small_1d"] = secondary_small(max(20, a.steps), 3)
+        log(f"[bench] small: {line['secondary']['small_1d']}")
     if not a.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline (B optimisation sampled on {a.cpu_sample} grid indices)")
         cb = cpu_baseline(x, fh, gf, rho, m, sigma, M, a.cpu_sample)

@@ -442,3 +442,35 @@ def test_dirichlet_apply_zeroes_the_unpaired_frequency_and_reconstructs():
     fc = bopt.apply(x, f, rows, p)
     assert fc[0] == 0
     assert rel(fc[1:], fh[1:]) < 1e-5
+
+
+# ------------------------------------------------------------------ gradient through B_opt(x)
+
+@pytest.mark.parametrize("d,kernel", [(1, "window"), (1, "dirichlet"), (2, "window")])
+def test_bopt_gradient_matches_finite_differences(d, kernel):
+    """dL/dx through B_opt(x) by implicit differentiation of the ridge normal equations, against
+    central differences of L(x) = Re <c, D^* F^* B_opt(x)^* f> with B_opt recomputed at the moved
+    nodes (the membership I(l) does not change for steps this small)."""
+    g = W.rng(80 + d)
+    M, N = ((12,), 30) if d == 1 else ((6, 8), 40)
+    p = nfft.Params(M, 2.0, 3 if d == 1 else 2, kernel=kernel)
+    x = W.uniform_nodes(g, N, d)
+    f = W.complex_normal(g, (2, N))
+    c = W.complex_normal(g, (2,) + M)
+    rho = 1e-4
+
+    def L(xx):
+        rows, _ = bopt.bopt_rows(xx, p, rho, "G")
+        return float(np.real(np.vdot(c, bopt.apply(xx, f, rows, p))))
+
+    an = grad.bopt_grad_x(x, f, c, p, rho)
+    fd = np.zeros_like(an)
+    h = 1e-6
+    for j in range(N):
+        for t in range(d):
+            xp = x.copy()
+            xp[j, t] += h
+            xm = x.copy()
+            xm[j, t] -= h
+            fd[j, t] = (L(xp) - L(xm)) / (2 * h)
+    assert rel(an, fd) < 1e-6

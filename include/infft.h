@@ -138,6 +138,16 @@ int infft_apply_adjoint(infft_plan p, const void* h, void* f, int nrhs);
  * (plan precision), gradx float64 [N][d]. */
 int nfft_grad_x(infft_plan p, const void* fhat, const void* gradf, double* gradx, int nrhs);
 
+/* Gradient of a real loss through B_opt(x) with respect to the nodes, for fcheck = infft_apply(f)
+ * with f held fixed: implicit differentiation of the ridge normal equations of Algorithm 3.17
+ * ((3.30)-(3.31)); membership I(l) is piecewise constant in x and contributes nothing.  f [nrhs][N]
+ * and gradfc [nrhs][M...] (the loss's gradient with respect to fcheck, PyTorch's convention) in the
+ * plan precision; gradx float64 [N][d] is overwritten.  The total node gradient of a loss through
+ * both the NFFT and the modified adjoint is the sum of nfft_grad_x and this.  Synchronises the
+ * stream; returns INFFT_ESTATE before infft_precompute_B, for batch plans, and when some |I(l)|
+ * exceeds 32. */
+int infft_grad_x_bopt(infft_plan p, const void* f, const void* gradfc, double* gradx, int nrhs);
+
 /* Copies B_opt to `rows` (device, complex128 [N][(2m+1)^d], caller node order, tap index
  * tau flattened with the first dimension slowest; entry (j, tau) multiplies grid index
  * (l0_j + tau) mod M_sigma).  Returns INFFT_ESTATE before infft_precompute_B. */

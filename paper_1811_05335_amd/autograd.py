@@ -3,10 +3,12 @@
 NfftFunction       f = A~ fhat with A~ = B(x) F D (the NFFT); gradients with respect to the
                    coefficients (the adjoint NFFT) and to the node positions (window derivative).
 InfftApplyFunction fcheck = D^* F^* B_opt^* f (the modified adjoint NFFT, (3.32)); gradient with
-                   respect to f is B_opt F D applied to the incoming gradient (Remark 3.24).
+                   respect to f is B_opt F D applied to the incoming gradient (Remark 3.24); when
+                   the nodes x are passed, also the gradient with respect to x through B_opt(x)
+                   (implicit differentiation of the local problems of Algorithm 3.17).
 
-B_opt is a constant of the node set it was computed for: the modified adjoint has no gradient with
-respect to x, and it runs on its own plan (loading new nodes into a plan invalidates its B_opt).
+The modified adjoint runs on its own plan (loading new nodes into a plan invalidates its B_opt),
+whose B_opt must have been computed for the nodes passed as x.
 Gradients follow PyTorch's convention for complex tensors (dL/dx = sum Re(conj(g) df/dx)).
 """
 from __future__ import annotations
@@ -36,13 +38,21 @@ class NfftFunction(torch.autograd.Function):
 
 class InfftApplyFunction(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, f: torch.Tensor, plan: NfftPlan):
+    def forward(ctx, f: torch.Tensor, plan: NfftPlan, x=None):
         ctx.plan = plan
+        ctx.with_x = x is not None
+        ctx.save_for_backward(f)
         return plan.apply(f)
 
     @staticmethod
     def backward(ctx, grad_h: torch.Tensor):
-        return ctx.plan.apply_adjoint(grad_h.contiguous()), None
+        (f,) = ctx.saved_tensors
+        g = grad_h.contiguous()
+        gf = ctx.plan.apply_adjoint(g) if ctx.needs_input_grad[0] else None
+        gx = None
+        if ctx.with_x and ctx.needs_input_grad[2]:
+            gx = ctx.plan.grad_x_bopt(f.detach().contiguous(), g)
+        return gf, None, gx
 
 
 def nfft(fhat: torch.Tensor, x: torch.Tensor, plan: NfftPlan) -> torch.Tensor:
@@ -50,6 +60,7 @@ def nfft(fhat: torch.Tensor, x: torch.Tensor, plan: NfftPlan) -> torch.Tensor:
     return NfftFunction.apply(fhat, x, plan)
 
 
-def infft(f: torch.Tensor, plan: NfftPlan) -> torch.Tensor:
-    """Differentiable modified adjoint NFFT with the plan's B_opt (call plan.precompute_B first)."""
-    return InfftApplyFunction.apply(f, plan)
+def infft(f: torch.Tensor, plan: NfftPlan, x: torch.Tensor | None = None) -> torch.Tensor:
+    """Differentiable modified adjoint NFFT with the plan's B_opt (call plan.precompute_B first).
+    Pass the plan's nodes as x to differentiate through B_opt(x) as well."""
+    return InfftApplyFunction.apply(f, plan, x)

@@ -1357,6 +1357,51 @@ int nfft_grad_x(infft_plan p, const void* fhat, const void* gradf, double* gradx
     return INFFT_OK;
 }
 
+int infft_grad_x_bopt(infft_plan p, const void* f, const void* gradfc, double* gradx, int nrhs) {
+    int rc = check_rhs(p, nrhs);
+    if (rc) return rc;
+    if (!f || !gradfc || !gradx) return fail(INFFT_EINVAL, "null data pointer");
+    if (p->batch) return fail(INFFT_ESTATE, "infft_grad_x_bopt takes a single-problem plan");
+    if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_grad_x_bopt before infft_precompute_B");
+    const Geo& g = p->g;
+    launch_fill_bytes0(gradx, (int64_t)sizeof(double) * g.N * g.d, p->stream);
+    const KTabDev kt = plan_ktab(p);
+    int* listA = p->lists;
+    int* listB = p->lists + g.G;
+    for (int r0 = 0; r0 < nrhs; r0 += p->max_rhs) {
+        const int c = std::min(p->max_rhs, nrhs - r0);
+        if ((rc = schedule_for(p, c))) return rc;
+        // upstream gradient on the grid: F D gfc with the inverse's D
+        if ((rc = run_fft(p, p->to_grid, cptr(p, gradfc, r0 * g.P), nullptr, true))) return rc;
+        launch_fill_i32(p->lcount, 4, 0, p->stream);
+        BoptGradArgs ga{};
+        ga.B64 = p->B64;
+        ga.grid = p->grid;
+        ga.f = cptr(p, f, r0 * g.N);
+        ga.nrhs = c;
+        ga.gradx = gradx;
+        ga.out_list = listA;
+        ga.out_count = p->lcount;
+        ProfScope ps(p, INFFT_K_SOLVE);
+        if (p->prec == INFFT_F32) launch_bopt_grad<float>(g, p->nd, kt, ga, 16, p->stream);
+        else launch_bopt_grad<double>(g, p->nd, kt, ga, 16, p->stream);
+        LAUNCH_CHECK();
+        ga.in_list = listA;
+        ga.in_count = p->lcount;
+        ga.out_list = listB;
+        ga.out_count = p->lcount + 1;
+        if (p->prec == INFFT_F32) launch_bopt_grad<float>(g, p->nd, kt, ga, 32, p->stream);
+        else launch_bopt_grad<double>(g, p->nd, kt, ga, 32, p->stream);
+        LAUNCH_CHECK();
+        int left = 0;
+        HIP_TRY(hipMemcpyAsync(&left, p->lcount + 1, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+        HIP_TRY(hipStreamSynchronize(p->stream));
+        if (left > 0)
+            return fail(INFFT_ESTATE, "infft_grad_x_bopt handles |I(l)| <= 32; %d local problems are larger", left);
+    }
+    return INFFT_OK;
+}
+
 int infft_get_B(infft_plan p, void* rows) {
     if (!p) return fail(INFFT_EINVAL, "null plan");
     if (!rows) return fail(INFFT_EINVAL, "rows is null");

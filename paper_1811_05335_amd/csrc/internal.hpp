@@ -143,6 +143,94 @@ __device__ inline double2 tay_eval(const double2* __restrict__ tab, int qmax, do
     return acc;
 }
 
+// ------------------------------------------------------------------ members of I(l) for lane groups
+
+// Ordering point for the LDS exchange inside one wavefront: LDS operations of a wave execute
+// in program order, so only the compiler has to be kept from moving accesses across it.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Members of I(l) for d = 1.  Nodes are sorted by stencil base l0, so the cells l-2m+1 .. l
+// (every node of them reaches l) form at most two contiguous ranges of the sorted order (two when
+// the window wraps around the torus); the cell l-2m contributes only nodes whose tap 2m is a member.
+__device__ inline void gather_1d(const Geo& g, const NodesDev& nd, int l, int lane, int NL, int gbase,
+                                 uint64_t gmask, int& n, int& my_p) {
+    const int w2 = 2 * g.m, Ms = g.Ms[0];
+    const int clo = l - w2 + 1;
+    int s0, e0, s1 = 0, e1 = 0;
+    if (clo >= 0) {
+        s0 = nd.start[clo];
+        e0 = nd.start[l + 1];
+    } else {
+        s0 = nd.start[clo + Ms];
+        e0 = nd.start[Ms];
+        s1 = nd.start[0];
+        e1 = nd.start[l + 1];
+    }
+    const int n0 = e0 - s0, n1 = e1 - s1;
+    if (lane < n0) my_p = s0 + lane;
+    else if (lane - n0 < n1) my_p = s1 + (lane - n0);
+    n = n0 + n1;
+    int ce = l - w2;
+    if (ce < 0) ce += Ms;
+    const int s = nd.start[ce], e = nd.start[ce + 1];
+    for (int base = s; base < e; base += NL) {
+        const int p = base + lane;
+        const bool mem = p < e && edge_tap_member(nd.us[p], g.m);
+        const uint64_t gm = (__ballot(mem) >> gbase) & gmask;
+        const int cnt = __popcll(gm);
+        const int k = lane - n;
+        if (k >= 0 && k < cnt) {
+            uint64_t mm = gm;
+            for (int i = 0; i < k; ++i) mm &= mm - 1ull;
+            my_p = base + (__ffsll((unsigned long long)mm) - 1);
+        }
+        n += cnt;
+    }
+}
+
+// Members of I(l) for d = 2: the (2m+1)^2 cells (l0 - tau0, l1 - tau1), cell by cell.
+__device__ inline void gather_2d(const Geo& g, const NodesDev& nd, int l, int lane, int NL, int gbase,
+                                 uint64_t gmask, int& n, int& my_p) {
+    const int W = 2 * g.m + 1, w2 = 2 * g.m;
+    const int lc0 = l / g.Ms[1], lc1 = l - lc0 * g.Ms[1];
+    n = 0;
+    for (int c = 0; c < W * W; ++c) {
+        const int tau0 = c / W, tau1 = c - tau0 * W;
+        int c0 = lc0 - tau0;
+        if (c0 < 0) c0 += g.Ms[0];
+        int c1 = lc1 - tau1;
+        if (c1 < 0) c1 += g.Ms[1];
+        const int64_t key = cell_key(g, c0, c1);
+        const int s = nd.start[key], e = nd.start[key + 1];
+        if (s == e) continue;
+        if (tau0 < w2 && tau1 < w2) {
+            const int k = lane - n;
+            if (k >= 0 && k < e - s) my_p = s + k;
+            n += e - s;
+        } else {
+            for (int base = s; base < e; base += NL) {
+                const int p = base + lane;
+                bool mem = p < e;
+                if (mem && tau0 == w2) mem = edge_tap_member(nd.us[(int64_t)p * 2], g.m);
+                if (mem && tau1 == w2) mem = edge_tap_member(nd.us[(int64_t)p * 2 + 1], g.m);
+                const uint64_t gm = (__ballot(mem) >> gbase) & gmask;
+                const int cnt = __popcll(gm);
+                const int k = lane - n;
+                if (k >= 0 && k < cnt) {
+                    uint64_t mm = gm;
+                    for (int i = 0; i < k; ++i) mm &= mm - 1ull;
+                    my_p = base + (__ffsll((unsigned long long)mm) - 1);
+                }
+                n += cnt;
+            }
+        }
+    }
+}
+
+
 // ------------------------------------------------------------------ large local problems
 
 constexpr int BIG_NB = 64;   // block size of the blocked Cholesky
@@ -322,6 +410,21 @@ constexpr int T1_CELLS = 128;   // cells per workgroup of the thread-per-problem
 void launch_solve_tier_batched(const SolveJob* jobs, int njobs, int nl, int blocks, hipStream_t s);
 int launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s);
 void launch_solve_stats(const long long* rec, int nrec, long long* status, hipStream_t s);
+
+// grad_bopt.hip: node gradient through B_opt(x)
+struct BoptGradArgs {
+    const double2* B64;   // B_opt [tap][N] (sorted order)
+    const void* grid;     // upstream grid gradient F D gfc, [R][G] (plan precision)
+    const void* f;        // samples [R][N] (caller order, plan precision)
+    int nrhs;
+    double* gradx;        // [N][d] (caller order), accumulated with atomics
+    const int* in_list;   // nullptr: all grid indices
+    const int* in_count;
+    int* out_list;        // problems with more members than the tier's lanes
+    int* out_count;
+};
+template <typename R>
+int launch_bopt_grad(const Geo& g, NodesDev nd, KTabDev kt, BoptGradArgs ga, int nl, hipStream_t s);
 
 // solve_big.hip
 void launch_big_count(const Geo& g, NodesDev nd, const int* list, int count, int* nout, hipStream_t s);

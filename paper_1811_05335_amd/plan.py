@@ -143,6 +143,18 @@ class NfftPlan:
         check(load().nfft_grad_x(self._h, C.c_void_p(_ptr(fh)), C.c_void_p(_ptr(gf)), C.c_void_p(_ptr(out)), R))
         return out
 
+    def grad_x_bopt(self, f: torch.Tensor, gradfc: torch.Tensor) -> torch.Tensor:
+        """Node gradient through B_opt(x) of a loss of fcheck = apply(f), f held fixed."""
+        ff, lead, R = self._samples(f)
+        gc, lead2, R2 = self._coeffs(gradfc)
+        if R2 != R:
+            raise ValueError("f and gradfc need the same number of right-hand sides")
+        out = torch.empty((self.N, self.d), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        check(load().infft_grad_x_bopt(self._h, C.c_void_p(_ptr(ff)), C.c_void_p(_ptr(gc)),
+                                       C.c_void_p(_ptr(out)), R))
+        return out
+
     def get_B(self) -> torch.Tensor:
         out = torch.empty((self.N, self.taps), dtype=torch.complex128, device=self.device)
         self._sync_stream()

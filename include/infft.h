@@ -144,8 +144,9 @@ int nfft_grad_x(infft_plan p, const void* fhat, const void* gradf, double* gradx
  * and gradfc [nrhs][M...] (the loss's gradient with respect to fcheck, PyTorch's convention) in the
  * plan precision; gradx float64 [N][d] is overwritten.  The total node gradient of a loss through
  * both the NFFT and the modified adjoint is the sum of nfft_grad_x and this.  Synchronises the
- * stream; returns INFFT_ESTATE before infft_precompute_B, for batch plans, and when some |I(l)|
- * exceeds 32. */
+ * stream (it reads the sizes of local problems above 32 members back, like infft_precompute_B, and
+ * solves those on the blocked Cholesky pass); returns INFFT_ESTATE before infft_precompute_B and
+ * for batch plans. */
 int infft_grad_x_bopt(infft_plan p, const void* f, const void* gradfc, double* gradx, int nrhs);
 
 /* Copies B_opt to `rows` (device, complex128 [N][(2m+1)^d], caller node order, tap index

@@ -155,6 +155,7 @@ struct infft_plan_s {
     int* big_mtap = nullptr;
     double2* big_mz = nullptr;
     double2* big_mr = nullptr;
+    double2* big_mb = nullptr;
     int64_t big_m_cap = 0;
     BigProb* big_probs = nullptr;
     int64_t big_probs_cap = 0;
@@ -488,7 +489,8 @@ KTabDev plan_ktab(const infft_plan_s* p) {
 // device count from the last tier).  Reads the count and the sizes back to the host, sorts the
 // problems by size, packs them into batches whose matrices fit the workspace and runs the
 // blocked Cholesky pipeline on each batch; adds one statistics record.
-int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* count_dev, int& stat_off) {
+int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* count_dev, int& stat_off,
+                const BoptGradArgs* grad = nullptr) {
     const Geo& g = p->g;
     hipStream_t st = p->stream;
     int count = 0;
@@ -558,9 +560,11 @@ int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* 
         seg.push_back((int64_t)tasks.size());
         if ((rc = p->grow(&p->big_A, p->big_A_cap, std::max<int64_t>(ent, 1)))) return rc;
         if (mem > p->big_m_cap) {
-            int64_t c1 = p->big_m_cap, c2 = p->big_m_cap, c3 = p->big_m_cap, c4 = p->big_m_cap;
+            int64_t c1 = p->big_m_cap, c2 = p->big_m_cap, c3 = p->big_m_cap, c4 = p->big_m_cap,
+                    c5 = p->big_m_cap;
             if ((rc = p->grow(&p->big_midx, c1, mem)) || (rc = p->grow(&p->big_mtap, c2, mem)) ||
-                (rc = p->grow(&p->big_mz, c3, mem)) || (rc = p->grow(&p->big_mr, c4, mem)))
+                (rc = p->grow(&p->big_mz, c3, mem)) || (rc = p->grow(&p->big_mr, c4, mem)) ||
+                (rc = p->grow(&p->big_mb, c5, mem)))
                 return rc;
             p->big_m_cap = c1;
         }
@@ -575,6 +579,7 @@ int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* 
         a.mtap = p->big_mtap;
         a.mz = p->big_mz;
         a.mr = p->big_mr;
+        a.mb = p->big_mb;
         a.fail = p->big_fail;
         launch_big_setup(g, p->nd, kt, a, np, st);
         LAUNCH_CHECK();
@@ -591,11 +596,13 @@ int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* 
             launch_big_herk(a, p->big_tasks + t1, (int)(t2 - t1), k, st);
             LAUNCH_CHECK();
         }
-        launch_big_solve(g, a, np, p->B64, p->B32, st);
+        if (grad) launch_big_grad(g, a, kt, *grad, p->nd.perm, np, p->prec == INFFT_F32, st);
+        else launch_big_solve(g, a, np, p->B64, p->B32, st);
         LAUNCH_CHECK();
         // the host task arrays are reused by the next batch
         HIP_TRY(hipStreamSynchronize(st));
     }
+    if (grad) return INFFT_OK;   // the precompute's statistics stay as they are
     launch_big_stats(p->big_fail, count, nmin, nmax, p->stat_rec + (int64_t)stat_off * 5, st);
     LAUNCH_CHECK();
     stat_off += 1;
@@ -1393,11 +1400,9 @@ int infft_grad_x_bopt(infft_plan p, const void* f, const void* gradfc, double* g
         if (p->prec == INFFT_F32) launch_bopt_grad<float>(g, p->nd, kt, ga, 32, p->stream);
         else launch_bopt_grad<double>(g, p->nd, kt, ga, 32, p->stream);
         LAUNCH_CHECK();
-        int left = 0;
-        HIP_TRY(hipMemcpyAsync(&left, p->lcount + 1, sizeof(int), hipMemcpyDeviceToHost, p->stream));
-        HIP_TRY(hipStreamSynchronize(p->stream));
-        if (left > 0)
-            return fail(INFFT_ESTATE, "infft_grad_x_bopt handles |I(l)| <= 32; %d local problems are larger", left);
+        // problems beyond 32 members: the blocked factorisation, then their gradient
+        int unused = 0;
+        if ((rc = solve_large(p, kt, listB, p->lcount + 1, unused, &ga))) return rc;
     }
     return INFFT_OK;
 }

@@ -238,4 +238,73 @@ int launch_bopt_grad(const Geo& g, NodesDev nd, KTabDev kt, BoptGradArgs ga, int
 template int launch_bopt_grad<float>(const Geo&, NodesDev, KTabDev, BoptGradArgs, int, hipStream_t);
 template int launch_bopt_grad<double>(const Geo&, NodesDev, KTabDev, BoptGradArgs, int, hipStream_t);
 
+// One workgroup per large problem of a batch, after the blocked factorisation: bdot from the
+// grid gradient and the samples, a = (L L^*)^{-1} bdot, then the member gradients (members in
+// the workgroup's threads, the sums over the other members in a loop).
+template <typename R, int D>
+__global__ void __launch_bounds__(BIG_TPB) k_big_grad(Geo g, BigArgs a, KTabDev kt, BoptGradArgs ga,
+                                                      const int* __restrict__ perm) {
+    using C = cx<R>;
+    const BigProb P = a.probs[blockIdx.x];
+    if (a.fail[P.id]) return;   // uniform: a failed problem has no usable factor
+    const double2* A = a.A + P.off;
+    double2* y = a.mr + P.moff;
+    double2* bv = a.mb + P.moff;
+    const double2* z = a.mz + P.moff;
+    const int* midx = a.midx + P.moff;
+    const int* mtap = a.mtap + P.moff;
+    const C* grid = (const C*)ga.grid;
+    const C* f = (const C*)ga.f;
+    for (int i = threadIdx.x; i < P.n; i += BIG_TPB) {
+        const int p = midx[i];
+        const int j = perm[p];
+        double2 s = make_double2(0.0, 0.0);
+        for (int r = 0; r < ga.nrhs; ++r) {
+            const C gv = grid[(int64_t)r * g.G + P.l];
+            const C fv = f[(int64_t)r * g.N + j];
+            s.x += (double)gv.x * (double)fv.x + (double)gv.y * (double)fv.y;
+            s.y += (double)gv.x * (double)fv.y - (double)gv.y * (double)fv.x;
+        }
+        y[i] = s;
+        bv[i] = ga.B64[(int64_t)mtap[i] * g.N + p];
+    }
+    __syncthreads();
+    big_substitute(P, A, y, P.nblk);
+    __syncthreads();
+    for (int k = threadIdx.x; k < P.n; k += BIG_TPB) {
+        const double2 zk = z[k], ak = y[k], bk = bv[k];
+        const int jk = perm[midx[k]];
+        for (int t = 0; t < D; ++t) {
+            const double Mt = (double)g.Ms[t];
+            const double2 dK = dkernel<D>(kt.K, kt.qK, zk, t);
+            double2 srow = make_double2(0.0, 0.0), scol = make_double2(0.0, 0.0);
+            for (int j = 0; j < P.n; ++j) {
+                const double2 zj = z[j];
+                const double2 dq_row = dkernel<D>(kt.Q, kt.qQ, make_double2(zj.x - zk.x, zj.y - zk.y), t);
+                const double2 dq_col = dkernel<D>(kt.Q, kt.qQ, make_double2(zk.x - zj.x, zk.y - zj.y), t);
+                srow = cadd(srow, cmul(dq_row, bv[j]));
+                scol = cadd(scol, cmul(cconj(y[j]), dq_col));
+            }
+            const double2 ca = cconj(ak);
+            const double2 dr = make_double2(-Mt * dK.x, Mt * dK.y);
+            const double2 v = cadd(csub(cmul(ca, dr), cscale(cmul(ca, srow), kt.scaleG * Mt)),
+                                   cscale(cmul(bk, scol), kt.scaleG * Mt));
+            atomicAdd(&ga.gradx[(int64_t)jk * D + t], v.x);
+        }
+    }
+}
+
+void launch_big_grad(const Geo& g, BigArgs a, KTabDev kt, BoptGradArgs ga, const int* perm, int nprob, bool f32,
+                     hipStream_t s) {
+    if (nprob <= 0) return;
+    const dim3 gr(nprob), bl(BIG_TPB);
+    if (g.d == 1) {
+        if (f32) hipLaunchKernelGGL((k_big_grad<float, 1>), gr, bl, 0, s, g, a, kt, ga, perm);
+        else hipLaunchKernelGGL((k_big_grad<double, 1>), gr, bl, 0, s, g, a, kt, ga, perm);
+    } else {
+        if (f32) hipLaunchKernelGGL((k_big_grad<float, 2>), gr, bl, 0, s, g, a, kt, ga, perm);
+        else hipLaunchKernelGGL((k_big_grad<double, 2>), gr, bl, 0, s, g, a, kt, ga, perm);
+    }
+}
+
 }  // namespace infft

@@ -252,8 +252,83 @@ struct BigArgs {
     int* mtap;     // member -> tap index (row of B_opt)
     double2* mz;   // member -> z = tau - u per dimension
     double2* mr;   // member -> right-hand side, then solution
+    double2* mb;   // member -> its B_opt entry (node gradient pass)
     int* fail;     // per problem id: non-positive pivot
 };
+
+constexpr int BIG_TPB = 256;   // threads of the large-problem kernels
+
+// X[c][q] = (L_kk^{-1})[c][q] from the diagonal block D of the factor.
+__device__ inline double2 inv_entry(const double2* D, int64_t ld, int c, int q) {
+    if (q < c) return cconj(D[(int64_t)q * ld + c]);
+    if (q == c) return make_double2(1.0 / D[(int64_t)c * ld + c].x, 0.0);
+    return make_double2(0.0, 0.0);
+}
+
+// Solves (L L^*) x = y in place for one large problem (the whole workgroup; y in device memory,
+// read and written between barriers by this workgroup only), with the factor of k_big_potrf..herk.
+__device__ inline void big_substitute(const BigProb& P, const double2* A, double2* y, int nblk) {
+    constexpr int NP = BIG_TPB / BIG_NB;
+    __shared__ double2 s_t[BIG_NB];
+    __shared__ double2 red[NP][BIG_NB];
+    const int64_t ld = P.n;
+    const int col = threadIdx.x % BIG_NB, part = threadIdx.x / BIG_NB;
+    // ---- L y = r: y_k = X_k (r_k - sum_{c < r0} L[r0 + i][c] y_c)
+    for (int k = 0; k < nblk; ++k) {
+        const int r0 = k * BIG_NB, nk = min(BIG_NB, P.n - r0);
+        const int i = threadIdx.x / NP, p4 = threadIdx.x % NP;   // NP threads per row
+        double2 acc = make_double2(0.0, 0.0);
+        if (i < nk) {
+            const double2* row = A + (int64_t)(r0 + i) * ld;
+            for (int c = p4; c < r0; c += NP) acc = cadd(acc, cmul(row[c], y[c]));
+        }
+#pragma unroll
+        for (int o = 1; o < NP; o <<= 1) {
+            acc.x += __shfl_xor(acc.x, o, 64);
+            acc.y += __shfl_xor(acc.y, o, 64);
+        }
+        if (p4 == 0 && i < nk) s_t[i] = csub(y[r0 + i], acc);
+        __syncthreads();
+        const double2* D = A + (int64_t)r0 * ld + r0;
+        double2 v = make_double2(0.0, 0.0);
+        if (i < nk)
+            for (int c = p4; c <= i; c += NP) v = cadd(v, cmul(inv_entry(D, ld, i, c), s_t[c]));
+#pragma unroll
+        for (int o = 1; o < NP; o <<= 1) {
+            v.x += __shfl_xor(v.x, o, 64);
+            v.y += __shfl_xor(v.y, o, 64);
+        }
+        if (p4 == 0 && i < nk) y[r0 + i] = v;
+        __syncthreads();
+    }
+    // ---- L^* b = y: b_k = X_k^* (y_k - sum_{i >= r0 + nk} conj(L[i][r0 + c]) b_i)
+    for (int k = nblk - 1; k >= 0; --k) {
+        const int r0 = k * BIG_NB, nk = min(BIG_NB, P.n - r0);
+        double2 acc = make_double2(0.0, 0.0);
+        if (col < nk)
+            for (int i = r0 + nk + part; i < P.n; i += NP) acc = cadd(acc, cmul(cconj(A[(int64_t)i * ld + r0 + col]), y[i]));
+        red[part][col] = acc;
+        __syncthreads();
+        if (part == 0 && col < nk) {
+            double2 s = red[0][col];
+            for (int pp = 1; pp < NP; ++pp) s = cadd(s, red[pp][col]);
+            s_t[col] = csub(y[r0 + col], s);
+        }
+        __syncthreads();
+        const double2* D = A + (int64_t)r0 * ld + r0;
+        double2 v = make_double2(0.0, 0.0);
+        if (col < nk)
+            for (int r = col + part; r < nk; r += NP) v = cadd(v, cmul(cconj(inv_entry(D, ld, r, col)), s_t[r]));
+        red[part][col] = v;
+        __syncthreads();
+        if (part == 0 && col < nk) {
+            double2 s = red[0][col];
+            for (int pp = 1; pp < NP; ++pp) s = cadd(s, red[pp][col]);
+            y[r0 + col] = s;
+        }
+        __syncthreads();
+    }
+}
 
 // ------------------------------------------------------------------ FFT pass description
 
@@ -425,6 +500,9 @@ struct BoptGradArgs {
 };
 template <typename R>
 int launch_bopt_grad(const Geo& g, NodesDev nd, KTabDev kt, BoptGradArgs ga, int nl, hipStream_t s);
+// the same for a batch of large problems, on factors from the blocked Cholesky pass
+void launch_big_grad(const Geo& g, BigArgs a, KTabDev kt, BoptGradArgs ga, const int* perm, int nprob, bool f32,
+                     hipStream_t s);
 
 // solve_big.hip
 void launch_big_count(const Geo& g, NodesDev nd, const int* list, int count, int* nout, hipStream_t s);

@@ -22,7 +22,6 @@
 
 namespace infft {
 
-constexpr int BIG_TPB = 256;
 constexpr int CELL_TPB = 128;
 constexpr int MAX_CELLS = (2 * MAX_M_CUT + 1) * (2 * MAX_M_CUT + 1);
 
@@ -247,13 +246,6 @@ __global__ void __launch_bounds__(BIG_TPB) k_big_potrf(BigArgs a, int k) {
     if (!ok && threadIdx.x == 0) a.fail[P.id] = 1;
 }
 
-// X[c][q] = (L_kk^{-1})[c][q] from the diagonal block D of the factor.
-__device__ inline double2 inv_entry(const double2* D, int64_t ld, int c, int q) {
-    if (q < c) return cconj(D[(int64_t)q * ld + c]);
-    if (q == c) return make_double2(1.0 / D[(int64_t)c * ld + c].x, 0.0);
-    return make_double2(0.0, 0.0);
-}
-
 void launch_big_potrf(BigArgs a, int nprob, int k, hipStream_t s) {
     if (nprob <= 0) return;
     hipLaunchKernelGGL(k_big_potrf, dim3(nprob), dim3(BIG_TPB), 0, s, a, k);
@@ -389,72 +381,13 @@ void launch_big_herk(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t
 // to its threads after each barrier.
 __global__ void __launch_bounds__(BIG_TPB) k_big_solve(Geo g, BigArgs a, double2* __restrict__ B64,
                                                        float2* __restrict__ B32) {
-    constexpr int NP = BIG_TPB / BIG_NB;
-    __shared__ double2 s_t[BIG_NB];
-    __shared__ double2 red[NP][BIG_NB];
     const BigProb P = a.probs[blockIdx.x];
     const int fl = a.fail[P.id];   // 1: non-positive pivot (zero column written), 2: no members known
     if (fl == 2) return;
     const double2* A = a.A + P.off;
-    const int64_t ld = P.n;
     double2* y = a.mr + P.moff;
-    const int col = threadIdx.x % BIG_NB, part = threadIdx.x / BIG_NB;
     const int nblk = fl ? 0 : P.nblk;
-    // ---- L y = r: y_k = X_k (r_k - sum_{c < r0} L[r0 + i][c] y_c)
-    for (int k = 0; k < nblk; ++k) {
-        const int r0 = k * BIG_NB, nk = min(BIG_NB, P.n - r0);
-        const int i = threadIdx.x / NP, p4 = threadIdx.x % NP;   // NP threads per row
-        double2 acc = make_double2(0.0, 0.0);
-        if (i < nk) {
-            const double2* row = A + (int64_t)(r0 + i) * ld;
-            for (int c = p4; c < r0; c += NP) acc = cadd(acc, cmul(row[c], y[c]));
-        }
-#pragma unroll
-        for (int o = 1; o < NP; o <<= 1) {
-            acc.x += __shfl_xor(acc.x, o, 64);
-            acc.y += __shfl_xor(acc.y, o, 64);
-        }
-        if (p4 == 0 && i < nk) s_t[i] = csub(y[r0 + i], acc);
-        __syncthreads();
-        const double2* D = A + (int64_t)r0 * ld + r0;
-        double2 v = make_double2(0.0, 0.0);
-        if (i < nk)
-            for (int c = p4; c <= i; c += NP) v = cadd(v, cmul(inv_entry(D, ld, i, c), s_t[c]));
-#pragma unroll
-        for (int o = 1; o < NP; o <<= 1) {
-            v.x += __shfl_xor(v.x, o, 64);
-            v.y += __shfl_xor(v.y, o, 64);
-        }
-        if (p4 == 0 && i < nk) y[r0 + i] = v;
-        __syncthreads();
-    }
-    // ---- L^* b = y: b_k = X_k^* (y_k - sum_{i >= r0 + nk} conj(L[i][r0 + c]) b_i)
-    for (int k = nblk - 1; k >= 0; --k) {
-        const int r0 = k * BIG_NB, nk = min(BIG_NB, P.n - r0);
-        double2 acc = make_double2(0.0, 0.0);
-        if (col < nk)
-            for (int i = r0 + nk + part; i < P.n; i += NP) acc = cadd(acc, cmul(cconj(A[(int64_t)i * ld + r0 + col]), y[i]));
-        red[part][col] = acc;
-        __syncthreads();
-        if (part == 0 && col < nk) {
-            double2 s = red[0][col];
-            for (int pp = 1; pp < NP; ++pp) s = cadd(s, red[pp][col]);
-            s_t[col] = csub(y[r0 + col], s);
-        }
-        __syncthreads();
-        const double2* D = A + (int64_t)r0 * ld + r0;
-        double2 v = make_double2(0.0, 0.0);
-        if (col < nk)
-            for (int r = col + part; r < nk; r += NP) v = cadd(v, cmul(cconj(inv_entry(D, ld, r, col)), s_t[r]));
-        red[part][col] = v;
-        __syncthreads();
-        if (part == 0 && col < nk) {
-            double2 s = red[0][col];
-            for (int pp = 1; pp < NP; ++pp) s = cadd(s, red[pp][col]);
-            y[r0 + col] = s;
-        }
-        __syncthreads();
-    }
+    big_substitute(P, A, y, nblk);
     for (int i = threadIdx.x; i < P.n; i += BIG_TPB) {
         const int64_t idx = (int64_t)a.mtap[P.moff + i] * g.N + a.midx[P.moff + i];
         const double2 b = fl ? make_double2(0.0, 0.0) : y[i];

@@ -46,15 +46,25 @@ def test_bopt_gradient_matches_oracle(precision, tol, M, N, d, kind, m, rho, ker
     P.close()
 
 
-def test_bopt_gradient_rejects_large_problems():
-    from paper_1811_05335_amd import InfftError, NfftPlan
-    g = W.rng(92)
-    M, N = (32, 32), 700
-    x = W.clustered_nodes(g, N, 2, 300, 2.5 / 64)
-    P = NfftPlan(M, nodes_dev(x), m=3, precision="f64", rho=1e-8)
+@pytest.mark.parametrize("d", [1, 2])
+def test_bopt_gradient_large_problems(d):
+    """Clustered nodes: local problems beyond 32 members go through the blocked pass."""
+    from paper_1811_05335_amd import NfftPlan
+    g = W.rng(92 + d)
+    if d == 2:
+        M, N, m, ncl, half = (32, 32), 700, 3, 300, 2.5
+    else:
+        M, N, m, ncl, half = (64,), 400, 4, 150, 2.0
+    x = W.clustered_nodes(g, N, d, ncl, half / (2 * M[0]))
+    p = onfft.Params(M, 2.0, m)
+    assert obopt.Members(x, p).sizes().max() > 64
+    f = W.complex_normal(g, (1, N))
+    c = W.complex_normal(g, (1,) + M)
+    P = NfftPlan(M, nodes_dev(x), m=m, precision="f64", rho=1e-6)
     P.precompute_B()
-    with pytest.raises(InfftError):
-        P.grad_x_bopt(dev(W.complex_normal(g, (1, N)), "f64"), dev(W.complex_normal(g, (1,) + M), "f64"))
+    gx = P.grad_x_bopt(dev(f, "f64"), dev(c, "f64")).cpu().numpy()
+    ref = ograd.bopt_grad_x(x, f, c, p, 1e-6)
+    assert rel(gx, ref) <= 1e-6
     P.close()
 
 

@@ -474,3 +474,146 @@ def test_bopt_gradient_matches_finite_differences(d, kernel):
             xm[j, t] -= h
             fd[j, t] = (L(xp) - L(xm)) / (2 * h)
     assert rel(an, fd) < 1e-6
+
+
+# ------------------------------------------------------------------ ansatz 1 (Section 3.2.1, Algorithm 3.10)
+
+from oracle import ansatz1 as a1  # noqa: E402
+
+
+def _a1_problem(seed, N, M, sigma=2.0, m=3, kernel="window"):
+    g = W.rng(seed)
+    return W.jittered_nodes(g, N), nfft.Params((M,), sigma, m, kernel=kernel)
+
+
+@pytest.mark.parametrize("kernel,sigma", [("window", 2.0), ("dirichlet", 2.0), ("window", 1.25)])
+def test_ansatz1_K_is_the_dense_factor_product(kernel, sigma):
+    """(3.14): K = A D^* F^* entry by entry, with F in FFT row order and the inverse's D; the
+    column route through e^{2 pi i k x_h} agrees."""
+    x, p = _a1_problem(70, 21, 16, sigma, 2, kernel)
+    K = a1.K_matrix(x, p)
+    Kd = direct.ndft_matrix(x, p.M) @ np.diag(p.deconv_inv_full().ravel()) @ nfft.dense_F(p).conj().T
+    assert rel(K, Kd) < 1e-13
+    cols = np.array([0, 3, p.Ms[0] - 1, p.Ms[0] // 2])
+    assert rel(a1.K_columns(x, cols, p), K[:, cols]) < 1e-13
+
+
+def test_ansatz1_dirichlet_K_closed_form():
+    """Remark 3.11 / (3.23): with the Dirichlet kernel K_j's entries are
+    D_{M/2-1}(x_h - l/M_sigma) / M_sigma, D_{M/2-1}(y) = sin((M-1) pi y) / sin(pi y)."""
+    x, p = _a1_problem(71, 13, 20, 2.0, 2, "dirichlet")
+    K = a1.K_matrix(x, p)
+    Ms = p.Ms[0]
+    lpos = np.arange(Ms)
+    y = x[:, 0][:, None] - np.where(lpos < Ms // 2, lpos, lpos - Ms)[None, :] / Ms
+    closed = np.sin((p.M[0] - 1) * np.pi * y) / np.sin(np.pi * y) / Ms
+    assert np.max(np.abs(K - closed)) < 1e-13 * np.max(np.abs(closed))
+
+
+def test_ansatz1_toeplitz_symbol_and_gram_band():
+    """A^* A is Toeplitz with symbol P(q) = sum_h e^{2 pi i q x_h}; the band of K^* K built from
+    P and R_d by direct sums equals the band read off the dense K^* K, for sigma = 2 and sigma < 2
+    (where 2M - 1 frequencies exceed M_sigma)."""
+    for kernel, sigma in (("window", 2.0), ("dirichlet", 2.0), ("window", 1.5)):
+        x, p = _a1_problem(72, 19, 16, sigma, 3, kernel)
+        A = direct.ndft_matrix(x, p.M)
+        AhA = A.conj().T @ A
+        P = a1.toeplitz_symbol(x, p)
+        M = p.M[0]
+        k = np.arange(M)
+        expect = P[(k[None, :] - k[:, None]) + M - 1]
+        assert rel(AhA, expect) < 1e-13
+        S = a1.gram_band(x, p)
+        Sd = a1.gram_band_direct(a1.K_matrix(x, p), p)
+        assert rel(S, Sd) < 1e-12
+
+
+@pytest.mark.parametrize("kernel,rho", [("window", 0.0), ("window", 1e-8), ("dirichlet", 0.0), ("dirichlet", 1e-6)])
+def test_ansatz1_routes_agree_and_stationarity(kernel, rho):
+    """Routes E (lstsq on the definition) and T (Toeplitz Gram, normal equations) agree, and
+    each y_j satisfies K_j^* (K_j y_j - e_j) + lambda_j y_j = 0 on I(x_j)."""
+    x, p = _a1_problem(73, 24, 64, 2.0, 3, kernel)
+    K = a1.K_matrix(x, p)
+    rE = a1.rows_E(x, p, rho, K=K)
+    rT = a1.rows_T(x, p, rho)
+    assert rel(rT, rE) < 1e-8
+    idx, mem = a1.stencil(x, p)
+    for j in range(x.shape[0]):
+        t = np.nonzero(mem[j])[0]
+        Kj = K[:, idx[j, t]]
+        y = np.conj(rE[j, t])
+        lam = rho * np.sum(np.abs(Kj) ** 2) / len(t)
+        e = np.zeros(x.shape[0])
+        e[j] = 1.0
+        grad_ = Kj.conj().T @ (Kj @ y - e) + lam * y
+        assert np.linalg.norm(grad_) < 1e-9 * np.linalg.norm(Kj.conj().T @ e)
+        assert np.all(rE[j, ~mem[j]] == 0)
+
+
+def test_ansatz1_columns_split_the_frobenius_problem():
+    """(3.18)-(3.19): minimising ||K B^* - M I||_F jointly over every nonzero of B^* (one stacked
+    least-squares problem) gives the per-node solutions."""
+    x, p = _a1_problem(74, 9, 32, 2.0, 2)
+    K = a1.K_matrix(x, p)
+    idx, mem = a1.stencil(x, p)
+    N, Mv = x.shape[0], p.M[0]
+    cols = [(j, t) for j in range(N) for t in np.nonzero(mem[j])[0]]
+    # vec(K B^*): entry (h, j) = sum_t K[h, idx[j,t]] B^*[idx[j,t], j]
+    Big = np.zeros((N * N, len(cols)), dtype=np.complex128)
+    for c, (j, t) in enumerate(cols):
+        Big[np.arange(N) * N + j, c] = K[:, idx[j, t]]
+    target = (Mv * np.eye(N)).ravel().astype(np.complex128)
+    sol = np.linalg.lstsq(Big, target, rcond=None)[0]
+    rows = a1.rows_E(x, p, 0.0, K=K)
+    per = np.array([Mv * np.conj(rows[j, t]) for (j, t) in cols])
+    assert rel(sol, per) < 1e-9
+
+
+def test_ansatz1_objective_monotone_rank_bound_and_underdetermined_gain():
+    """Example 3.13's findings as inequalities: the optimised B^* never does worse than the window's
+    on (3.24) nor than random perturbations of itself; for M < N no B reaches below the rank bound
+    M sqrt(N - M) (K B^* has rank <= M), and the optimum sits at it; for M = 4N the optimisation cuts
+    the norm by orders of magnitude."""
+    g = W.rng(75)
+    N = 32
+    x = W.jittered_nodes(g, N)
+    for M, m in ((8, 2), (16, 2), (128, 4)):
+        p = nfft.Params((M,), 2.0, m)
+        K = a1.K_matrix(x, p)
+        rows = a1.rows_E(x, p, 0.0, K=K)
+        o = a1.objective(x, rows, p, K=K)
+        o_plain = a1.objective(x, a1.plain_rows(x, p), p, K=K)
+        assert o <= o_plain
+        _, mem = a1.stencil(x, p)
+        for _ in range(3):
+            pert = rows + 1e-3 * np.abs(rows).max() * W.complex_normal(g, rows.shape) * mem
+            assert o <= a1.objective(x, pert, p, K=K)
+        if M < N:
+            bound = M * np.sqrt(N - M)
+            assert o >= bound * (1 - 1e-12)
+            assert o <= bound * 1.05
+        else:
+            assert o < 1e-2 * o_plain
+
+
+def test_ansatz1_reconstruction_and_inverse_adjoint_example_3_14():
+    """Example 3.14 / 3.16 setting (Dirichlet kernel, sigma = 2, jittered nodes, M = 4N, m = 4):
+    A f_check reproduces f = A fhat closely, and f_tilde = (1/M) B_opt F D (A^* f) of Remark 3.15
+    reproduces f; both estimates are adjoint to each other; B_opt is real."""
+    g = W.rng(76)
+    N = 32
+    M = 4 * N
+    x = W.jittered_nodes(g, N)
+    p = nfft.Params((M,), 2.0, 4, kernel="dirichlet")
+    rows = a1.rows_E(x, p, 0.0)
+    assert np.max(np.abs(rows.imag)) < 1e-9 * np.max(np.abs(rows))
+    fh = W.complex_normal(g, (M,))
+    f = direct.ndft(x, fh)
+    fc = bopt.apply(x, f, rows, p)
+    r_inv = rel(direct.ndft(x, fc), f)
+    ft = bopt.apply_adjoint(x, direct.ndft_adjoint(x, f, p.M), rows, p)
+    r_adj = rel(ft, f)
+    r_plain = rel(direct.ndft(x, nfft.adjoint(x, f, nfft.Params((M,), 2.0, 4)) / M), f)
+    assert r_inv < 1e-2 and r_adj < 1e-2 and r_inv < 1e-1 * r_plain
+    hh = W.complex_normal(g, (M,))
+    assert abs(np.vdot(f, bopt.apply_adjoint(x, hh, rows, p)) - np.vdot(fc, hh)) < 1e-12 * np.linalg.norm(f) * np.linalg.norm(hh) * np.abs(rows).max() * M

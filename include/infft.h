@@ -79,7 +79,7 @@ typedef struct {
 #define INFFT_KERNEL_DIRICHLET 1
 
 typedef struct {
-    int64_t nonfinite_nodes;  /* nodes rejected as NaN/Inf (their samples are set to 0) */
+    int64_t nonfinite_nodes;  /* nodes with a NaN/Inf coordinate (counted; the coordinate is taken as 0) */
     int64_t failed_solves;    /* local problems whose Cholesky met a pivot <= 0 */
     int64_t empty_columns;    /* grid indices l with empty I(l): zero column of B_opt */
     int64_t oversized;        /* local problems not solved because the precompute ran under
@@ -124,6 +124,21 @@ int nfft_adjoint(infft_plan p, const void* f, void* h, int nrhs);
  * graph capture that pass is skipped and the problems are counted in infft_status.oversized. */
 int infft_precompute_B(infft_plan p);
 
+/* Algorithm 3.10 (ansatz 1 of Section 3.2.1, the underdetermined inverse NFFT): optimises the
+ * nonzero entries of B^* column by column, one regularised least-squares problem per node j over
+ * the grid indices I(x_j) of (3.16), b~_j = M (K_j^* K_j + lambda_j I)^{-1} K_j^* e_j ((3.21)-(3.22))
+ * with K = A D^* F^* (3.14) built on the inverse's D (window or Dirichlet, Remark 3.11) and
+ * lambda_j = rho trace(K_j^* K_j) / |I(x_j)|.  The Gram matrices come from one banded table of
+ * K^* K computed through the Toeplitz structure of A^* A (an adjoint NFFT of bandwidth 2M on the
+ * plan's nodes and length-M_sigma FFTs, all FP64), the solves are FP64 whatever the plan precision.
+ * Replaces the plan's B_opt: afterwards infft_apply computes the paper's estimate
+ * f_check = (1/M) D^* F^* B_opt^* f and infft_apply_adjoint the inverse adjoint
+ * f_tilde = (1/M) B_opt F D h of Remark 3.15; infft_get_B returns conj(b~_j) / M per node.
+ * d = 1 single-problem plans only (INFFT_EINVAL otherwise); INFFT_ESTATE under graph capture.  The
+ * first call creates two inner plans (allocates and synchronises); failed solves are counted in
+ * infft_status.failed_solves and leave zero rows. */
+int infft_precompute_Bstar(infft_plan p);
+
 /* Modified adjoint NFFT (3.32): fcheck = D^* F^* B_opt^* f ~ fhat.  f [nrhs][N],
  * fcheck [nrhs][M...].  Returns INFFT_ESTATE before infft_precompute_B. */
 int infft_apply(infft_plan p, const void* f, void* fcheck, int nrhs);
@@ -145,8 +160,8 @@ int nfft_grad_x(infft_plan p, const void* fhat, const void* gradf, double* gradx
  * plan precision; gradx float64 [N][d] is overwritten.  The total node gradient of a loss through
  * both the NFFT and the modified adjoint is the sum of nfft_grad_x and this.  Synchronises the
  * stream (it reads the sizes of local problems above 32 members back, like infft_precompute_B, and
- * solves those on the blocked Cholesky pass); returns INFFT_ESTATE before infft_precompute_B and
- * for batch plans. */
+ * solves those on the blocked Cholesky pass); returns INFFT_ESTATE before infft_precompute_B, for
+ * batch plans, and when B holds the result of infft_precompute_Bstar. */
 int infft_grad_x_bopt(infft_plan p, const void* f, const void* gradfc, double* gradx, int nrhs);
 
 /* Copies B_opt to `rows` (device, complex128 [N][(2m+1)^d], caller node order, tap index

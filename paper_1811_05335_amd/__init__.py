@@ -9,6 +9,7 @@ from .plan import (  # noqa: F401
     infft_apply_adjoint,
     infft_get_B,
     infft_precompute_B,
+    infft_precompute_Bstar,
     nfft_adjoint,
     nfft_grad_x,
     nfft_plan,

@@ -85,6 +85,7 @@ def load() -> C.CDLL:
         "nfft_trafo": (i32, [vp, vp, vp, i32]),
         "nfft_adjoint": (i32, [vp, vp, vp, i32]),
         "infft_precompute_B": (i32, [vp]),
+        "infft_precompute_Bstar": (i32, [vp]),
         "infft_apply": (i32, [vp, vp, vp, i32]),
         "infft_apply_adjoint": (i32, [vp, vp, vp, i32]),
         "nfft_grad_x": (i32, [vp, vp, vp, vp, i32]),

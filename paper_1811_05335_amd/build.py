@@ -14,7 +14,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libinfft.so")
 
-SOURCES = ["nodes.hip", "tables.hip", "fft.hip", "spread.hip", "solve.hip", "solve_big.hip", "grad_bopt.hip", "abi.cpp"]
+SOURCES = ["nodes.hip", "tables.hip", "fft.hip", "spread.hip", "solve.hip", "solve_big.hip", "grad_bopt.hip", "ansatz1.hip", "abi.cpp"]
 ARCH = os.environ.get("INFFT_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

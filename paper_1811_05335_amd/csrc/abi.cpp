@@ -135,6 +135,12 @@ struct infft_plan_s {
 
     double2* B64 = nullptr;
     float2* B32 = nullptr;
+    int bopt_kind = 0;         // what B holds: 0 B_opt of Algorithm 3.17, 1 B_opt^* of Algorithm 3.10
+    // Algorithm 3.10: inner FP64 plans and work arrays, made on first use
+    infft_plan_s* a1_pplan = nullptr;   // bandwidth 2M, sigma 2: the Toeplitz symbol P(q)
+    infft_plan_s* a1_fplan = nullptr;   // FP64 twin of an FP32 plan: length-M_sigma FFTs in FP64
+    double2* a1_buf = nullptr;
+    int64_t a1_cap = 0;
     int* lists = nullptr;      // one list of grid indices for problems passed to the wider tier
     int* lcount = nullptr;
     long long* stat_rec = nullptr;   // per-block statistics of the solve kernels
@@ -203,6 +209,8 @@ struct infft_plan_s {
 
     ~infft_plan_s() {
         if (batch) batch_free(batch);
+        delete a1_pplan;
+        delete a1_fplan;
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
     }
@@ -354,13 +362,14 @@ int build_schedule(infft_plan_s* P, int nrhs, std::vector<FftStep>& to_grid, std
 }
 
 int run_fft(infft_plan_s* P, const std::vector<FftStep>& steps, const void* user_in, void* user_out,
-            bool inv = false) {
+            bool inv = false, void* buf1 = nullptr, void* buf2 = nullptr) {
     const Geo& g = P->g;
     for (const FftStep& s : steps) {
         FftIO io{};
         auto buf = [&](int which, bool input) -> void* {
             if (which == 0) return input ? (void*)user_in : user_out;
-            return which == 1 ? P->grid : P->grid2;
+            if (which == 1) return buf1 ? buf1 : P->grid;
+            return buf2 ? buf2 : P->grid2;
         };
         io.in = buf(s.in_buf, true);
         io.out = buf(s.out_buf, false);
@@ -465,6 +474,29 @@ int check_rhs(infft_plan_s* P, int nrhs) {
 // Schedules are built per chunk size (the number of sequences enters the pass descriptors).
 int schedule_for(infft_plan_s* P, int rc) {
     return build_schedule(P, rc, P->to_grid, P->to_coeff);
+}
+
+// Plain DFTs of length M_sigma (1-D plans) over `nrhs` rows in grid order,
+// out[r][l] = sum_s in[r][s] e^{sign 2 pi i s l / M_sigma}: the plan's own passes with grid loads and
+// stores; buffer 0 in and out, buffer 2 between the two passes of a split length.
+int build_plain_fft(infft_plan_s* P, int nrhs, int sign, std::vector<FftStep>& steps) {
+    std::vector<FftStep> tg, tc;
+    int rc = build_schedule(P, nrhs, tg, tc);
+    if (rc) return rc;
+    const int64_t G = P->g.G;
+    steps = sign > 0 ? tg : tc;
+    for (size_t i = 0; i < steps.size(); ++i) {
+        FftStep& st = steps[i];
+        const bool last = i + 1 == steps.size();
+        st.pass.sign = sign;
+        st.ld = LD_GRID;
+        st.st = last ? ST_GRID : ST_TWIDDLE;
+        st.in_buf = i == 0 ? 0 : 2;
+        st.out_buf = last ? 0 : 2;
+        st.pass.in_rs = G;
+        st.pass.out_rs = G;
+    }
+    return INFFT_OK;
 }
 
 KTabDev plan_ktab(const infft_plan_s* p) {
@@ -865,6 +897,7 @@ int batch_precompute(infft_plan_s* P) {
             sub->stat_nrec = off;
         }
     }
+    P->bopt_kind = 0;
     P->bopt_ready = true;
     return INFFT_OK;
 }
@@ -1294,6 +1327,97 @@ int infft_precompute_B(infft_plan p) {
         if (rc) return rc;
     }
     p->stat_nrec = stat_off;   // folded into the status block by nfft_plan_status
+    p->bopt_kind = 0;
+    p->bopt_ready = true;
+    return INFFT_OK;
+}
+
+int infft_precompute_Bstar(infft_plan p) {
+    if (!p) return fail(INFFT_EINVAL, "null plan");
+    if (p->batch) return fail(INFFT_EINVAL, "infft_precompute_Bstar takes a single-problem plan");
+    const Geo& g = p->g;
+    if (g.d != 1) return fail(INFFT_EINVAL, "infft_precompute_Bstar is defined for d = 1");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(p->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(INFFT_ESTATE, "infft_precompute_Bstar cannot run under graph capture");
+    int rc;
+    const int M = g.M[0], Ms = g.Ms[0], m = g.m;
+    const int nd_all = 2 * m + 1;
+    hipStream_t s = p->stream;
+    p->bopt_ready = false;
+    // Toeplitz symbol P(q), |q| < M: adjoint NFFT of ones at bandwidth 2M, sigma 2 and the largest
+    // cut-off (FP64 accuracy whatever the plan's own m and sigma)
+    if (!p->a1_pplan) {
+        infft_options o;
+        infft_default_options(&o);
+        o.precision = INFFT_F64;
+        const int64_t M2 = 2 * (int64_t)M;
+        const int m2 = std::min<int>(MAX_M_CUT, (int)(2 * M2 - 2) / 2);
+        infft_plan q = nullptr;
+        if ((rc = nfft_plan(&q, 1, &M2, g.N, 2.0, m2, p->nd.xw, &o, s))) return rc;
+        p->a1_pplan = q;
+    } else if ((rc = set_nodes_impl(p->a1_pplan, p->nd.xw))) {
+        return rc;
+    }
+    // length-M_sigma FFTs in FP64: the plan itself, or an FP64 twin of an FP32 plan
+    infft_plan_s* F = p;
+    if (p->prec != INFFT_F64) {
+        if (!p->a1_fplan) {
+            infft_options o;
+            infft_default_options(&o);
+            o.precision = INFFT_F64;
+            o.inverse_kernel = p->inv_kernel;
+            const int64_t Mv = M;
+            infft_plan q = nullptr;
+            if ((rc = nfft_plan(&q, 1, &Mv, 1, p->sigma, m, p->nd.xw, &o, s))) return rc;
+            p->a1_fplan = q;
+        }
+        F = p->a1_fplan;
+    }
+    // work arrays (complex128): S [2m+1][Ms], a [2][Ms], then per chunk of dc shifts d:
+    // products [4][dc][Ms], R [4][dc][Ms], V [dc][Ms], FFT intermediate [4][dc][Ms]; h [2M], bands
+    // [2][M], ones [N]
+    const int dc = (int)std::max<int64_t>(1, std::min<int64_t>(nd_all, ((int64_t)1 << 27) / (13 * (int64_t)Ms)));
+    const int64_t need = (int64_t)(nd_all + 2 + 13 * dc) * Ms + 4 * (int64_t)M + g.N;
+    if ((rc = p->grow(&p->a1_buf, p->a1_cap, need))) return rc;
+    double2* S = p->a1_buf;
+    double2* a = S + (int64_t)nd_all * Ms;
+    double2* prod = a + 2 * (int64_t)Ms;
+    double2* Rb = prod + 4 * (int64_t)dc * Ms;
+    double2* V = Rb + 4 * (int64_t)dc * Ms;
+    double2* tmp = V + (int64_t)dc * Ms;
+    double2* h = tmp + 4 * (int64_t)dc * Ms;
+    double2* bands = h + 2 * (int64_t)M;
+    double2* ones = bands + 2 * (int64_t)M;
+    launch_status_init(p->status, 1, s);
+    launch_a1_ones(ones, g.N, s);
+    LAUNCH_CHECK();
+    if ((rc = nfft_adjoint(p->a1_pplan, ones, h, 1))) return rc;
+    // a^lo, a^hi: the two half bands of K on the grid, F D 1_band with the inverse's D
+    launch_a1_bands(bands, M, s);
+    LAUNCH_CHECK();
+    std::vector<FftStep> tg, tc, fw, bw;
+    if ((rc = build_schedule(F, 2, tg, tc))) return rc;
+    if ((rc = run_fft(F, tg, bands, nullptr, true, a, tmp))) return rc;
+    for (int d0 = 0; d0 < nd_all; d0 += dc) {
+        const int nd = std::min(dc, nd_all - d0);
+        if ((rc = build_plain_fft(F, 4 * nd, -1, fw))) return rc;
+        if ((rc = build_plain_fft(F, nd, -1, bw))) return rc;
+        launch_a1_products(a, prod, Ms, d0, nd, 1.0 / (double)Ms, s);
+        LAUNCH_CHECK();
+        if ((rc = run_fft(F, fw, prod, Rb, false, nullptr, tmp))) return rc;
+        launch_a1_fold(Rb, h, V, M, Ms, nd, s);
+        LAUNCH_CHECK();
+        if ((rc = run_fft(F, bw, V, S + (int64_t)d0 * Ms, false, nullptr, tmp))) return rc;
+    }
+    {
+        ProfScope ps(p, INFFT_K_SOLVE);
+        launch_a1_solve(g, p->nd, S, p->Ktab[0], p->qK, p->rho, p->B64, p->B32, p->status, s);
+    }
+    LAUNCH_CHECK();
+    p->stat_nrec = 0;
+    p->bopt_kind = 1;
     p->bopt_ready = true;
     return INFFT_OK;
 }
@@ -1370,6 +1494,8 @@ int infft_grad_x_bopt(infft_plan p, const void* f, const void* gradfc, double* g
     if (!f || !gradfc || !gradx) return fail(INFFT_EINVAL, "null data pointer");
     if (p->batch) return fail(INFFT_ESTATE, "infft_grad_x_bopt takes a single-problem plan");
     if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_grad_x_bopt before infft_precompute_B");
+    if (p->bopt_kind != 0)
+        return fail(INFFT_ESTATE, "infft_grad_x_bopt differentiates the B_opt of infft_precompute_B, not of infft_precompute_Bstar");
     const Geo& g = p->g;
     launch_fill_bytes0(gradx, (int64_t)sizeof(double) * g.N * g.d, p->stream);
     const KTabDev kt = plan_ktab(p);
@@ -1473,6 +1599,8 @@ int nfft_plan_status(infft_plan p, infft_status* out) {
 int64_t nfft_plan_device_bytes(infft_plan p) {
     if (!p) return 0;
     int64_t b = p->bytes;
+    if (p->a1_pplan) b += p->a1_pplan->bytes;
+    if (p->a1_fplan) b += p->a1_fplan->bytes;
     if (p->batch)
         for (const infft_plan_s* s : p->batch->subs) b += s->bytes;
     return b;

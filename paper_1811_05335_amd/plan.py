@@ -119,6 +119,12 @@ class NfftPlan:
         self._sync_stream()
         check(load().infft_precompute_B(self._h))
 
+    def precompute_Bstar(self) -> None:
+        """Algorithm 3.10 (ansatz 1): per-node optimisation of B^*; afterwards `apply` is the
+        estimate (1/M) D^* F^* B_opt^* f and `apply_adjoint` the inverse adjoint of Remark 3.15."""
+        self._sync_stream()
+        check(load().infft_precompute_Bstar(self._h))
+
     def apply(self, f: torch.Tensor) -> torch.Tensor:
         ff, lead, R = self._samples(f)
         out = torch.empty(tuple(lead) + self.M, dtype=self.ctype, device=self.device)
@@ -345,6 +351,10 @@ def nfft_adjoint(plan: NfftPlan, f):
 
 def infft_precompute_B(plan: NfftPlan):
     return plan.precompute_B()
+
+
+def infft_precompute_Bstar(plan: NfftPlan):
+    return plan.precompute_Bstar()
 
 
 def infft_apply(plan: NfftPlan, f):

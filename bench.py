@@ -412,6 +412,44 @@ def secondary_small(steps, warmup):
             "timing": "hipGraph replay of the whole path (launch-latency bound at this size)"}
 
 
+def secondary_ansatz1(steps, warmup):
+    """Algorithm 3.10 (ansatz 1) at Example 3.14's largest case and at GPU scale (Dirichlet kernel,
+    sigma 2, m 4, M = 4N, FP64): the precompute of B_opt^* (eager: it creates inner plans on first
+    use and is not capturable), then the estimate f_check and the inverse adjoint (graph replays),
+    and the relative residual ||A f_check - f|| / ||f|| with A applied by the plan's NFFT."""
+    import torch
+    from paper_1811_05335_amd import NfftPlan
+    out = {}
+    for name in ("a1", "a1_large"):
+        cfg = W.CONFIGS[name]
+        x, fh = W.make_problem(cfg, seed=0, rhs=1)
+        xd = torch.from_numpy(x).cuda()
+        P = NfftPlan(cfg["M"], xd, sigma=cfg["sigma"], m=cfg["m"], precision="f64", rho=cfg["rho"],
+                     kernel=cfg["kernel"])
+        f = P.trafo(torch.from_numpy(fh).cuda())
+        P.precompute_Bstar()            # first call: inner plans
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        reps = max(3, steps // 4)
+        ev[0].record()
+        for _ in range(reps):
+            P.precompute_Bstar()
+        ev[1].record()
+        torch.cuda.synchronize()
+        pre_ms = ev[0].elapsed_time(ev[1]) / reps
+        st = P.status()
+        fc = P.apply(f)
+        ap_ms = timed_graph(torch, lambda: P.apply(f), steps, warmup)
+        ad_ms = timed_graph(torch, lambda: P.apply_adjoint(fc), steps, warmup)
+        res = float(torch.linalg.vector_norm(P.trafo(fc) - f) / torch.linalg.vector_norm(f))
+        out[name] = {"N": cfg["N"], "M": cfg["M"][0], "m": cfg["m"], "kernel": cfg["kernel"],
+                     "precompute_ms": pre_ms, "apply_ms": ap_ms, "apply_adjoint_ms": ad_ms,
+                     "nodes_per_s_precompute": cfg["N"] / (pre_ms * 1e-3),
+                     "failed_solves": st["failed_solves"], "residual": res}
+        P.close()
+    return out
+
+
 def cpu_baseline(x, fh, gf, rho, m, sigma, M, sample):
     from oracle import bopt, grad, nfft
 
@@ -570,6 +608,9 @@ def main():
         log(f"[bench] spiral: {line['secondary']['spiral_2d_autograd']}")
         line["secondary"]["small_1d"] = secondary_small(max(20, a.steps), 3)
         log(f"[bench] small: {line['secondary']['small_1d']}")
+        log("[bench] ansatz 1 (Algorithm 3.10): N = 4096, M = 16384 and N = 262144, M = 1048576")
+        line["secondary"]["ansatz1_1d"] = secondary_ansatz1(max(10, a.steps), 3)
+        log(f"[bench] ansatz 1: {line['secondary']['ansatz1_1d']}")
     if not a.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline (B optimisation sampled on {a.cpu_sample} grid indices)")
         cb = cpu_baseline(x, fh, gf, rho, m, sigma, M, a.cpu_sample)

@@ -141,6 +141,7 @@ struct infft_plan_s {
     infft_plan_s* a1_fplan = nullptr;   // FP64 twin of an FP32 plan: length-M_sigma FFTs in FP64
     double2* a1_buf = nullptr;
     int64_t a1_cap = 0;
+    bool a1_R_ready = false;            // the node-independent correlations R_d are in a1_buf
     int* lists = nullptr;      // one list of grid indices for problems passed to the wider tier
     int* lcount = nullptr;
     long long* stat_rec = nullptr;   // per-block statistics of the solve kernels
@@ -1375,42 +1376,52 @@ int infft_precompute_Bstar(infft_plan p) {
         }
         F = p->a1_fplan;
     }
-    // work arrays (complex128): S [2m+1][Ms], a [2][Ms], then per chunk of dc shifts d:
-    // products [4][dc][Ms], R [4][dc][Ms], V [dc][Ms], FFT intermediate [4][dc][Ms]; h [2M], bands
-    // [2][M], ones [N]
-    const int dc = (int)std::max<int64_t>(1, std::min<int64_t>(nd_all, ((int64_t)1 << 27) / (13 * (int64_t)Ms)));
-    const int64_t need = (int64_t)(nd_all + 2 + 13 * dc) * Ms + 4 * (int64_t)M + g.N;
+    // K on the grid, whole (M_sigma >= 2M - 1: the products' frequencies |q| < M do not alias) or
+    // in two half bands (four products per shift)
+    const int nb = Ms >= 2 * M - 1 ? 1 : 2;
+    const int npair = nb == 1 ? 1 : 4;
+    // work arrays (complex128): S [2m+1][Ms]; R_d [npair][2m+1][Ms], which depends only on M, sigma, m
+    // and the kernel and is kept; V [2m+1][Ms]; the FFT intermediate [2m+1][Ms]; the products
+    // [npair][2m+1][Ms] (first call only); h [2M], bands [2][M], ones [N]
+    const int64_t rows = nd_all;
+    const int64_t need = (rows * (3 + 2 * npair)) * Ms + 4 * (int64_t)M + g.N;
+    const bool fresh = need > p->a1_cap;
     if ((rc = p->grow(&p->a1_buf, p->a1_cap, need))) return rc;
+    if (fresh) p->a1_R_ready = false;
     double2* S = p->a1_buf;
-    double2* a = S + (int64_t)nd_all * Ms;
-    double2* prod = a + 2 * (int64_t)Ms;
-    double2* Rb = prod + 4 * (int64_t)dc * Ms;
-    double2* V = Rb + 4 * (int64_t)dc * Ms;
-    double2* tmp = V + (int64_t)dc * Ms;
-    double2* h = tmp + 4 * (int64_t)dc * Ms;
+    double2* Rc = S + rows * Ms;
+    double2* V = Rc + npair * rows * Ms;
+    double2* tmp = V + rows * Ms;
+    double2* prod = tmp + rows * Ms;
+    double2* h = prod + npair * rows * Ms;
     double2* bands = h + 2 * (int64_t)M;
     double2* ones = bands + 2 * (int64_t)M;
     launch_status_init(p->status, 1, s);
+    std::vector<FftStep> tg, tc, fw, bw;
+    if (!p->a1_R_ready) {
+        // a = K's band(s) on the grid, F D 1_band with the inverse's D (into V), then
+        // R_d = DFT(conj(a^b) a^c(. - d)) / M_sigma for every pair and shift
+        double2* a = V;
+        launch_a1_bands(bands, M, nb, s);
+        LAUNCH_CHECK();
+        if ((rc = build_schedule(F, nb, tg, tc))) return rc;
+        if ((rc = run_fft(F, tg, bands, nullptr, true, a, tmp))) return rc;
+        launch_a1_products(a, prod, Ms, 0, nd_all, npair, 1.0 / (double)Ms, s);
+        LAUNCH_CHECK();
+        if ((rc = build_plain_fft(F, nd_all, -1, fw))) return rc;
+        for (int c = 0; c < npair; ++c)
+            if ((rc = run_fft(F, fw, prod + c * rows * Ms, Rc + c * rows * Ms, false, nullptr, tmp))) return rc;
+        p->a1_R_ready = true;
+    }
+    // Toeplitz symbol P(q) at |q| < M: adjoint NFFT of ones at bandwidth 2M
     launch_a1_ones(ones, g.N, s);
     LAUNCH_CHECK();
     if ((rc = nfft_adjoint(p->a1_pplan, ones, h, 1))) return rc;
-    // a^lo, a^hi: the two half bands of K on the grid, F D 1_band with the inverse's D
-    launch_a1_bands(bands, M, s);
+    // S(., d) = DFT(fold of P R_d)
+    launch_a1_fold(Rc, h, V, M, Ms, nd_all, npair, s);
     LAUNCH_CHECK();
-    std::vector<FftStep> tg, tc, fw, bw;
-    if ((rc = build_schedule(F, 2, tg, tc))) return rc;
-    if ((rc = run_fft(F, tg, bands, nullptr, true, a, tmp))) return rc;
-    for (int d0 = 0; d0 < nd_all; d0 += dc) {
-        const int nd = std::min(dc, nd_all - d0);
-        if ((rc = build_plain_fft(F, 4 * nd, -1, fw))) return rc;
-        if ((rc = build_plain_fft(F, nd, -1, bw))) return rc;
-        launch_a1_products(a, prod, Ms, d0, nd, 1.0 / (double)Ms, s);
-        LAUNCH_CHECK();
-        if ((rc = run_fft(F, fw, prod, Rb, false, nullptr, tmp))) return rc;
-        launch_a1_fold(Rb, h, V, M, Ms, nd, s);
-        LAUNCH_CHECK();
-        if ((rc = run_fft(F, bw, V, S + (int64_t)d0 * Ms, false, nullptr, tmp))) return rc;
-    }
+    if ((rc = build_plain_fft(F, nd_all, -1, bw))) return rc;
+    if ((rc = run_fft(F, bw, V, S, false, nullptr, tmp))) return rc;
     {
         ProfScope ps(p, INFFT_K_SOLVE);
         launch_a1_solve(g, p->nd, S, p->Ktab[0], p->qK, p->rho, p->B64, p->B32, p->status, s);

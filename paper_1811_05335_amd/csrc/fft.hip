@@ -274,13 +274,13 @@ __device__ inline void store_elem(const FftIO& io, const FftPass& P, const Geo& 
 
 // One workgroup's share of a pass: sub-transforms blk * rows .. of the pass.
 template <typename R, int E, int LD, int ST>
-__device__ inline void fft_block(const FftPass& P, const FftIO& io, const Geo& g, int64_t blk) {
+__device__ inline void fft_block(const FftPass& P, int64_t nseq, const FftIO& io, const Geo& g, int64_t blk) {
     extern __shared__ char smem_raw[];
     cx<R>* lds = (cx<R>*)smem_raw;
     const int ld = P.n + 1;
     const int64_t seq0 = blk * (int64_t)P.rows;
-    if (seq0 >= P.nseq) return;
-    const int rows = (int)min((int64_t)P.rows, P.nseq - seq0);
+    if (seq0 >= nseq) return;
+    const int rows = (int)min((int64_t)P.rows, nseq - seq0);
     const int tot = rows * P.n;
     // the twiddle table follows the data in LDS, loaded together with it (one wait on memory
     // instead of one per stage)
@@ -309,7 +309,7 @@ __device__ inline void fft_block(const FftPass& P, const FftIO& io, const Geo& g
 
 template <typename R, int E, int LD, int ST>
 __global__ void __launch_bounds__(FFT_THREADS) k_fft(FftPass P, FftIO io, Geo g) {
-    fft_block<R, E, LD, ST>(P, io, g, blockIdx.x);
+    fft_block<R, E, LD, ST>(P, P.nseq, io, g, blockIdx.x);
 }
 
 // Passes of many problems in one launch: workgroup -> (job, block of that job's pass).  A job's
@@ -322,12 +322,12 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_batched(const FftJob* __res
                                                              void* user_out, int nrhs) {
     const int2 b = bmap[blockIdx.x];
     const FftJob& J = jobs[b.x];
-    FftPass P = J.pass;
-    P.nseq = P.nq * nrhs;
+    // the pass is read in place (a local copy would put its radix table, indexed per stage, in
+    // scratch); only the sequence count follows the call's nrhs
     FftIO io = J.io;
     if (J.user_in) io.in = (const cx<R>*)user_in + (int64_t)nrhs * J.user_off;
     if (J.user_out) io.out = (cx<R>*)user_out + (int64_t)nrhs * J.user_off;
-    fft_block<R, E, LD, ST>(P, io, J.g, b.y);
+    fft_block<R, E, LD, ST>(J.pass, J.pass.nq * nrhs, io, J.g, b.y);
 }
 
 template <typename R>

@@ -515,10 +515,11 @@ void launch_big_solve(const Geo& g, BigArgs a, int nprob, double2* B64, float2* 
 void launch_big_stats(const int* fail, int n, int nmin, int nmax, long long* rec, hipStream_t s);
 
 // ansatz1.hip: per-node optimisation of B^* (FP64)
-void launch_a1_bands(double2* out, int M, hipStream_t s);
+void launch_a1_bands(double2* out, int M, int nb, hipStream_t s);
 void launch_a1_ones(double2* out, int64_t n, hipStream_t s);
-void launch_a1_products(const double2* a, double2* prod, int Ms, int d0, int nd, double scale, hipStream_t s);
-void launch_a1_fold(const double2* R, const double2* h, double2* V, int M, int Ms, int nd, hipStream_t s);
+void launch_a1_products(const double2* a, double2* prod, int Ms, int d0, int nd, int npair, double scale,
+                        hipStream_t s);
+void launch_a1_fold(const double2* R, const double2* h, double2* V, int M, int Ms, int nd, int npair, hipStream_t s);
 void launch_a1_solve(const Geo& g, const NodesDev& nd, const double2* S, const double2* Ktab, int qK, double rho,
                      double2* B64, float2* B32, long long* status, hipStream_t s);
 

@@ -30,12 +30,26 @@ __device__ inline void window_row(const Geo& g, double u, R* w) {
     constexpr int NC = WPoly<R>::NC;
     const R* cf = (const R*)g.wpoly;
     const R y = (R)(2.0 * (u - (double)(g.m - 1)) - 1.0);
+    if constexpr ((W - 1) * NC > 210) {
+        // many coefficients (FP64, m >= 7): the same Horner steps per tap with the power loop
+        // outermost, so that one coefficient per tap is live instead of all of them
 #pragma unroll
-    for (int tau = 0; tau < W - 1; ++tau) {
-        R acc = cf[tau * NC + NC - 1];
+        for (int tau = 0; tau < W - 1; ++tau) w[tau] = cf[tau * NC + NC - 1];
+#pragma unroll 1
+        for (int k = NC - 2; k >= 0; --k) {
 #pragma unroll
-        for (int k = NC - 2; k >= 0; --k) acc = acc * y + cf[tau * NC + k];
-        w[tau] = (fabs(u - (double)tau) <= (double)g.m) ? acc : (R)0;
+            for (int tau = 0; tau < W - 1; ++tau) w[tau] = w[tau] * y + cf[tau * NC + k];
+        }
+#pragma unroll
+        for (int tau = 0; tau < W - 1; ++tau) w[tau] = (fabs(u - (double)tau) <= (double)g.m) ? w[tau] : (R)0;
+    } else {
+#pragma unroll
+        for (int tau = 0; tau < W - 1; ++tau) {
+            R acc = cf[tau * NC + NC - 1];
+#pragma unroll
+            for (int k = NC - 2; k >= 0; --k) acc = acc * y + cf[tau * NC + k];
+            w[tau] = (fabs(u - (double)tau) <= (double)g.m) ? acc : (R)0;
+        }
     }
     w[W - 1] = edge_tap_member(u, g.m) ? (R)(g.b / M_PI) : (R)0;
 }
@@ -140,10 +154,13 @@ __device__ inline void interp_B_item(const Geo& g, const NodesDev& nd, const cx<
     const int j = nd.perm[p];
     const int a0 = nd.l0s[p * D];
     const int a1 = (D == 2) ? nd.l0s[p * D + 1] : 0;
+    // 2-D with many taps: the outer tap loop stays rolled so the loads of one row are in flight at a
+    // time (unrolled, all W^2 entries of B and the grid would be hoisted and spill)
+    constexpr int UNR0 = (D == 2 && W * W * (int)sizeof(C) > 1024) ? 1 : W;
     for (int r = 0; r < nrhs; ++r) {
         const C* gr = grid + r * grs;
         C acc = cmake((R)0, (R)0);
-#pragma unroll
+#pragma unroll UNR0
         for (int t0 = 0; t0 < W; ++t0) {
             if (D == 1) {
                 const C wv = B[(int64_t)t0 * g.N + p];

@@ -154,6 +154,12 @@ CONFIGS = {
     # batched uneven 1-D problems (M_i, N_i from batched_sizes), 8 right-hand sides each
     "c4": dict(d=1, nprob=256, lo=1024, hi=16384, sigma=2.0, m=4, nodes="uniform", rho=1e-8, rhs=8),
     "c5": dict(d=2, M=(256, 256), N=65536, sigma=2.0, m=4, nodes="spiral", rho=1e-8, rhs=16),
+    # ansatz 1 (underdetermined, M = 4N): Example 3.14's largest first-experiment case, Dirichlet
+    # kernel, sigma 2, jittered nodes (3.8); then the same shape at GPU scale
+    "a1": dict(d=1, M=(16384,), N=4096, sigma=2.0, m=4, nodes="jittered_paper", rho=0.0, rhs=1,
+               kernel="dirichlet"),
+    "a1_large": dict(d=1, M=(1048576,), N=262144, sigma=2.0, m=4, nodes="jittered_paper", rho=0.0, rhs=1,
+                     kernel="dirichlet"),
 }
 
 

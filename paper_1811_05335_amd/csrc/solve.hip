@@ -533,21 +533,20 @@ __global__ void __launch_bounds__(128) k_solve_r1_batched(const SolveJob* __rest
 // entries directly.  Problems with more members or with a member on the window edge (tap 2m
 // inside the support) are appended to the list of the group kernels.
 constexpr int T1_TPB = T1_CELLS;
-constexpr int T1_NODECAP = 320;   // staged nodes per workgroup (density up to ~2.4 per cell)
+constexpr int T1_NODECAP = 224;   // staged nodes per workgroup (density up to ~1.6 per cell)
 
 template <int NMAX>
 __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a,
                                      int blk) {
-    extern __shared__ double s_tabq[];                      // Qs, then Ks Taylor tables
+    extern __shared__ double s_tabk[];                      // Ks Taylor table
     __shared__ double s_band[T1_NODECAP * NMAX];       // band of the workgroup's nodes
     __shared__ int s_l0[T1_NODECAP];                   // stencil base of the staged nodes
     __shared__ double s_u[T1_NODECAP];                 // offsets: t_p = l0_p + u_p
     __shared__ double2 s_phi[T1_NODECAP];              // e^{-i pi t_p / sigma}
     __shared__ int s_range[2];
-    const int nQ = (kt.qQ + 1) * TAY_NC, nK = (kt.qK + 1) * TAY_NC;
-    stage_to_lds(s_tabq, kt.Qs, nQ);
-    stage_to_lds(s_tabq + nQ, kt.Ks, nK);
-    const double* s_tabk = s_tabq + nQ;
+    // Ks, read per member in the solves, is staged in LDS; Qs, read once per band entry, stays in
+    // global memory (keeping LDS to four workgroups per CU)
+    stage_to_lds(s_tabk, kt.Ks, (kt.qK + 1) * TAY_NC);
 
     const int Ms = g.Ms[0], w2 = 2 * g.m;
     const int L0 = blk * T1_TPB;
@@ -579,7 +578,7 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
         double v = 0.0;
         // t_{i+d} - t_i with the integer parts subtracted exactly
         if (i + d < nnode)
-            v = kt.scaleG * tay_eval_r(s_tabq, kt.qQ, (double)(s_l0[i + d] - s_l0[i]) + (s_u[i + d] - s_u[i]));
+            v = kt.scaleG * tay_eval_r(kt.Qs, kt.qQ, (double)(s_l0[i + d] - s_l0[i]) + (s_u[i + d] - s_u[i]));
         s_band[e] = v;
     }
     __syncthreads();
@@ -753,7 +752,7 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
 }
 
 template <int NMAX>
-__global__ void __launch_bounds__(T1_TPB) k_solve_t1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
+__global__ void __launch_bounds__(T1_TPB, 2) k_solve_t1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
     solve_t1_body<NMAX>(g, nd, kt, a, blockIdx.x);
 }
 
@@ -767,7 +766,7 @@ __global__ void __launch_bounds__(T1_TPB) k_solve_t1_batched(const SolveJob* __r
 
 void launch_solve_t1_batched(const SolveJob* jobs, const int2* t1_map, int t1_blocks, int qQ, int qK,
                              hipStream_t s) {
-    const size_t shm = (size_t)((qQ + 1) + (qK + 1)) * TAY_NC * sizeof(double);
+    const size_t shm = (size_t)(qK + 1) * TAY_NC * sizeof(double);
     if (t1_blocks > 0)
         hipLaunchKernelGGL((k_solve_t1_batched<13>), dim3(t1_blocks), dim3(T1_TPB), shm, s, jobs, t1_map);
 }
@@ -805,7 +804,7 @@ void launch_solve_tier_batched(const SolveJob* jobs, int njobs, int nl, int bloc
 }
 
 int launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s) {
-    const size_t shm = (size_t)((kt.qQ + 1) + (kt.qK + 1)) * TAY_NC * sizeof(double);
+    const size_t shm = (size_t)(kt.qK + 1) * TAY_NC * sizeof(double);
     const unsigned blocks = (unsigned)((g.Ms[0] + T1_TPB - 1) / T1_TPB);
     hipLaunchKernelGGL((k_solve_t1<13>), dim3(blocks), dim3(T1_TPB), shm, s, g, nd, kt, a);
     return (int)blocks;

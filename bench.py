@@ -44,7 +44,11 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=192, help="grid indices of the sampled oracle B solve")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph replay")
     ap.add_argument("--no-overlap", action="store_true",
-                    help="run the B optimisation on the main stream instead of overlapping it with the transforms")
+                    help="run every call on the main stream (same as --overlap none)")
+    ap.add_argument("--overlap", choices=("none", "pre", "tail", "full"), default="tail",
+                    help="pre: the B optimisation on a second stream; tail: also the node gradient beside "
+                         "the inverse adjoint (own stream and work slot); full: the adjoint and the node "
+                         "gradient on their own streams and work slots from the start")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration under a profiler)")
     ap.add_argument("--no-secondary", action="store_true",
@@ -84,7 +88,7 @@ class Stage:
         return {k: float(np.mean([s.elapsed_time(e) for s, e in v])) for k, v in self.pairs.items()}
 
 
-def gpu_run(precision, x, fh, gf, steps, warmup, rho, m, sigma, M, use_graph=True, overlap=True):
+def gpu_run(precision, x, fh, gf, steps, warmup, rho, m, sigma, M, use_graph=True, overlap="full"):
     import torch
     from paper_1811_05335_amd import NfftPlan
 
@@ -93,32 +97,60 @@ def gpu_run(precision, x, fh, gf, steps, warmup, rho, m, sigma, M, use_graph=Tru
     fhd = torch.from_numpy(fh).to(ct).cuda()
     gfd = torch.from_numpy(gf).to(ct).cuda()
     R = fh.shape[0]
-    P = NfftPlan(M, xd, sigma=sigma, m=m, precision=precision, rho=rho, max_rhs=R)
+    P = NfftPlan(M, xd, sigma=sigma, m=m, precision=precision, rho=rho, max_rhs=R, work_slots=3)
     tuned = P.autotune()   # FFT workgroup shapes, measured once per plan like an FFT plan
 
-    side = torch.cuda.Stream()
+    side, s_adj, s_grad = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
 
     def step(stage=None):
-        """One pass of the path.  The B optimisation depends only on the nodes and touches none
-        of the buffers of the transforms, so (unless a per-call breakdown is being timed) it runs
-        on a second stream, overlapped with the NFFT and the adjoint, and joins before the
-        modified adjoint."""
+        """One pass of the path.  Unless a per-call breakdown is being timed, the calls that do not
+        depend on each other overlap: the B optimisation (nodes only, none of the transforms'
+        buffers) on a second stream, joined before the modified adjoint; the adjoint of the NFFT's
+        output on a third stream and work slot; the node gradient on a fourth."""
         run = (lambda n, f: stage.run(n, f)) if stage else (lambda n, f: f())
         cur = torch.cuda.current_stream()
+        pre = stage is None and overlap in ("pre", "tail", "full")
+        par = stage is None and overlap == "full"
+        tail = stage is None and overlap == "tail"
+        P.set_slot(0)
         run("a1_nodes", lambda: P.set_nodes(xd))
-        if stage is None and overlap:
+        if pre:
             side.wait_stream(cur)
             with torch.cuda.stream(side):
                 P.precompute_B()
+        if par:
+            s_grad.wait_stream(cur)
+            with torch.cuda.stream(s_grad):
+                P.set_slot(2)
+                gx = P.grad_x(fhd, gfd)
+            P.set_slot(0)
         f = run("a2-a4_trafo", lambda: P.trafo(fhd))
-        h = run("a5_adjoint", lambda: P.adjoint(f))
-        if stage is None and overlap:
+        if par:
+            s_adj.wait_stream(cur)
+            with torch.cuda.stream(s_adj):
+                P.set_slot(1)
+                h = P.adjoint(f)
+            P.set_slot(0)
+        else:
+            h = run("a5_adjoint", lambda: P.adjoint(f))
+        if pre:
             cur.wait_stream(side)
         else:
             run("a6_precompute_B", lambda: P.precompute_B())
         fc = run("a7_apply", lambda: P.apply(f))
+        if tail:
+            s_grad.wait_stream(cur)
+            with torch.cuda.stream(s_grad):
+                P.set_slot(2)
+                gx = P.grad_x(fhd, gfd)
+            P.set_slot(0)
         fa = run("a8_apply_adjoint", lambda: P.apply_adjoint(fc))
-        gx = run("a8_grad_x", lambda: P.grad_x(fhd, gfd))
+        if par:
+            cur.wait_stream(s_adj)
+        if par or tail:
+            cur.wait_stream(s_grad)
+        else:
+            gx = run("a8_grad_x", lambda: P.grad_x(fhd, gfd))
         return f, h, fc, fa, gx
 
     # eager launches
@@ -490,6 +522,7 @@ def cpu_baseline(x, fh, gf, rho, m, sigma, M, sample):
 
 def main():
     a = parse()
+    ovl = "none" if a.no_overlap else a.overlap
     if a.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -509,7 +542,7 @@ def main():
     gf32 = W.round_to(gf, "f32")
     log(f"[bench] workload: {WORKLOAD_NAME}, rhs={R}; FP32 run")
     r32 = gpu_run("f32", x, fh32, gf32, a.steps, a.warmup, rho, m, sigma, M, use_graph=not a.eager,
-                  overlap=not a.no_overlap)
+                  overlap=ovl)
     ms32 = r32["ms_graph"] if r32["ms_graph"] else r32["ms_eager"]
     br32, st32, out32, rows32 = r32["breakdown"], r32["status"], r32["outs"], r32["rows"]
     log(f"[bench] FP32 graph {r32['ms_graph']} ms/step, eager {r32['ms_eager']:.3f} ms/step {br32}")
@@ -517,7 +550,7 @@ def main():
     if a.fp64:
         log("[bench] FP64 run")
         r64 = gpu_run("f64", x, fh, gf, a.steps, a.warmup, rho, m, sigma, M, use_graph=not a.eager,
-                      overlap=not a.no_overlap)
+                      overlap=ovl)
         ms64 = r64["ms_graph"] if r64["ms_graph"] else r64["ms_eager"]
         out64, rows64 = r64["outs"], r64["rows"]
         log(f"[bench] FP64 graph {r64['ms_graph']} ms/step, eager {r64['ms_eager']:.3f} ms/step {r64['breakdown']}")
@@ -586,7 +619,13 @@ def main():
         "dominant_kernel_class": dom_k,
         "streaming_kernels_hbm": kroof,
         "timing": ("hipGraph replay of the whole step" if r32["ms_graph"] else "eager launches")
-                  + ("; B optimisation on a second stream, overlapped with NFFT and adjoint" if not a.no_overlap else ""),
+                  + {"none": "; every call on one stream",
+                     "pre": "; B optimisation on a second stream, overlapped with the NFFT and the adjoint",
+                     "tail": "; B optimisation on a second stream, overlapped with the NFFT and the adjoint; "
+                             "node gradient on a third stream and work slot, beside the inverse adjoint",
+                     "full": "; independent calls overlapped on four streams and three work slots: the B "
+                             "optimisation with the NFFT and the adjoint, the adjoint with the B optimisation, "
+                             "the node gradient with the rest"}[ovl],
         "eager_ms_per_step": r32["ms_eager"],
         "graph_vs_eager_rel": r32["graph_vs_eager"],
         "breakdown_ms": br32,

@@ -72,7 +72,10 @@ typedef struct {
                            INFFT_KERNEL_DIRICHLET: Remark 3.19, w_hat = 1 for |k| < M/2 and the
                            entry of k = -M/2 set to zero, so K is the Dirichlet kernel (3.23)
                            divided by M_sigma (the NFFT and its adjoint keep the window) */
-    int reserved[5];
+    int work_slots;  /* sets of transform work buffers (oversampled grid, FFT scratch, spreading
+                        halos), 1..8 (default 1; 0 means 1).  nfft_set_slot picks the set later
+                        calls use, so calls on different slots and streams may run concurrently */
+    int reserved[4];
 } infft_options;
 
 #define INFFT_KERNEL_WINDOW 0
@@ -109,6 +112,14 @@ int nfft_set_nodes(infft_plan p, const double* x);
 
 /* Changes the stream subsequent calls enqueue on. */
 int nfft_set_stream(infft_plan p, void* stream);
+
+/* Selects the set of work buffers (0 .. work_slots-1) that subsequent nfft_trafo, nfft_adjoint,
+ * infft_apply, infft_apply_adjoint and nfft_grad_x calls use.  Those calls write nothing else of
+ * the plan, so calls on different slots, enqueued on different streams, may overlap on the device
+ * (the B optimisation and the node preprocessing use none of these buffers; the caller orders them
+ * against the transforms that read their results).  Calls that share a slot must be ordered by the
+ * caller.  INFFT_EINVAL for a slot out of range and for batch plans. */
+int nfft_set_slot(infft_plan p, int slot);
 
 /* NFFT: f = B F D fhat ~ A fhat (Section 2.1).  fhat [nrhs][M...], f [nrhs][N]. */
 int nfft_trafo(infft_plan p, const void* fhat, void* f, int nrhs);

@@ -38,7 +38,8 @@ class Options(C.Structure):
         ("rho", C.c_double),
         ("tile", C.c_int * 2),
         ("inverse_kernel", C.c_int),
-        ("reserved", C.c_int * 5),
+        ("work_slots", C.c_int),
+        ("reserved", C.c_int * 4),
     ]
 
 
@@ -82,6 +83,7 @@ def load() -> C.CDLL:
                                     C.POINTER(Options), vp]),
         "nfft_set_nodes": (i32, [vp, vp]),
         "nfft_set_stream": (i32, [vp, vp]),
+        "nfft_set_slot": (i32, [vp, C.c_int]),
         "nfft_trafo": (i32, [vp, vp, vp, i32]),
         "nfft_adjoint": (i32, [vp, vp, vp, i32]),
         "infft_precompute_B": (i32, [vp]),

@@ -117,11 +117,15 @@ struct infft_plan_s {
     std::vector<FftStep> to_grid;    // coefficients -> grid (sign +1, with D)
     std::vector<FftStep> to_coeff;   // grid + halos -> coefficients (sign -1, with D^*)
 
-    void* grid = nullptr;
+    void* grid = nullptr;      // the work buffers of the current slot
     void* grid2 = nullptr;
     void* h0 = nullptr;
     void* h1 = nullptr;
     void* h01 = nullptr;
+    struct Slot {
+        void *grid, *grid2, *h0, *h1, *h01;
+    };
+    std::vector<Slot> slots;   // work_slots sets of the five buffers above
     int64_t hrs0 = 0, hrs1 = 0, hrs01 = 0;
     SpreadWork spwork{};            // 2-D: work list of the tiled spreading (rebuilt by set_nodes)
     int* sp_offs = nullptr;
@@ -938,6 +942,8 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
     if (o.inverse_kernel != INFFT_KERNEL_WINDOW && o.inverse_kernel != INFFT_KERNEL_DIRICHLET)
         return fail(INFFT_EINVAL, "bad inverse_kernel");
     if (o.max_rhs < 1 || o.max_rhs > 64) return fail(INFFT_EINVAL, "max_rhs must be in 1..64");
+    const int nslots = o.work_slots == 0 ? 1 : o.work_slots;
+    if (nslots < 1 || nslots > 8) return fail(INFFT_EINVAL, "work_slots must be in 1..8 (got %d)", o.work_slots);
     if (!(o.rho >= 0.0) || !std::isfinite(o.rho)) return fail(INFFT_EINVAL, "rho must be finite and >= 0");
 
     Geo g{};
@@ -1111,17 +1117,26 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
     P->hrs0 = ntiles * w2 * (d == 2 ? g.TS[1] : 1);
     P->hrs1 = d == 2 ? ntiles * g.TS[0] * w2 : 0;
     P->hrs01 = d == 2 ? ntiles * w2 * w2 : 0;
-    char* tmp = nullptr;
-    TRY(P->alloc(&tmp, (int64_t)cs * g.G * P->max_rhs));
-    P->grid = tmp;
-    TRY(P->alloc(&tmp, (int64_t)cs * g.G * P->max_rhs));
-    P->grid2 = tmp;
-    TRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs0, 1) * P->max_rhs));
-    P->h0 = tmp;
-    TRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs1, 1) * P->max_rhs));
-    P->h1 = tmp;
-    TRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs01, 1) * P->max_rhs));
-    P->h01 = tmp;
+    for (int k = 0; k < nslots; ++k) {
+        char* tmp = nullptr;
+        infft_plan_s::Slot sl{};
+        TRY(P->alloc(&tmp, (int64_t)cs * g.G * P->max_rhs));
+        sl.grid = tmp;
+        TRY(P->alloc(&tmp, (int64_t)cs * g.G * P->max_rhs));
+        sl.grid2 = tmp;
+        TRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs0, 1) * P->max_rhs));
+        sl.h0 = tmp;
+        TRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs1, 1) * P->max_rhs));
+        sl.h1 = tmp;
+        TRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs01, 1) * P->max_rhs));
+        sl.h01 = tmp;
+        P->slots.push_back(sl);
+    }
+    P->grid = P->slots[0].grid;
+    P->grid2 = P->slots[0].grid2;
+    P->h0 = P->slots[0].h0;
+    P->h1 = P->slots[0].h1;
+    P->h01 = P->slots[0].h01;
     if (d == 2) {
         const int nt = g.ntile[0] * g.ntile[1];
         P->spwork.chunk = 1024;
@@ -1171,6 +1186,20 @@ int nfft_set_nodes(infft_plan p, const double* x) {
         return INFFT_OK;
     }
     return set_nodes_impl(p, x);
+}
+
+int nfft_set_slot(infft_plan p, int slot) {
+    if (!p) return fail(INFFT_EINVAL, "null plan");
+    if (p->batch) return fail(INFFT_EINVAL, "nfft_set_slot takes a single-problem plan");
+    if (slot < 0 || slot >= (int)p->slots.size())
+        return fail(INFFT_EINVAL, "slot %d out of range (the plan has %d)", slot, (int)p->slots.size());
+    const infft_plan_s::Slot& sl = p->slots[slot];
+    p->grid = sl.grid;
+    p->grid2 = sl.grid2;
+    p->h0 = sl.h0;
+    p->h1 = sl.h1;
+    p->h01 = sl.h01;
+    return INFFT_OK;
 }
 
 int nfft_set_stream(infft_plan p, void* stream) {
@@ -1705,6 +1734,7 @@ int nfft_plan_batched(infft_plan* out, int nprob, const int64_t* M, const int64_
     infft_options o;
     if (opts) o = *opts;
     else infft_default_options(&o);
+    o.work_slots = 1;   // a batch plan runs its problems through one launch per stage, one slot
     auto* P = new infft_plan_s();
     P->batch = new BatchState();
     P->prec = o.precision;

@@ -27,10 +27,13 @@ class NfftPlan:
     precision  "f32" (complex64 data, FP32 spreading/FFT) or "f64" (complex128)
     rho        ridge of the local least-squares problems of the B optimisation
     kernel     kernel of the inverse: "window" (the NFFT's window) or "dirichlet" (Remark 3.19)
+    work_slots sets of transform work buffers; `set_slot` picks one, so that transforms on different
+               slots and streams may overlap
     """
 
     def __init__(self, M, x: torch.Tensor, sigma: float = 2.0, m: int = 4, precision: str = "f64",
-                 rho: float = 1e-8, max_rhs: int = 1, tile=None, kernel: str = "window"):
+                 rho: float = 1e-8, max_rhs: int = 1, tile=None, kernel: str = "window",
+                 work_slots: int = 1):
         lib = load()
         self.M = tuple(int(v) for v in (M if isinstance(M, (tuple, list)) else (M,)))
         self.d = len(self.M)
@@ -46,6 +49,7 @@ class NfftPlan:
         o.max_rhs = int(max_rhs)
         o.rho = float(rho)
         o.inverse_kernel = _lib.KERNELS[kernel]
+        o.work_slots = int(work_slots)
         if tile is not None:
             for t, v in enumerate(tile):
                 o.tile[t] = int(v)
@@ -114,6 +118,11 @@ class NfftPlan:
         self._sync_stream()
         check(load().nfft_adjoint(self._h, C.c_void_p(_ptr(ff)), C.c_void_p(_ptr(out)), R))
         return out
+
+    def set_slot(self, slot: int) -> None:
+        """Work-buffer set of the following transforms (calls on different slots and streams may
+        overlap on the device)."""
+        check(load().nfft_set_slot(self._h, int(slot)))
 
     def precompute_B(self) -> None:
         self._sync_stream()

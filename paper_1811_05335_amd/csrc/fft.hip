@@ -129,6 +129,20 @@ template <typename C> struct Dft<C, 3> : DftOdd<C, 3> {};
 template <typename C> struct Dft<C, 5> : DftOdd<C, 5> {};
 template <typename C> struct Dft<C, 7> : DftOdd<C, 7> {};
 
+// ------------------------------------------------------------------ index division
+
+// Division by a workgroup-uniform divisor: a shift when it is a power of two (every length of a
+// power-of-two grid, and the autotuned row counts), the integer division otherwise.  The test is
+// uniform, so only one path runs.
+struct UDiv {
+    uint32_t d;
+    int sh;
+    bool p2;
+    __device__ explicit UDiv(uint32_t dv) : d(dv), sh(__builtin_ctz(dv)), p2((dv & (dv - 1)) == 0) {}
+    __device__ uint32_t div(uint32_t x) const { return p2 ? (x >> sh) : x / d; }
+    __device__ uint32_t mod(uint32_t x) const { return p2 ? (x & (d - 1)) : x - (x / d) * d; }
+};
+
 // ------------------------------------------------------------------ one Stockham stage in LDS
 
 template <typename R, int RADIX, int E>
@@ -138,12 +152,13 @@ __device__ inline void stage(cx<R>* lds, int ld, int rows, int n, int Ns, int si
     constexpr int CM = (E + RADIX - 1) / RADIX;
     const int nbr = n / RADIX;
     const int nb = rows * nbr;
+    const UDiv dnbr((uint32_t)nbr), dNs((uint32_t)Ns);
     C v[CM][RADIX];
 #pragma unroll
     for (int ci = 0; ci < CM; ++ci) {
         const int b = threadIdx.x + ci * FFT_THREADS;
         if (b < nb) {
-            const int row = b / nbr, j = b - row * nbr;
+            const int row = (int)dnbr.div((uint32_t)b), j = b - row * nbr;
 #pragma unroll
             for (int q = 0; q < RADIX; ++q) v[ci][q] = lds[row * ld + j + q * nbr];
         }
@@ -154,8 +169,8 @@ __device__ inline void stage(cx<R>* lds, int ld, int rows, int n, int Ns, int si
     for (int ci = 0; ci < CM; ++ci) {
         const int b = threadIdx.x + ci * FFT_THREADS;
         if (b < nb) {
-            const int row = b / nbr, j = b - row * nbr;
-            const int jm = j % Ns;
+            const int row = (int)dnbr.div((uint32_t)b), j = b - row * nbr;
+            const int jm = (int)dNs.mod((uint32_t)j);
 #pragma unroll
             for (int q = 1; q < RADIX; ++q) {
                 C w = tw[q * jm * tstride];
@@ -171,7 +186,7 @@ __device__ inline void stage(cx<R>* lds, int ld, int rows, int n, int Ns, int si
 #pragma unroll
                 for (int q = 0; q < RADIX; ++q) v[ci][q].y = -v[ci][q].y;
             }
-            const int idxD = (j / Ns) * Ns * RADIX + jm;
+            const int idxD = (j - jm) * RADIX + jm;
 #pragma unroll
             for (int q = 0; q < RADIX; ++q) lds[row * ld + idxD + q * Ns] = v[ci][q];
         }
@@ -282,6 +297,7 @@ __device__ inline void fft_block(const FftPass& P, int64_t nseq, const FftIO& io
     if (seq0 >= nseq) return;
     const int rows = (int)min((int64_t)P.rows, nseq - seq0);
     const int tot = rows * P.n;
+    const UDiv drows((uint32_t)rows), dn((uint32_t)P.n), dnq((uint32_t)P.nq);
     // the twiddle table follows the data in LDS, loaded together with it (one wait on memory
     // instead of one per stage)
     cx<R>* s_tw = lds + (int64_t)P.rows * ld;
@@ -289,20 +305,20 @@ __device__ inline void fft_block(const FftPass& P, int64_t nseq, const FftIO& io
     for (int i = threadIdx.x; i < P.n; i += FFT_THREADS) s_tw[i] = gtw[i];
     for (int L = threadIdx.x; L < tot; L += FFT_THREADS) {
         int row, i;
-        if (P.in_rowfast) { row = L % rows; i = L / rows; }
-        else { row = L / P.n; i = L - row * P.n; }
+        if (P.in_rowfast) { i = (int)drows.div((uint32_t)L); row = L - i * rows; }
+        else { row = (int)dn.div((uint32_t)L); i = L - row * P.n; }
         const uint32_t s = (uint32_t)(seq0 + row);
-        const uint32_t r = s / (uint32_t)P.nq, q = s - r * (uint32_t)P.nq;
+        const uint32_t r = dnq.div(s), q = s - r * (uint32_t)P.nq;
         lds[row * ld + i] = load_elem<R, LD>(io, P, g, r, (int64_t)q * P.in_qs + (int64_t)i * P.in_is);
     }
     __syncthreads();
     lds_fft<R, E>(lds, ld, rows, P, s_tw);
     for (int L = threadIdx.x; L < tot; L += FFT_THREADS) {
         int row, k;
-        if (P.out_rowfast) { row = L % rows; k = L / rows; }
-        else { row = L / P.n; k = L - row * P.n; }
+        if (P.out_rowfast) { k = (int)drows.div((uint32_t)L); row = L - k * rows; }
+        else { row = (int)dn.div((uint32_t)L); k = L - row * P.n; }
         const uint32_t s = (uint32_t)(seq0 + row);
-        const uint32_t r = s / (uint32_t)P.nq, q = s - r * (uint32_t)P.nq;
+        const uint32_t r = dnq.div(s), q = s - r * (uint32_t)P.nq;
         store_elem<R, ST>(io, P, g, r, (int64_t)q * P.out_qs + (int64_t)k * P.out_ks, q, k, lds[row * ld + k]);
     }
 }

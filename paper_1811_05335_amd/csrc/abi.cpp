@@ -455,14 +455,10 @@ int set_nodes_impl(infft_plan_s* P, const double* x) {
     const Geo& g = P->g;
     hipStream_t s = P->stream;
     ProfScope ps(P, INFFT_K_NODES);
-    launch_fill_bytes0(P->status, sizeof(long long) * STATUS_WORDS, s);
-    launch_status_init(P->status, 0, s);
-    launch_fill_i32(P->counts, g.G + 1, 0, s);
-    launch_fill_i32(P->fill, g.G, 0, s);
+    launch_nodes_reset(P->status, P->counts, g.G + 1, P->fill, g.G, P->lcount, s);
     launch_prep_nodes(g, x, P->nd, P->counts, P->status, s);
     launch_exclusive_scan(P->counts, P->nd.start, g.G, P->bsum, s);
     launch_scatter_nodes(g, P->nd, P->fill, s);
-    launch_fill_i32(P->lcount, 4, 0, s);
     launch_cell_sort(g, P->nd, P->lists, P->lcount + 2, s);
     if (g.d == 2) launch_spread_worklist(g, P->nd, P->spwork, P->sp_offs, P->sp_bsum, s);
     LAUNCH_CHECK();

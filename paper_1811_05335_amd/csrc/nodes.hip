@@ -3,6 +3,8 @@
 // spreading tiles and the grid-index -> node lists I(l) of (3.29) are read.
 #include "internal.hpp"
 
+#include <algorithm>
+
 #include <limits.h>
 
 namespace infft {
@@ -46,6 +48,23 @@ __global__ void k_status_init(long long* st, int keep_node_words) {
 
 void launch_status_init(long long* status, int keep_node_words, hipStream_t s) {
     hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, s, status, keep_node_words);
+}
+
+// Start of the node preprocessing in one launch: the status block, the per-cell counters and fill
+// cursors, and the four list counters.
+__global__ void k_nodes_reset(long long* st, int* counts, int64_t ncounts, int* fill, int64_t nfill, int* lcount) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < ncounts) counts[i] = 0;
+    if (i < nfill) fill[i] = 0;
+    if (i < 4) lcount[i] = 0;
+    if (i < STATUS_WORDS) st[i] = (i == ST_MIN_N) ? LLONG_MAX : 0;
+}
+
+void launch_nodes_reset(long long* status, int* counts, int64_t ncounts, int* fill, int64_t nfill, int* lcount,
+                        hipStream_t s) {
+    const int64_t n = std::max<int64_t>(std::max<int64_t>(ncounts, nfill), STATUS_WORDS);
+    hipLaunchKernelGGL(k_nodes_reset, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, status, counts, ncounts,
+                       fill, nfill, lcount);
 }
 
 // Per node: wrap, t = x M_sigma, l0 = ceil(t - m), u = t - l0.  The float64 operations are

@@ -591,6 +591,23 @@ int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* 
                     for (int J = k + 1; J <= I; ++J) tasks.push_back(make_int4(i, I, J, 0));
         }
         seg.push_back((int64_t)tasks.size());
+        // substitution steps (right-looking, one launch per block step): forward (problem, I >= k),
+        // backward (problem, J <= k)
+        std::vector<int64_t> fseg, bseg;
+        if (!grad) {
+            for (int k = 0; k < T0; ++k) {
+                fseg.push_back((int64_t)tasks.size());
+                for (int i = 0; i < np && probs[i].nblk > k; ++i)
+                    for (int I = k; I < probs[i].nblk; ++I) tasks.push_back(make_int4(i, I, 0, 0));
+            }
+            fseg.push_back((int64_t)tasks.size());
+            for (int k = 0; k < T0; ++k) {
+                bseg.push_back((int64_t)tasks.size());
+                for (int i = 0; i < np && probs[i].nblk > k; ++i)
+                    for (int J = 0; J <= k; ++J) tasks.push_back(make_int4(i, J, 0, 0));
+            }
+            bseg.push_back((int64_t)tasks.size());
+        }
         if ((rc = p->grow(&p->big_A, p->big_A_cap, std::max<int64_t>(ent, 1)))) return rc;
         if (mem > p->big_m_cap) {
             int64_t c1 = p->big_m_cap, c2 = p->big_m_cap, c3 = p->big_m_cap, c4 = p->big_m_cap,
@@ -629,8 +646,19 @@ int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* 
             launch_big_herk(a, p->big_tasks + t1, (int)(t2 - t1), k, st);
             LAUNCH_CHECK();
         }
-        if (grad) launch_big_grad(g, a, kt, *grad, p->nd.perm, np, p->prec == INFFT_F32, st);
-        else launch_big_solve(g, a, np, p->B64, p->B32, st);
+        if (grad) {
+            launch_big_grad(g, a, kt, *grad, p->nd.perm, np, p->prec == INFFT_F32, st);
+        } else {
+            for (int k = 0; k < T0; ++k) {
+                launch_big_fwd(a, p->big_tasks + fseg[k], (int)(fseg[k + 1] - fseg[k]), k, st);
+                LAUNCH_CHECK();
+            }
+            for (int k = T0 - 1; k >= 0; --k) {
+                launch_big_bwd(a, p->big_tasks + bseg[k], (int)(bseg[k + 1] - bseg[k]), k, st);
+                LAUNCH_CHECK();
+            }
+            launch_big_write(g, a, np, p->B64, p->B32, st);
+        }
         LAUNCH_CHECK();
         // the host task arrays are reused by the next batch
         HIP_TRY(hipStreamSynchronize(st));

@@ -514,6 +514,9 @@ void launch_big_potrf(BigArgs a, int nprob, int k, hipStream_t s);
 void launch_big_trsm(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t s);
 void launch_big_herk(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t s);
 void launch_big_solve(const Geo& g, BigArgs a, int nprob, double2* B64, float2* B32, hipStream_t s);
+void launch_big_fwd(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t s);
+void launch_big_bwd(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t s);
+void launch_big_write(const Geo& g, BigArgs a, int nprob, double2* B64, float2* B32, hipStream_t s);
 void launch_big_stats(const int* fail, int n, int nmin, int nmax, long long* rec, hipStream_t s);
 
 // ansatz1.hip: per-node optimisation of B^* (FP64)

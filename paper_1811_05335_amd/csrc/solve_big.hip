@@ -401,6 +401,133 @@ void launch_big_solve(const Geo& g, BigArgs a, int nprob, double2* B64, float2* 
     hipLaunchKernelGGL(k_big_solve, dim3(nprob), dim3(BIG_TPB), 0, s, g, a, B64, B32);
 }
 
+// The same two substitutions spread over the whole GPU, one launch per block step (right-looking):
+// a problem of n = 5000 members holds 200 MB of factor, which one workgroup reads at a fraction of
+// HBM bandwidth.  Forward step k, per task (problem, I >= k): y_k = X_k r_k (X_k = L_kk^{-1}, every
+// task recomputes it from r_k, which no task of step k writes); task I = k stores y_k, tasks I > k
+// update r_I -= L[I][k] y_k.  Backward step k, per task (problem, J <= k): b_k = X_k^* y_k; task J = k
+// stores b_k over r_k, tasks J < k update y_J -= L[k][J]^* b_k.  r lives in mr, y in mb.
+__device__ inline void big_block_vec(const double2* D, int64_t ld, int nk, const double2* v, double2* out,
+                                     bool adjoint, double2 (&red)[BIG_TPB / BIG_NB][BIG_NB]) {
+    // out = X v (adjoint: X^* v) for the inverse X of the diagonal block D; 64 x 64, in LDS
+    constexpr int NP = BIG_TPB / BIG_NB;
+    const int c = threadIdx.x % BIG_NB, part = threadIdx.x / BIG_NB;
+    double2 acc = make_double2(0.0, 0.0);
+    if (c < nk) {
+        if (!adjoint) {
+            for (int q = part; q <= c; q += NP) acc = cadd(acc, cmul(inv_entry(D, ld, c, q), v[q]));
+        } else {
+            for (int q = c + part; q < nk; q += NP) acc = cadd(acc, cmul(cconj(inv_entry(D, ld, q, c)), v[q]));
+        }
+    }
+    red[part][c] = acc;
+    __syncthreads();
+    if (part == 0) {
+        double2 sum = red[0][c];
+        for (int pp = 1; pp < NP; ++pp) sum = cadd(sum, red[pp][c]);
+        out[c] = c < nk ? sum : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(BIG_TPB) k_big_fwd(BigArgs a, const int4* __restrict__ tasks, int k) {
+    constexpr int NP = BIG_TPB / BIG_NB;
+    __shared__ double2 s_r[BIG_NB], s_y[BIG_NB];
+    __shared__ double2 red[NP][BIG_NB];
+    const int4 t = tasks[blockIdx.x];
+    const BigProb P = a.probs[t.x];
+    if (a.fail[P.id]) return;
+    const int64_t ld = P.n;
+    const int r0 = k * BIG_NB, nk = min(BIG_NB, P.n - r0);
+    const double2* A = a.A + P.off;
+    double2* r = a.mr + P.moff;
+    double2* y = a.mb + P.moff;
+    if (threadIdx.x < BIG_NB) s_r[threadIdx.x] = threadIdx.x < nk ? r[r0 + threadIdx.x] : make_double2(0.0, 0.0);
+    __syncthreads();
+    big_block_vec(A + (int64_t)r0 * ld + r0, ld, nk, s_r, s_y, false, red);
+    if (t.y == k) {
+        if (threadIdx.x < nk) y[r0 + threadIdx.x] = s_y[threadIdx.x];
+        return;
+    }
+    // r_I -= L[I][k] y_k: NP threads per row
+    const int I0 = t.y * BIG_NB, nr = min(BIG_NB, P.n - I0);
+    const int row = threadIdx.x / NP, p4 = threadIdx.x % NP;
+    double2 acc = make_double2(0.0, 0.0);
+    if (row < nr) {
+        const double2* Lr = A + (int64_t)(I0 + row) * ld + r0;
+        for (int c = p4; c < nk; c += NP) acc = cadd(acc, cmul(Lr[c], s_y[c]));
+    }
+#pragma unroll
+    for (int o = 1; o < NP; o <<= 1) {
+        acc.x += __shfl_xor(acc.x, o, 64);
+        acc.y += __shfl_xor(acc.y, o, 64);
+    }
+    if (p4 == 0 && row < nr) r[I0 + row] = csub(r[I0 + row], acc);
+}
+
+__global__ void __launch_bounds__(BIG_TPB) k_big_bwd(BigArgs a, const int4* __restrict__ tasks, int k) {
+    constexpr int NP = BIG_TPB / BIG_NB;
+    __shared__ double2 s_v[BIG_NB], s_b[BIG_NB];
+    __shared__ double2 red[NP][BIG_NB];
+    const int4 t = tasks[blockIdx.x];
+    const BigProb P = a.probs[t.x];
+    if (a.fail[P.id]) return;
+    const int64_t ld = P.n;
+    const int r0 = k * BIG_NB, nk = min(BIG_NB, P.n - r0);
+    const double2* A = a.A + P.off;
+    double2* b = a.mr + P.moff;
+    double2* y = a.mb + P.moff;
+    if (threadIdx.x < BIG_NB) s_v[threadIdx.x] = threadIdx.x < nk ? y[r0 + threadIdx.x] : make_double2(0.0, 0.0);
+    __syncthreads();
+    big_block_vec(A + (int64_t)r0 * ld + r0, ld, nk, s_v, s_b, true, red);
+    if (t.y == k) {
+        if (threadIdx.x < nk) b[r0 + threadIdx.x] = s_b[threadIdx.x];
+        return;
+    }
+    // y_J -= L[k][J]^* b_k: column col of block (k, J), rows summed in NP parts
+    const int J0 = t.y * BIG_NB;
+    const int col = threadIdx.x % BIG_NB, part = threadIdx.x / BIG_NB;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int c = part; c < nk; c += NP) acc = cadd(acc, cmul(cconj(A[(int64_t)(r0 + c) * ld + J0 + col]), s_b[c]));
+    red[part][col] = acc;
+    __syncthreads();
+    if (part == 0) {
+        double2 sum = red[0][col];
+        for (int pp = 1; pp < NP; ++pp) sum = cadd(sum, red[pp][col]);
+        y[J0 + col] = csub(y[J0 + col], sum);
+    }
+}
+
+// The solutions into B_opt (zeros for failed problems; nothing for problems without members).
+__global__ void __launch_bounds__(BIG_TPB) k_big_write(Geo g, BigArgs a, double2* __restrict__ B64,
+                                                       float2* __restrict__ B32) {
+    const BigProb P = a.probs[blockIdx.x];
+    const int fl = a.fail[P.id];
+    if (fl == 2) return;
+    const double2* b = a.mr + P.moff;
+    for (int i = threadIdx.x; i < P.n; i += BIG_TPB) {
+        const int64_t idx = (int64_t)a.mtap[P.moff + i] * g.N + a.midx[P.moff + i];
+        const double2 v = fl ? make_double2(0.0, 0.0) : b[i];
+        B64[idx] = v;
+        if (B32) B32[idx] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+void launch_big_fwd(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t s) {
+    if (ntask <= 0) return;
+    hipLaunchKernelGGL(k_big_fwd, dim3(ntask), dim3(BIG_TPB), 0, s, a, tasks, k);
+}
+
+void launch_big_bwd(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t s) {
+    if (ntask <= 0) return;
+    hipLaunchKernelGGL(k_big_bwd, dim3(ntask), dim3(BIG_TPB), 0, s, a, tasks, k);
+}
+
+void launch_big_write(const Geo& g, BigArgs a, int nprob, double2* B64, float2* B32, hipStream_t s) {
+    if (nprob <= 0) return;
+    hipLaunchKernelGGL(k_big_write, dim3(nprob), dim3(BIG_TPB), 0, s, g, a, B64, B32);
+}
+
 // One statistics record for the whole pass: sizes known on the host, failures counted here.
 __global__ void __launch_bounds__(256) k_big_stats(const int* fail, int n, int nmin, int nmax, long long* rec) {
     __shared__ int sh[256];

@@ -547,7 +547,12 @@ int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* 
     if ((rc = p->grow(&p->big_fail, p->big_fail_cap, count))) return rc;
     launch_fill_i32(p->big_fail, count, 0, st);
     // workspace of one batch: matrices plus member data (40 bytes per member)
-    constexpr int64_t kBudget = (int64_t)1 << 30;
+    // batch budget: a quarter of the free device memory, between 1 and 16 GiB.  Every batch runs its
+    // block steps in sequence, so fewer, larger batches shorten the chain of dependent launches.
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    const int64_t kBudget = std::min<int64_t>(std::max<int64_t>((int64_t)(free_b / 4), (int64_t)1 << 30),
+                                              (int64_t)16 << 30);
     const int64_t cap_bytes = std::max<int64_t>(kBudget, (int64_t)nmax * nmax * 16 + (int64_t)nmax * 40 + 4096);
     std::vector<BigProb> probs;
     std::vector<int4> tasks;

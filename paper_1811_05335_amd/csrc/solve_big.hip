@@ -186,8 +186,9 @@ void launch_big_gram(const Geo& g, KTabDev kt, BigArgs a, const int4* tasks, int
 // (X[i][j] = (delta_ij - sum_{j<=q<i} L[i][q] X[q][j]) / L[i][i]).  A non-positive pivot marks
 // the problem failed (its later steps run on zeros and its solution is not written).
 __global__ void __launch_bounds__(BIG_TPB) k_big_potrf(BigArgs a, int k) {
+    // L in the lower triangle of T; the inverse X, conjugated, in its strictly upper triangle
+    // (T[j][i] = conj X[i][j], i > j), so that two workgroups fit a CU
     __shared__ double2 T[BIG_NB][BIG_NB + 1];
-    __shared__ double2 X[BIG_NB][BIG_NB + 1];
     __shared__ double2 red[BIG_TPB / BIG_NB][BIG_NB];
     const BigProb P = a.probs[blockIdx.x];
     const int r0 = k * BIG_NB, nk = min(BIG_NB, P.n - r0);
@@ -218,21 +219,23 @@ __global__ void __launch_bounds__(BIG_TPB) k_big_potrf(BigArgs a, int k) {
         __syncthreads();
     }
     if (ok) {
+        // row i of X from the rows before it: X[q][j] = conj T[j][q] for q > j, 1/L[j][j] for q = j
         const int j = threadIdx.x % BIG_NB, part = threadIdx.x / BIG_NB;
         constexpr int NP = BIG_TPB / BIG_NB;
-        for (int i = 0; i < nk; ++i) {
+        for (int i = 1; i < nk; ++i) {
             double2 acc = make_double2(0.0, 0.0);
-            for (int q = j + part; q < i; q += NP) acc = cadd(acc, cmul(T[i][q], X[q][j]));
+            if (j < i) {
+                for (int q = j + part; q < i; q += NP) {
+                    const double2 xq = q == j ? make_double2(1.0 / T[j][j].x, 0.0) : cconj(T[j][q]);
+                    acc = cadd(acc, cmul(T[i][q], xq));
+                }
+            }
             red[part][j] = acc;
             __syncthreads();
-            if (part == 0) {
-                double2 v = make_double2(0.0, 0.0);
-                if (j <= i) {
-                    double2 s = red[0][j];
-                    for (int pp = 1; pp < NP; ++pp) s = cadd(s, red[pp][j]);
-                    v = cscale(make_double2((i == j ? 1.0 : 0.0) - s.x, -s.y), 1.0 / T[i][i].x);
-                }
-                X[i][j] = v;
+            if (part == 0 && j < i) {
+                double2 s = red[0][j];
+                for (int pp = 1; pp < NP; ++pp) s = cadd(s, red[pp][j]);
+                T[j][i] = cconj(cscale(s, -1.0 / T[i][i].x));
             }
             __syncthreads();
         }
@@ -241,7 +244,7 @@ __global__ void __launch_bounds__(BIG_TPB) k_big_potrf(BigArgs a, int k) {
         const int i = e / BIG_NB, j = e % BIG_NB;
         if (i >= nk || j >= nk) continue;
         if (j <= i) D[(int64_t)i * ld + j] = T[i][j];
-        else D[(int64_t)i * ld + j] = ok ? cconj(X[j][i]) : make_double2(0.0, 0.0);
+        else D[(int64_t)i * ld + j] = ok ? T[i][j] : make_double2(0.0, 0.0);
     }
     if (!ok && threadIdx.x == 0) a.fail[P.id] = 1;
 }

@@ -86,7 +86,8 @@ typedef struct {
     int64_t failed_solves;    /* local problems whose Cholesky met a pivot <= 0 */
     int64_t empty_columns;    /* grid indices l with empty I(l): zero column of B_opt */
     int64_t oversized;        /* local problems not solved because the precompute ran under
-                                 graph capture and |I(l)| exceeds 32 (their columns are zero) */
+                                 graph capture and |I(l)| exceeds 64 in 1-D, 32 in 2-D (their
+                                 columns are zero) */
     int64_t min_members;      /* min |I(l)| over non-empty l of the last precompute */
     int64_t max_members;      /* max |I(l)| */
     int32_t bopt_ready;       /* 1 after a successful infft_precompute_B for the current nodes */
@@ -130,9 +131,10 @@ int nfft_adjoint(infft_plan p, const void* f, void* h, int nrhs);
 /* Algorithm 3.17: optimises the nonzero entries of B, one regularised least-squares problem
  * per oversampled grid index l over the nodes I(l) of (3.29), solved through its normal
  * equations in FP64 on the GPU (whatever the plan precision).  Stores B_opt in the plan.
- * Problems with more than 32 members are solved by a blocked Cholesky pass whose sizes are read
- * back to the host, so the call synchronises the stream when such problems exist; under HIP
- * graph capture that pass is skipped and the problems are counted in infft_status.oversized. */
+ * Problems with more than 64 members (1-D; 32 in 2-D) are solved by a blocked Cholesky pass
+ * whose sizes are read back to the host, so the call synchronises the stream when such problems
+ * exist; under HIP graph capture that pass is skipped and the problems are counted in
+ * infft_status.oversized. */
 int infft_precompute_B(infft_plan p);
 
 /* Algorithm 3.10 (ansatz 1 of Section 3.2.1, the underdetermined inverse NFFT): optimises the

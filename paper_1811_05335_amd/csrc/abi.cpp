@@ -703,7 +703,7 @@ struct BatchState {
     int node_blocks = 0;
     int2* cell_map = nullptr;   // tiles of the 1-D spreading
     int cell_blocks = 0;
-    SolveJob* solve_jobs = nullptr;   // [4][nprob]: thread tier, 16 lanes, 32 lanes, 32 lanes under capture
+    SolveJob* solve_jobs = nullptr;   // [5][nprob]: thread tier, 16, 32 and 64 lanes, 64 lanes under capture
     int2* t1_map = nullptr;
     int t1_blocks = 0;
     std::vector<int> t1_per_prob;
@@ -815,7 +815,7 @@ int batch_build(infft_plan_s* P) {
         (rc = upload(P, &B.cell_map, cmap)) || (rc = upload(P, &B.t1_map, tmap)))
         return rc;
     // ---- solver tiers: thread per problem, then 16- and 32-lane groups over each problem's lists
-    std::vector<SolveJob> sj(4 * (size_t)np);
+    std::vector<SolveJob> sj(5 * (size_t)np);
     for (int i = 0; i < np; ++i) {
         infft_plan_s* sub = B.subs[i];
         SolveJob base{};
@@ -842,13 +842,19 @@ int batch_build(infft_plan_s* P) {
         t2.a.out_list = listA;
         t2.a.out_count = sub->lcount + 2;
         t2.a.stat_off = B.t1_per_prob[i] + B.tier_blocks;
-        t3 = t2;
-        t3.a.out_list = nullptr;
-        t3.a.out_count = nullptr;
+        t3.a.in_list = listA;
+        t3.a.in_count = sub->lcount + 2;
+        t3.a.out_list = listB;
+        t3.a.out_count = sub->lcount + 3;
+        t3.a.stat_off = B.t1_per_prob[i] + 2 * B.tier_blocks;
+        SolveJob t4 = t3;
+        t4.a.out_list = nullptr;
+        t4.a.out_count = nullptr;
         sj[i] = t0;
         sj[np + i] = t1;
         sj[2 * (size_t)np + i] = t2;
         sj[3 * (size_t)np + i] = t3;
+        sj[4 * (size_t)np + i] = t4;
     }
     if ((rc = upload(P, &B.solve_jobs, sj))) return rc;
     if ((rc = P->alloc(&B.counts, np))) return rc;
@@ -910,14 +916,16 @@ int batch_precompute(infft_plan_s* P) {
     LAUNCH_CHECK();
     launch_solve_tier_batched(B.solve_jobs + np, np, 16, B.tier_blocks, P->stream);
     LAUNCH_CHECK();
-    launch_solve_tier_batched(B.solve_jobs + (capturing ? 3 : 2) * (size_t)np, np, 32, B.tier_blocks, P->stream);
+    launch_solve_tier_batched(B.solve_jobs + 2 * (size_t)np, np, 32, B.tier_blocks, P->stream);
+    LAUNCH_CHECK();
+    launch_solve_tier_batched(B.solve_jobs + (capturing ? 4 : 3) * (size_t)np, np, 64, B.tier_blocks, P->stream);
     LAUNCH_CHECK();
     for (int i = 0; i < np; ++i) {
-        B.subs[i]->stat_nrec = B.t1_per_prob[i] + 2 * B.tier_blocks;
+        B.subs[i]->stat_nrec = B.t1_per_prob[i] + 3 * B.tier_blocks;
         B.subs[i]->bopt_ready = true;
     }
     if (!capturing) {
-        launch_batch_counts(B.solve_jobs + 2 * (size_t)np, np, B.counts, P->stream);
+        launch_batch_counts(B.solve_jobs + 3 * (size_t)np, np, B.counts, P->stream);
         LAUNCH_CHECK();
         std::vector<int> cnt(np);
         HIP_TRY(hipMemcpyAsync(cnt.data(), B.counts, sizeof(int) * np, hipMemcpyDeviceToHost, P->stream));
@@ -926,7 +934,7 @@ int batch_precompute(infft_plan_s* P) {
             if (cnt[i] == 0) continue;
             infft_plan_s* sub = B.subs[i];
             int off = sub->stat_nrec;
-            int rc = solve_large(sub, plan_ktab(sub), sub->lists, sub->lcount + 2, off);
+            int rc = solve_large(sub, plan_ktab(sub), sub->lists + sub->g.G, sub->lcount + 3, off);
             if (rc) return rc;
             sub->stat_nrec = off;
         }
@@ -1355,8 +1363,15 @@ int infft_precompute_B(infft_plan p) {
         a.in_count = p->lcount + 1;
         a.out_list = listA;
         a.out_count = p->lcount + 2;
-        last_list = listA;
-        last_count = p->lcount + 2;
+        a.stat_off += launch_solve_tier(g, p->nd, kt, a, 32, p->stream);
+        LAUNCH_CHECK();
+        // 1-D: a wavefront per problem up to 64 members (also under capture)
+        a.in_list = listA;
+        a.in_count = p->lcount + 2;
+        a.out_list = listB;
+        a.out_count = p->lcount + 3;
+        last_list = listB;
+        last_count = p->lcount + 3;
     } else {
         a.in_list = nullptr;
         a.in_count = nullptr;
@@ -1378,7 +1393,7 @@ int infft_precompute_B(infft_plan p) {
         a.out_list = nullptr;
         a.out_count = nullptr;
     }
-    a.stat_off += launch_solve_tier(g, p->nd, kt, a, 32, p->stream);
+    a.stat_off += launch_solve_tier(g, p->nd, kt, a, g.d == 1 ? 64 : 32, p->stream);
     LAUNCH_CHECK();
     int stat_off = a.stat_off;
     if (!capturing) {

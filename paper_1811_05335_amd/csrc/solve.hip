@@ -800,7 +800,8 @@ void launch_batch_counts(const SolveJob* jobs, int njobs, int* out, hipStream_t 
 void launch_solve_tier_batched(const SolveJob* jobs, int njobs, int nl, int blocks, hipStream_t s) {
     if (njobs <= 0 || blocks <= 0) return;
     if (nl == 16) hipLaunchKernelGGL((k_solve_r1_batched<16>), dim3(blocks), dim3(128), 0, s, jobs, njobs);
-    else hipLaunchKernelGGL((k_solve_r1_batched<32>), dim3(blocks), dim3(128), 0, s, jobs, njobs);
+    else if (nl == 32) hipLaunchKernelGGL((k_solve_r1_batched<32>), dim3(blocks), dim3(128), 0, s, jobs, njobs);
+    else hipLaunchKernelGGL((k_solve_r1_batched<64>), dim3(blocks), dim3(128), 0, s, jobs, njobs);
 }
 
 int launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s) {
@@ -820,7 +821,8 @@ int launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl
         const int64_t cap1 = a.in_list ? 1024 : 4096;
         if (b1 > cap1) b1 = cap1;
         if (nl == 16) hipLaunchKernelGGL((k_solve_r1<16>), dim3((unsigned)b1), dim3(128), shm, s, g, nd, kt, a);
-        else hipLaunchKernelGGL((k_solve_r1<32>), dim3((unsigned)b1), dim3(128), shm, s, g, nd, kt, a);
+        else if (nl == 32) hipLaunchKernelGGL((k_solve_r1<32>), dim3((unsigned)b1), dim3(128), shm, s, g, nd, kt, a);
+        else hipLaunchKernelGGL((k_solve_r1<64>), dim3((unsigned)b1), dim3(128), shm, s, g, nd, kt, a);
         return (int)b1;
     }
     const int64_t groups_per_block = 256 / nl;

@@ -52,13 +52,16 @@ def test_large_problems_match_oracle(M, N, d, m, ncl, half, rho):
     P.close()
 
 
-def test_large_problems_under_graph_capture_are_counted_not_solved():
-    """Under graph capture the large-problem pass cannot read sizes back: its problems are
-    reported as oversized and their columns are zero, while the captured small ones match."""
+@pytest.mark.parametrize("M,N,d,m,ncl,half,thr", [((32, 32), 700, 2, 3, 300, 2.5, 32),
+                                                   ((64,), 600, 1, 4, 200, 2.0, 64)])
+def test_large_problems_under_graph_capture_are_counted_not_solved(M, N, d, m, ncl, half, thr):
+    """Under graph capture the large-problem pass cannot read sizes back: its problems (beyond
+    32 members in 2-D, beyond 64 in 1-D, where a wavefront per problem takes 33..64) are reported
+    as oversized and their columns are zero, while the captured smaller ones match."""
     from paper_1811_05335_amd import NfftPlan
-    M, N, d, m = (32, 32), 700, 2, 3
-    x, p = clustered(M, N, d, m, 300, 2.5, seed=12)
+    x, p = clustered(M, N, d, m, ncl, half, seed=12)
     sizes = obopt.Members(x, p).sizes()
+    assert np.any(sizes > thr) and (d == 2 or np.any((sizes > 32) & (sizes <= thr)))
     xd = nodes_dev(x)
     P = NfftPlan(M, xd, sigma=2.0, m=m, precision="f64", rho=1e-8)
     P.precompute_B()
@@ -74,14 +77,14 @@ def test_large_problems_under_graph_capture_are_counted_not_solved():
     graph.replay()
     torch.cuda.synchronize()
     st = P.status()
-    assert st["oversized"] == int(np.sum(sizes > 32))
+    assert st["oversized"] == int(np.sum(sizes > thr))
     captured = host(P.get_B())
     mem = obopt.Members(x, p)
     big_mask = np.zeros(captured.shape, dtype=bool)
     small_mask = np.zeros(captured.shape, dtype=bool)
     for l in range(mem.G):
         js, ts, _ = mem.of(l)
-        if len(js) > 32:
+        if len(js) > thr:
             big_mask[js, ts] = True
         elif len(js) > 0:
             small_mask[js, ts] = True

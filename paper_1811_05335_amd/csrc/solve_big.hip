@@ -12,7 +12,7 @@
 //   for each block column k:
 //     k_big_potrf   factor the diagonal block in LDS and invert the factor (lower triangular)
 //     k_big_trsm    panel below it: L[i][k] = A[i][k] L_kk^{-*} (a product with the inverse)
-//     k_big_herk    trailing tiles: A[i][j] -= L[i][k] L[j][k]^*, k < j <= i
+//     k_big_herk    trailing tiles: A[i][j] -= L[i][k] L[j][k]^*, k < j <= i (FP64 matrix cores)
 //   k_big_solve   L y = r and L^* b = y with the inverse diagonal blocks, b written to B_opt
 // The inverse X = L_kk^{-1} needs no storage of its own: its strictly lower part, conjugated and
 // transposed, fills the unused strictly upper part of the diagonal block, and X[i][i] = 1/L[i][i].
@@ -326,7 +326,13 @@ void launch_big_trsm(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t
     hipLaunchKernelGGL(k_big_trsm, dim3(ntask), dim3(BIG_TPB), 0, s, a, tasks, k);
 }
 
-// Trailing tile (I, J), k < J <= I: A[I][J] -= L[I][k] L[J][k]^* (lower part only when I == J).
+// Trailing tile (I, J), k < J <= I: A[I][J] -= L[I][k] L[J][k]^* (lower part only when I == J), on
+// the FP64 matrix cores: C = L[I][k] L[J][k]^* as four real products, Re C = Ar Jr^T + Ai Ji^T and
+// Im C = Ai Jr^T - Ar Ji^T, with v_mfma_f64_16x16x4.  Each wavefront owns a 32 x 32 quadrant of the
+// 64 x 64 tile (2 x 2 blocks of 16 x 16).  Operand layout of the instruction: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16]; result element i of lane l is C[l / 16 + 4 i][l % 16].
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(BIG_TPB) k_big_herk(BigArgs a, const int4* __restrict__ tasks, int k) {
     constexpr int KC = 16;
     __shared__ double2 sI[KC][BIG_NB + 1];
@@ -337,41 +343,83 @@ __global__ void __launch_bounds__(BIG_TPB) k_big_herk(BigArgs a, const int4* __r
     const int nI = min(BIG_NB, P.n - rI), nJ = min(BIG_NB, P.n - rJ), nk = min(BIG_NB, P.n - c0);
     double2* A = a.A + P.off;
     const int64_t ld = P.n;
-    const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
-    Tile4 acc;
-    acc.zero();
-    for (int q0 = 0; q0 < nk; q0 += KC) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;   // quadrant of this wavefront
+    const int lr = lane & 15, lk = lane >> 4;
+    v4d cr[2][2], ci[2][2];
 #pragma unroll
-        for (int s = 0; s < BIG_NB * KC / BIG_TPB; ++s) {
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) {
+            cr[u][v] = v4d{0.0, 0.0, 0.0, 0.0};
+            ci[u][v] = v4d{0.0, 0.0, 0.0, 0.0};
+        }
+    // the next chunk is loaded into registers while the current one is multiplied
+    constexpr int PER = BIG_NB * KC / BIG_TPB;
+    double2 nxI[PER], nxJ[PER];
+    auto fetch = [&](int q0) {
+#pragma unroll
+        for (int s = 0; s < PER; ++s) {
             const int e = threadIdx.x + s * BIG_TPB;
             const int r = e / KC, qq = e % KC, q = q0 + qq;
-            sI[qq][r] = (r < nI && q < nk) ? A[(int64_t)(rI + r) * ld + c0 + q] : make_double2(0.0, 0.0);
-            sJ[qq][r] = (r < nJ && q < nk) ? A[(int64_t)(rJ + r) * ld + c0 + q] : make_double2(0.0, 0.0);
+            nxI[s] = (r < nI && q < nk) ? A[(int64_t)(rI + r) * ld + c0 + q] : make_double2(0.0, 0.0);
+            nxJ[s] = (r < nJ && q < nk) ? A[(int64_t)(rJ + r) * ld + c0 + q] : make_double2(0.0, 0.0);
+        }
+    };
+    fetch(0);
+    for (int q0 = 0; q0 < nk; q0 += KC) {
+#pragma unroll
+        for (int s = 0; s < PER; ++s) {
+            const int e = threadIdx.x + s * BIG_TPB;
+            const int r = e / KC, qq = e % KC;
+            sI[qq][r] = nxI[s];
+            sJ[qq][r] = nxJ[s];
         }
         __syncthreads();
+        if (q0 + KC < nk) fetch(q0 + KC);
 #pragma unroll
-        for (int qq = 0; qq < KC; ++qq) {
-            double2 x[4], y[4];
+        for (int qs = 0; qs < KC; qs += 4) {
+            double ar[2], ai[2], jr[2], ji[2];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                x[u] = sI[qq][tr * 4 + u];
-                y[u] = sJ[qq][tc * 4 + u];
+            for (int u = 0; u < 2; ++u) {
+                const double2 x = sI[qs + lk][wr + 16 * u + lr];
+                ar[u] = x.x;
+                ai[u] = x.y;
+                const double2 y = sJ[qs + lk][wc + 16 * u + lr];
+                jr[u] = y.x;
+                ji[u] = y.y;
             }
-            acc.acc(x, y);
+            // consecutive instructions update different accumulators
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    cr[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[u], jr[v], cr[u][v], 0, 0, 0);
+                    ci[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], jr[v], ci[u][v], 0, 0, 0);
+                }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    cr[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[u], ji[v], cr[u][v], 0, 0, 0);
+                    ci[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ar[u], ji[v], ci[u][v], 0, 0, 0);
+                }
         }
         __syncthreads();
     }
     const bool diag = t.y == t.z;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = tr * 4 + u, c = tc * 4 + v;
-            if (r < nI && c < nJ && (!diag || c <= r)) {
-                double2* dst = &A[(int64_t)(rI + r) * ld + rJ + c];
-                *dst = csub(*dst, acc.v[u][v]);
+        for (int v = 0; v < 2; ++v)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = wr + 16 * u + lk + 4 * i, c = wc + 16 * v + lr;
+                if (r < nI && c < nJ && (!diag || c <= r)) {
+                    double2* dst = &A[(int64_t)(rI + r) * ld + rJ + c];
+                    *dst = csub(*dst, make_double2(cr[u][v][i], ci[u][v][i]));
+                }
             }
-        }
 }
 
 void launch_big_herk(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t s) {

@@ -361,6 +361,11 @@ __device__ inline void solve_r1_body(const Geo& g, const NodesDev& nd, const KTa
     const int64_t gid = (blk * (int64_t)blockDim.x + threadIdx.x) / NL;
     const int64_t ngroups = nblk * blockDim.x / NL;
     const int64_t count = a.in_list ? (int64_t)(*a.in_count) : g.G;
+    if (blk * (int64_t)GPB >= count) {
+        // no problem for this workgroup (a short list): skip the table staging, leave a neutral record
+        write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, blk, ULLONG_MAX, 0, 0, 0, 0);
+        return;
+    }
 
     const double* tQ = kt.Qs;
     if (TAB_LDS) {

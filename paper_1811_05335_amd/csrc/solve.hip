@@ -548,7 +548,7 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
     __shared__ int s_l0[T1_NODECAP];                   // stencil base of the staged nodes
     __shared__ double s_u[T1_NODECAP];                 // offsets: t_p = l0_p + u_p
     __shared__ double2 s_phi[T1_NODECAP];              // e^{-i pi t_p / sigma}
-    __shared__ int s_range[2];
+    __shared__ int s_range[4];
     // Ks, read per member in the solves, is staged in LDS; Qs, read once per band entry, stays in
     // global memory (keeping LDS to four workgroups per CU)
     stage_to_lds(s_tabk, kt.Ks, (kt.qK + 1) * TAY_NC);
@@ -556,20 +556,29 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
     const int Ms = g.Ms[0], w2 = 2 * g.m;
     const int L0 = blk * T1_TPB;
     const int l = L0 + threadIdx.x;
+    // the first workgroup's windows wrap around the torus: it stages the nodes of the last 2m-1
+    // cells first, with their stencil base shifted by -M_sigma, so that every window is one
+    // contiguous range of the staged nodes (when the grid is long enough that the two parts differ)
+    const bool circ = L0 == 0 && Ms > T1_TPB + w2;
     // node range of the workgroup: from the first member of problem L0 to the last of L0+TPB-1
     if (threadIdx.x == 0) {
         const int lo = max(L0 - w2 + 1, 0);
         const int hi = min(L0 + T1_TPB, Ms);
         s_range[0] = nd.start[lo];
         s_range[1] = nd.start[hi];
+        s_range[2] = circ ? nd.start[Ms - w2 + 1] : 0;
+        s_range[3] = circ ? nd.start[Ms] : 0;
     }
     __syncthreads();
     const int P0 = s_range[0];
-    const int nnode = min(s_range[1] - P0, T1_NODECAP);
-    const bool staged = (s_range[1] - P0) <= T1_NODECAP;
+    const int tS = s_range[2], ntail = s_range[3] - s_range[2];
+    const int total = ntail + (s_range[1] - P0);
+    const int nnode = min(total, T1_NODECAP);
+    const bool staged = total <= T1_NODECAP;
     for (int i = threadIdx.x; i < nnode; i += blockDim.x) {
-        const int p = P0 + i;
-        s_l0[i] = nd.l0s[p];
+        const bool tail = i < ntail;
+        const int p = tail ? tS + i : P0 + (i - ntail);
+        s_l0[i] = nd.l0s[p] - (tail ? Ms : 0);
         s_u[i] = nd.us[p];
         // e^{-i pi t / sigma}, the integer part reduced exactly modulo 2 M_sigma
         const int64_t lm = ((int64_t)nd.l0s[p] * g.M[0]) % (2 * (int64_t)Ms);
@@ -605,9 +614,9 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
             n1 = nd.start[l + 1] - s1;
         }
         const int n = n0 + n1;
-        // windows that wrap around the torus, unstaged node ranges and oversized problems go to
-        // the group kernels
-        bool fallback = wrap || n > NMAX || !staged;
+        // unstaged node ranges, oversized problems and (on short grids) windows that wrap around
+        // the torus go to the group kernels
+        bool fallback = (wrap && !circ) || n > NMAX || !staged;
         {
             // the cell l-2m reaches l through its tap 2m only for nodes with u at m; the tap
             // 2m of every other node belongs to no problem and is zeroed here
@@ -631,7 +640,7 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
         } else {
             st_min = n;
             st_max = n;
-            const int b0 = s0 - P0;   // first member in the staged node range
+            const int b0 = wrap ? s0 - tS : ntail + (s0 - P0);   // first member in the staged range
             // e^{i pi l / sigma}, reduced exactly; w_i = e^{i pi (l - t_i) / sigma} from the staged
             // phases e^{-i pi t_i / sigma}
             double sl, cl;
@@ -745,7 +754,8 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
                 for (int i = 0; i < NMAX; ++i) {
                     if (i < n) {
                         const double2 bb = make_double2(xr[i], xi[i]);
-                        const int64_t idx = (int64_t)(l - s_l0[b0 + i]) * g.N + (s0 + i);
+                        const int p = i < n0 ? s0 + i : s1 + (i - n0);   // sorted position
+                        const int64_t idx = (int64_t)(l - s_l0[b0 + i]) * g.N + p;
                         a.B64[idx] = bb;
                         if (a.B32) a.B32[idx] = make_float2((float)bb.x, (float)bb.y);
                     }

@@ -274,30 +274,23 @@ __global__ void k_scan1(const int* __restrict__ in, int* __restrict__ out, int64
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-__global__ void k_scan2(int* bsum, int64_t nb) {
-    __shared__ int sh[SCAN_T / 64];
-    const int64_t base = threadIdx.x * (int64_t)SCAN_ITEMS;
-    int v[SCAN_ITEMS];
-    int s = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        v[i] = (base + i < nb) ? bsum[base + i] : 0;
-        s += v[i];
-    }
-    int total;
-    int run = block_exclusive_scan(s, sh, &total);
-#pragma unroll
-    for (int i = 0; i < SCAN_ITEMS; ++i) {
-        if (base + i < nb) bsum[base + i] = run;
-        run += v[i];
-    }
-    if (threadIdx.x == 0) bsum[nb] = total;
-}
-
+// Adds the sum of the preceding blocks' totals.  A workgroup of 256 lies inside one scan block, so
+// its first wavefront sums those totals itself (at most 2048 of them) instead of a separate scan.
 __global__ void k_scan3(int* __restrict__ out, int64_t n, const int* __restrict__ bsum, int64_t nb) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i < n) out[i] += bsum[i / SCAN_BLOCK];
-    if (i == n) out[n] = bsum[nb];
+    __shared__ int s_off;
+    const int64_t i0 = blockIdx.x * (int64_t)blockDim.x;
+    const int64_t b = i0 / SCAN_BLOCK;                       // scan block of this workgroup
+    if (threadIdx.x < 64) {
+        int acc = 0;
+        for (int64_t j = threadIdx.x; j < b; j += 64) acc += bsum[j];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (threadIdx.x == 0) s_off = acc;
+    }
+    __syncthreads();
+    const int64_t i = i0 + threadIdx.x;
+    if (i < n) out[i] += s_off;
+    if (i == n) out[n] = s_off + (b < nb ? bsum[b] : 0);   // the grand total
 }
 
 int64_t scan_blocksum_len(int64_t n) { return (n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1; }
@@ -305,7 +298,6 @@ int64_t scan_blocksum_len(int64_t n) { return (n + SCAN_BLOCK - 1) / SCAN_BLOCK 
 void launch_exclusive_scan(const int* in, int* out, int64_t n, int* blocksums, hipStream_t s) {
     const int64_t nb = (n + SCAN_BLOCK - 1) / SCAN_BLOCK;
     hipLaunchKernelGGL(k_scan1, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, out, n, blocksums);
-    hipLaunchKernelGGL(k_scan2, dim3(1), dim3(SCAN_T), 0, s, blocksums, nb);
     hipLaunchKernelGGL(k_scan3, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s, out, n,
                        (const int*)blocksums, nb);
 }

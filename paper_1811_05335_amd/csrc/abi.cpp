@@ -1176,7 +1176,7 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
     P->h01 = P->slots[0].h01;
     if (d == 2) {
         const int nt = g.ntile[0] * g.ntile[1];
-        P->spwork.chunk = 1024;
+        P->spwork.chunk = 128;
         P->spwork.cap = (int)(nt + N / P->spwork.chunk + 1);
         TRY(P->alloc(&P->spwork.nchunk, nt));
         TRY(P->alloc(&P->spwork.items, P->spwork.cap));

@@ -217,7 +217,9 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
     const int pbeg = min(tbeg + item.y * wk.chunk, tend), pend = min(pbeg + wk.chunk, tend);
     const R b = (R)g.b;
 
-    for (int r0 = 0; r0 < nrhs; r0 += rchunk) {
+    // blockIdx.y picks the chunk of right-hand sides: each workgroup holds rc of them in LDS
+    {
+        const int r0 = (int)blockIdx.y * rchunk;
         const int rc = min(rchunk, nrhs - r0);
         for (int c = threadIdx.x; c < 2 * rc * cells; c += blockDim.x) acc[c] = (R)0;
         __syncthreads();
@@ -672,8 +674,9 @@ void launch_spread(const Geo& g, NodesDev nd, const cx<R>* f, const cx<R>* B, cx
     const int64_t cells = (int64_t)(g.TS[0] + 2 * g.m) * (g.d == 2 ? g.TS[1] + 2 * g.m : 1);
     const int rc = min(rchunk, nrhs);
     const size_t shm = (size_t)rc * cells * sizeof(cx<R>);
+    const unsigned nrc = (unsigned)((nrhs + rc - 1) / rc);
 #define INFFT_SPREAD(D_, USEB_)                                                                   \
-    INFFT_DISPATCH_W(g.m, hipLaunchKernelGGL((k_spread<R, D_, W, USEB_>), dim3(blocks), dim3(256), shm, s, \
+    INFFT_DISPATCH_W(g.m, hipLaunchKernelGGL((k_spread<R, D_, W, USEB_>), dim3(blocks, nrc), dim3(256), shm, s, \
                                              g, nd, f, B, grid, grs, h0, h1, h01, hrs0, hrs1, hrs01, nrhs, rc, wk))
     if (B) { INFFT_SPREAD(2, true) } else { INFFT_SPREAD(2, false) }
 #undef INFFT_SPREAD

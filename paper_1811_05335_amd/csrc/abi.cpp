@@ -1184,7 +1184,7 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
         TRY(P->alloc(&P->sp_offs, nt));
         TRY(P->alloc(&P->sp_bsum, scan_blocksum_len(nt)));
     }
-    P->rchunk = spread_rhs_chunk(g, P->prec == INFFT_F64);
+    P->rchunk = spread_rhs_chunk(g);
     TRY(P->alloc(&P->B64, (int64_t)T * N));
     if (P->prec == INFFT_F32) TRY(P->alloc(&P->B32, (int64_t)T * N));
     TRY(P->alloc(&P->lists, 2 * g.G));

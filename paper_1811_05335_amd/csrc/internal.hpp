@@ -448,7 +448,7 @@ void launch_interp_B(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grid_
 template <typename R>
 void launch_grad_x(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grid_rs, const cx<R>* gradf,
                    double* gradx, int nrhs, int accumulate, hipStream_t s);
-int spread_rhs_chunk(const Geo& g, bool fp64);
+int spread_rhs_chunk(const Geo& g);
 int spread1d_tiles(const Geo& g);   // workgroups of the tiled 1-D spreading
 // kind NB_*: interpolation reads the grid and writes `out`; gathers read `in` and write the grid;
 // the gradient reads `in` (gradient of f) and writes `gradx`

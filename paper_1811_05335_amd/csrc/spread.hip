@@ -200,7 +200,10 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
                                                 int64_t hrs01, int nrhs, int rchunk, SpreadWork wk) {
     using C = cx<R>;
     extern __shared__ char smem_raw[];
-    R* acc = (R*)smem_raw;  // [rc][E0][E1][2]
+    // [rc][E0][E1][2] in float64 for both precisions: LDS float32 atomic adds stall the issue of
+    // LDS instructions many times longer than float64 ones here (measured), and the sums gain
+    // accuracy besides
+    double* acc = (double*)smem_raw;
     const int w2 = 2 * g.m;
     if ((int)blockIdx.x >= *wk.total) return;
     const int2 item = wk.items[blockIdx.x];
@@ -221,7 +224,7 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
     {
         const int r0 = (int)blockIdx.y * rchunk;
         const int rc = min(rchunk, nrhs - r0);
-        for (int c = threadIdx.x; c < 2 * rc * cells; c += blockDim.x) acc[c] = (R)0;
+        for (int c = threadIdx.x; c < 2 * rc * cells; c += blockDim.x) acc[c] = 0.0;
         __syncthreads();
         // Nodes are sorted by cell, so the lanes of a wave holding nodes of one cell form
         // contiguous segments whose taps hit the same LDS words.  When a wave has few segments
@@ -254,7 +257,7 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
             const int seg_end = above ? __ffsll((unsigned long long)above) - 1 : 64;
             for (int rr = 0; rr < rc; ++rr) {
                 const C fv = valid ? f[(int64_t)(r0 + rr) * g.N + j] : cmake((R)0, (R)0);
-                R* a = acc + (int64_t)rr * cells * 2;
+                double* a = acc + (int64_t)rr * cells * 2;
 #pragma unroll
                 for (int s0 = 0; s0 < W; ++s0) {
                     C fs;
@@ -278,12 +281,12 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
                                 }
                             }
                             if (head && valid) {
-                                lds_add(&a[2 * cidx], v.x);
-                                lds_add(&a[2 * cidx + 1], v.y);
+                                lds_add(&a[2 * cidx], (double)v.x);
+                                lds_add(&a[2 * cidx + 1], (double)v.y);
                             }
                         } else if (valid) {
-                            lds_add(&a[2 * cidx], v.x);
-                            lds_add(&a[2 * cidx + 1], v.y);
+                            lds_add(&a[2 * cidx], (double)v.x);
+                            lds_add(&a[2 * cidx + 1], (double)v.y);
                         }
                     }
                 }
@@ -293,7 +296,7 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
         for (int c = threadIdx.x; c < rc * cells; c += blockDim.x) {
             const int rr = c / cells, cc = c - rr * cells;
             const int e0 = cc / E1, e1 = cc - e0 * E1;
-            const C v = cmake(acc[2 * c], acc[2 * c + 1]);
+            const C v = cmake((R)acc[2 * c], (R)acc[2 * c + 1]);
             const int64_t r = r0 + rr;
             C* dst;
             if (e0 < TS0 && e1 < TS1) {
@@ -307,7 +310,8 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
             }
             if (nch == 1) {
                 *dst = v;
-            } else {
+            } else if (v.x != (R)0 || v.y != (R)0) {
+                // a chunk's nodes reach a few rows of the tile; cells they miss hold exact zeros
                 gadd(&dst->x, v.x);
                 gadd(&dst->y, v.y);
             }
@@ -647,9 +651,9 @@ void launch_interp_B(const Geo& g, NodesDev nd, const cx<R>* grid, int64_t grs, 
     }
 }
 
-int spread_rhs_chunk(const Geo& g, bool fp64) {
+int spread_rhs_chunk(const Geo& g) {
     const int64_t cells = (int64_t)(g.TS[0] + 2 * g.m) * (g.d == 2 ? g.TS[1] + 2 * g.m : 1);
-    const int64_t per = cells * (fp64 ? 16 : 8);
+    const int64_t per = cells * 2 * (int64_t)sizeof(double);
     int rc = (int)((48 * 1024) / per);
     if (rc < 1) rc = 1;
     if (rc > 16) rc = 16;
@@ -673,7 +677,7 @@ void launch_spread(const Geo& g, NodesDev nd, const cx<R>* f, const cx<R>* B, cx
     const unsigned blocks = (unsigned)wk.cap;
     const int64_t cells = (int64_t)(g.TS[0] + 2 * g.m) * (g.d == 2 ? g.TS[1] + 2 * g.m : 1);
     const int rc = min(rchunk, nrhs);
-    const size_t shm = (size_t)rc * cells * sizeof(cx<R>);
+    const size_t shm = (size_t)rc * cells * 2 * sizeof(double);
     const unsigned nrc = (unsigned)((nrhs + rc - 1) / rc);
 #define INFFT_SPREAD(D_, USEB_)                                                                   \
     INFFT_DISPATCH_W(g.m, hipLaunchKernelGGL((k_spread<R, D_, W, USEB_>), dim3(blocks, nrc), dim3(256), shm, s, \

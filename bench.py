@@ -45,9 +45,11 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph replay")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run every call on the main stream (same as --overlap none)")
-    ap.add_argument("--overlap", choices=("none", "pre", "tail", "full"), default="tail",
-                    help="pre: the B optimisation on a second stream; tail: also the node gradient beside "
-                         "the inverse adjoint (own stream and work slot); full: the adjoint and the node "
+    ap.add_argument("--overlap", choices=("none", "pre", "tail", "full"), default="none",
+                    help="none: one stream (the fastest replay: the B optimisation's first solve fills "
+                         "every CU, so branches gain little and cost cross-queue waits); pre: the B "
+                         "optimisation on a second stream; tail: also the node gradient beside the "
+                         "inverse adjoint (own stream and work slot); full: the adjoint and the node "
                          "gradient on their own streams and work slots from the start")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="run one device-to-device copy of this size first (counter calibration under a profiler)")

@@ -1323,13 +1323,12 @@ int infft_precompute_B(infft_plan p) {
     const Geo& g = p->g;
     const int64_t TN = (int64_t)p->taps() * g.N;
     p->bopt_ready = false;
-    launch_status_init(p->status, 1, p->stream);
+    launch_solve_reset(p->status, p->lcount, p->stream);
     if (g.d == 2) {
         // 1-D tiers write every entry of B_opt themselves (zeros where no problem reaches)
         launch_fill_bytes0(p->B64, TN * (int64_t)sizeof(double2), p->stream);
         if (p->B32) launch_fill_bytes0(p->B32, TN * (int64_t)sizeof(float2), p->stream);
     }
-    launch_fill_i32(p->lcount, 4, 0, p->stream);
     const KTabDev kt = plan_ktab(p);
     SolveArgs a{};
     a.B64 = p->B64;

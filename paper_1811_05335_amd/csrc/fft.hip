@@ -219,28 +219,41 @@ __device__ inline int coeff_index(int p, int Ms, int M) {
     return (k >= -M / 2 && k < M / 2) ? k + M / 2 : -1;
 }
 
-template <typename R, int LD>
+// Grid position -> (row, column) of a D-dimensional grid (D = 1: the position itself).
+template <int D> __device__ inline void grid_rc(const Geo& g, int64_t pos, int& p0, int& p1) {
+    if (D == 1) {
+        p0 = (int)pos;
+        p1 = 0;
+    } else {
+        p0 = (int)(pos / g.Ms[1]);
+        p1 = (int)(pos - (int64_t)p0 * g.Ms[1]);
+    }
+}
+
+// The element loads are branch-free where the pass is one-dimensional (a coefficient outside the
+// M range is loaded at index 0 and replaced by zero), so that the loads of a thread's elements
+// can all be in flight together.
+template <typename R, int LD, int D>
 __device__ inline cx<R> load_elem(const FftIO& io, const FftPass& P, const Geo& g, int64_t r, int64_t pos) {
     using C = cx<R>;
     if (LD == LD_GRID) {
         return ((const C*)io.in)[r * P.in_rs + pos];
     } else if (LD == LD_DECONV) {
-        int p0, p1 = 0;
-        if (g.d == 1) p0 = (int)pos;
-        else { p0 = (int)(pos / g.Ms[1]); p1 = (int)(pos - (int64_t)p0 * g.Ms[1]); }
+        int p0, p1;
+        grid_rc<D>(g, pos, p0, p1);
         const int i0 = coeff_index(p0, g.Ms[0], g.M[0]);
-        const int i1 = (g.d == 1) ? 0 : coeff_index(p1, g.Ms[1], g.M[1]);
-        if (i0 < 0 || i1 < 0) return cmake((R)0, (R)0);
-        R s = ((const R*)io.D0)[i0];
-        if (g.d == 2) s *= ((const R*)io.D1)[i1];
-        const C v = ((const C*)io.in)[r * P.in_rs + (int64_t)i0 * g.M[1] + i1];
-        return cscale(v, s);
+        const int i1 = (D == 1) ? 0 : coeff_index(p1, g.Ms[1], g.M[1]);
+        const bool ok = i0 >= 0 && i1 >= 0;
+        const int j0 = max(i0, 0), j1 = max(i1, 0);
+        R s = ((const R*)io.D0)[j0];
+        if (D == 2) s *= ((const R*)io.D1)[j1];
+        const C v = ((const C*)io.in)[r * P.in_rs + (int64_t)j0 * g.M[1] + j1];
+        return ok ? cscale(v, s) : cmake((R)0, (R)0);
     } else {  // LD_HALO
         C v = ((const C*)io.in)[r * P.in_rs + pos];
         const int w2 = 2 * g.m;
-        int p0, p1 = 0;
-        if (g.d == 1) p0 = (int)pos;
-        else { p0 = (int)(pos / g.Ms[1]); p1 = (int)(pos - (int64_t)p0 * g.Ms[1]); }
+        int p0, p1;
+        grid_rc<D>(g, pos, p0, p1);
         const int t0 = p0 / g.TS[0], o0 = p0 - t0 * g.TS[0];
         const int t1 = p1 / g.TS[1], o1 = p1 - t1 * g.TS[1];
         const int tm0 = (t0 == 0) ? g.ntile[0] - 1 : t0 - 1;
@@ -249,7 +262,7 @@ __device__ inline cx<R> load_elem(const FftIO& io, const FftPass& P, const Geo& 
             const int64_t tile = (int64_t)tm0 * g.ntile[1] + t1;
             v = cadd(v, ((const C*)io.h0)[r * io.halo_rs0 + (tile * w2 + o0) * g.TS[1] + o1]);
         }
-        if (g.d == 2 && o1 < w2) {
+        if (D == 2 && o1 < w2) {
             const int64_t tile = (int64_t)t0 * g.ntile[1] + tm1;
             v = cadd(v, ((const C*)io.h1)[r * io.halo_rs1 + (tile * g.TS[0] + o0) * w2 + o1]);
             if (o0 < w2) {
@@ -261,71 +274,143 @@ __device__ inline cx<R> load_elem(const FftIO& io, const FftPass& P, const Geo& 
     }
 }
 
-template <typename R, int ST>
+// What a store needs from memory besides the transformed value, loaded with the pass's input:
+// the two table entries of the inter-pass twiddle (ST_TWIDDLE) or the deconvolution factor
+// (ST_DECONV).
+template <typename R> struct StoreOperand {
+    cx<R> hi, lo;
+    R scale;
+};
+
+template <typename R, int ST, int D>
+__device__ inline void store_prefetch(const FftIO& io, const FftPass& P, const Geo& g, int64_t pos, int64_t q,
+                                      int k, StoreOperand<R>& o) {
+    using C = cx<R>;
+    if (ST == ST_TWIDDLE) {
+        // q < n2 and k < n1, so e = q k < N: no reduction; twB is a power of two
+        const uint32_t e = (uint32_t)q * (uint32_t)k;
+        o.hi = ((const C*)P.twHi)[e >> P.twShift];
+        o.lo = ((const C*)P.twLo)[e & (uint32_t)(P.twB - 1)];
+    } else if (ST == ST_DECONV) {
+        int p0, p1;
+        grid_rc<D>(g, pos, p0, p1);
+        const int i0 = coeff_index(p0, g.Ms[0], g.M[0]);
+        const int i1 = (D == 1) ? 0 : coeff_index(p1, g.Ms[1], g.M[1]);
+        o.scale = ((const R*)io.D0)[max(i0, 0)];
+        if (D == 2) o.scale *= ((const R*)io.D1)[max(i1, 0)];
+    }
+}
+
+template <typename R, int ST, int D>
 __device__ inline void store_elem(const FftIO& io, const FftPass& P, const Geo& g, int64_t r, int64_t pos,
-                                  int64_t q, int k, cx<R> v) {
+                                  const StoreOperand<R>& o, cx<R> v) {
     using C = cx<R>;
     if (ST == ST_GRID) {
         ((C*)io.out)[r * P.out_rs + pos] = v;
     } else if (ST == ST_TWIDDLE) {
-        // q < n2 and k < n1, so e = q k < N: no reduction; twB is a power of two
-        const uint32_t e = (uint32_t)q * (uint32_t)k;
-        const uint32_t hi = e >> P.twShift, lo = e & (uint32_t)(P.twB - 1);
-        C w = cmul(((const C*)P.twHi)[hi], ((const C*)P.twLo)[lo]);
+        C w = cmul(o.hi, o.lo);
         if (P.sign > 0) w.y = -w.y;
         ((C*)io.out)[r * P.out_rs + pos] = cmul(v, w);
-    } else {  // ST_DECONV
-        int p0, p1 = 0;
-        if (g.d == 1) p0 = (int)pos;
-        else { p0 = (int)(pos / g.Ms[1]); p1 = (int)(pos - (int64_t)p0 * g.Ms[1]); }
+    } else {  // ST_DECONV: truncation to the M range
+        int p0, p1;
+        grid_rc<D>(g, pos, p0, p1);
         const int i0 = coeff_index(p0, g.Ms[0], g.M[0]);
-        const int i1 = (g.d == 1) ? 0 : coeff_index(p1, g.Ms[1], g.M[1]);
+        const int i1 = (D == 1) ? 0 : coeff_index(p1, g.Ms[1], g.M[1]);
         if (i0 < 0 || i1 < 0) return;
-        R s = ((const R*)io.D0)[i0];
-        if (g.d == 2) s *= ((const R*)io.D1)[i1];
-        ((C*)io.out)[r * P.out_rs + (int64_t)i0 * g.M[1] + i1] = cscale(v, s);
+        ((C*)io.out)[r * P.out_rs + (int64_t)i0 * g.M[1] + i1] = cscale(v, o.scale);
     }
 }
 
-// One workgroup's share of a pass: sub-transforms blk * rows .. of the pass.
-template <typename R, int E, int LD, int ST>
+// One workgroup's share of a pass: sub-transforms blk * rows .. of the pass.  A pass moves little
+// data per workgroup (a few elements per thread), so its time is memory latency: every global
+// load of the workgroup (the elements, the stage twiddle table, the store operands) is issued
+// before the first is used, and the pass waits on memory once instead of once per element.
+template <typename R, int E, int LD, int ST, int D>
 __device__ inline void fft_block(const FftPass& P, int64_t nseq, const FftIO& io, const Geo& g, int64_t blk) {
+    using C = cx<R>;
     extern __shared__ char smem_raw[];
-    cx<R>* lds = (cx<R>*)smem_raw;
+    C* lds = (C*)smem_raw;
     const int ld = P.n + 1;
     const int64_t seq0 = blk * (int64_t)P.rows;
     if (seq0 >= nseq) return;
     const int rows = (int)min((int64_t)P.rows, nseq - seq0);
-    const int tot = rows * P.n;
+    const int tot = rows * P.n;   // at most FFT_THREADS * E
     const UDiv drows((uint32_t)rows), dn((uint32_t)P.n), dnq((uint32_t)P.nq);
-    // the twiddle table follows the data in LDS, loaded together with it (one wait on memory
-    // instead of one per stage)
-    cx<R>* s_tw = lds + (int64_t)P.rows * ld;
-    const cx<R>* gtw = (const cx<R>*)P.tw;
-    for (int i = threadIdx.x; i < P.n; i += FFT_THREADS) s_tw[i] = gtw[i];
-    for (int L = threadIdx.x; L < tot; L += FFT_THREADS) {
+    // the stage twiddle table follows the data in LDS
+    C* s_tw = lds + (int64_t)P.rows * ld;
+    const C* gtw = (const C*)P.tw;
+    // Every load runs unconditionally, at an index clamped into range: a thread past the end
+    // re-reads the last element (or table entry) and writes it to the same LDS slot as its owner,
+    // with the same value.  Without branches the unrolled loops are straight-line code and the
+    // loads are issued back to back.
+    C dat[E], twt[E];
+    StoreOperand<R> so[(ST == ST_GRID) ? 1 : E];
+    int slot[E];
+#pragma unroll
+    for (int it = 0; it < E; ++it) {
+        const int L = threadIdx.x + it * FFT_THREADS;
+        twt[it] = gtw[min(L, P.n - 1)];
+        const int Lc = min(L, tot - 1);
         int row, i;
-        if (P.in_rowfast) { i = (int)drows.div((uint32_t)L); row = L - i * rows; }
-        else { row = (int)dn.div((uint32_t)L); i = L - row * P.n; }
+        if (P.in_rowfast) { i = (int)drows.div((uint32_t)Lc); row = Lc - i * rows; }
+        else { row = (int)dn.div((uint32_t)Lc); i = Lc - row * P.n; }
+        slot[it] = row * ld + i;
         const uint32_t s = (uint32_t)(seq0 + row);
         const uint32_t r = dnq.div(s), q = s - r * (uint32_t)P.nq;
-        lds[row * ld + i] = load_elem<R, LD>(io, P, g, r, (int64_t)q * P.in_qs + (int64_t)i * P.in_is);
+        dat[it] = load_elem<R, LD, D>(io, P, g, r, (int64_t)q * P.in_qs + (int64_t)i * P.in_is);
+        if (ST != ST_GRID) {
+            int orow, k;
+            if (P.out_rowfast) { k = (int)drows.div((uint32_t)Lc); orow = Lc - k * rows; }
+            else { orow = (int)dn.div((uint32_t)Lc); k = Lc - orow * P.n; }
+            const uint32_t os = (uint32_t)(seq0 + orow);
+            const uint32_t oq = os - dnq.div(os) * (uint32_t)P.nq;
+            store_prefetch<R, ST, D>(io, P, g, (int64_t)oq * P.out_qs + (int64_t)k * P.out_ks, oq, k, so[it]);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < E; ++it) {
+        s_tw[min((int)threadIdx.x + it * FFT_THREADS, P.n - 1)] = twt[it];
+        lds[slot[it]] = dat[it];
     }
     __syncthreads();
     lds_fft<R, E>(lds, ld, rows, P, s_tw);
-    for (int L = threadIdx.x; L < tot; L += FFT_THREADS) {
-        int row, k;
-        if (P.out_rowfast) { k = (int)drows.div((uint32_t)L); row = L - k * rows; }
-        else { row = (int)dn.div((uint32_t)L); k = L - row * P.n; }
-        const uint32_t s = (uint32_t)(seq0 + row);
-        const uint32_t r = dnq.div(s), q = s - r * (uint32_t)P.nq;
-        store_elem<R, ST>(io, P, g, r, (int64_t)q * P.out_qs + (int64_t)k * P.out_ks, q, k, lds[row * ld + k]);
+#pragma unroll
+    for (int it = 0; it < E; ++it) {
+        const int L = threadIdx.x + it * FFT_THREADS;
+        if (L < tot) {
+            int row, k;
+            if (P.out_rowfast) { k = (int)drows.div((uint32_t)L); row = L - k * rows; }
+            else { row = (int)dn.div((uint32_t)L); k = L - row * P.n; }
+            const uint32_t s = (uint32_t)(seq0 + row);
+            const uint32_t r = dnq.div(s), q = s - r * (uint32_t)P.nq;
+            store_elem<R, ST, D>(io, P, g, r, (int64_t)q * P.out_qs + (int64_t)k * P.out_ks,
+                                 so[(ST == ST_GRID) ? 0 : it], lds[row * ld + k]);
+        }
     }
+}
+
+// The body is instantiated for the elements per thread the pass needs (a power of two up to the
+// capacity E), so no thread loads more than one element past the end; the choice and the
+// dimension are uniform branches at the kernel's entry.
+template <typename R, int E, int LD, int ST, int D>
+__device__ inline void fft_block_e(const FftPass& P, int64_t nseq, const FftIO& io, const Geo& g, int64_t blk) {
+    const int ept = (P.rows * P.n + FFT_THREADS - 1) / FFT_THREADS;
+    if (ept <= 1) fft_block<R, 1, LD, ST, D>(P, nseq, io, g, blk);
+    else if (ept <= 2) fft_block<R, 2, LD, ST, D>(P, nseq, io, g, blk);
+    else if (ept <= 4) fft_block<R, 4, LD, ST, D>(P, nseq, io, g, blk);
+    else if (E <= 8 || ept <= 8) fft_block<R, (E < 8 ? E : 8), LD, ST, D>(P, nseq, io, g, blk);
+    else fft_block<R, E, LD, ST, D>(P, nseq, io, g, blk);
+}
+
+template <typename R, int E, int LD, int ST>
+__device__ inline void fft_block_d(const FftPass& P, int64_t nseq, const FftIO& io, const Geo& g, int64_t blk) {
+    if (g.d == 1) fft_block_e<R, E, LD, ST, 1>(P, nseq, io, g, blk);
+    else fft_block_e<R, E, LD, ST, 2>(P, nseq, io, g, blk);
 }
 
 template <typename R, int E, int LD, int ST>
 __global__ void __launch_bounds__(FFT_THREADS) k_fft(FftPass P, FftIO io, Geo g) {
-    fft_block<R, E, LD, ST>(P, P.nseq, io, g, blockIdx.x);
+    fft_block_d<R, E, LD, ST>(P, P.nseq, io, g, blockIdx.x);
 }
 
 // Passes of many problems in one launch: workgroup -> (job, block of that job's pass).  A job's
@@ -343,7 +428,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_batched(const FftJob* __res
     FftIO io = J.io;
     if (J.user_in) io.in = (const cx<R>*)user_in + (int64_t)nrhs * J.user_off;
     if (J.user_out) io.out = (cx<R>*)user_out + (int64_t)nrhs * J.user_off;
-    fft_block<R, E, LD, ST>(J.pass, J.pass.nq * nrhs, io, J.g, b.y);
+    fft_block_e<R, E, LD, ST, 1>(J.pass, J.pass.nq * nrhs, io, J.g, b.y);   // batches are 1-D
 }
 
 template <typename R>

@@ -402,6 +402,7 @@ void launch_scatter_nodes(const Geo& g, NodesDev nd, int* fill, hipStream_t s);
 void launch_cell_sort(const Geo& g, NodesDev nd, int* big_list, int* big_count, hipStream_t s);
 void launch_export_B(const Geo& g, const int* perm, const double2* B, double2* rows, hipStream_t s);
 void launch_status_init(long long* status, int keep_node_words, hipStream_t s);
+void launch_solve_reset(long long* status, int* lcount, hipStream_t s);
 void launch_nodes_reset(long long* status, int* counts, int64_t ncounts, int* fill, int64_t nfill, int* lcount,
                         hipStream_t s);
 

@@ -50,6 +50,19 @@ void launch_status_init(long long* status, int keep_node_words, hipStream_t s) {
     hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, s, status, keep_node_words);
 }
 
+// Start of a B optimisation: the solve words of the status block (the node words are kept) and
+// the four list counters, in one launch.
+__global__ void k_solve_reset(long long* st, int* lcount) {
+    const int i = threadIdx.x;
+    if (i < 4) lcount[i] = 0;
+    if (i >= STATUS_WORDS || i == ST_NONFINITE) return;
+    st[i] = (i == ST_MIN_N) ? LLONG_MAX : 0;
+}
+
+void launch_solve_reset(long long* status, int* lcount, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve_reset, dim3(1), dim3(64), 0, s, status, lcount);
+}
+
 // Start of the node preprocessing in one launch: the status block, the per-cell counters and fill
 // cursors, and the four list counters.
 __global__ void k_nodes_reset(long long* st, int* counts, int64_t ncounts, int* fill, int64_t nfill, int* lcount) {

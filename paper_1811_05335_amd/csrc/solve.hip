@@ -833,7 +833,11 @@ int launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl
         const size_t shm = (size_t)(kt.qQ + 1) * TAY_NC * sizeof(double);
         a.tables_in_lds = 1;
         int64_t b1 = (g.G + (128 / nl) - 1) / (128 / nl);
-        const int64_t cap1 = a.in_list ? 1024 : 4096;
+        // A list tier's problems are counted on the device, so its grid is sized for the longest
+        // list; workgroups past the list exit at once.  Their LDS (matrices plus the Q table, about
+        // 37, 53 and 86 KB for 16, 32 and 64 lanes) still bounds how many are resident per CU, so
+        // the cap is one dispatch round of 256 CUs: 4, 3 and 1 workgroups per CU.
+        const int64_t cap1 = !a.in_list ? 4096 : nl == 16 ? 1024 : nl == 32 ? 768 : 256;
         if (b1 > cap1) b1 = cap1;
         if (nl == 16) hipLaunchKernelGGL((k_solve_r1<16>), dim3((unsigned)b1), dim3(128), shm, s, g, nd, kt, a);
         else if (nl == 32) hipLaunchKernelGGL((k_solve_r1<32>), dim3((unsigned)b1), dim3(128), shm, s, g, nd, kt, a);

@@ -459,7 +459,7 @@ int set_nodes_impl(infft_plan_s* P, const double* x) {
     launch_prep_nodes(g, x, P->nd, P->counts, P->status, s);
     launch_exclusive_scan(P->counts, P->nd.start, g.G, P->bsum, s);
     launch_scatter_nodes(g, P->nd, P->fill, s);
-    launch_cell_sort(g, P->nd, P->lists, P->lcount + 2, s);
+    launch_cell_sort(g, P->nd, s);
     if (g.d == 2) launch_spread_worklist(g, P->nd, P->spwork, P->sp_offs, P->sp_bsum, s);
     LAUNCH_CHECK();
     P->bopt_ready = false;

@@ -399,7 +399,7 @@ void launch_prep_nodes(const Geo& g, const double* x, NodesDev nd, int* counts, 
 void launch_exclusive_scan(const int* in, int* out, int64_t n, int* blocksums, hipStream_t s);
 int64_t scan_blocksum_len(int64_t n);
 void launch_scatter_nodes(const Geo& g, NodesDev nd, int* fill, hipStream_t s);
-void launch_cell_sort(const Geo& g, NodesDev nd, int* big_list, int* big_count, hipStream_t s);
+void launch_cell_sort(const Geo& g, NodesDev nd, hipStream_t s);
 void launch_export_B(const Geo& g, const int* perm, const double2* B, double2* rows, hipStream_t s);
 void launch_status_init(long long* status, int keep_node_words, hipStream_t s);
 void launch_solve_reset(long long* status, int* lcount, hipStream_t s);

@@ -150,7 +150,7 @@ void launch_scatter_nodes(const Geo& g, NodesDev nd, int* fill, hipStream_t s) {
 // The scatter places the nodes of one cell in atomic order.  Sorting each cell's range by caller
 // index makes the sorted order, and with it every member order of the local problems, a function
 // of the input alone.  Cells of up to CELL_SORT_SMALL nodes are sorted by one thread in place;
-// larger cells (dense 2-D centres) by one workgroup with a bitonic sort in LDS.
+// larger cells (dense 2-D centres) by the workgroup that found them, with a bitonic sort in LDS.
 
 constexpr int CELL_SORT_SMALL = 32;
 constexpr int CELL_SORT_BIG = 4096;
@@ -165,37 +165,41 @@ __device__ inline void refresh_sorted(NodesDev& nd, int pos) {
     }
 }
 
-template <int D>
-__global__ void k_cell_sort_small(Geo g, NodesDev nd, int* big_list, int* big_count) {
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= g.G) return;
-    const int s = nd.start[c], e = nd.start[c + 1];
-    const int cnt = e - s;
-    if (cnt <= 1) return;
-    if (cnt > CELL_SORT_SMALL) {
-        big_list[atomicAdd(big_count, 1)] = (int)c;
-        return;
-    }
-    for (int i = s + 1; i < e; ++i) {  // insertion sort of perm[s..e)
-        const int v = nd.perm[i];
-        int k = i - 1;
-        while (k >= s && nd.perm[k] > v) {
-            nd.perm[k + 1] = nd.perm[k];
-            --k;
-        }
-        nd.perm[k + 1] = v;
-    }
-    for (int i = s; i < e; ++i) refresh_sorted<D>(nd, i);
-}
+// One workgroup per CELL_SORT_TPB cells: each thread sorts a small cell by itself; the cells above
+// CELL_SORT_SMALL nodes are collected in LDS and sorted afterwards by the whole workgroup.
+constexpr int CELL_SORT_TPB = 256;
 
 template <int D>
-__global__ void __launch_bounds__(1024) k_cell_sort_big(Geo g, NodesDev nd, const int* big_list,
-                                                        const int* big_count) {
+__global__ void __launch_bounds__(CELL_SORT_TPB) k_cell_sort(Geo g, NodesDev nd) {
     __shared__ int buf[CELL_SORT_BIG];
-    const int nbig = *big_count;
-    for (int b = blockIdx.x; b < nbig; b += gridDim.x) {
-        const int c = big_list[b];
+    __shared__ int s_big[CELL_SORT_TPB];
+    __shared__ int s_nbig;
+    if (threadIdx.x == 0) s_nbig = 0;
+    __syncthreads();
+    const int64_t c = blockIdx.x * (int64_t)CELL_SORT_TPB + threadIdx.x;
+    if (c < g.G) {
         const int s = nd.start[c], e = nd.start[c + 1];
+        const int cnt = e - s;
+        if (cnt > CELL_SORT_SMALL) {
+            s_big[atomicAdd(&s_nbig, 1)] = (int)c;
+        } else if (cnt > 1) {
+            for (int i = s + 1; i < e; ++i) {  // insertion sort of perm[s..e)
+                const int v = nd.perm[i];
+                int k = i - 1;
+                while (k >= s && nd.perm[k] > v) {
+                    nd.perm[k + 1] = nd.perm[k];
+                    --k;
+                }
+                nd.perm[k + 1] = v;
+            }
+            for (int i = s; i < e; ++i) refresh_sorted<D>(nd, i);
+        }
+    }
+    __syncthreads();
+    const int nbig = s_nbig;
+    for (int b = 0; b < nbig; ++b) {
+        const int cb = s_big[b];
+        const int s = nd.start[cb], e = nd.start[cb + 1];
         const int cnt = e - s;
         if (cnt > CELL_SORT_BIG) continue;  // left in scatter order
         int n2 = 1;
@@ -225,15 +229,10 @@ __global__ void __launch_bounds__(1024) k_cell_sort_big(Geo g, NodesDev nd, cons
     }
 }
 
-void launch_cell_sort(const Geo& g, NodesDev nd, int* big_list, int* big_count, hipStream_t s) {
-    const unsigned blocks = (unsigned)((g.G + 255) / 256);
-    if (g.d == 1) {
-        hipLaunchKernelGGL(k_cell_sort_small<1>, dim3(blocks), dim3(256), 0, s, g, nd, big_list, big_count);
-        hipLaunchKernelGGL(k_cell_sort_big<1>, dim3(64), dim3(1024), 0, s, g, nd, big_list, big_count);
-    } else {
-        hipLaunchKernelGGL(k_cell_sort_small<2>, dim3(blocks), dim3(256), 0, s, g, nd, big_list, big_count);
-        hipLaunchKernelGGL(k_cell_sort_big<2>, dim3(64), dim3(1024), 0, s, g, nd, big_list, big_count);
-    }
+void launch_cell_sort(const Geo& g, NodesDev nd, hipStream_t s) {
+    const unsigned blocks = (unsigned)((g.G + CELL_SORT_TPB - 1) / CELL_SORT_TPB);
+    if (g.d == 1) hipLaunchKernelGGL(k_cell_sort<1>, dim3(blocks), dim3(CELL_SORT_TPB), 0, s, g, nd);
+    else hipLaunchKernelGGL(k_cell_sort<2>, dim3(blocks), dim3(CELL_SORT_TPB), 0, s, g, nd);
 }
 
 // ------------------------------------------------------------------ exclusive scan

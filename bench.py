@@ -260,9 +260,9 @@ def solve_traffic(precision):
 def solve_flops(n):
     """FP64 flops of one local problem as the 1-D kernel computes it (real Sherman-Morrison form):
     Gram entries n(n+1)/2 Taylor evaluations (10 fma), right-hand side n (10 fma), Cholesky n^3/3,
-    three right-hand sides forward and back 6 n^2, combination 10 n."""
+    three right-hand sides forward (3 n^2) and two back (2 n^2), combination 10 n."""
     n = np.asarray(n, dtype=np.float64)
-    return n * (n + 1) / 2 * 20 + n * 20 + n ** 3 / 3 + 6 * n ** 2 + 10 * n
+    return n * (n + 1) / 2 * 20 + n * 20 + n ** 3 / 3 + 5 * n ** 2 + 10 * n
 
 
 def timed_graph(torch, fn, steps, warmup):

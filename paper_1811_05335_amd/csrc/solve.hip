@@ -680,76 +680,68 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
             if (!ok) {
                 ++st_fail;
             } else {
-                // two real right-hand sides x, y through L L^T
-                auto solve2 = [&](double (&x)[NMAX], double (&y)[NMAX]) {
-#pragma unroll
-                    for (int k = 0; k < NMAX; ++k) {
-                        const double iv = A[k * (k + 1) / 2 + k];
-                        x[k] *= iv;
-                        y[k] *= iv;
-#pragma unroll
-                        for (int i = k + 1; i < NMAX; ++i) {
-                            const double lik = A[i * (i + 1) / 2 + k];
-                            x[i] = fma(-lik, x[k], x[i]);
-                            y[i] = fma(-lik, y[k], y[i]);
-                        }
-                    }
-#pragma unroll
-                    for (int k = NMAX - 1; k >= 0; --k) {
-                        const double iv = A[k * (k + 1) / 2 + k];
-                        x[k] *= iv;
-                        y[k] *= iv;
-#pragma unroll
-                        for (int i = 0; i < k; ++i) {
-                            const double lki = A[k * (k + 1) / 2 + i];
-                            x[i] = fma(-lki, x[k], x[i]);
-                            y[i] = fma(-lki, y[k], y[i]);
-                        }
-                    }
-                };
+                // Sherman-Morrison through L alone: with y_w = L^{-1} w and y_k = L^{-1} Ks,
+                //   s = w^* A0^{-1} w = |y_w|^2,   u^* Ks = w^* A0^{-1} Ks = y_w^* y_k,
+                //   b = A0^{-1} (Ks + c' w) = L^{-T} (y_k + c' y_w),
+                // so three right-hand sides go forward and two come back
                 auto phase = [&](int i, double& wr, double& wi) {
                     const double2 ph = s_phi[b0 + i];
                     wr = cl * ph.x - sl * ph.y;
                     wi = cl * ph.y + sl * ph.x;
                 };
-                auto ks = [&](int i) {
-                    return tay_eval_r(s_tabk, kt.qK, (double)(l - s_l0[b0 + i]) - s_u[b0 + i]);
-                };
-                // ---- u = A0^{-1} w
-                double xr[NMAX], xi[NMAX];
+                double xr[NMAX], xi[NMAX], xk[NMAX];
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
-                    xr[i] = xi[i] = 0.0;
-                    if (i < n) phase(i, xr[i], xi[i]);
+                    xr[i] = xi[i] = xk[i] = 0.0;
+                    if (i < n) {
+                        phase(i, xr[i], xi[i]);
+                        xk[i] = tay_eval_r(s_tabk, kt.qK, (double)(l - s_l0[b0 + i]) - s_u[b0 + i]);
+                    }
                 }
-                solve2(xr, xi);
-                // ---- s = w^* u (real), u^* Ks = w^* A0^{-1} Ks
+                // forward: L y = x for the three right-hand sides
+#pragma unroll
+                for (int k = 0; k < NMAX; ++k) {
+                    const double iv = A[k * (k + 1) / 2 + k];
+                    xr[k] *= iv;
+                    xi[k] *= iv;
+                    xk[k] *= iv;
+#pragma unroll
+                    for (int i = k + 1; i < NMAX; ++i) {
+                        const double lik = A[i * (i + 1) / 2 + k];
+                        xr[i] = fma(-lik, xr[k], xr[i]);
+                        xi[i] = fma(-lik, xi[k], xi[i]);
+                        xk[i] = fma(-lik, xk[k], xk[i]);
+                    }
+                }
                 double sdot = 0.0, wtr = 0.0, wti = 0.0;
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
-                    if (i < n) {
-                        double wr, wi;
-                        phase(i, wr, wi);
-                        const double k_i = ks(i);
-                        sdot = fma(wr, xr[i], fma(wi, xi[i], sdot));
-                        wtr = fma(xr[i], k_i, wtr);
-                        wti = fma(-xi[i], k_i, wti);
-                    }
+                    sdot = fma(xr[i], xr[i], fma(xi[i], xi[i], sdot));
+                    wtr = fma(xr[i], xk[i], wtr);
+                    wti = fma(-xi[i], xk[i], wti);
                 }
                 const double den = 1.0 + c1 * sdot;
                 const double cr = (kt.dM - c1 * wtr) / den, ci = (-c1 * wti) / den;
-                // ---- b = A0^{-1} (Ks + c' w), c' = (d - c u^* Ks) / (1 + c s)
+                // z = y_k + c' y_w, then back: L^T b = z (rows past n stay zero)
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
-                    xr[i] = xi[i] = 0.0;
-                    if (i < n) {
-                        double wr, wi;
-                        phase(i, wr, wi);
-                        xr[i] = ks(i) + cr * wr - ci * wi;
-                        xi[i] = cr * wi + ci * wr;
+                    const double zr = xk[i] + cr * xr[i] - ci * xi[i];
+                    const double zi = cr * xi[i] + ci * xr[i];
+                    xr[i] = zr;
+                    xi[i] = zi;
+                }
+#pragma unroll
+                for (int k = NMAX - 1; k >= 0; --k) {
+                    const double iv = A[k * (k + 1) / 2 + k];
+                    xr[k] *= iv;
+                    xi[k] *= iv;
+#pragma unroll
+                    for (int i = 0; i < k; ++i) {
+                        const double lki = A[k * (k + 1) / 2 + i];
+                        xr[i] = fma(-lki, xr[k], xr[i]);
+                        xi[i] = fma(-lki, xi[k], xi[i]);
                     }
                 }
-                solve2(xr, xi);
 #pragma unroll
                 for (int i = 0; i < NMAX; ++i) {
                     if (i < n) {

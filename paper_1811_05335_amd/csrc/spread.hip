@@ -255,18 +255,31 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
             const bool reduce = __popcll(hm) <= 16;   // the same in every lane of the wave
             const uint64_t above = hm & ~((2ull << lane) - 1ull);
             const int seg_end = above ? __ffsll((unsigned long long)above) - 1 : 64;
+            // B_opt entries: the W entries of tap row s0 + 1 are loaded while row s0 is added (rows
+            // rolled, so one row is buffered; lanes past the chunk read a valid position, unused)
+            const int64_t pb = valid ? p : pbeg;
             for (int rr = 0; rr < rc; ++rr) {
                 const C fv = valid ? f[(int64_t)(r0 + rr) * g.N + j] : cmake((R)0, (R)0);
                 double* a = acc + (int64_t)rr * cells * 2;
+                C brow[USEB ? W : 1], bnext[USEB ? W : 1];
+                if (USEB) {
 #pragma unroll
+                    for (int s1 = 0; s1 < W; ++s1) brow[s1] = B[(int64_t)s1 * g.N + pb];
+                }
+#pragma unroll(USEB ? 1 : W)
                 for (int s0 = 0; s0 < W; ++s0) {
                     C fs;
                     if (!USEB) fs = cscale(fv, w0[s0]);
+                    if (USEB) {
+                        const int sn = min(s0 + 1, W - 1);
+#pragma unroll
+                        for (int s1 = 0; s1 < W; ++s1) bnext[s1] = B[(int64_t)(sn * W + s1) * g.N + pb];
+                    }
 #pragma unroll
                     for (int s1 = 0; s1 < W; ++s1) {
                         C v = cmake((R)0, (R)0);
                         if (USEB) {
-                            if (valid) v = cmulc(fv, B[(int64_t)(s0 * W + s1) * g.N + p]);
+                            if (valid) v = cmulc(fv, brow[s1]);
                         } else {
                             v = cscale(fs, w1[s1]);
                         }
@@ -288,6 +301,10 @@ __global__ void __launch_bounds__(256) k_spread(Geo g, NodesDev nd, const cx<R>*
                             lds_add(&a[2 * cidx], (double)v.x);
                             lds_add(&a[2 * cidx + 1], (double)v.y);
                         }
+                    }
+                    if (USEB) {
+#pragma unroll
+                        for (int s1 = 0; s1 < W; ++s1) brow[s1] = bnext[s1];
                     }
                 }
             }

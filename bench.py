@@ -105,10 +105,11 @@ def gpu_run(precision, x, fh, gf, steps, warmup, rho, m, sigma, M, use_graph=Tru
     side, s_adj, s_grad = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
 
     def step(stage=None):
-        """One pass of the path.  Unless a per-call breakdown is being timed, the calls that do not
-        depend on each other overlap: the B optimisation (nodes only, none of the transforms'
-        buffers) on a second stream, joined before the modified adjoint; the adjoint of the NFFT's
-        output on a third stream and work slot; the node gradient on a fourth."""
+        """One pass of the path.  overlap "none" (the default) runs every call on one stream, the
+        NFFT's node gradient right after the NFFT from the grid it left.  The other modes overlap
+        the calls that do not depend on each other: the B optimisation (nodes only, none of the
+        transforms' buffers) on a second stream, joined before the modified adjoint; the adjoint
+        of the NFFT's output on a third stream and work slot; the node gradient on a fourth."""
         run = (lambda n, f: stage.run(n, f)) if stage else (lambda n, f: f())
         cur = torch.cuda.current_stream()
         pre = stage is None and overlap in ("pre", "tail", "full")
@@ -127,6 +128,11 @@ def gpu_run(precision, x, fh, gf, steps, warmup, rho, m, sigma, M, use_graph=Tru
                 gx = P.grad_x(fhd, gfd)
             P.set_slot(0)
         f = run("a2-a4_trafo", lambda: P.trafo(fhd))
+        serial = not (pre or par or tail)
+        if serial:
+            # the NFFT's node gradient from the grid the NFFT just left (its backward, without a
+            # second FFT of fhat)
+            gx = run("a8_grad_x", lambda: P.grad_x_after_trafo(gfd))
         if par:
             s_adj.wait_stream(cur)
             with torch.cuda.stream(s_adj):
@@ -151,7 +157,7 @@ def gpu_run(precision, x, fh, gf, steps, warmup, rho, m, sigma, M, use_graph=Tru
             cur.wait_stream(s_adj)
         if par or tail:
             cur.wait_stream(s_grad)
-        else:
+        elif not serial:
             gx = run("a8_grad_x", lambda: P.grad_x(fhd, gfd))
         return f, h, fc, fa, gx
 
@@ -621,7 +627,7 @@ def main():
         "dominant_kernel_class": dom_k,
         "streaming_kernels_hbm": kroof,
         "timing": ("hipGraph replay of the whole step" if r32["ms_graph"] else "eager launches")
-                  + {"none": "; every call on one stream",
+                  + {"none": "; every call on one stream, the NFFT's node gradient from the grid the NFFT left",
                      "pre": "; B optimisation on a second stream, overlapped with the NFFT and the adjoint",
                      "tail": "; B optimisation on a second stream, overlapped with the NFFT and the adjoint; "
                              "node gradient on a third stream and work slot, beside the inverse adjoint",

@@ -166,6 +166,17 @@ int infft_apply_adjoint(infft_plan p, const void* h, void* f, int nrhs);
  * (plan precision), gradx float64 [N][d]. */
 int nfft_grad_x(infft_plan p, const void* fhat, const void* gradf, double* gradx, int nrhs);
 
+/* The same node gradient from the oversampled grid F D fhat that the last nfft_trafo on the
+ * current work slot left (the backward of an NFFT whose forward just ran: no second FFT of fhat).
+ * gradf [nrhs][N] (plan precision), gradx float64 [N][d] overwritten; nrhs must equal that
+ * nfft_trafo's, which must have fitted in one pass (nrhs <= max_rhs).  Every other call that
+ * writes the slot's grid (nfft_adjoint, infft_apply, infft_apply_adjoint, nfft_grad_x,
+ * infft_grad_x_bopt on that slot; nfft_set_nodes, infft_precompute_Bstar and infft_autotune on
+ * any) ends the grid's validity: then INFFT_ESTATE.  INFFT_EINVAL for batch plans and a
+ * different nrhs.  The validity is tracked on the host in call order, so under graph capture it
+ * follows the captured order. */
+int nfft_grad_x_after_trafo(infft_plan p, const void* gradf, double* gradx, int nrhs);
+
 /* Gradient of a real loss through B_opt(x) with respect to the nodes, for fcheck = infft_apply(f)
  * with f held fixed: implicit differentiation of the ridge normal equations of Algorithm 3.17
  * ((3.30)-(3.31)); membership I(l) is piecewise constant in x and contributes nothing.  f [nrhs][N]

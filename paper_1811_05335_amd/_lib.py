@@ -91,6 +91,7 @@ def load() -> C.CDLL:
         "infft_apply": (i32, [vp, vp, vp, i32]),
         "infft_apply_adjoint": (i32, [vp, vp, vp, i32]),
         "nfft_grad_x": (i32, [vp, vp, vp, vp, i32]),
+        "nfft_grad_x_after_trafo": (i32, [vp, vp, vp, i32]),
         "infft_grad_x_bopt": (i32, [vp, vp, vp, vp, i32]),
         "infft_get_B": (i32, [vp, vp]),
         "nfft_plan_status": (i32, [vp, C.POINTER(Status)]),

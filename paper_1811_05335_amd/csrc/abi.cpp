@@ -124,8 +124,10 @@ struct infft_plan_s {
     void* h01 = nullptr;
     struct Slot {
         void *grid, *grid2, *h0, *h1, *h01;
+        int trafo_rhs = 0;   // > 0: grid holds F D fhat of the last nfft_trafo (that many RHS)
     };
     std::vector<Slot> slots;   // work_slots sets of the five buffers above
+    int cur_slot = 0;
     int64_t hrs0 = 0, hrs1 = 0, hrs01 = 0;
     SpreadWork spwork{};            // 2-D: work list of the tiled spreading (rebuilt by set_nodes)
     int* sp_offs = nullptr;
@@ -451,10 +453,23 @@ int auto_tile(int Ms, int m, int want) {
     return 0;
 }
 
+// Records what the current slot's grid holds: the oversampled F D fhat of an nfft_trafo of
+// `trafo_rhs` right-hand sides, or (0) anything else.  all_slots: every slot (node changes,
+// autotuning).
+static void grid_holds(infft_plan_s* p, int trafo_rhs, bool all_slots = false) {
+    if (!p || p->batch || p->slots.empty()) return;
+    if (all_slots) {
+        for (auto& sl : p->slots) sl.trafo_rhs = 0;
+        return;
+    }
+    p->slots[p->cur_slot].trafo_rhs = trafo_rhs;
+}
+
 int set_nodes_impl(infft_plan_s* P, const double* x) {
     const Geo& g = P->g;
     hipStream_t s = P->stream;
     ProfScope ps(P, INFFT_K_NODES);
+    grid_holds(P, 0, true);
     launch_nodes_reset(P->status, P->counts, g.G + 1, P->fill, g.G, P->lcount, s);
     launch_prep_nodes(g, x, P->nd, P->counts, P->status, s);
     launch_exclusive_scan(P->counts, P->nd.start, g.G, P->bsum, s);
@@ -1231,6 +1246,7 @@ int nfft_set_slot(infft_plan p, int slot) {
     if (slot < 0 || slot >= (int)p->slots.size())
         return fail(INFFT_EINVAL, "slot %d out of range (the plan has %d)", slot, (int)p->slots.size());
     const infft_plan_s::Slot& sl = p->slots[slot];
+    p->cur_slot = slot;
     p->grid = sl.grid;
     p->grid2 = sl.grid2;
     p->h0 = sl.h0;
@@ -1251,6 +1267,7 @@ static const char* cptr(const infft_plan_s* P, const void* base, int64_t elem_of
     return (const char*)base + (int64_t)P->csize() * elem_off;
 }
 
+
 int nfft_trafo(infft_plan p, const void* fhat, void* f, int nrhs) {
     int rc = check_rhs(p, nrhs);
     if (rc) return rc;
@@ -1261,6 +1278,7 @@ int nfft_trafo(infft_plan p, const void* fhat, void* f, int nrhs) {
         return node_batched(p, NB_INTERP, nullptr, f, nullptr, nrhs);
     }
     const Geo& g = p->g;
+    grid_holds(p, 0);
     for (int r0 = 0; r0 < nrhs; r0 += p->max_rhs) {
         const int c = std::min(p->max_rhs, nrhs - r0);
         if ((rc = schedule_for(p, c))) return rc;
@@ -1273,6 +1291,7 @@ int nfft_trafo(infft_plan p, const void* fhat, void* f, int nrhs) {
             launch_interp<double>(g, p->nd, (const double2*)p->grid, g.G, (double2*)fo, c, p->stream);
         LAUNCH_CHECK();
     }
+    if (nrhs <= p->max_rhs) grid_holds(p, nrhs);   // a single chunk: the grid holds all of it
     return INFFT_OK;
 }
 
@@ -1304,6 +1323,7 @@ int nfft_adjoint(infft_plan p, const void* f, void* h, int nrhs) {
     int rc = check_rhs(p, nrhs);
     if (rc) return rc;
     if (!f || !h) return fail(INFFT_EINVAL, "null data pointer");
+    grid_holds(p, 0);
     if (p->batch) {
         if ((rc = batch_check_rhs(p, nrhs)) || (rc = node_batched(p, NB_GATHER, f, nullptr, nullptr, nrhs)))
             return rc;
@@ -1408,6 +1428,7 @@ int infft_precompute_B(infft_plan p) {
 int infft_precompute_Bstar(infft_plan p) {
     if (!p) return fail(INFFT_EINVAL, "null plan");
     if (p->batch) return fail(INFFT_EINVAL, "infft_precompute_Bstar takes a single-problem plan");
+    grid_holds(p, 0, true);
     const Geo& g = p->g;
     if (g.d != 1) return fail(INFFT_EINVAL, "infft_precompute_Bstar is defined for d = 1");
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -1509,6 +1530,7 @@ int infft_apply(infft_plan p, const void* f, void* fcheck, int nrhs) {
     int rc = check_rhs(p, nrhs);
     if (rc) return rc;
     if (!f || !fcheck) return fail(INFFT_EINVAL, "null data pointer");
+    grid_holds(p, 0);
     if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_apply before infft_precompute_B");
     if (p->batch) {
         if ((rc = batch_check_rhs(p, nrhs)) || (rc = node_batched(p, NB_GATHER_B, f, nullptr, nullptr, nrhs)))
@@ -1522,6 +1544,7 @@ int infft_apply_adjoint(infft_plan p, const void* h, void* f, int nrhs) {
     int rc = check_rhs(p, nrhs);
     if (rc) return rc;
     if (!h || !f) return fail(INFFT_EINVAL, "null data pointer");
+    grid_holds(p, 0);
     if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_apply_adjoint before infft_precompute_B");
     if (p->batch) {
         if ((rc = batch_check_rhs(p, nrhs)) || (rc = run_fft_batched(p, p->batch->to_grid, h, nullptr, nrhs, true)))
@@ -1548,6 +1571,7 @@ int nfft_grad_x(infft_plan p, const void* fhat, const void* gradf, double* gradx
     int rc = check_rhs(p, nrhs);
     if (rc) return rc;
     if (!fhat || !gradf || !gradx) return fail(INFFT_EINVAL, "null data pointer");
+    grid_holds(p, 0);
     if (p->batch) {
         if ((rc = batch_check_rhs(p, nrhs)) || (rc = run_fft_batched(p, p->batch->to_grid, fhat, nullptr, nrhs)))
             return rc;
@@ -1571,10 +1595,32 @@ int nfft_grad_x(infft_plan p, const void* fhat, const void* gradf, double* gradx
     return INFFT_OK;
 }
 
+int nfft_grad_x_after_trafo(infft_plan p, const void* gradf, double* gradx, int nrhs) {
+    int rc = check_rhs(p, nrhs);
+    if (rc) return rc;
+    if (!gradf || !gradx) return fail(INFFT_EINVAL, "null data pointer");
+    if (p->batch) return fail(INFFT_EINVAL, "nfft_grad_x_after_trafo takes a single-problem plan");
+    const int held = p->slots[p->cur_slot].trafo_rhs;
+    if (held == 0)
+        return fail(INFFT_ESTATE, "work slot %d holds no nfft_trafo result (another call wrote its grid since)",
+                    p->cur_slot);
+    if (held != nrhs) return fail(INFFT_EINVAL, "nrhs %d differs from the last nfft_trafo's %d", nrhs, held);
+    const Geo& g = p->g;
+    ProfScope ps(p, INFFT_K_INTERP);
+    if (p->prec == INFFT_F32)
+        launch_grad_x<float>(g, p->nd, (const float2*)p->grid, g.G, (const float2*)gradf, gradx, nrhs, 0, p->stream);
+    else
+        launch_grad_x<double>(g, p->nd, (const double2*)p->grid, g.G, (const double2*)gradf, gradx, nrhs, 0,
+                              p->stream);
+    LAUNCH_CHECK();
+    return INFFT_OK;
+}
+
 int infft_grad_x_bopt(infft_plan p, const void* f, const void* gradfc, double* gradx, int nrhs) {
     int rc = check_rhs(p, nrhs);
     if (rc) return rc;
     if (!f || !gradfc || !gradx) return fail(INFFT_EINVAL, "null data pointer");
+    grid_holds(p, 0);
     if (p->batch) return fail(INFFT_ESTATE, "infft_grad_x_bopt takes a single-problem plan");
     if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_grad_x_bopt before infft_precompute_B");
     if (p->bopt_kind != 0)
@@ -1695,6 +1741,7 @@ int infft_autotune(infft_plan p, int reps) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(p->stream, &cs));
     if (cs != hipStreamCaptureStatusNone) return fail(INFFT_ESTATE, "infft_autotune cannot run under graph capture");
+    grid_holds(p, 0, true);
     if (reps < 1) reps = 10;
     const Geo& g = p->g;
     const int cap = fft_capacity(p->prec == INFFT_F64);

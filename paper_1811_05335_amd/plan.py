@@ -158,6 +158,15 @@ class NfftPlan:
         check(load().nfft_grad_x(self._h, C.c_void_p(_ptr(fh)), C.c_void_p(_ptr(gf)), C.c_void_p(_ptr(out)), R))
         return out
 
+    def grad_x_after_trafo(self, gradf: torch.Tensor) -> torch.Tensor:
+        """The node gradient of grad_x, from the grid the last trafo on the current work slot left
+        (no FFT of fhat); the library raises if another call has written that grid since."""
+        gf, lead, R = self._samples(gradf)
+        out = torch.empty((self.N, self.d), dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        check(load().nfft_grad_x_after_trafo(self._h, C.c_void_p(_ptr(gf)), C.c_void_p(_ptr(out)), R))
+        return out
+
     def grad_x_bopt(self, f: torch.Tensor, gradfc: torch.Tensor) -> torch.Tensor:
         """Node gradient through B_opt(x) of a loss of fcheck = apply(f), f held fixed."""
         ff, lead, R = self._samples(f)

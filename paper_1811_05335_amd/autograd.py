@@ -15,7 +15,8 @@ from __future__ import annotations
 
 import torch
 
-from .plan import NfftPlan
+from ._lib import InfftError
+from .plan import NfftBatchPlan, NfftPlan
 
 
 class NfftFunction(torch.autograd.Function):
@@ -24,15 +25,29 @@ class NfftFunction(torch.autograd.Function):
         plan.set_nodes(x.detach())
         ctx.plan = plan
         ctx.save_for_backward(fhat)
-        return plan.trafo(fhat)
+        f = plan.trafo(fhat)
+        ctx.trafo = (getattr(plan, "_trafo_seq", None), getattr(plan, "_slot", 0))
+        return f
 
     @staticmethod
     def backward(ctx, grad_f: torch.Tensor):
         (fhat,) = ctx.saved_tensors
         plan = ctx.plan
         g = grad_f.contiguous()
+        gx = None
+        if ctx.needs_input_grad[1]:
+            # the node gradient first: if this forward's trafo was the plan's last and its slot is
+            # current, the grid may still hold F D fhat (the library checks that no other call
+            # wrote it since); otherwise it is recomputed from fhat
+            if not isinstance(plan, NfftBatchPlan) and ctx.trafo[0] is not None and \
+                    ctx.trafo == (getattr(plan, "_trafo_seq", None), getattr(plan, "_slot", 0)):
+                try:
+                    gx = plan.grad_x_after_trafo(g)
+                except InfftError:
+                    gx = None
+            if gx is None:
+                gx = plan.grad_x(fhat, g)
         gfh = plan.adjoint(g) if ctx.needs_input_grad[0] else None
-        gx = plan.grad_x(fhat, g) if ctx.needs_input_grad[1] else None
         return gfh, gx, None
 
 

@@ -110,6 +110,8 @@ class NfftPlan:
         out = torch.empty(tuple(lead) + (self.N,), dtype=self.ctype, device=self.device)
         self._sync_stream()
         check(load().nfft_trafo(self._h, C.c_void_p(_ptr(fh)), C.c_void_p(_ptr(out)), R))
+        # which trafo the current slot's grid may hold (read by the autograd backward)
+        self._trafo_seq = getattr(self, "_trafo_seq", 0) + 1
         return out
 
     def adjoint(self, f: torch.Tensor) -> torch.Tensor:
@@ -123,6 +125,7 @@ class NfftPlan:
         """Work-buffer set of the following transforms (calls on different slots and streams may
         overlap on the device)."""
         check(load().nfft_set_slot(self._h, int(slot)))
+        self._slot = int(slot)
 
     def precompute_B(self) -> None:
         self._sync_stream()

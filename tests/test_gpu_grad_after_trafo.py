@@ -115,3 +115,33 @@ def test_captured_trafo_and_gradient_replay():
         P.adjoint(P.trafo(fh))                # eager work between replays
         torch.cuda.synchronize()
     assert np.isfinite(ref.cpu().numpy()).all()
+
+
+def test_autograd_backward_reuses_the_forward_grid_only_when_it_is_current():
+    """autograd.nfft's backward takes the node gradient from the forward's grid when that trafo was
+    the plan's last and nothing wrote the grid since, else recomputes it: the gradients are the
+    same bit for bit either way, including after another trafo on the plan (a different grid)."""
+    from paper_1811_05335_amd import NfftPlan, autograd
+    M, N = (1024,), 1500
+    g = W.rng(143)
+    x = nodes_dev(W.uniform_nodes(g, N, 1))
+    fh0 = dev(W.complex_normal(g, (2,) + M), "f64")
+    other = dev(W.complex_normal(g, (2,) + M), "f64")
+    w = dev(W.complex_normal(g, (2, N)), "f64")
+    P = NfftPlan(M, x, sigma=2.0, m=4, precision="f64", max_rhs=2, work_slots=2)
+
+    def grads(between):
+        fh = fh0.clone().requires_grad_(True)
+        xx = x.clone().requires_grad_(True)
+        f = autograd.nfft(fh, xx, P)
+        between()
+        loss = torch.sum(torch.real(torch.conj(w) * f))
+        loss.backward()
+        return fh.grad.clone(), xx.grad.clone()
+
+    ref = grads(lambda: None)                               # grid current: reused
+    for between in (lambda: P.adjoint(w),                   # grid written: recomputed
+                    lambda: P.trafo(other),                 # another trafo's grid: recomputed
+                    lambda: (P.set_slot(1), P.trafo(other), P.set_slot(0))):
+        got = grads(between)
+        assert torch.equal(got[0], ref[0]) and torch.equal(got[1], ref[1])

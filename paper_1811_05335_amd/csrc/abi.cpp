@@ -1361,8 +1361,10 @@ int infft_precompute_B(infft_plan p) {
     const int* last_list;
     const int* last_count;
     if (g.d == 1) {
-        // one thread per problem for small I(l); the rest in groups of 16, then 32 lanes, then
-        // the blocked pass
+        // one thread per problem for small I(l); the rest in groups of 16 lanes, then a wavefront
+        // per problem up to 64 members, then the blocked pass.  (No 32-lane tier: each tier is a
+        // launch on the critical path even when its list is empty, and problems of 17-32 members
+        // are rare at the densities this path is built for; the wavefront tier takes them.)
         a.in_list = nullptr;
         a.in_count = nullptr;
         a.out_list = listA;
@@ -1378,19 +1380,13 @@ int infft_precompute_B(infft_plan p) {
         a.out_count = p->lcount + 1;
         a.stat_off += launch_solve_tier(g, p->nd, kt, a, 16, p->stream);
         LAUNCH_CHECK();
+        // 1-D: a wavefront per problem up to 64 members (also under capture)
         a.in_list = listB;
         a.in_count = p->lcount + 1;
         a.out_list = listA;
         a.out_count = p->lcount + 2;
-        a.stat_off += launch_solve_tier(g, p->nd, kt, a, 32, p->stream);
-        LAUNCH_CHECK();
-        // 1-D: a wavefront per problem up to 64 members (also under capture)
-        a.in_list = listA;
-        a.in_count = p->lcount + 2;
-        a.out_list = listB;
-        a.out_count = p->lcount + 3;
-        last_list = listB;
-        last_count = p->lcount + 3;
+        last_list = listA;
+        last_count = p->lcount + 2;
     } else {
         a.in_list = nullptr;
         a.in_count = nullptr;

@@ -427,6 +427,45 @@ def secondary_spiral(steps, warmup):
     return out
 
 
+def secondary_variants(steps, warmup):
+    """Rows beside the headline path, at its workload (1-D jittered, M = 2^16, N = 2^17, FP32
+    transforms, FP64 solves): the Dirichlet-kernel variant of Algorithm 3.17 (B optimisation and
+    modified adjoint, graph replays) next to the window kernel, and the node gradient through
+    B_opt(x) (eager: the call reads the sizes of problems above 32 members back)."""
+    import torch
+    from paper_1811_05335_amd import NfftPlan
+    cfg = W.CONFIGS["c2"]
+    x, _ = W.make_problem(cfg, seed=0, rhs=1)
+    g = W.rng(7)
+    xd = torch.from_numpy(x).cuda()
+    fd = torch.from_numpy(W.round_to(W.complex_normal(g, (1, cfg["N"])), "f32")).to(torch.complex64).cuda()
+    gcd = torch.from_numpy(W.round_to(W.complex_normal(g, (1,) + tuple(cfg["M"])), "f32")).to(torch.complex64).cuda()
+    out = {}
+    for kernel in ("window", "dirichlet"):
+        P = NfftPlan(cfg["M"], xd, sigma=cfg["sigma"], m=cfg["m"], precision="f32", rho=cfg["rho"], max_rhs=1,
+                     kernel=kernel)
+        P.autotune()
+        ms_pre = timed_graph(torch, P.precompute_B, steps, warmup)
+        ms_apply = timed_graph(torch, lambda: P.apply(fd), steps, warmup)
+        ms_apply_adj = timed_graph(torch, lambda: P.apply_adjoint(gcd), steps, warmup)
+        st = P.status()
+        r = dict(ms_precompute_B=ms_pre, ms_apply=ms_apply, ms_apply_adjoint=ms_apply_adj,
+                 failed_solves=st["failed_solves"])
+        if kernel == "window":
+            for _ in range(warmup):
+                P.grad_x_bopt(fd, gcd)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                P.grad_x_bopt(fd, gcd)
+            torch.cuda.synchronize()
+            r["ms_grad_x_bopt"] = (time.perf_counter() - t0) * 1e3 / steps
+        out[kernel] = r
+        P.close()
+    out["timing"] = "graph replays per call; the node gradient through B_opt(x) eager"
+    return out
+
+
 def secondary_small(steps, warmup):
     """The small 1-D uniform workload (M = 256, N = 512, m = 4, FP64): the whole path per step."""
     import torch
@@ -661,6 +700,9 @@ def main():
         log("[bench] ansatz 1 (Algorithm 3.10): N = 4096, M = 16384 and N = 262144, M = 1048576")
         line["secondary"]["ansatz1_1d"] = secondary_ansatz1(max(10, a.steps), 3)
         log(f"[bench] ansatz 1: {line['secondary']['ansatz1_1d']}")
+        log("[bench] Dirichlet-kernel B optimisation and the node gradient through B_opt(x), 1-D jittered")
+        line["secondary"]["variants_1d"] = secondary_variants(max(10, a.steps // 2), 3)
+        log(f"[bench] variants: {line['secondary']['variants_1d']}")
     if not a.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline (B optimisation sampled on {a.cpu_sample} grid indices)")
         cb = cpu_baseline(x, fh, gf, rho, m, sigma, M, a.cpu_sample)

@@ -56,13 +56,36 @@ __device__ inline double2 dkernel(const double2* const* tab, int qmax, double2 w
     return t == 0 ? cmul(dF0, F1) : cmul(F0, dF1);
 }
 
-template <typename R, int D, int NL>
+// QL: the Q Taylor table (1-D) is staged in LDS first; every lane evaluates it about 3n times per
+// problem (its row of G, and dQ against each member), and from global memory each evaluation
+// waited on ten dependent coefficient loads.
+template <typename R, int D, int NL, bool QL>
 __global__ void __launch_bounds__(256) k_bopt_grad(Geo g, NodesDev nd, KTabDev kt, BoptGradArgs ga) {
     using C = cx<R>;
     __shared__ double2 s_col[256];
     __shared__ double2 s_z[256];
     __shared__ double2 s_a[256];
     __shared__ double2 s_b[256];
+    extern __shared__ double2 s_qtab[];
+    const double2* qtab[MAX_D] = {kt.Q[0], kt.Q[1]};
+    if (QL) {
+        const int nq = (kt.qQ + 1) * TAY_NC;
+        for (int i0 = threadIdx.x; i0 < nq; i0 += 8 * blockDim.x) {
+            double2 v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int i = i0 + k * blockDim.x;
+                v[k] = kt.Q[0][min(i, nq - 1)];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int i = i0 + k * blockDim.x;
+                if (i < nq) s_qtab[i] = v[k];
+            }
+        }
+        __syncthreads();
+        qtab[0] = s_qtab;
+    }
     const int lane = threadIdx.x & (NL - 1);
     const int sb = threadIdx.x - lane;
     const int gbase = (threadIdx.x & 63) - lane;
@@ -128,8 +151,8 @@ __global__ void __launch_bounds__(256) k_bopt_grad(Geo g, NodesDev nd, KTabDev k
             A[j] = make_double2(0.0, 0.0);
             if (j < n) {
                 const double2 zj = s_z[sb + j];
-                double2 qv = tay_eval(kt.Q[0], kt.qQ, zj.x - z0);
-                if (D == 2) qv = cmul(qv, tay_eval(kt.Q[1], kt.qQ, zj.y - z1));
+                double2 qv = tay_eval(qtab[0], kt.qQ, zj.x - z0);
+                if (D == 2) qv = cmul(qv, tay_eval(qtab[1], kt.qQ, zj.y - z1));
                 A[j] = cscale(qv, kt.scaleG);
                 if (j == lane) A[j] = make_double2(A[j].x + kt.lam, 0.0);
             }
@@ -200,8 +223,11 @@ __global__ void __launch_bounds__(256) k_bopt_grad(Geo g, NodesDev nd, KTabDev k
                 double2 srow = make_double2(0.0, 0.0), scol = make_double2(0.0, 0.0);
                 for (int j = 0; j < n; ++j) {
                     const double2 zj = s_z[sb + j];
-                    const double2 dq_row = dkernel<D>(kt.Q, kt.qQ, make_double2(zj.x - zk.x, zj.y - zk.y), t);
-                    const double2 dq_col = dkernel<D>(kt.Q, kt.qQ, make_double2(zk.x - zj.x, zk.y - zj.y), t);
+                    // dQ_t(-w) = -conj dQ_t(w) (the tables hold w >= 0 and the sign is applied after
+                    // the evaluation, so this is exact for w != 0; at w = 0, j = k, the real part
+                    // of dQ_t(0) is zero up to rounding)
+                    const double2 dq_row = dkernel<D>(qtab, kt.qQ, make_double2(zj.x - zk.x, zj.y - zk.y), t);
+                    const double2 dq_col = make_double2(-dq_row.x, dq_row.y);
                     srow = cadd(srow, cmul(dq_row, s_b[sb + j]));
                     scol = cadd(scol, cmul(cconj(s_a[sb + j]), dq_col));
                 }
@@ -220,16 +246,26 @@ template <typename R>
 int launch_bopt_grad(const Geo& g, NodesDev nd, KTabDev kt, BoptGradArgs ga, int nl, hipStream_t s) {
     const int64_t groups_per_block = 256 / nl;
     int64_t blocks = (g.G + groups_per_block - 1) / groups_per_block;
-    const int64_t cap = ga.in_list ? 512 : 2048;
+    // 1-D: the Q table in LDS when it fits beside the 16 KB of the kernel's own arrays within
+    // 64 KB (m <= 9); then two workgroups per CU, each staging it once for many problems
+    const size_t qbytes = (size_t)(kt.qQ + 1) * TAY_NC * sizeof(double2);
+    const bool ql = g.d == 1 && qbytes <= 48 * 1024;
+    const int64_t cap = ql ? 512 : ga.in_list ? 512 : 2048;
     if (blocks > cap) blocks = cap;
-#define INFFT_BG(D_, NL_) \
-    hipLaunchKernelGGL((k_bopt_grad<R, D_, NL_>), dim3((unsigned)blocks), dim3(256), 0, s, g, nd, kt, ga)
+#define INFFT_BG(D_, NL_, QL_)                                                                              \
+    hipLaunchKernelGGL((k_bopt_grad<R, D_, NL_, QL_>), dim3((unsigned)blocks), dim3(256), QL_ ? qbytes : 0, s, \
+                       g, nd, kt, ga)
     if (g.d == 1) {
-        if (nl == 16) INFFT_BG(1, 16);
-        else INFFT_BG(1, 32);
+        if (ql) {
+            if (nl == 16) INFFT_BG(1, 16, true);
+            else INFFT_BG(1, 32, true);
+        } else {
+            if (nl == 16) INFFT_BG(1, 16, false);
+            else INFFT_BG(1, 32, false);
+        }
     } else {
-        if (nl == 16) INFFT_BG(2, 16);
-        else INFFT_BG(2, 32);
+        if (nl == 16) INFFT_BG(2, 16, false);
+        else INFFT_BG(2, 32, false);
     }
 #undef INFFT_BG
     return (int)blocks;

@@ -157,8 +157,9 @@ __global__ void __launch_bounds__(256) k_bopt_grad(Geo g, NodesDev nd, KTabDev k
                 if (j == lane) A[j] = make_double2(A[j].x + kt.lam, 0.0);
             }
         }
-        // ---- Cholesky, lane i keeps row i of L (as in the solve tiers)
+        // ---- Cholesky, lane i keeps row i of L (as in the solve tiers) and 1 / L[i][i]
         bool ok = true;
+        double dinv = 1.0;
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             if (k < n && ok) {
@@ -178,8 +179,12 @@ __global__ void __launch_bounds__(256) k_bopt_grad(Geo g, NodesDev nd, KTabDev k
                         }
                     }
                 }
-                if (lane == k) A[k] = make_double2(sq, 0.0);
-                else if (lane > k) A[k] = cscale(A[k], inv);
+                if (lane == k) {
+                    A[k] = make_double2(sq, 0.0);
+                    dinv = inv;
+                } else if (lane > k) {
+                    A[k] = cscale(A[k], inv);
+                }
                 wave_sync();
             }
         }
@@ -188,7 +193,7 @@ __global__ void __launch_bounds__(256) k_bopt_grad(Geo g, NodesDev nd, KTabDev k
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             if (k < n) {
-                if (lane == k) y = cscale(y, 1.0 / A[k].x);
+                if (lane == k) y = cscale(y, dinv);
                 s_col[threadIdx.x] = y;
                 wave_sync();
                 const double2 yk = s_col[sb + k];
@@ -206,7 +211,7 @@ __global__ void __launch_bounds__(256) k_bopt_grad(Geo g, NodesDev nd, KTabDev k
                     double2 sum = make_double2(0.0, 0.0);
 #pragma unroll
                     for (int j = k + 1; j < NL; ++j) sum = cadd(sum, s_col[sb + j]);
-                    a = cscale(csub(y, sum), 1.0 / A[k].x);
+                    a = cscale(csub(y, sum), dinv);
                 }
                 wave_sync();
             }

@@ -93,6 +93,8 @@ struct infft_plan_s {
 
     NodesDev nd{};
     int* counts = nullptr;
+    int* nonfinite = nullptr;     // per-workgroup non-finite node counts of the preprocessing
+    bool nodes_zeroed = false;    // counters and fill cursors are zero (after the first reset)
     int* fill = nullptr;
     int* bsum = nullptr;
     long long* status = nullptr;
@@ -470,11 +472,16 @@ int set_nodes_impl(infft_plan_s* P, const double* x) {
     hipStream_t s = P->stream;
     ProfScope ps(P, INFFT_K_NODES);
     grid_holds(P, 0, true);
-    launch_nodes_reset(P->status, P->counts, g.G + 1, P->fill, g.G, P->lcount, s);
-    launch_prep_nodes(g, x, P->nd, P->counts, P->status, s);
+    // the cell sort leaves the counters and fill cursors at zero for the next call; the plan's
+    // first call (fresh allocations) zeroes them first
+    if (!P->nodes_zeroed) {
+        launch_nodes_reset(P->status, P->counts, g.G + 1, P->fill, g.G, P->lcount, s);
+        P->nodes_zeroed = true;
+    }
+    launch_prep_nodes(g, x, P->nd, P->counts, P->nonfinite, s);
     launch_exclusive_scan(P->counts, P->nd.start, g.G, P->bsum, s);
     launch_scatter_nodes(g, P->nd, P->fill, s);
-    launch_cell_sort(g, P->nd, s);
+    launch_cell_sort(g, P->nd, P->counts, P->fill, P->nonfinite, P->status, s);
     if (g.d == 2) launch_spread_worklist(g, P->nd, P->spwork, P->sp_offs, P->sp_bsum, s);
     LAUNCH_CHECK();
     P->bopt_ready = false;
@@ -1083,6 +1090,7 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
     TRY(P->alloc(&P->nd.us, Nd));
     TRY(P->alloc(&P->nd.start, g.G + 1));
     TRY(P->alloc(&P->counts, g.G + 1));
+    TRY(P->alloc(&P->nonfinite, prep_blocks(g)));
     TRY(P->alloc(&P->fill, g.G));
     TRY(P->alloc(&P->bsum, scan_blocksum_len(g.G) + 1));
     TRY(P->alloc(&P->status, STATUS_WORDS));

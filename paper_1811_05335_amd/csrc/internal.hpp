@@ -394,12 +394,13 @@ enum NodeBatchKind { NB_INTERP = 0, NB_INTERP_B = 1, NB_GATHER = 2, NB_GATHER_B 
 // nodes.hip
 void launch_fill_i32(int* p, int64_t n, int v, hipStream_t s);
 void launch_fill_bytes0(void* p, int64_t nbytes, hipStream_t s);
-void launch_prep_nodes(const Geo& g, const double* x, NodesDev nd, int* counts, long long* status,
-                       hipStream_t s);
+void launch_prep_nodes(const Geo& g, const double* x, NodesDev nd, int* counts, int* nonfinite, hipStream_t s);
+int prep_blocks(const Geo& g);
 void launch_exclusive_scan(const int* in, int* out, int64_t n, int* blocksums, hipStream_t s);
 int64_t scan_blocksum_len(int64_t n);
 void launch_scatter_nodes(const Geo& g, NodesDev nd, int* fill, hipStream_t s);
-void launch_cell_sort(const Geo& g, NodesDev nd, hipStream_t s);
+void launch_cell_sort(const Geo& g, NodesDev nd, int* counts, int* fill, const int* nonfinite, long long* status,
+                      hipStream_t s);
 void launch_export_B(const Geo& g, const int* perm, const double2* B, double2* rows, hipStream_t s);
 void launch_status_init(long long* status, int keep_node_words, hipStream_t s);
 void launch_solve_reset(long long* status, int* lcount, hipStream_t s);

@@ -84,13 +84,10 @@ void launch_nodes_reset(long long* status, int* counts, int64_t ncounts, int* fi
 // kept separate (no contraction into fused multiply-adds) so the stencil, and therefore the
 // sparsity pattern of B and B_opt, follows exactly these roundings.
 template <int D>
-__global__ void k_prep(Geo g, const double* __restrict__ x, NodesDev nd, int* __restrict__ counts,
-                       long long* status) {
+__device__ inline void prep_node(const Geo& g, const double* __restrict__ x, NodesDev& nd, int* __restrict__ counts,
+                                 int64_t j, bool& bad) {
 #pragma clang fp contract(off)
-    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (j >= g.N) return;
     int c[2] = {0, 0};
-    bool bad = false;
 #pragma unroll
     for (int t = 0; t < D; ++t) {
         double xv = x[j * D + t];
@@ -109,19 +106,31 @@ __global__ void k_prep(Geo g, const double* __restrict__ x, NodesDev nd, int* __
         nd.uc[j * D + t] = u;
         c[t] = lm;
     }
-    if (bad) atomicAdd((unsigned long long*)&status[ST_NONFINITE], 1ull);
     const int key = (int)cell_key(g, c[0], c[1]);
     nd.key[j] = key;
     atomicAdd(&counts[key], 1);
 }
 
-void launch_prep_nodes(const Geo& g, const double* x, NodesDev nd, int* counts, long long* status,
-                       hipStream_t s) {
-    const int blocks = (int)((g.N + 255) / 256);
+template <int D>
+__global__ void __launch_bounds__(256) k_prep(Geo g, const double* __restrict__ x, NodesDev nd,
+                                              int* __restrict__ counts, int* __restrict__ nonfinite) {
+#pragma clang fp contract(off)
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (j < g.N) prep_node<D>(g, x, nd, counts, j, bad);
+    // the workgroup's count of non-finite nodes (the cell sort folds them into the status block)
+    const int nbad = __syncthreads_count(bad);
+    if (threadIdx.x == 0) nonfinite[blockIdx.x] = nbad;
+}
+
+int prep_blocks(const Geo& g) { return (int)((g.N + 255) / 256); }
+
+void launch_prep_nodes(const Geo& g, const double* x, NodesDev nd, int* counts, int* nonfinite, hipStream_t s) {
+    const int blocks = prep_blocks(g);
     if (g.d == 1)
-        hipLaunchKernelGGL(k_prep<1>, dim3(blocks), dim3(256), 0, s, g, x, nd, counts, status);
+        hipLaunchKernelGGL(k_prep<1>, dim3(blocks), dim3(256), 0, s, g, x, nd, counts, nonfinite);
     else
-        hipLaunchKernelGGL(k_prep<2>, dim3(blocks), dim3(256), 0, s, g, x, nd, counts, status);
+        hipLaunchKernelGGL(k_prep<2>, dim3(blocks), dim3(256), 0, s, g, x, nd, counts, nonfinite);
 }
 
 template <int D>
@@ -167,17 +176,36 @@ __device__ inline void refresh_sorted(NodesDev& nd, int pos) {
 
 // One workgroup per CELL_SORT_TPB cells: each thread sorts a small cell by itself; the cells above
 // CELL_SORT_SMALL nodes are collected in LDS and sorted afterwards by the whole workgroup.
+// The last kernel of the node preprocessing also ends it: each thread clears its cell's counter
+// and fill cursor (read for the last time by the scan and the scatter), so the next call starts
+// from zeros without a reset launch, and workgroup 0 writes the status block: the node words
+// (the non-finite count, summed from the preprocessing's per-workgroup counts) and the solve
+// words at their initial values.
 constexpr int CELL_SORT_TPB = 256;
 
 template <int D>
-__global__ void __launch_bounds__(CELL_SORT_TPB) k_cell_sort(Geo g, NodesDev nd) {
+__global__ void __launch_bounds__(CELL_SORT_TPB) k_cell_sort(Geo g, NodesDev nd, int* __restrict__ counts,
+                                                             int* __restrict__ fill,
+                                                             const int* __restrict__ nonfinite, int nprep,
+                                                             long long* __restrict__ status) {
     __shared__ int buf[CELL_SORT_BIG];
     __shared__ int s_big[CELL_SORT_TPB];
     __shared__ int s_nbig;
-    if (threadIdx.x == 0) s_nbig = 0;
+    __shared__ long long s_bad;
+    if (threadIdx.x == 0) {
+        s_nbig = 0;
+        s_bad = 0;
+    }
     __syncthreads();
+    if (blockIdx.x == 0) {
+        long long bad = 0;
+        for (int b = threadIdx.x; b < nprep; b += blockDim.x) bad += nonfinite[b];
+        if (bad) atomicAdd((unsigned long long*)&s_bad, (unsigned long long)bad);
+    }
     const int64_t c = blockIdx.x * (int64_t)CELL_SORT_TPB + threadIdx.x;
     if (c < g.G) {
+        counts[c] = 0;
+        fill[c] = 0;
         const int s = nd.start[c], e = nd.start[c + 1];
         const int cnt = e - s;
         if (cnt > CELL_SORT_SMALL) {
@@ -227,12 +255,22 @@ __global__ void __launch_bounds__(CELL_SORT_TPB) k_cell_sort(Geo g, NodesDev nd)
         for (int i = threadIdx.x; i < cnt; i += blockDim.x) refresh_sorted<D>(nd, s + i);
         __syncthreads();
     }
+    if (blockIdx.x == 0 && threadIdx.x < STATUS_WORDS) {
+        const int i = threadIdx.x;
+        status[i] = (i == ST_NONFINITE) ? s_bad : (i == ST_MIN_N) ? LLONG_MAX : 0;
+    }
 }
 
-void launch_cell_sort(const Geo& g, NodesDev nd, hipStream_t s) {
+void launch_cell_sort(const Geo& g, NodesDev nd, int* counts, int* fill, const int* nonfinite, long long* status,
+                      hipStream_t s) {
     const unsigned blocks = (unsigned)((g.G + CELL_SORT_TPB - 1) / CELL_SORT_TPB);
-    if (g.d == 1) hipLaunchKernelGGL(k_cell_sort<1>, dim3(blocks), dim3(CELL_SORT_TPB), 0, s, g, nd);
-    else hipLaunchKernelGGL(k_cell_sort<2>, dim3(blocks), dim3(CELL_SORT_TPB), 0, s, g, nd);
+    const int np = prep_blocks(g);
+    if (g.d == 1)
+        hipLaunchKernelGGL(k_cell_sort<1>, dim3(blocks), dim3(CELL_SORT_TPB), 0, s, g, nd, counts, fill, nonfinite,
+                           np, status);
+    else
+        hipLaunchKernelGGL(k_cell_sort<2>, dim3(blocks), dim3(CELL_SORT_TPB), 0, s, g, nd, counts, fill, nonfinite,
+                           np, status);
 }
 
 // ------------------------------------------------------------------ exclusive scan

@@ -30,9 +30,11 @@ __device__ inline void window_row(const Geo& g, double u, R* w) {
     constexpr int NC = WPoly<R>::NC;
     const R* cf = (const R*)g.wpoly;
     const R y = (R)(2.0 * (u - (double)(g.m - 1)) - 1.0);
-    if constexpr ((W - 1) * NC > 210) {
-        // many coefficients (FP64, m >= 7): the same Horner steps per tap with the power loop
-        // outermost, so that one coefficient per tap is live instead of all of them
+    if constexpr ((W - 1) * NC > 135) {
+        // many coefficients (FP64 from m = 4, FP32 from m = 7): the same Horner steps per tap with
+        // the power loop outermost and rolled, so that one coefficient per tap is live.  Unrolled,
+        // a kernel that evaluates rows in a loop keeps every coefficient in vector registers
+        // (the FP64 1-D spreading at m = 6 held 452 of them and ran one wave per SIMD)
 #pragma unroll
         for (int tau = 0; tau < W - 1; ++tau) w[tau] = cf[tau * NC + NC - 1];
 #pragma unroll 1

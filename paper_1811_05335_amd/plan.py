@@ -60,6 +60,9 @@ class NfftPlan:
         self._h = h
         self._x = x
         self.device = x.device
+        # node-set version: bumped by set_nodes; B_opt records the version it was computed for
+        self.nodes_version = 0
+        self.bopt_version = -1
 
     # -------------------------------------------------------------- helpers
     def _nodes(self, x: torch.Tensor) -> torch.Tensor:
@@ -104,6 +107,7 @@ class NfftPlan:
         self._sync_stream()
         check(load().nfft_set_nodes(self._h, C.c_void_p(_ptr(x))))
         self._x = x
+        self.nodes_version += 1
 
     def trafo(self, fhat: torch.Tensor) -> torch.Tensor:
         fh, lead, R = self._coeffs(fhat)
@@ -130,12 +134,14 @@ class NfftPlan:
     def precompute_B(self) -> None:
         self._sync_stream()
         check(load().infft_precompute_B(self._h))
+        self.bopt_version = self.nodes_version
 
     def precompute_Bstar(self) -> None:
         """Algorithm 3.10 (ansatz 1): per-node optimisation of B^*; afterwards `apply` is the
         estimate (1/M) D^* F^* B_opt^* f and `apply_adjoint` the inverse adjoint of Remark 3.15."""
         self._sync_stream()
         check(load().infft_precompute_Bstar(self._h))
+        self.bopt_version = self.nodes_version
 
     def apply(self, f: torch.Tensor) -> torch.Tensor:
         ff, lead, R = self._samples(f)
@@ -275,6 +281,8 @@ class NfftBatchPlan(NfftPlan):
         self._h = h
         self._x = x
         self.device = x.device
+        self.nodes_version = 0
+        self.bopt_version = -1
 
     def _flat(self, a: torch.Tensor, per: int):
         if a.dtype != self.ctype or not a.is_cuda:

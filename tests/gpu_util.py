@@ -65,3 +65,22 @@ def check_columns(x, p, rho, mem, ls, rows_gpu):
             assert excess <= 1e-10 * J, (int(l), n, excess, J)
             nobj += 1
     return nobj
+
+
+def check_all_columns(x, p, rho, rows_gpu):
+    """check_columns over every grid index with members; grid indices with no member must leave
+    no entry (the rows of B_opt hold entries only for members)."""
+    mem = obopt.Members(x, p)
+    ls = np.nonzero(mem.sizes())[0]
+    return check_columns(x, p, rho, mem, ls, rows_gpu)
+
+
+def apply_own_vs_oracle(x, p, rho, rows_gpu, fs, out_gpu, tol=1e-8):
+    """The modified adjoint computed with the GPU's own B_opt against the oracle's modified adjoint
+    with the oracle's B_opt (Gram route), on samples fs of a trigonometric polynomial (the paper's
+    setting f = A fhat): <= 1e-8 relative."""
+    rows_o, _ = obopt.bopt_rows(x, p, rho, route="G")
+    ref = obopt.apply(x, fs, rows_o, p)
+    err = rel(out_gpu, ref)
+    assert err <= tol, ("apply with own B_opt vs oracle", err)
+    return err

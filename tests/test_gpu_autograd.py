@@ -120,3 +120,41 @@ def test_reconstruction_loss_gradients_fp64(d):
             xm = x.copy(); xm[j, t] -= h
             fd = (L(xp) - L(xm)) / (2 * h)
             assert abs(fd - g_x[j, t]) <= 1e-4 * max(abs(g_x[j, t]), 1e-6)
+
+
+def test_backward_uses_the_nodes_of_its_own_forward():
+    """Two forwards through one NFFT plan at different node sets before either backward: each
+    backward gives the gradients at its own forward's nodes (the plan reloads them), checked
+    against the oracle; the modified adjoint refuses a plan whose B_opt predates its nodes, and
+    nodes that are not the plan's."""
+    from paper_1811_05335_amd import InfftError, NfftPlan, infft, nfft
+    M, N, m = (32,), 90, 4
+    g = W.rng(64)
+    x1, x2 = W.uniform_nodes(g, N, 1), W.uniform_nodes(g, N, 1)
+    fh_np = W.complex_normal(g, (2,) + M)
+    gf_np = W.complex_normal(g, (2, N))
+    p = onfft.Params(M, 2.0, m)
+    P = NfftPlan(M, nodes_dev(x1), sigma=2.0, m=m, precision="f64", max_rhs=2)
+    outs = []
+    for x in (x1, x2):
+        a = torch.from_numpy(fh_np).cuda().requires_grad_(True)
+        xx = nodes_dev(x).requires_grad_(True)
+        outs.append((nfft(a, xx, P), a, xx, x))
+    gf = torch.from_numpy(gf_np).cuda()
+    for f, a, xx, x in outs:          # the first backward runs after the second forward
+        f.backward(gf)
+        assert rel(a.grad.cpu().numpy(), onfft.adjoint(x, gf_np, p)) <= 1e-12
+        assert rel(xx.grad.cpu().numpy(), ograd.nfft_grad_x(x, fh_np, gf_np, p)) <= 1e-10
+    Pi = NfftPlan(M, nodes_dev(x1), sigma=2.0, m=m, precision="f64", rho=1e-8)
+    fs = torch.from_numpy(gf_np[0]).cuda()
+    with pytest.raises(InfftError, match="ESTATE"):
+        infft(fs, Pi)                              # no B_opt yet
+    Pi.precompute_B()
+    with pytest.raises(InfftError, match="EINVAL"):
+        infft(fs, Pi, nodes_dev(x2))                # not the plan's nodes
+    out = infft(fs.clone().requires_grad_(True), Pi, nodes_dev(x1).requires_grad_(True))
+    Pi.set_nodes(nodes_dev(x2))
+    with pytest.raises(InfftError, match="ESTATE"):
+        out.abs().pow(2).sum().backward()           # B_opt changed before the backward
+    P.close()
+    Pi.close()

@@ -27,7 +27,9 @@ def nodes(kind, N, d, seed):
     return W.jittered_nodes(g, N) if kind == "jittered" else W.uniform_nodes(g, N, d)
 
 
-@pytest.mark.parametrize("precision,tol", [("f64", 1e-8), ("f32", 1e-4)])
+# FP64: the gradient solves each local system twice (B_opt, then the adjoint system), so its error
+# carries the conditioning of G + lambda I once more than B_opt's; observed <= 1.4e-10 on these cases
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-9), ("f32", 1e-4)])
 @pytest.mark.parametrize("M,N,d,kind,m,rho,kernel", CASES)
 def test_bopt_gradient_matches_oracle(precision, tol, M, N, d, kind, m, rho, kernel):
     from paper_1811_05335_amd import NfftPlan

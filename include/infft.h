@@ -22,9 +22,10 @@
  *          INFFT_F64 plans.
  *
  * Ownership: the caller owns every buffer it passes; pointers are only read/written during the
- * call's stream work.  A plan owns its device workspace (allocated by nfft_plan, freed by
- * nfft_plan_destroy) and keeps a copy of the nodes, so `x` may be freed after nfft_plan /
- * nfft_set_nodes return.
+ * call's stream work.  A plan made by nfft_plan owns its device memory (allocated there, freed by
+ * nfft_plan_destroy); a plan made by nfft_plan_ws lives in a workspace the caller owns and keeps
+ * alive until nfft_plan_destroy, and no call on it allocates device memory.  Either keeps a copy
+ * of the nodes, so `x` may be freed after nfft_plan / nfft_set_nodes return.
  *
  * Streams: every call enqueues work on the plan's stream (a hipStream_t passed as void*; NULL =
  * the default stream) and returns without synchronising, except nfft_plan_status,
@@ -75,7 +76,13 @@ typedef struct {
     int work_slots;  /* sets of transform work buffers (oversampled grid, FFT scratch, spreading
                         halos), 1..8 (default 1; 0 means 1).  nfft_set_slot picks the set later
                         calls use, so calls on different slots and streams may run concurrently */
-    int reserved[4];
+    int large_mib;   /* workspace plans (nfft_plan_ws) only: MiB of the workspace kept for the local
+                        problems of Algorithm 3.17 beyond the register tiers (more than 64 members in
+                        1-D, 32 in 2-D; a problem of n members needs 16 n^2 + 40 n bytes); 0 means
+                        256.  Ordinary plans size that memory when needed (must be 0 there). */
+    int ansatz1;     /* workspace plans only: 1 places the work arrays and inner plans of
+                        infft_precompute_Bstar in the workspace (d = 1; must be 0 otherwise) */
+    int reserved[2];
 } infft_options;
 
 #define INFFT_KERNEL_WINDOW 0
@@ -85,9 +92,10 @@ typedef struct {
     int64_t nonfinite_nodes;  /* nodes with a NaN/Inf coordinate (counted; the coordinate is taken as 0) */
     int64_t failed_solves;    /* local problems whose Cholesky met a pivot <= 0 */
     int64_t empty_columns;    /* grid indices l with empty I(l): zero column of B_opt */
-    int64_t oversized;        /* local problems not solved because the precompute ran under
-                                 graph capture and |I(l)| exceeds 64 in 1-D, 32 in 2-D (their
-                                 columns are zero) */
+    int64_t oversized;        /* local problems not solved (zero columns): under graph capture,
+                                 problems beyond the register tiers whose set differs from the one
+                                 recorded by the last infft_precompute_B outside capture; for batch
+                                 plans under capture, every problem beyond 64 members */
     int64_t min_members;      /* min |I(l)| over non-empty l of the last precompute */
     int64_t max_members;      /* max |I(l)| */
     int32_t bopt_ready;       /* 1 after a successful infft_precompute_B for the current nodes */
@@ -105,6 +113,26 @@ void infft_default_options(infft_options* o);
  * On success *out holds the plan; on failure *out is NULL. */
 int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma, int m,
               const double* x, const infft_options* opts, void* stream);
+
+/* Device bytes a plan made by nfft_plan_ws with these arguments occupies (host only: no device
+ * work, no allocation).  The same validation as nfft_plan; *bytes = 0 on failure.  The size covers
+ * the nodes and their sorted copies, the plan tables, work_slots sets of transform buffers for
+ * max_rhs right-hand sides, B_opt, the solver lists, opts->large_mib MiB (256 if 0) for local
+ * problems beyond the register tiers, and with opts->ansatz1 the work arrays and inner plans of
+ * Algorithm 3.10. */
+int nfft_plan_workspace_bytes(int d, const int64_t* M, int64_t N, double sigma, int m,
+                              const infft_options* opts, size_t* bytes);
+
+/* As nfft_plan, with every device buffer of the plan placed in `workspace` (device memory the
+ * caller allocated, 256-byte aligned, at least nfft_plan_workspace_bytes long; INFFT_ENOMEM if
+ * shorter).  Neither this call nor any later call on the plan allocates device memory: the local
+ * problems of Algorithm 3.17 beyond the register tiers use the part sized by opts->large_mib
+ * (INFFT_ENOMEM from infft_precompute_B if a problem does not fit), infft_autotune a buffer placed
+ * here, and infft_precompute_Bstar the arrays placed when opts->ansatz1 is 1 (INFFT_ESTATE
+ * otherwise).  The workspace must stay allocated until nfft_plan_destroy, which does not free it. */
+int nfft_plan_ws(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma, int m,
+                 const double* x, const infft_options* opts, void* workspace, size_t workspace_bytes,
+                 void* stream);
 
 /* Replaces the node set (same N) and reruns the node preprocessing: wrap onto the torus,
  * stencil base l0 = ceil(M_sigma x - m) and offset per dimension, sort into grid tiles, and the
@@ -131,10 +159,15 @@ int nfft_adjoint(infft_plan p, const void* f, void* h, int nrhs);
 /* Algorithm 3.17: optimises the nonzero entries of B, one regularised least-squares problem
  * per oversampled grid index l over the nodes I(l) of (3.29), solved through its normal
  * equations in FP64 on the GPU (whatever the plan precision).  Stores B_opt in the plan.
- * Problems with more than 64 members (1-D; 32 in 2-D) are solved by a blocked Cholesky pass
- * whose sizes are read back to the host, so the call synchronises the stream when such problems
- * exist; under HIP graph capture that pass is skipped and the problems are counted in
- * infft_status.oversized. */
+ * Problems with more than 64 members (1-D; 32 in 2-D) go to a blocked Cholesky pass.  Outside
+ * graph capture the call records that pass: it reads the number and sizes of those problems back
+ * (synchronising the stream), packs them into batches and uploads their task lists.  Under HIP
+ * graph capture it replays the last record without touching the host: a kernel first checks that
+ * the problems the tiers list are those recorded (same grid indices and sizes); if not (the nodes
+ * changed since the record), their columns are zero and they are counted in
+ * infft_status.oversized.  INFFT_ESTATE under capture when no record exists yet (call it once
+ * outside capture first).  Workspace plans: INFFT_ENOMEM when a problem does not fit the memory
+ * kept for large problems. */
 int infft_precompute_B(infft_plan p);
 
 /* Algorithm 3.10 (ansatz 1 of Section 3.2.1, the underdetermined inverse NFFT): optimises the
@@ -193,21 +226,36 @@ int infft_grad_x_bopt(infft_plan p, const void* f, const void* gradfc, double* g
  * (l0_j + tau) mod M_sigma).  Returns INFFT_ESTATE before infft_precompute_B. */
 int infft_get_B(infft_plan p, void* rows);
 
+/* Serialises B_opt with what identifies it: plan parameters (d, M, N, sigma, m, rho, kernel of
+ * the inverse, which algorithm made it), the wrapped nodes and the rows of B_opt in caller order
+ * (the layout of infft_get_B), into host memory `host_buf` of *bytes bytes.  host_buf == NULL:
+ * only sets *bytes to the size needed.  Synchronises the stream.  INFFT_ESTATE before a
+ * precompute, INFFT_EINVAL for a short buffer or a batch plan. */
+int infft_plan_export(infft_plan p, void* host_buf, size_t* bytes);
+
+/* Loads what infft_plan_export wrote (host memory) into a plan made with the same d, M, N, sigma,
+ * m, rho and kernel of the inverse (INFFT_EINVAL otherwise): the nodes go through the node
+ * preprocessing, which is deterministic, so sorted order and lists I(l) match the exported B_opt;
+ * then B_opt is loaded and the plan is ready for infft_apply without Algorithm 3.17.  The status
+ * block's solve counts restart at zero.  Synchronises the stream; not under graph capture
+ * (INFFT_ESTATE); not for batch plans. */
+int infft_plan_import(infft_plan p, const void* host_buf, size_t bytes);
+
 /* Synchronises the plan's stream and reports the device status block. */
 int nfft_plan_status(infft_plan p, infft_status* out);
 
 /* Bytes of device memory the plan holds. */
 int64_t nfft_plan_device_bytes(infft_plan p);
 
-/* Releases the plan and its device workspace (waits for the plan's stream first). */
+/* Releases the plan (waits for the plan's stream first) and the device memory nfft_plan
+ * allocated; a workspace passed to nfft_plan_ws stays the caller's. */
 void nfft_plan_destroy(infft_plan p);
 
 /* Autotuner: times every FFT pass of the plan's two schedules (coefficients -> grid and back)
  * with 1, 2, 4, 8 and 16 sub-transforms per workgroup (as far as LDS holds them), `reps` launches
- * each on the plan's buffers, and keeps the fastest for later calls.  Synchronous; allocates a
- * temporary buffer of max_rhs x prod(M) coefficients for the duration of the call; not under graph
- * capture (INFFT_ESTATE).  A no-op for batch plans, whose launches pack workgroups as full as LDS
- * allows. */
+ * each on the plan's buffers (and a coefficient buffer placed with the plan), and keeps the
+ * fastest for later calls.  Synchronous; not under graph capture (INFFT_ESTATE).  A no-op for
+ * batch plans, whose launches pack workgroups as full as LDS allows. */
 int infft_autotune(infft_plan p, int reps);
 
 /* Sub-transforms per workgroup the autotuner chose for step `step` (0 or 1) of direction `dir`

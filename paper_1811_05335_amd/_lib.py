@@ -39,7 +39,9 @@ class Options(C.Structure):
         ("tile", C.c_int * 2),
         ("inverse_kernel", C.c_int),
         ("work_slots", C.c_int),
-        ("reserved", C.c_int * 4),
+        ("large_mib", C.c_int),
+        ("ansatz1", C.c_int),
+        ("reserved", C.c_int * 2),
     ]
 
 
@@ -81,6 +83,12 @@ def load() -> C.CDLL:
         "nfft_plan": (i32, [C.POINTER(vp), i32, C.POINTER(i64), i64, dbl, i32, vp, C.POINTER(Options), vp]),
         "nfft_plan_batched": (i32, [C.POINTER(vp), i32, C.POINTER(i64), C.POINTER(i64), dbl, i32, vp,
                                     C.POINTER(Options), vp]),
+        "nfft_plan_workspace_bytes": (i32, [i32, C.POINTER(i64), i64, dbl, i32, C.POINTER(Options),
+                                            C.POINTER(C.c_size_t)]),
+        "nfft_plan_ws": (i32, [C.POINTER(vp), i32, C.POINTER(i64), i64, dbl, i32, vp, C.POINTER(Options), vp,
+                               C.c_size_t, vp]),
+        "infft_plan_export": (i32, [vp, vp, C.POINTER(C.c_size_t)]),
+        "infft_plan_import": (i32, [vp, vp, C.c_size_t]),
         "nfft_set_nodes": (i32, [vp, vp]),
         "nfft_set_stream": (i32, [vp, vp]),
         "nfft_set_slot": (i32, [vp, C.c_int]),

@@ -81,6 +81,37 @@ struct FftStep {
 struct BatchState;
 void batch_free(BatchState* b);
 
+// One batch of a recorded large-problem pass: its problems (a range of the record's descriptors,
+// sorted by size, largest first) and the task segments of its launches.
+struct BigBatch {
+    int np = 0;
+    int T0 = 0;                  // block columns of its largest problem
+    int64_t prob_off = 0;
+    std::vector<int> nblk;       // block columns per problem
+    std::vector<int64_t> seg;    // Gram tiles, then per block column the panel and trailing tiles
+    std::vector<int64_t> fseg;   // forward substitution per block step
+    std::vector<int64_t> bseg;   // backward substitution per block step
+};
+
+// A recorded large-problem pass: built outside graph capture, replayed under capture.
+struct BigSched {
+    bool built = false;
+    int count = 0;
+    int nmin = 0, nmax = 0;
+    std::vector<BigBatch> batches;
+    BigProb* probs = nullptr;    // descriptors of all batches
+    int4* tasks = nullptr;       // task lists of all batches
+    int* fail = nullptr;         // per problem: non-positive pivot
+    int* slot = nullptr;         // per grid index: its problem in the record, -1 otherwise
+    int* flag = nullptr;         // [0] set when the listed problems differ from the record;
+                                 // [1] the generation of the current record
+    int gen = 0;
+    int64_t probs_cap = 0, tasks_cap = 0, fail_cap = 0;
+};
+
+// alignment of every buffer carved from a workspace (and of the workspace itself)
+constexpr int WS_ALIGN = 256;
+
 struct infft_plan_s {
     Geo g{};
     int prec = INFFT_F64;
@@ -90,6 +121,13 @@ struct infft_plan_s {
     hipStream_t stream = nullptr;
     std::vector<void*> allocs;
     int64_t bytes = 0;
+    // workspace plans carve every buffer from the caller's workspace (ws_base, ws_size); a
+    // measuring plan only counts the bytes (no device memory, no device work)
+    bool ws_mode = false;
+    bool measure = false;
+    char* ws_base = nullptr;
+    size_t ws_size = 0;
+    size_t ws_used = 0;
 
     NodesDev nd{};
     int* counts = nullptr;
@@ -114,6 +152,14 @@ struct infft_plan_s {
     int qK = 0, qQ = 0;
     double lam = 0.0;
 
+    std::vector<long double> wpoly_host;   // window polynomial coefficients, uploaded at set-up
+    void* tune_buf = nullptr;              // coefficient buffer of the autotuner
+    // workspace plans: memory for local problems beyond the register tiers, and the work arrays and
+    // inner-plan workspaces of Algorithm 3.10 (when the plan was made with ansatz1)
+    char* large_arena = nullptr;
+    int64_t large_arena_bytes = 0;
+    void* a1_ws[2] = {nullptr, nullptr};
+    size_t a1_ws_bytes[2] = {0, 0};
     std::vector<TwTable> tw;
     TwTable split_lo, split_hi;
     std::vector<FftStep> to_grid;    // coefficients -> grid (sign +1, with D)
@@ -159,11 +205,11 @@ struct infft_plan_s {
     // many 1-D problems in one plan (nullptr for a single problem)
     struct BatchState* batch = nullptr;
 
-    // large local problems: sizes, failure flags and one batch of matrices and members,
-    // allocated when first needed and grown on demand
+    // large local problems: sizes, one batch of matrices and members (allocated when first
+    // needed and grown on demand, or placed in a workspace plan's workspace), and the records of
+    // the pass (0: the precompute, 1: the node gradient through B_opt(x))
     int* big_n = nullptr;
-    int* big_fail = nullptr;
-    int64_t big_fail_cap = 0;
+    BigSched big_sched[2];
     double2* big_A = nullptr;
     int64_t big_A_cap = 0;
     int* big_midx = nullptr;
@@ -172,10 +218,6 @@ struct infft_plan_s {
     double2* big_mr = nullptr;
     double2* big_mb = nullptr;
     int64_t big_m_cap = 0;
-    BigProb* big_probs = nullptr;
-    int64_t big_probs_cap = 0;
-    int4* big_tasks = nullptr;
-    int64_t big_tasks_cap = 0;
 
     // optional event timing of one kernel class
     int prof_class = 0;
@@ -189,6 +231,16 @@ struct infft_plan_s {
     int alloc(T** p, int64_t count) {
         void* q = nullptr;
         const size_t nb = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+        if (ws_mode) {
+            const size_t off = (ws_used + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN;
+            if (off + nb > ws_size || off + nb < off)
+                return fail(INFFT_ENOMEM, "workspace of %zu bytes exhausted (%zu more needed)", ws_size, off + nb - ws_size);
+            ws_used = off + nb;
+            bytes += (int64_t)nb;
+            // a measuring plan hands out addresses that are never used
+            *p = (T*)((measure ? (char*)(uintptr_t)WS_ALIGN : ws_base) + off);
+            return INFFT_OK;
+        }
         hipError_t e = hipMalloc(&q, nb);
         if (e != hipSuccess) return fail(INFFT_ENOMEM, "hipMalloc(%zu) failed: %s", nb, hipGetErrorString(e));
         allocs.push_back(q);
@@ -201,6 +253,9 @@ struct infft_plan_s {
     template <typename T>
     int grow(T** p, int64_t& cap, int64_t need) {
         if (need <= cap) return INFFT_OK;
+        if (ws_mode)   // workspace plans place everything at plan time
+            return fail(INFFT_ENOMEM, "workspace plan: %lld elements needed where %lld were placed",
+                        (long long)need, (long long)cap);
         if (*p) {
             auto it = std::find(allocs.begin(), allocs.end(), (void*)*p);
             if (it != allocs.end()) allocs.erase(it);
@@ -216,12 +271,28 @@ struct infft_plan_s {
         return INFFT_OK;
     }
 
+    // As grow, but the replaced allocation is kept until the plan is destroyed: graphs captured
+    // earlier may still hold its address (their kernels return at once, yet read it in bounds).
+    template <typename T>
+    int grow_retire(T** p, int64_t& cap, int64_t need) {
+        if (need <= cap) return INFFT_OK;
+        if (ws_mode) return grow(p, cap, need);
+        *p = nullptr;   // the old block stays in `allocs`, freed with the plan
+        cap = 0;
+        const int64_t n = need + need / 4;
+        int rc = alloc(p, n);
+        if (rc) return rc;
+        cap = n;
+        return INFFT_OK;
+    }
+
     ~infft_plan_s() {
         if (batch) batch_free(batch);
         delete a1_pplan;
         delete a1_fplan;
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-        for (void* p : allocs) (void)hipFree(p);
+        if (!ws_mode)
+            for (void* p : allocs) (void)hipFree(p);
     }
 };
 
@@ -257,14 +328,14 @@ const TwTable* find_tw(const infft_plan_s* P, int64_t n) {
     return nullptr;
 }
 
-int ensure_tw(infft_plan_s* P, int64_t n) {
+// Places the twiddle table of sub-length n (filled at plan set-up).
+int reserve_tw(infft_plan_s* P, int64_t n) {
     if (find_tw(P, n)) return INFFT_OK;
     TwTable t;
     t.n = n;
     int rc = P->alloc(&t.t64, n);
     if (rc) return rc;
     if (P->prec == INFFT_F32 && (rc = P->alloc(&t.t32, n))) return rc;
-    launch_twiddles(n, t.t64, t.t32, P->stream);
     P->tw.push_back(t);
     return INFFT_OK;
 }
@@ -540,19 +611,44 @@ KTabDev plan_ktab(const infft_plan_s* p) {
     return kt;
 }
 
-// Local problems with more members than the register tiers hold (list of grid indices and its
-// device count from the last tier).  Reads the count and the sizes back to the host, sorts the
-// problems by size, packs them into batches whose matrices fit the workspace and runs the
-// blocked Cholesky pipeline on each batch; adds one statistics record.
-int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* count_dev, int& stat_off,
-                const BoptGradArgs* grad = nullptr) {
+// Carves `count` elements of T from a workspace region [base + used, base + size).
+template <typename T>
+int carve(char* base, int64_t size, int64_t& used, T** p, int64_t count) {
+    const int64_t off = (used + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN;
+    const int64_t nb = std::max<int64_t>(count, 1) * (int64_t)sizeof(T);
+    if (off + nb > size)
+        return fail(INFFT_ENOMEM, "the workspace kept for large local problems (%lld bytes) is too small: "
+                    "%lld bytes needed (option large_mib)", (long long)size, (long long)(off + nb));
+    *p = (T*)(base + off);
+    used = off + nb;
+    return INFFT_OK;
+}
+
+// Records the large-problem pass for the problems the last tier listed (count and list on the
+// device): reads the count and the sizes back, sorts the problems by size, packs them into
+// batches whose matrices fit the workspace, and uploads problem descriptors and task lists of
+// every batch.  Synchronises the stream.
+int big_record(infft_plan_s* p, BigSched& S, const int* list, const int* count_dev) {
     const Geo& g = p->g;
     hipStream_t st = p->stream;
+    int rc;
+    S.built = false;
+    S.batches.clear();
+    // a new generation: graphs that replay an earlier record find it stale on the device
+    S.gen += 1;
     int count = 0;
     HIP_TRY(hipMemcpyAsync(&count, count_dev, sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (count <= 0) return INFFT_OK;
-    int rc;
+    if (!S.slot && (rc = p->alloc(&S.slot, g.G))) return rc;
+    if (!S.flag && (rc = p->alloc(&S.flag, 2))) return rc;
+    launch_fill_i32(S.slot, g.G, -1, st);
+    launch_fill_i32(S.flag + 1, 1, S.gen, st);
+    LAUNCH_CHECK();
+    S.count = count;
+    if (count <= 0) {
+        S.built = true;
+        return INFFT_OK;
+    }
     if (!p->big_n && (rc = p->alloc(&p->big_n, g.G))) return rc;
     launch_big_count(g, p->nd, list, count, p->big_n, st);
     LAUNCH_CHECK();
@@ -565,136 +661,227 @@ int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* 
     std::sort(order.begin(), order.end(), [&](int a, int b) {
         return ns[a] != ns[b] ? ns[a] > ns[b] : ls[a] < ls[b];
     });
-    const int nmax = ns[order.front()], nmin = ns[order.back()];
-    if ((rc = p->grow(&p->big_fail, p->big_fail_cap, count))) return rc;
-    launch_fill_i32(p->big_fail, count, 0, st);
-    // workspace of one batch: matrices plus member data (40 bytes per member)
-    // batch budget: a quarter of the free device memory, between 1 and 16 GiB.  Every batch runs its
-    // block steps in sequence, so fewer, larger batches shorten the chain of dependent launches.
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
-    const int64_t kBudget = std::min<int64_t>(std::max<int64_t>((int64_t)(free_b / 4), (int64_t)1 << 30),
-                                              (int64_t)16 << 30);
-    const int64_t cap_bytes = std::max<int64_t>(kBudget, (int64_t)nmax * nmax * 16 + (int64_t)nmax * 40 + 4096);
+    S.nmax = ns[order.front()];
+    S.nmin = ns[order.back()];
+    // batch budget for matrices and member data (40 bytes per member).  Ordinary plans: a quarter
+    // of the free device memory, between 1 and 16 GiB (every batch runs its block steps in sequence,
+    // so fewer, larger batches shorten the chain of dependent launches); workspace plans: three
+    // quarters of the part of the workspace kept for large problems, the rest for the descriptors
+    // and task lists of both records.
+    int64_t budget;
+    if (p->ws_mode) {
+        budget = p->large_arena_bytes / 4 * 3;
+    } else {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+        budget = std::min<int64_t>(std::max<int64_t>((int64_t)(free_b / 4), (int64_t)1 << 30), (int64_t)16 << 30);
+    }
+    const int64_t one = (int64_t)S.nmax * S.nmax * 16 + (int64_t)S.nmax * 40 + 4096;
+    if (p->ws_mode && one > budget)
+        return fail(INFFT_ENOMEM, "a local problem of %d members needs %lld bytes; the workspace keeps %lld for "
+                    "large problems (option large_mib)", S.nmax, (long long)one, (long long)budget);
+    const int64_t cap_bytes = std::max<int64_t>(budget, one);
     std::vector<BigProb> probs;
     std::vector<int4> tasks;
+    probs.reserve(count);
+    int64_t maxA = 1, maxM = 1;
     size_t pos = 0;
     while (pos < order.size()) {
-        probs.clear();
+        BigBatch b;
+        b.prob_off = (int64_t)probs.size();
         int64_t ent = 0, mem = 0;
         while (pos < order.size()) {
             const int q = order[pos];
             const int64_t n = ns[q];
             const int64_t e = (n * n + 31) / 32 * 32;
-            if (!probs.empty() && (ent + e) * 16 + (mem + n) * 40 > cap_bytes) break;
-            BigProb b{};
-            b.l = ls[q];
-            b.n = (int)n;
-            b.nblk = (int)((n + BIG_NB - 1) / BIG_NB);
-            b.id = q;
-            b.off = ent;
-            b.moff = mem;
-            probs.push_back(b);
+            if (b.np > 0 && (ent + e) * 16 + (mem + n) * 40 > cap_bytes) break;
+            BigProb bp{};
+            bp.l = ls[q];
+            bp.n = (int)n;
+            bp.nblk = (int)((n + BIG_NB - 1) / BIG_NB);
+            bp.id = (int)probs.size();   // index of the failure flag: position in the sorted order
+            bp.off = ent;
+            bp.moff = mem;
+            probs.push_back(bp);
+            b.nblk.push_back(bp.nblk);
             ent += e;
             mem += n;
+            ++b.np;
             ++pos;
         }
-        const int np = (int)probs.size();
-        const int T0 = probs.front().nblk;
+        maxA = std::max(maxA, ent);
+        maxM = std::max(maxM, mem);
+        b.T0 = b.nblk.front();
+        const BigProb* pb = probs.data() + b.prob_off;
         // task lists: Gram tiles, then per block column k the panel and trailing tiles
-        tasks.clear();
-        std::vector<int64_t> seg;   // [gram, trsm_0, herk_0, trsm_1, herk_1, ...] starts
-        seg.push_back(0);
-        for (int i = 0; i < np; ++i)
-            for (int I = 0; I < probs[i].nblk; ++I)
+        b.seg.push_back((int64_t)tasks.size());
+        for (int i = 0; i < b.np; ++i)
+            for (int I = 0; I < pb[i].nblk; ++I)
                 for (int J = 0; J <= I; ++J) tasks.push_back(make_int4(i, I, J, 0));
-        for (int k = 0; k < T0; ++k) {
-            seg.push_back((int64_t)tasks.size());
-            for (int i = 0; i < np && probs[i].nblk > k; ++i)
-                for (int I = k + 1; I < probs[i].nblk; ++I) tasks.push_back(make_int4(i, I, 0, 0));
-            seg.push_back((int64_t)tasks.size());
-            for (int i = 0; i < np && probs[i].nblk > k; ++i)
-                for (int I = k + 1; I < probs[i].nblk; ++I)
+        for (int k = 0; k < b.T0; ++k) {
+            b.seg.push_back((int64_t)tasks.size());
+            for (int i = 0; i < b.np && pb[i].nblk > k; ++i)
+                for (int I = k + 1; I < pb[i].nblk; ++I) tasks.push_back(make_int4(i, I, 0, 0));
+            b.seg.push_back((int64_t)tasks.size());
+            for (int i = 0; i < b.np && pb[i].nblk > k; ++i)
+                for (int I = k + 1; I < pb[i].nblk; ++I)
                     for (int J = k + 1; J <= I; ++J) tasks.push_back(make_int4(i, I, J, 0));
         }
-        seg.push_back((int64_t)tasks.size());
+        b.seg.push_back((int64_t)tasks.size());
         // substitution steps (right-looking, one launch per block step): forward (problem, I >= k),
         // backward (problem, J <= k)
-        std::vector<int64_t> fseg, bseg;
-        if (!grad) {
-            for (int k = 0; k < T0; ++k) {
-                fseg.push_back((int64_t)tasks.size());
-                for (int i = 0; i < np && probs[i].nblk > k; ++i)
-                    for (int I = k; I < probs[i].nblk; ++I) tasks.push_back(make_int4(i, I, 0, 0));
-            }
-            fseg.push_back((int64_t)tasks.size());
-            for (int k = 0; k < T0; ++k) {
-                bseg.push_back((int64_t)tasks.size());
-                for (int i = 0; i < np && probs[i].nblk > k; ++i)
-                    for (int J = 0; J <= k; ++J) tasks.push_back(make_int4(i, J, 0, 0));
-            }
-            bseg.push_back((int64_t)tasks.size());
+        for (int k = 0; k < b.T0; ++k) {
+            b.fseg.push_back((int64_t)tasks.size());
+            for (int i = 0; i < b.np && pb[i].nblk > k; ++i)
+                for (int I = k; I < pb[i].nblk; ++I) tasks.push_back(make_int4(i, I, 0, 0));
         }
-        if ((rc = p->grow(&p->big_A, p->big_A_cap, std::max<int64_t>(ent, 1)))) return rc;
-        if (mem > p->big_m_cap) {
+        b.fseg.push_back((int64_t)tasks.size());
+        for (int k = 0; k < b.T0; ++k) {
+            b.bseg.push_back((int64_t)tasks.size());
+            for (int i = 0; i < b.np && pb[i].nblk > k; ++i)
+                for (int J = 0; J <= k; ++J) tasks.push_back(make_int4(i, J, 0, 0));
+        }
+        b.bseg.push_back((int64_t)tasks.size());
+        S.batches.push_back(std::move(b));
+    }
+    const int64_t ntask = std::max<int64_t>((int64_t)tasks.size(), 1);
+    // device arrays: the shared matrices and member data, this record's descriptors and tasks
+    if (p->ws_mode) {
+        char* base = p->large_arena;
+        int64_t used = 0;
+        const int64_t wsz = budget;
+        if ((rc = carve(base, wsz, used, &p->big_A, maxA)) || (rc = carve(base, wsz, used, &p->big_midx, maxM)) ||
+            (rc = carve(base, wsz, used, &p->big_mtap, maxM)) || (rc = carve(base, wsz, used, &p->big_mz, maxM)) ||
+            (rc = carve(base, wsz, used, &p->big_mr, maxM)) || (rc = carve(base, wsz, used, &p->big_mb, maxM)))
+            return rc;
+        // each record owns one eighth of the part kept for large problems
+        const int64_t rsz = p->large_arena_bytes / 8;
+        char* rbase = base + budget + (int64_t)(&S - p->big_sched) * rsz;
+        int64_t rused = 0;
+        if ((rc = carve(rbase, rsz, rused, &S.probs, count)) || (rc = carve(rbase, rsz, rused, &S.tasks, ntask)) ||
+            (rc = carve(rbase, rsz, rused, &S.fail, count)))
+            return rc;
+    } else {
+        if ((rc = p->grow_retire(&p->big_A, p->big_A_cap, maxA))) return rc;
+        if (maxM > p->big_m_cap) {
             int64_t c1 = p->big_m_cap, c2 = p->big_m_cap, c3 = p->big_m_cap, c4 = p->big_m_cap,
                     c5 = p->big_m_cap;
-            if ((rc = p->grow(&p->big_midx, c1, mem)) || (rc = p->grow(&p->big_mtap, c2, mem)) ||
-                (rc = p->grow(&p->big_mz, c3, mem)) || (rc = p->grow(&p->big_mr, c4, mem)) ||
-                (rc = p->grow(&p->big_mb, c5, mem)))
+            if ((rc = p->grow_retire(&p->big_midx, c1, maxM)) || (rc = p->grow_retire(&p->big_mtap, c2, maxM)) ||
+                (rc = p->grow_retire(&p->big_mz, c3, maxM)) || (rc = p->grow_retire(&p->big_mr, c4, maxM)) ||
+                (rc = p->grow_retire(&p->big_mb, c5, maxM)))
                 return rc;
             p->big_m_cap = c1;
         }
-        if ((rc = p->grow(&p->big_probs, p->big_probs_cap, np))) return rc;
-        if ((rc = p->grow(&p->big_tasks, p->big_tasks_cap, std::max<int64_t>((int64_t)tasks.size(), 1)))) return rc;
-        HIP_TRY(hipMemcpyAsync(p->big_probs, probs.data(), sizeof(BigProb) * np, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(p->big_tasks, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice, st));
+        if ((rc = p->grow_retire(&S.probs, S.probs_cap, count)) ||
+            (rc = p->grow_retire(&S.tasks, S.tasks_cap, ntask)) || (rc = p->grow_retire(&S.fail, S.fail_cap, count)))
+            return rc;
+    }
+    HIP_TRY(hipMemcpy(S.probs, probs.data(), sizeof(BigProb) * probs.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(S.tasks, tasks.data(), sizeof(int4) * tasks.size(), hipMemcpyHostToDevice));
+    launch_big_slots(S.probs, count, S.slot, st);
+    LAUNCH_CHECK();
+    S.built = true;
+    return INFFT_OK;
+}
+
+// Enqueues a recorded large-problem pass (no host synchronisation: also under graph capture).
+// A check kernel first compares the problems the last tier listed with the record; if they differ
+// (the nodes changed since the record), every large-problem kernel returns at once and the listed
+// problems get zero columns and are counted as oversized.  grad: the node-gradient pass instead of
+// the solutions.  Adds one statistics record for the precompute.
+int big_enqueue(infft_plan_s* p, BigSched& S, const KTabDev& kt, const int* list, const int* count_dev,
+                int& stat_off, const BoptGradArgs* grad, bool capturing) {
+    const Geo& g = p->g;
+    hipStream_t st = p->stream;
+    if (S.count == 0) {
+        // nothing recorded: outside capture the count was just read back, so there is nothing to
+        // do; under capture one kernel checks that the tiers still list no problem (and that the
+        // record is current), else zeroes the listed problems' columns and counts them
+        if (capturing && !grad) {
+            launch_big_guard_empty(g, p->nd, list, count_dev, S.flag + 1, S.gen, p->B64, p->B32, p->stat_rec, p->status, st);
+            LAUNCH_CHECK();
+        }
+        return INFFT_OK;
+    }
+    // outside capture the record was just made from these lists: no check
+    if (capturing) {
+        launch_fill_i32(S.flag, 1, 0, st);
+        launch_big_check(g, p->nd, list, count_dev, S.slot, S.probs, S.count, S.gen, S.flag, st);
+        LAUNCH_CHECK();
+    }
+    {
+        launch_fill_i32(S.fail, S.count, 0, st);
         BigArgs a{};
-        a.probs = p->big_probs;
         a.A = p->big_A;
         a.midx = p->big_midx;
         a.mtap = p->big_mtap;
         a.mz = p->big_mz;
         a.mr = p->big_mr;
         a.mb = p->big_mb;
-        a.fail = p->big_fail;
-        launch_big_setup(g, p->nd, kt, a, np, st);
-        LAUNCH_CHECK();
-        launch_big_gram(g, kt, a, p->big_tasks + seg[0], (int)(seg[1] - seg[0]), st);
-        LAUNCH_CHECK();
-        int active = np;
-        for (int k = 0; k < T0; ++k) {
-            while (active > 0 && probs[active - 1].nblk <= k) --active;
-            launch_big_potrf(a, active, k, st);
+        a.fail = S.fail;
+        a.stale = capturing ? S.flag : nullptr;
+        for (const BigBatch& b : S.batches) {
+            a.probs = S.probs + b.prob_off;
+            launch_big_setup(g, p->nd, kt, a, b.np, st);
             LAUNCH_CHECK();
-            const int64_t t0 = seg[1 + 2 * k], t1 = seg[2 + 2 * k], t2 = seg[3 + 2 * k];
-            launch_big_trsm(a, p->big_tasks + t0, (int)(t1 - t0), k, st);
+            launch_big_gram(g, kt, a, S.tasks + b.seg[0], (int)(b.seg[1] - b.seg[0]), st);
             LAUNCH_CHECK();
-            launch_big_herk(a, p->big_tasks + t1, (int)(t2 - t1), k, st);
-            LAUNCH_CHECK();
-        }
-        if (grad) {
-            launch_big_grad(g, a, kt, *grad, p->nd.perm, np, p->prec == INFFT_F32, st);
-        } else {
-            for (int k = 0; k < T0; ++k) {
-                launch_big_fwd(a, p->big_tasks + fseg[k], (int)(fseg[k + 1] - fseg[k]), k, st);
+            int active = b.np;
+            for (int k = 0; k < b.T0; ++k) {
+                while (active > 0 && b.nblk[active - 1] <= k) --active;
+                launch_big_potrf(a, active, k, st);
+                LAUNCH_CHECK();
+                const int64_t t0 = b.seg[1 + 2 * k], t1 = b.seg[2 + 2 * k], t2 = b.seg[3 + 2 * k];
+                launch_big_trsm(a, S.tasks + t0, (int)(t1 - t0), k, st);
+                LAUNCH_CHECK();
+                launch_big_herk(a, S.tasks + t1, (int)(t2 - t1), k, st);
                 LAUNCH_CHECK();
             }
-            for (int k = T0 - 1; k >= 0; --k) {
-                launch_big_bwd(a, p->big_tasks + bseg[k], (int)(bseg[k + 1] - bseg[k]), k, st);
-                LAUNCH_CHECK();
+            if (grad) {
+                launch_big_grad(g, a, kt, *grad, p->nd.perm, b.np, p->prec == INFFT_F32, st);
+            } else {
+                for (int k = 0; k < b.T0; ++k) {
+                    launch_big_fwd(a, S.tasks + b.fseg[k], (int)(b.fseg[k + 1] - b.fseg[k]), k, st);
+                    LAUNCH_CHECK();
+                }
+                for (int k = b.T0 - 1; k >= 0; --k) {
+                    launch_big_bwd(a, S.tasks + b.bseg[k], (int)(b.bseg[k + 1] - b.bseg[k]), k, st);
+                    LAUNCH_CHECK();
+                }
+                launch_big_write(g, a, b.np, p->B64, p->B32, st);
             }
-            launch_big_write(g, a, np, p->B64, p->B32, st);
+            LAUNCH_CHECK();
         }
-        LAUNCH_CHECK();
-        // the host task arrays are reused by the next batch
-        HIP_TRY(hipStreamSynchronize(st));
     }
     if (grad) return INFFT_OK;   // the precompute's statistics stay as they are
-    launch_big_stats(p->big_fail, count, nmin, nmax, p->stat_rec + (int64_t)stat_off * 5, st);
+    if (capturing) {
+        launch_big_zero_stale(g, p->nd, list, count_dev, S.flag, p->B64, p->B32, p->stat_rec, p->status, st);
+        LAUNCH_CHECK();
+    }
+    launch_big_stats(S.fail, S.count, S.nmin, S.nmax, p->stat_rec + (int64_t)stat_off * 5, st);
     LAUNCH_CHECK();
     stat_off += 1;
     return INFFT_OK;
+}
+
+// Local problems with more members than the register tiers hold (list of grid indices and its
+// device count from the last tier): recorded anew outside graph capture, replayed from the last
+// record under capture (INFFT_ESTATE when there is none).  Record 0 serves the precompute, record 1
+// the node gradient through B_opt(x), whose tiers pass on a different set of problems.
+int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* count_dev, int& stat_off,
+                const BoptGradArgs* grad = nullptr) {
+    BigSched& S = p->big_sched[grad ? 1 : 0];
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(p->stream, &cs));
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    if (!capturing) {
+        int rc = big_record(p, S, list, count_dev);
+        if (rc) return rc;
+    } else if (!S.built) {
+        return fail(INFFT_ESTATE, "under graph capture the pass for local problems beyond the register tiers "
+                    "replays the one recorded by the last call outside capture, and there is none yet");
+    }
+    return big_enqueue(p, S, kt, list, count_dev, stat_off, grad, capturing);
 }
 
 }  // namespace
@@ -983,29 +1170,40 @@ void infft_default_options(infft_options* o) {
 
 const char* infft_last_error(void) { return g_err.c_str(); }
 
-int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma, int m, const double* x,
-              const infft_options* opts, void* stream) {
-    g_err.clear();
-    if (!out) return fail(INFFT_EINVAL, "out is null");
-    *out = nullptr;
+}  // extern "C"
+
+namespace {
+
+// A validated parameter set: geometry, options, work slots and the split of a long 1-D FFT.
+struct PlanSpec {
+    Geo g{};
+    infft_options o{};
+    double sigma = 2.0;
+    int nslots = 1;
+    int64_t n1_split = 0;
+};
+
+int plan_validate(int d, const int64_t* M, int64_t N, double sigma, int m, const infft_options* opts,
+                  PlanSpec& S) {
     if (d < 1 || d > 2) return fail(INFFT_EINVAL, "d must be 1 or 2 (got %d)", d);
     if (!M) return fail(INFFT_EINVAL, "M is null");
-    if (!x) return fail(INFFT_EINVAL, "x is null");
     if (N <= 0 || N >= (int64_t)1 << 31) return fail(INFFT_EINVAL, "N out of range (%lld)", (long long)N);
     if (m < MIN_M_CUT || m > MAX_M_CUT) return fail(INFFT_EINVAL, "m must be in %d..%d (got %d)", MIN_M_CUT, MAX_M_CUT, m);
     if (!(sigma >= 1.0) || !std::isfinite(sigma)) return fail(INFFT_EINVAL, "sigma must be >= 1");
-    infft_options o;
+    infft_options& o = S.o;
     infft_default_options(&o);
     if (opts) o = *opts;
     if (o.precision != INFFT_F32 && o.precision != INFFT_F64) return fail(INFFT_EINVAL, "bad precision");
     if (o.inverse_kernel != INFFT_KERNEL_WINDOW && o.inverse_kernel != INFFT_KERNEL_DIRICHLET)
         return fail(INFFT_EINVAL, "bad inverse_kernel");
     if (o.max_rhs < 1 || o.max_rhs > 64) return fail(INFFT_EINVAL, "max_rhs must be in 1..64");
-    const int nslots = o.work_slots == 0 ? 1 : o.work_slots;
-    if (nslots < 1 || nslots > 8) return fail(INFFT_EINVAL, "work_slots must be in 1..8 (got %d)", o.work_slots);
+    S.nslots = o.work_slots == 0 ? 1 : o.work_slots;
+    if (S.nslots < 1 || S.nslots > 8) return fail(INFFT_EINVAL, "work_slots must be in 1..8 (got %d)", o.work_slots);
     if (!(o.rho >= 0.0) || !std::isfinite(o.rho)) return fail(INFFT_EINVAL, "rho must be finite and >= 0");
-
-    Geo g{};
+    if (o.large_mib < 0 || o.large_mib > (1 << 20)) return fail(INFFT_EINVAL, "large_mib out of range");
+    if (o.ansatz1 != 0 && o.ansatz1 != 1) return fail(INFFT_EINVAL, "ansatz1 must be 0 or 1");
+    S.sigma = sigma;
+    Geo& g = S.g;
     g.d = d;
     g.m = m;
     g.N = N;
@@ -1029,6 +1227,7 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
         g.P *= M[t];
     }
     if (g.G > ((int64_t)1 << 22)) return fail(INFFT_EINVAL, "oversampled grid too large (%lld points)", (long long)g.G);
+    if (o.ansatz1 && d != 1) return fail(INFFT_EINVAL, "ansatz1 work arrays are for d = 1 plans");
     // tiles
     for (int t = 0; t < d; ++t) {
         const int want = o.tile[t] > 0 ? o.tile[t] : (d == 1 ? 256 : 32);
@@ -1039,7 +1238,6 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
     }
     // FFT feasibility
     const int cap = fft_capacity(o.precision == INFFT_F64);
-    int64_t n1_split = 0;
     for (int t = 0; t < d; ++t) {
         std::vector<int> rad;
         if (!factor_radices(g.Ms[t], rad))
@@ -1057,117 +1255,137 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
                 if (!best || std::llabs(a - b) < std::llabs(best - g.Ms[t] / best)) best = a;
             }
             if (!best) return fail(INFFT_EINVAL, "M_sigma = %d cannot be split into two FFT passes", g.Ms[t]);
-            n1_split = best;
+            S.n1_split = best;
         }
     }
+    return INFFT_OK;
+}
 
-    infft_plan_s* P = new infft_plan_s();
-    P->g = g;
-    P->prec = o.precision;
-    P->max_rhs = o.max_rhs;
-    P->rho = o.rho;
-    P->sigma = sigma;
-    P->stream = (hipStream_t)stream;
-    P->inv_kernel = o.inverse_kernel;
-    int rc = INFFT_OK;
-#define TRY(e)                     \
-    do {                           \
-        if ((rc = (e)) != 0) {     \
-            delete P;              \
-            return rc;             \
-        }                          \
-    } while (0)
+// Parameters of the two inner plans of Algorithm 3.10 (made on the first infft_precompute_Bstar):
+// the Toeplitz symbol at bandwidth 2M, sigma 2, the largest cut-off; and for FP32 plans an FP64
+// twin with one node for the length-M_sigma FFTs.
+struct InnerSpec {
+    int64_t M;
+    int64_t N;
+    double sigma;
+    int m;
+    infft_options o;
+};
+
+InnerSpec a1_symbol_spec(const Geo& g) {
+    InnerSpec s{};
+    infft_default_options(&s.o);
+    s.o.precision = INFFT_F64;
+    s.M = 2 * (int64_t)g.M[0];
+    s.N = g.N;
+    s.sigma = 2.0;
+    s.m = std::min<int>(MAX_M_CUT, (int)(2 * s.M - 2) / 2);
+    return s;
+}
+
+InnerSpec a1_twin_spec(const Geo& g, double sigma, int inv_kernel) {
+    InnerSpec s{};
+    infft_default_options(&s.o);
+    s.o.precision = INFFT_F64;
+    s.o.inverse_kernel = inv_kernel;
+    s.M = g.M[0];
+    s.N = 1;
+    s.sigma = sigma;
+    s.m = g.m;
+    return s;
+}
+
+// complex128 elements of the work arrays of Algorithm 3.10
+int64_t a1_work_elems(const Geo& g) {
+    const int M = g.M[0], Ms = g.Ms[0];
+    const int npair = Ms >= 2 * M - 1 ? 1 : 4;
+    const int64_t rows = 2 * g.m + 1;
+    return (rows * (3 + 2 * npair)) * Ms + 4 * (int64_t)M + g.N;
+}
+
+int plan_measure(const PlanSpec& S, size_t* bytes);
+
+// Places every device buffer of the plan (through P->alloc: device allocations, carving from a
+// caller's workspace, or only counting bytes) and fixes the host-side layout; no device work.
+int plan_layout(infft_plan_s* P, const PlanSpec& S) {
+    const Geo& g = S.g;
+    const int d = g.d, m = g.m;
+    const int64_t N = g.N;
     const int64_t Nd = N * d;
     const int T = P->taps();
+    int rc;
+#define LTRY(e)                 \
+    do {                        \
+        if ((rc = (e)) != 0) return rc; \
+    } while (0)
     double* xw = nullptr;
-    TRY(P->alloc(&xw, Nd));
+    LTRY(P->alloc(&xw, Nd));
     P->nd.xw = xw;
-    TRY(P->alloc(&P->nd.l0c, Nd));
-    TRY(P->alloc(&P->nd.uc, Nd));
-    TRY(P->alloc(&P->nd.key, N));
-    TRY(P->alloc(&P->nd.perm, N));
-    TRY(P->alloc(&P->nd.l0s, Nd));
-    TRY(P->alloc(&P->nd.us, Nd));
-    TRY(P->alloc(&P->nd.start, g.G + 1));
-    TRY(P->alloc(&P->counts, g.G + 1));
-    TRY(P->alloc(&P->nonfinite, prep_blocks(g)));
-    TRY(P->alloc(&P->fill, g.G));
-    TRY(P->alloc(&P->bsum, scan_blocksum_len(g.G) + 1));
-    TRY(P->alloc(&P->status, STATUS_WORDS));
+    LTRY(P->alloc(&P->nd.l0c, Nd));
+    LTRY(P->alloc(&P->nd.uc, Nd));
+    LTRY(P->alloc(&P->nd.key, N));
+    LTRY(P->alloc(&P->nd.perm, N));
+    LTRY(P->alloc(&P->nd.l0s, Nd));
+    LTRY(P->alloc(&P->nd.us, Nd));
+    LTRY(P->alloc(&P->nd.start, g.G + 1));
+    LTRY(P->alloc(&P->counts, g.G + 1));
+    LTRY(P->alloc(&P->nonfinite, prep_blocks(g)));
+    LTRY(P->alloc(&P->fill, g.G));
+    LTRY(P->alloc(&P->bsum, scan_blocksum_len(g.G) + 1));
+    LTRY(P->alloc(&P->status, STATUS_WORDS));
     // deconvolution factors and kernel tables
     P->qK = m * TAY_S + 1;
     P->qQ = 2 * m * TAY_S + 1;
     for (int t = 0; t < d; ++t) {
-        TRY(P->alloc(&P->D64[t], g.M[t]));
-        if (P->prec == INFFT_F32) TRY(P->alloc(&P->D32[t], g.M[t]));
-        TRY(P->alloc(&P->Ktab[t], (int64_t)(P->qK + 1) * TAY_NC));
-        TRY(P->alloc(&P->Qtab[t], (int64_t)(P->qQ + 1) * TAY_NC));
-        launch_deconv_table(g.M[t], g.Ms[t], m, g.b, P->D64[t], P->D32[t], P->stream);
+        LTRY(P->alloc(&P->D64[t], g.M[t]));
+        if (P->prec == INFFT_F32) LTRY(P->alloc(&P->D32[t], g.M[t]));
+        LTRY(P->alloc(&P->Ktab[t], (int64_t)(P->qK + 1) * TAY_NC));
+        LTRY(P->alloc(&P->Qtab[t], (int64_t)(P->qQ + 1) * TAY_NC));
         if (P->inv_kernel == INFFT_KERNEL_DIRICHLET) {
-            std::vector<double> h64(g.M[t], 1.0 / (double)g.Ms[t]);
-            h64[0] = 0.0;   // k = -M/2
-            std::vector<float> h32(h64.begin(), h64.end());
-            TRY(P->alloc(&P->Di64[t], g.M[t]));
-            HIP_TRY(hipMemcpy(P->Di64[t], h64.data(), sizeof(double) * g.M[t], hipMemcpyHostToDevice));
-            if (P->prec == INFFT_F32) {
-                TRY(P->alloc(&P->Di32[t], g.M[t]));
-                HIP_TRY(hipMemcpy(P->Di32[t], h32.data(), sizeof(float) * g.M[t], hipMemcpyHostToDevice));
-            }
+            LTRY(P->alloc(&P->Di64[t], g.M[t]));
+            if (P->prec == INFFT_F32) LTRY(P->alloc(&P->Di32[t], g.M[t]));
         } else {
             P->Di64[t] = P->D64[t];
             P->Di32[t] = P->D32[t];
         }
-        launch_taylor_table(g.M[t], g.Ms[t], P->Di64[t], 1, P->qK, P->Ktab[t], P->stream);
-        launch_taylor_table(g.M[t], g.Ms[t], P->Di64[t], 2, P->qQ, P->Qtab[t], P->stream);
-        if (hipGetLastError() != hipSuccess) TRY(fail(INFFT_EDEVICE, "table kernels failed to launch"));
     }
     if (d == 1) {
-        TRY(P->alloc(&P->Kstab, (int64_t)(P->qK + 1) * TAY_NC));
-        TRY(P->alloc(&P->Qstab, (int64_t)(P->qQ + 1) * TAY_NC));
-        launch_taylor_table_sym(g.M[0], g.Ms[0], P->Di64[0], 1, P->qK, P->Kstab, P->stream);
-        launch_taylor_table_sym(g.M[0], g.Ms[0], P->Di64[0], 2, P->qQ, P->Qstab, P->stream);
-        if (hipGetLastError() != hipSuccess) TRY(fail(INFFT_EDEVICE, "table kernels failed to launch"));
+        LTRY(P->alloc(&P->Kstab, (int64_t)(P->qK + 1) * TAY_NC));
+        LTRY(P->alloc(&P->Qstab, (int64_t)(P->qQ + 1) * TAY_NC));
     }
-    // FFT twiddles
+    // FFT twiddles (filled by plan_setup)
+    const int cap = fft_capacity(P->prec == INFFT_F64);
     for (int t = 0; t < d; ++t) {
         if (g.Ms[t] <= cap) {
-            TRY(ensure_tw(P, g.Ms[t]));
+            LTRY(reserve_tw(P, g.Ms[t]));
         } else {
-            TRY(ensure_tw(P, n1_split));
-            TRY(ensure_tw(P, g.Ms[t] / n1_split));
+            LTRY(reserve_tw(P, S.n1_split));
+            LTRY(reserve_tw(P, g.Ms[t] / S.n1_split));
             int64_t Bsz = 1;   // power of two near sqrt(M_sigma): the split of a twiddle exponent is a shift
             while (Bsz * Bsz < g.Ms[t]) Bsz *= 2;
             P->split_lo.n = Bsz;
-            P->split_hi.n = n1_split;  // remembered sub-length of the first pass
+            P->split_hi.n = S.n1_split;  // remembered sub-length of the first pass
             const int64_t nhi = (g.Ms[t] + Bsz - 1) / Bsz;
-            TRY(P->alloc(&P->split_lo.t64, Bsz));
-            TRY(P->alloc(&P->split_hi.t64, nhi));
+            LTRY(P->alloc(&P->split_lo.t64, Bsz));
+            LTRY(P->alloc(&P->split_hi.t64, nhi));
             if (P->prec == INFFT_F32) {
-                TRY(P->alloc(&P->split_lo.t32, Bsz));
-                TRY(P->alloc(&P->split_hi.t32, nhi));
+                LTRY(P->alloc(&P->split_lo.t32, Bsz));
+                LTRY(P->alloc(&P->split_hi.t32, nhi));
             }
-            launch_twiddles_strided(g.Ms[t], Bsz, 1, P->split_lo.t64, P->split_lo.t32, P->stream);
-            launch_twiddles_strided(g.Ms[t], nhi, Bsz, P->split_hi.t64, P->split_hi.t32, P->stream);
         }
     }
-    // window polynomials
+    // window polynomials (coefficients fitted here, uploaded by plan_setup)
     {
         const int nc = P->prec == INFFT_F32 ? WPoly<float>::NC : WPoly<double>::NC;
-        const std::vector<long double> cf = window_poly_coeffs(m, (long double)M_PI * (2.0L - 1.0L / sigma), nc);
+        P->wpoly_host = window_poly_coeffs(m, (long double)M_PI * (2.0L - 1.0L / S.sigma), nc);
         if (P->prec == INFFT_F32) {
-            std::vector<float> h(cf.begin(), cf.end());
-            float* d = nullptr;
-            TRY(P->alloc(&d, (int64_t)h.size()));
-            if (hipMemcpy(d, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
-                TRY(fail(INFFT_EDEVICE, "uploading the window polynomials failed"));
-            P->g.wpoly = d;
+            float* dptr = nullptr;
+            LTRY(P->alloc(&dptr, (int64_t)P->wpoly_host.size()));
+            P->g.wpoly = dptr;
         } else {
-            std::vector<double> h(cf.begin(), cf.end());
-            double* d = nullptr;
-            TRY(P->alloc(&d, (int64_t)h.size()));
-            if (hipMemcpy(d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
-                TRY(fail(INFFT_EDEVICE, "uploading the window polynomials failed"));
-            P->g.wpoly = d;
+            double* dptr = nullptr;
+            LTRY(P->alloc(&dptr, (int64_t)P->wpoly_host.size()));
+            P->g.wpoly = dptr;
         }
     }
     // grids, halos, B_opt, solver lists
@@ -1177,18 +1395,18 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
     P->hrs0 = ntiles * w2 * (d == 2 ? g.TS[1] : 1);
     P->hrs1 = d == 2 ? ntiles * g.TS[0] * w2 : 0;
     P->hrs01 = d == 2 ? ntiles * w2 * w2 : 0;
-    for (int k = 0; k < nslots; ++k) {
+    for (int k = 0; k < S.nslots; ++k) {
         char* tmp = nullptr;
         infft_plan_s::Slot sl{};
-        TRY(P->alloc(&tmp, (int64_t)cs * g.G * P->max_rhs));
+        LTRY(P->alloc(&tmp, (int64_t)cs * g.G * P->max_rhs));
         sl.grid = tmp;
-        TRY(P->alloc(&tmp, (int64_t)cs * g.G * P->max_rhs));
+        LTRY(P->alloc(&tmp, (int64_t)cs * g.G * P->max_rhs));
         sl.grid2 = tmp;
-        TRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs0, 1) * P->max_rhs));
+        LTRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs0, 1) * P->max_rhs));
         sl.h0 = tmp;
-        TRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs1, 1) * P->max_rhs));
+        LTRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs1, 1) * P->max_rhs));
         sl.h1 = tmp;
-        TRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs01, 1) * P->max_rhs));
+        LTRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(P->hrs01, 1) * P->max_rhs));
         sl.h01 = tmp;
         P->slots.push_back(sl);
     }
@@ -1201,36 +1419,211 @@ int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma,
         const int nt = g.ntile[0] * g.ntile[1];
         P->spwork.chunk = 128;
         P->spwork.cap = (int)(nt + N / P->spwork.chunk + 1);
-        TRY(P->alloc(&P->spwork.nchunk, nt));
-        TRY(P->alloc(&P->spwork.items, P->spwork.cap));
-        TRY(P->alloc(&P->spwork.total, 1));
-        TRY(P->alloc(&P->sp_offs, nt));
-        TRY(P->alloc(&P->sp_bsum, scan_blocksum_len(nt)));
+        LTRY(P->alloc(&P->spwork.nchunk, nt));
+        LTRY(P->alloc(&P->spwork.items, P->spwork.cap));
+        LTRY(P->alloc(&P->spwork.total, 1));
+        LTRY(P->alloc(&P->sp_offs, nt));
+        LTRY(P->alloc(&P->sp_bsum, scan_blocksum_len(nt)));
     }
     P->rchunk = spread_rhs_chunk(g);
-    TRY(P->alloc(&P->B64, (int64_t)T * N));
-    if (P->prec == INFFT_F32) TRY(P->alloc(&P->B32, (int64_t)T * N));
-    TRY(P->alloc(&P->lists, 2 * g.G));
-    TRY(P->alloc(&P->lcount, 4));
+    LTRY(P->alloc(&P->B64, (int64_t)T * N));
+    if (P->prec == INFFT_F32) LTRY(P->alloc(&P->B32, (int64_t)T * N));
+    LTRY(P->alloc(&P->lists, 2 * g.G));
+    LTRY(P->alloc(&P->lcount, 4));
     // records: one per block of each solve tier (first tier G/128 blocks at most, the others capped)
-    TRY(P->alloc(&P->stat_rec, (g.G / 64 + 8192) * 5));
+    LTRY(P->alloc(&P->stat_rec, (g.G / 64 + 8192) * 5));
+    // coefficient buffer of the autotuner (max_rhs x prod(M))
+    {
+        char* tmp = nullptr;
+        LTRY(P->alloc(&tmp, (int64_t)cs * g.P * P->max_rhs));
+        P->tune_buf = tmp;
+    }
+    if (P->ws_mode) {
+        // workspace plans: everything later calls need is placed now
+        LTRY(P->alloc(&P->big_n, g.G));
+        for (BigSched& bs : P->big_sched) {
+            LTRY(P->alloc(&bs.slot, g.G));
+            LTRY(P->alloc(&bs.flag, 2));
+        }
+        const int64_t lb = (int64_t)(S.o.large_mib > 0 ? S.o.large_mib : 256) << 20;
+        char* tmp = nullptr;
+        LTRY(P->alloc(&tmp, lb));
+        P->large_arena = tmp;
+        P->large_arena_bytes = lb;
+        if (S.o.ansatz1) {
+            LTRY(P->alloc(&P->a1_buf, a1_work_elems(g)));
+            P->a1_cap = a1_work_elems(g);
+            PlanSpec in1{}, in2{};
+            const InnerSpec s1 = a1_symbol_spec(g);
+            LTRY(plan_validate(1, &s1.M, s1.N, s1.sigma, s1.m, &s1.o, in1));
+            size_t b1 = 0;
+            LTRY(plan_measure(in1, &b1));
+            LTRY(P->alloc(&tmp, (int64_t)b1));
+            P->a1_ws[0] = tmp;
+            P->a1_ws_bytes[0] = b1;
+            if (P->prec != INFFT_F64) {
+                const InnerSpec s2 = a1_twin_spec(g, S.sigma, P->inv_kernel);
+                LTRY(plan_validate(1, &s2.M, s2.N, s2.sigma, s2.m, &s2.o, in2));
+                size_t b2 = 0;
+                LTRY(plan_measure(in2, &b2));
+                LTRY(P->alloc(&tmp, (int64_t)b2));
+                P->a1_ws[1] = tmp;
+                P->a1_ws_bytes[1] = b2;
+            }
+        }
+    }
+#undef LTRY
+    return INFFT_OK;
+}
+
+// Fills the node-independent tables (deconvolution factors, kernel Taylor tables, twiddles, window
+// polynomials), reads the ridge's scale and runs the node preprocessing for x.
+int plan_setup(infft_plan_s* P, const PlanSpec& S, const double* x) {
+    const Geo& g = P->g;
+    const int d = g.d, m = g.m;
+    int rc;
+    for (int t = 0; t < d; ++t) {
+        launch_deconv_table(g.M[t], g.Ms[t], m, g.b, P->D64[t], P->D32[t], P->stream);
+        if (P->inv_kernel == INFFT_KERNEL_DIRICHLET) {
+            std::vector<double> h64(g.M[t], 1.0 / (double)g.Ms[t]);
+            h64[0] = 0.0;   // k = -M/2
+            std::vector<float> h32(h64.begin(), h64.end());
+            HIP_TRY(hipMemcpy(P->Di64[t], h64.data(), sizeof(double) * g.M[t], hipMemcpyHostToDevice));
+            if (P->prec == INFFT_F32)
+                HIP_TRY(hipMemcpy(P->Di32[t], h32.data(), sizeof(float) * g.M[t], hipMemcpyHostToDevice));
+        }
+        launch_taylor_table(g.M[t], g.Ms[t], P->Di64[t], 1, P->qK, P->Ktab[t], P->stream);
+        launch_taylor_table(g.M[t], g.Ms[t], P->Di64[t], 2, P->qQ, P->Qtab[t], P->stream);
+        if (hipGetLastError() != hipSuccess) return fail(INFFT_EDEVICE, "table kernels failed to launch");
+    }
+    if (d == 1) {
+        launch_taylor_table_sym(g.M[0], g.Ms[0], P->Di64[0], 1, P->qK, P->Kstab, P->stream);
+        launch_taylor_table_sym(g.M[0], g.Ms[0], P->Di64[0], 2, P->qQ, P->Qstab, P->stream);
+        if (hipGetLastError() != hipSuccess) return fail(INFFT_EDEVICE, "table kernels failed to launch");
+    }
+    for (const TwTable& t : P->tw) launch_twiddles(t.n, t.t64, t.t32, P->stream);
+    if (P->split_lo.t64) {
+        const int64_t Ms = g.Ms[0], Bsz = P->split_lo.n;
+        const int64_t nhi = (Ms + Bsz - 1) / Bsz;
+        launch_twiddles_strided(Ms, Bsz, 1, P->split_lo.t64, P->split_lo.t32, P->stream);
+        launch_twiddles_strided(Ms, nhi, Bsz, P->split_hi.t64, P->split_hi.t32, P->stream);
+    }
+    LAUNCH_CHECK();
+    if (P->prec == INFFT_F32) {
+        std::vector<float> h(P->wpoly_host.begin(), P->wpoly_host.end());
+        if (hipMemcpy((void*)P->g.wpoly, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(INFFT_EDEVICE, "uploading the window polynomials failed");
+    } else {
+        std::vector<double> h(P->wpoly_host.begin(), P->wpoly_host.end());
+        if (hipMemcpy((void*)P->g.wpoly, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(INFFT_EDEVICE, "uploading the window polynomials failed");
+    }
     // ridge: lambda = rho * (diagonal of G_l) = rho * prod_t M_sigma_t Q_t(0)
     HIP_TRY(hipStreamSynchronize(P->stream));
     double q0 = 1.0;
     for (int t = 0; t < d; ++t) {
         double2 v;
         if (hipMemcpy(&v, P->Qtab[t], sizeof(v), hipMemcpyDeviceToHost) != hipSuccess)
-            TRY(fail(INFFT_EDEVICE, "reading the kernel table failed"));
+            return fail(INFFT_EDEVICE, "reading the kernel table failed");
         q0 *= v.x * (double)g.Ms[t];
     }
     P->lam = P->rho * q0;
     if (d == 1 && hipMemcpy(&P->dM, P->Di64[0], sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-        TRY(fail(INFFT_EDEVICE, "reading the deconvolution table failed"));
-    TRY(set_nodes_impl(P, x));
-    if (hipStreamSynchronize(P->stream) != hipSuccess) TRY(fail(INFFT_EDEVICE, "plan set-up failed on the device"));
-#undef TRY
+        return fail(INFFT_EDEVICE, "reading the deconvolution table failed");
+    if ((rc = set_nodes_impl(P, x))) return rc;
+    if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(INFFT_EDEVICE, "plan set-up failed on the device");
+    (void)S;
+    return INFFT_OK;
+}
+
+infft_plan_s* plan_new(const PlanSpec& S, void* stream) {
+    infft_plan_s* P = new infft_plan_s();
+    P->g = S.g;
+    P->prec = S.o.precision;
+    P->max_rhs = S.o.max_rhs;
+    P->rho = S.o.rho;
+    P->sigma = S.sigma;
+    P->stream = (hipStream_t)stream;
+    P->inv_kernel = S.o.inverse_kernel;
+    return P;
+}
+
+// Bytes of device memory a workspace plan of this specification occupies.
+int plan_measure(const PlanSpec& S, size_t* bytes) {
+    infft_plan_s* P = plan_new(S, nullptr);
+    P->ws_mode = true;
+    P->measure = true;
+    P->ws_size = SIZE_MAX;
+    int rc = plan_layout(P, S);
+    *bytes = P->ws_used;
+    delete P;
+    return rc;
+}
+
+// A plan on a caller's workspace (or, with workspace == nullptr, on its own allocations).
+int plan_create(infft_plan* out, const PlanSpec& S, const double* x, void* workspace, size_t workspace_bytes,
+                void* stream) {
+    infft_plan_s* P = plan_new(S, stream);
+    if (workspace) {
+        P->ws_mode = true;
+        P->ws_base = (char*)workspace;
+        P->ws_size = workspace_bytes;
+    }
+    int rc = plan_layout(P, S);
+    if (rc == INFFT_OK) rc = plan_setup(P, S, x);
+    if (rc) {
+        delete P;
+        return rc;
+    }
     *out = P;
     return INFFT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nfft_plan(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma, int m, const double* x,
+              const infft_options* opts, void* stream) {
+    g_err.clear();
+    if (!out) return fail(INFFT_EINVAL, "out is null");
+    *out = nullptr;
+    if (!x) return fail(INFFT_EINVAL, "x is null");
+    PlanSpec S;
+    int rc = plan_validate(d, M, N, sigma, m, opts, S);
+    if (rc) return rc;
+    if (S.o.large_mib || S.o.ansatz1) return fail(INFFT_EINVAL, "large_mib and ansatz1 are options of workspace plans");
+    return plan_create(out, S, x, nullptr, 0, stream);
+}
+
+int nfft_plan_workspace_bytes(int d, const int64_t* M, int64_t N, double sigma, int m, const infft_options* opts,
+                              size_t* bytes) {
+    g_err.clear();
+    if (!bytes) return fail(INFFT_EINVAL, "bytes is null");
+    *bytes = 0;
+    PlanSpec S;
+    int rc = plan_validate(d, M, N, sigma, m, opts, S);
+    if (rc) return rc;
+    return plan_measure(S, bytes);
+}
+
+int nfft_plan_ws(infft_plan* out, int d, const int64_t* M, int64_t N, double sigma, int m, const double* x,
+                 const infft_options* opts, void* workspace, size_t workspace_bytes, void* stream) {
+    g_err.clear();
+    if (!out) return fail(INFFT_EINVAL, "out is null");
+    *out = nullptr;
+    if (!x) return fail(INFFT_EINVAL, "x is null");
+    if (!workspace) return fail(INFFT_EINVAL, "workspace is null");
+    if ((uintptr_t)workspace % WS_ALIGN) return fail(INFFT_EINVAL, "workspace must be %d-byte aligned", WS_ALIGN);
+    PlanSpec S;
+    int rc = plan_validate(d, M, N, sigma, m, opts, S);
+    if (rc) return rc;
+    size_t need = 0;
+    if ((rc = plan_measure(S, &need))) return rc;
+    if (workspace_bytes < need)
+        return fail(INFFT_ENOMEM, "workspace of %zu bytes is smaller than the %zu bytes the plan needs",
+                    workspace_bytes, need);
+    return plan_create(out, S, x, workspace, workspace_bytes, stream);
 }
 
 int nfft_set_nodes(infft_plan p, const double* x) {
@@ -1343,15 +1736,17 @@ int nfft_adjoint(infft_plan p, const void* f, void* h, int nrhs) {
 int infft_precompute_B(infft_plan p) {
     if (!p) return fail(INFFT_EINVAL, "null plan");
     if (p->batch) return batch_precompute(p);
-    // The pass for problems beyond the register tiers reads their sizes back to the host; under
-    // graph capture it cannot run, and such problems are counted as oversized (zero columns).
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    HIP_TRY(hipStreamIsCapturing(p->stream, &cs));
-    const bool capturing = cs != hipStreamCaptureStatusNone;
+    {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIP_TRY(hipStreamIsCapturing(p->stream, &cs));
+        if (cs != hipStreamCaptureStatusNone && !p->big_sched[0].built)
+            return fail(INFFT_ESTATE, "infft_precompute_B under graph capture replays the pass for large local "
+                        "problems recorded by the last call outside capture, and there is none yet");
+    }
     const Geo& g = p->g;
     const int64_t TN = (int64_t)p->taps() * g.N;
     p->bopt_ready = false;
-    launch_solve_reset(p->status, p->lcount, p->stream);
+    launch_solve_reset(p->status, p->lcount, p->stat_rec, p->stream);
     if (g.d == 2) {
         // 1-D tiers write every entry of B_opt themselves (zeros where no problem reaches)
         launch_fill_bytes0(p->B64, TN * (int64_t)sizeof(double2), p->stream);
@@ -1363,7 +1758,7 @@ int infft_precompute_B(infft_plan p) {
     a.B32 = p->B32;
     a.status = p->status;
     a.stat_rec = p->stat_rec;
-    a.stat_off = 0;
+    a.stat_off = 1;   // record 0: the large-problem guard
     int* listA = p->lists;
     int* listB = p->lists + g.G;
     const int* last_list;
@@ -1412,17 +1807,12 @@ int infft_precompute_B(infft_plan p) {
         last_list = listB;
         last_count = p->lcount + 1;
     }
-    if (capturing) {
-        a.out_list = nullptr;
-        a.out_count = nullptr;
-    }
     a.stat_off += launch_solve_tier(g, p->nd, kt, a, g.d == 1 ? 64 : 32, p->stream);
     LAUNCH_CHECK();
+    // problems beyond the register tiers: recorded outside graph capture, replayed under it
     int stat_off = a.stat_off;
-    if (!capturing) {
-        int rc = solve_large(p, kt, last_list, last_count, stat_off);
-        if (rc) return rc;
-    }
+    int rc = solve_large(p, kt, last_list, last_count, stat_off);
+    if (rc) return rc;
     p->stat_nrec = stat_off;   // folded into the status block by nfft_plan_status
     p->bopt_kind = 0;
     p->bopt_ready = true;
@@ -1443,17 +1833,21 @@ int infft_precompute_Bstar(infft_plan p) {
     const int M = g.M[0], Ms = g.Ms[0], m = g.m;
     const int nd_all = 2 * m + 1;
     hipStream_t s = p->stream;
+    if (p->ws_mode && !p->a1_ws[0])
+        return fail(INFFT_ESTATE, "a workspace plan needs the ansatz1 option for infft_precompute_Bstar");
     p->bopt_ready = false;
+    // inner plans: on their own allocations, or on the parts of a workspace plan's workspace that
+    // nfft_plan_ws placed for them
+    auto make_inner = [&](const InnerSpec& is, int k, infft_plan* q) {
+        if (p->ws_mode)
+            return nfft_plan_ws(q, 1, &is.M, is.N, is.sigma, is.m, p->nd.xw, &is.o, p->a1_ws[k], p->a1_ws_bytes[k], s);
+        return nfft_plan(q, 1, &is.M, is.N, is.sigma, is.m, p->nd.xw, &is.o, s);
+    };
     // Toeplitz symbol P(q), |q| < M: adjoint NFFT of ones at bandwidth 2M, sigma 2 and the largest
     // cut-off (FP64 accuracy whatever the plan's own m and sigma)
     if (!p->a1_pplan) {
-        infft_options o;
-        infft_default_options(&o);
-        o.precision = INFFT_F64;
-        const int64_t M2 = 2 * (int64_t)M;
-        const int m2 = std::min<int>(MAX_M_CUT, (int)(2 * M2 - 2) / 2);
         infft_plan q = nullptr;
-        if ((rc = nfft_plan(&q, 1, &M2, g.N, 2.0, m2, p->nd.xw, &o, s))) return rc;
+        if ((rc = make_inner(a1_symbol_spec(g), 0, &q))) return rc;
         p->a1_pplan = q;
     } else if ((rc = set_nodes_impl(p->a1_pplan, p->nd.xw))) {
         return rc;
@@ -1462,13 +1856,8 @@ int infft_precompute_Bstar(infft_plan p) {
     infft_plan_s* F = p;
     if (p->prec != INFFT_F64) {
         if (!p->a1_fplan) {
-            infft_options o;
-            infft_default_options(&o);
-            o.precision = INFFT_F64;
-            o.inverse_kernel = p->inv_kernel;
-            const int64_t Mv = M;
             infft_plan q = nullptr;
-            if ((rc = nfft_plan(&q, 1, &Mv, 1, p->sigma, m, p->nd.xw, &o, s))) return rc;
+            if ((rc = make_inner(a1_twin_spec(g, p->sigma, p->inv_kernel), 1, &q))) return rc;
             p->a1_fplan = q;
         }
         F = p->a1_fplan;
@@ -1481,8 +1870,8 @@ int infft_precompute_Bstar(infft_plan p) {
     // and the kernel and is kept; V [2m+1][Ms]; the FFT intermediate [2m+1][Ms]; the products
     // [npair][2m+1][Ms] (first call only); h [2M], bands [2][M], ones [N]
     const int64_t rows = nd_all;
-    const int64_t need = (rows * (3 + 2 * npair)) * Ms + 4 * (int64_t)M + g.N;
-    const bool fresh = need > p->a1_cap;
+    const int64_t need = a1_work_elems(g);
+    const bool fresh = need > p->a1_cap || (p->ws_mode && !p->a1_R_ready);
     if ((rc = p->grow(&p->a1_buf, p->a1_cap, need))) return rc;
     if (fresh) p->a1_R_ready = false;
     double2* S = p->a1_buf;
@@ -1684,6 +2073,130 @@ int infft_get_B(infft_plan p, void* rows) {
     return INFFT_OK;
 }
 
+// Serialised B_opt: a header with the plan's parameters, the wrapped nodes in caller order and
+// the rows of B_opt in caller order (the layout of infft_get_B).
+struct ExportHeader {
+    char magic[8];
+    int32_t version;
+    int32_t d;
+    int64_t M[2];
+    int64_t N;
+    double sigma;
+    int32_t m;
+    int32_t inverse_kernel;
+    int32_t bopt_kind;
+    int32_t taps;
+    double rho;
+};
+
+static_assert(sizeof(ExportHeader) == 72, "the exported header is 72 bytes");
+
+static const char kExportMagic[8] = {'I', 'N', 'F', 'F', 'T', 'B', 'O', 'P'};
+
+static size_t export_bytes(const infft_plan_s* p) {
+    return sizeof(ExportHeader) + (size_t)p->g.N * p->g.d * sizeof(double) +
+           (size_t)p->g.N * p->taps() * sizeof(double2);
+}
+
+int infft_plan_export(infft_plan p, void* host_buf, size_t* bytes) {
+    if (!p || !bytes) return fail(INFFT_EINVAL, "null argument");
+    if (p->batch) return fail(INFFT_EINVAL, "infft_plan_export takes a single-problem plan");
+    const size_t need = export_bytes(p);
+    if (!host_buf) {
+        *bytes = need;
+        return INFFT_OK;
+    }
+    if (*bytes < need) return fail(INFFT_EINVAL, "buffer of %zu bytes, %zu needed", *bytes, need);
+    if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_plan_export before infft_precompute_B");
+    const Geo& g = p->g;
+    const int T = p->taps();
+    ExportHeader h{};
+    std::memcpy(h.magic, kExportMagic, 8);
+    h.version = 1;
+    h.d = g.d;
+    h.M[0] = g.M[0];
+    h.M[1] = g.d == 2 ? g.M[1] : 0;
+    h.N = g.N;
+    h.sigma = p->sigma;
+    h.m = g.m;
+    h.inverse_kernel = p->inv_kernel;
+    h.bopt_kind = p->bopt_kind;
+    h.taps = T;
+    h.rho = p->rho;
+    // the caller's buffer is only byte aligned as far as this layout goes: complex entries are
+    // handled as pairs of doubles and copied bytewise
+    char* out = (char*)host_buf;
+    std::memcpy(out, &h, sizeof(h));
+    char* xo = out + sizeof(h);
+    char* rows = xo + sizeof(double) * g.N * g.d;
+    std::vector<double> Bs((size_t)2 * T * g.N), R((size_t)2 * T * g.N);
+    std::vector<int> perm(g.N);
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    HIP_TRY(hipMemcpy(xo, p->nd.xw, sizeof(double) * g.N * g.d, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(Bs.data(), p->B64, sizeof(double) * Bs.size(), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(perm.data(), p->nd.perm, sizeof(int) * g.N, hipMemcpyDeviceToHost));
+    // internal layout [tap][sorted node] -> caller order [node][tap]
+    for (int tau = 0; tau < T; ++tau)
+        for (int64_t q = 0; q < g.N; ++q) {
+            const size_t dst = 2 * ((size_t)perm[q] * T + tau), src = 2 * ((size_t)tau * g.N + q);
+            R[dst] = Bs[src];
+            R[dst + 1] = Bs[src + 1];
+        }
+    std::memcpy(rows, R.data(), sizeof(double) * R.size());
+    *bytes = need;
+    return INFFT_OK;
+}
+
+int infft_plan_import(infft_plan p, const void* host_buf, size_t bytes) {
+    if (!p || !host_buf) return fail(INFFT_EINVAL, "null argument");
+    if (p->batch) return fail(INFFT_EINVAL, "infft_plan_import takes a single-problem plan");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(p->stream, &cs));
+    if (cs != hipStreamCaptureStatusNone) return fail(INFFT_ESTATE, "infft_plan_import cannot run under graph capture");
+    const Geo& g = p->g;
+    const int T = p->taps();
+    if (bytes < sizeof(ExportHeader)) return fail(INFFT_EINVAL, "buffer too short for a header");
+    ExportHeader h;
+    std::memcpy(&h, host_buf, sizeof(h));
+    if (std::memcmp(h.magic, kExportMagic, 8) || h.version != 1) return fail(INFFT_EINVAL, "not an exported B_opt");
+    if (h.d != g.d || h.M[0] != g.M[0] || (g.d == 2 && h.M[1] != g.M[1]) || h.N != g.N || h.m != g.m ||
+        h.sigma != p->sigma || h.inverse_kernel != p->inv_kernel || h.taps != T || h.rho != p->rho ||
+        (h.bopt_kind != 0 && h.bopt_kind != 1))
+        return fail(INFFT_EINVAL, "the exported B_opt was made for other plan parameters");
+    if (bytes < export_bytes(p)) return fail(INFFT_EINVAL, "buffer of %zu bytes, %zu needed", bytes, export_bytes(p));
+    // bytewise copies out of the caller's buffer (its layout does not align complex entries)
+    const char* xi = (const char*)host_buf + sizeof(h);
+    std::vector<double> R((size_t)2 * T * g.N), Bs((size_t)2 * T * g.N);
+    std::memcpy(R.data(), xi + sizeof(double) * g.N * g.d, sizeof(double) * R.size());
+    // the nodes, staged in B_opt's storage, through the node preprocessing (which is deterministic,
+    // so the sorted order and the lists I(l) are those the B_opt was computed on)
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    HIP_TRY(hipMemcpy(p->B64, xi, sizeof(double) * g.N * g.d, hipMemcpyHostToDevice));
+    int rc = set_nodes_impl(p, (const double*)p->B64);
+    if (rc) return rc;
+    std::vector<int> perm(g.N);
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    HIP_TRY(hipMemcpy(perm.data(), p->nd.perm, sizeof(int) * g.N, hipMemcpyDeviceToHost));
+    for (int tau = 0; tau < T; ++tau)
+        for (int64_t q = 0; q < g.N; ++q) {
+            const size_t dst = 2 * ((size_t)tau * g.N + q), src = 2 * ((size_t)perm[q] * T + tau);
+            Bs[dst] = R[src];
+            Bs[dst + 1] = R[src + 1];
+        }
+    HIP_TRY(hipMemcpy(p->B64, Bs.data(), sizeof(double) * Bs.size(), hipMemcpyHostToDevice));
+    if (p->B32) {
+        std::vector<float> b32(Bs.size());
+        for (size_t i = 0; i < Bs.size(); ++i) b32[i] = (float)Bs[i];
+        HIP_TRY(hipMemcpy(p->B32, b32.data(), sizeof(float) * b32.size(), hipMemcpyHostToDevice));
+    }
+    launch_status_init(p->status, 1, p->stream);
+    LAUNCH_CHECK();
+    p->stat_nrec = 0;
+    p->bopt_kind = h.bopt_kind;
+    p->bopt_ready = true;
+    return INFFT_OK;
+}
+
 int nfft_plan_status(infft_plan p, infft_status* out) {
     if (!p || !out) return fail(INFFT_EINVAL, "null argument");
     if (p->batch) {
@@ -1748,49 +2261,52 @@ int infft_autotune(infft_plan p, int reps) {
     grid_holds(p, 0, true);
     if (reps < 1) reps = 10;
     const Geo& g = p->g;
-    const int cap = fft_capacity(p->prec == INFFT_F64);
     const int R = p->max_rhs;
-    void* tmp = nullptr;
+    void* tmp = p->tune_buf;   // max_rhs x prod(M) coefficients, placed with the plan
     const size_t tbytes = (size_t)R * (size_t)g.P * p->csize();
-    HIP_TRY(hipMalloc(&tmp, tbytes));
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        (void)hipFree(tmp);
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(INFFT_EDEVICE, "hipEventCreate failed");
-    }
     int rc = INFFT_OK;
     if (hipMemsetAsync(tmp, 0, tbytes, p->stream) != hipSuccess) rc = fail(INFFT_EDEVICE, "hipMemsetAsync failed");
+    const bool f32 = p->prec == INFFT_F32;
+    auto launch = [&](const FftStep& st) {
+        FftIO io{};
+        io.in = st.in_buf == 0 ? tmp : st.in_buf == 1 ? p->grid : p->grid2;
+        io.out = st.out_buf == 0 ? tmp : st.out_buf == 1 ? p->grid : p->grid2;
+        io.D0 = f32 ? (const void*)p->D32[0] : (const void*)p->D64[0];
+        io.D1 = f32 ? (const void*)p->D32[1] : (const void*)p->D64[1];
+        io.h0 = p->h0;
+        io.h1 = p->h1;
+        io.h01 = p->h01;
+        io.halo_rs0 = p->hrs0;
+        io.halo_rs1 = p->hrs1;
+        io.halo_rs01 = p->hrs01;
+        if (f32) launch_fft_pass<float>(st.pass, io, g, st.ld, st.st, p->stream);
+        else launch_fft_pass<double>(st.pass, io, g, st.ld, st.st, p->stream);
+    };
+    // Each direction is timed as it runs: its passes in sequence, each consuming the last one's
+    // output, `reps` times back to back.  Every pair of row counts (1, 2, 4, 8, 16 sub-transforms
+    // per workgroup, as far as LDS holds them) is tried; timing a pass alone, repeated on the same
+    // data, favoured packings that lose once the pass reads what the previous kernel wrote.
     for (int dir = 0; dir < 2 && rc == INFFT_OK; ++dir) {
-        for (int k = 0; k < 2 && rc == INFFT_OK; ++k) {
-            float best = 1e30f;
-            int best_rows = 0;
-            for (int rows = 1; rows <= 16 && rc == INFFT_OK; rows *= 2) {
-                p->fft_rows[dir][k] = rows;
+        float best = 1e30f;
+        int best_r[2] = {0, 0};
+        for (int ra = 1; ra <= 16 && rc == INFFT_OK; ra *= 2) {
+            for (int rb = 1; rb <= 16 && rc == INFFT_OK; rb *= 2) {
+                p->fft_rows[dir][0] = ra;
+                p->fft_rows[dir][1] = rb;
                 if ((rc = build_schedule(p, R, p->to_grid, p->to_coeff))) break;
                 const std::vector<FftStep>& v = dir == 0 ? p->to_grid : p->to_coeff;
-                if ((int)v.size() <= k) break;
-                const FftStep& st = v[k];
-                if (st.pass.rows != rows) continue;   // beyond the LDS capacity for this length
-                if (rows > 1 && rows > st.pass.nseq) break;
-                FftIO io{};
-                io.in = st.in_buf == 0 ? tmp : st.in_buf == 1 ? p->grid : p->grid2;
-                io.out = st.out_buf == 0 ? tmp : st.out_buf == 1 ? p->grid : p->grid2;
-                const bool f32 = p->prec == INFFT_F32;
-                io.D0 = f32 ? (const void*)p->D32[0] : (const void*)p->D64[0];
-                io.D1 = f32 ? (const void*)p->D32[1] : (const void*)p->D64[1];
-                io.h0 = p->h0;
-                io.h1 = p->h1;
-                io.h01 = p->h01;
-                io.halo_rs0 = p->hrs0;
-                io.halo_rs1 = p->hrs1;
-                io.halo_rs01 = p->hrs01;
-                auto launch = [&]() {
-                    if (f32) launch_fft_pass<float>(st.pass, io, g, st.ld, st.st, p->stream);
-                    else launch_fft_pass<double>(st.pass, io, g, st.ld, st.st, p->stream);
-                };
-                launch();   // warm-up
+                if (v.empty()) break;
+                bool valid = v[0].pass.rows == ra && (ra == 1 || ra <= v[0].pass.nseq);
+                if (v.size() > 1) valid = valid && v[1].pass.rows == rb && (rb == 1 || rb <= v[1].pass.nseq);
+                else valid = valid && rb == 1;
+                if (!valid) continue;
+                for (const FftStep& st : v) launch(st);   // warm-up
                 (void)hipEventRecord(e0, p->stream);
-                for (int i = 0; i < reps; ++i) launch();
+                for (int i = 0; i < reps; ++i)
+                    for (const FftStep& st : v) launch(st);
                 (void)hipEventRecord(e1, p->stream);
                 if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
                     rc = fail(INFFT_EDEVICE, "autotune launch failed");
@@ -1800,16 +2316,17 @@ int infft_autotune(infft_plan p, int reps) {
                 (void)hipEventElapsedTime(&ms, e0, e1);
                 if (ms < best) {
                     best = ms;
-                    best_rows = rows;
+                    best_r[0] = ra;
+                    best_r[1] = rb;
                 }
             }
-            p->fft_rows[dir][k] = best_rows;
         }
+        p->fft_rows[dir][0] = best_r[0];
+        p->fft_rows[dir][1] = best_r[1];
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(p->stream);
-    (void)hipFree(tmp);
     if (rc == INFFT_OK) rc = build_schedule(p, R, p->to_grid, p->to_coeff);
     return rc;
 }

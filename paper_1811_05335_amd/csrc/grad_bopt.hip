@@ -286,6 +286,7 @@ template <typename R, int D>
 __global__ void __launch_bounds__(BIG_TPB) k_big_grad(Geo g, BigArgs a, KTabDev kt, BoptGradArgs ga,
                                                       const int* __restrict__ perm) {
     using C = cx<R>;
+    if (a.stale && *a.stale) return;
     const BigProb P = a.probs[blockIdx.x];
     if (a.fail[P.id]) return;   // uniform: a failed problem has no usable factor
     const double2* A = a.A + P.off;

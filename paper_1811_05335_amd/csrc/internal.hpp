@@ -254,6 +254,8 @@ struct BigArgs {
     double2* mr;   // member -> right-hand side, then solution
     double2* mb;   // member -> its B_opt entry (node gradient pass)
     int* fail;     // per problem id: non-positive pivot
+    const int* stale;   // device flag: the recorded problems do not match the current lists, so
+                        // every large-problem kernel returns at once (nullptr: never)
 };
 
 constexpr int BIG_TPB = 256;   // threads of the large-problem kernels
@@ -403,7 +405,7 @@ void launch_cell_sort(const Geo& g, NodesDev nd, int* counts, int* fill, const i
                       hipStream_t s);
 void launch_export_B(const Geo& g, const int* perm, const double2* B, double2* rows, hipStream_t s);
 void launch_status_init(long long* status, int keep_node_words, hipStream_t s);
-void launch_solve_reset(long long* status, int* lcount, hipStream_t s);
+void launch_solve_reset(long long* status, int* lcount, long long* rec0, hipStream_t s);
 void launch_nodes_reset(long long* status, int* counts, int64_t ncounts, int* fill, int64_t nfill, int* lcount,
                         hipStream_t s);
 
@@ -520,6 +522,23 @@ void launch_big_fwd(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t 
 void launch_big_bwd(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t s);
 void launch_big_write(const Geo& g, BigArgs a, int nprob, double2* B64, float2* B32, hipStream_t s);
 void launch_big_stats(const int* fail, int n, int nmin, int nmax, long long* rec, hipStream_t s);
+// slot[probs[i].l] = i for the recorded problems (slot cleared to -1 beforehand)
+void launch_big_slots(const BigProb* probs, int count, int* slot, hipStream_t s);
+// Compares the device list of problems beyond the register tiers (count on the device) with the
+// record of generation `gen`: stale[1] must still hold gen (no newer record), the count must match
+// and every listed grid index be recorded with the same |I(l)|; any difference sets stale[0]
+// (cleared by the caller beforehand).
+void launch_big_check(const Geo& g, NodesDev nd, const int* list, const int* count, const int* slot,
+                      const BigProb* probs, int rec_count, int gen, int* stale, hipStream_t s);
+// A record without problems, replayed: if the tiers list any problem or *gen_dev is no longer
+// gen, zero the listed problems' B_opt entries (1-D) and count them as oversized in statistics
+// record 0 (one launch).
+void launch_big_guard_empty(const Geo& g, NodesDev nd, const int* list, const int* count, const int* gen_dev, int gen,
+                            double2* B64, float2* B32, long long* rec0, long long* status, hipStream_t s);
+// When *stale: zero the B_opt entries of every listed problem (1-D; 2-D columns start zeroed) and
+// count the listed problems as oversized in statistics record 0.
+void launch_big_zero_stale(const Geo& g, NodesDev nd, const int* list, const int* count, const int* stale,
+                           double2* B64, float2* B32, long long* rec0, long long* status, hipStream_t s);
 
 // ansatz1.hip: per-node optimisation of B^* (FP64)
 void launch_a1_bands(double2* out, int M, int nb, hipStream_t s);

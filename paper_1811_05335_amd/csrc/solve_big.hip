@@ -97,6 +97,7 @@ void launch_big_count(const Geo& g, NodesDev nd, const int* list, int count, int
 // Members of one problem (cells in order, nodes of a cell in sorted order), then per member the
 // tap index, z = tau - u per dimension and r = conj K(z).
 __global__ void __launch_bounds__(CELL_TPB) k_big_setup(Geo g, NodesDev nd, KTabDev kt, BigArgs a) {
+    if (a.stale && *a.stale) return;
     __shared__ int s_base[MAX_CELLS + 1];
     const BigProb P = a.probs[blockIdx.x];
     const int ncell = num_cells(g);
@@ -152,6 +153,7 @@ void launch_big_setup(const Geo& g, NodesDev nd, KTabDev kt, BigArgs a, int npro
 
 // Tile (I, J), J <= I, of the lower triangle of G + lambda I.
 __global__ void __launch_bounds__(BIG_TPB) k_big_gram(Geo g, KTabDev kt, BigArgs a, const int4* __restrict__ tasks) {
+    if (a.stale && *a.stale) return;
     __shared__ double2 s_zi[BIG_NB];
     const int4 t = tasks[blockIdx.x];
     const BigProb P = a.probs[t.x];
@@ -186,6 +188,7 @@ void launch_big_gram(const Geo& g, KTabDev kt, BigArgs a, const int4* tasks, int
 // (X[i][j] = (delta_ij - sum_{j<=q<i} L[i][q] X[q][j]) / L[i][i]).  A non-positive pivot marks
 // the problem failed (its later steps run on zeros and its solution is not written).
 __global__ void __launch_bounds__(BIG_TPB) k_big_potrf(BigArgs a, int k) {
+    if (a.stale && *a.stale) return;
     // L in the lower triangle of T; the inverse X, conjugated, in its strictly upper triangle
     // (T[j][i] = conj X[i][j], i > j), so that two workgroups fit a CU
     __shared__ double2 T[BIG_NB][BIG_NB + 1];
@@ -278,6 +281,7 @@ struct Tile4 {
 
 // Panel block (I, k): A[I][k] <- A[I][k] X^*, X = L_kk^{-1}.
 __global__ void __launch_bounds__(BIG_TPB) k_big_trsm(BigArgs a, const int4* __restrict__ tasks, int k) {
+    if (a.stale && *a.stale) return;
     constexpr int KC = 16;
     __shared__ double2 sA[KC][BIG_NB + 1];   // [q][row]
     __shared__ double2 sX[KC][BIG_NB + 1];   // [q][col]
@@ -334,6 +338,7 @@ void launch_big_trsm(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(BIG_TPB) k_big_herk(BigArgs a, const int4* __restrict__ tasks, int k) {
+    if (a.stale && *a.stale) return;
     constexpr int KC = 16;
     __shared__ double2 sI[KC][BIG_NB + 1];
     __shared__ double2 sJ[KC][BIG_NB + 1];
@@ -432,6 +437,7 @@ void launch_big_herk(BigArgs a, const int4* tasks, int ntask, int k, hipStream_t
 // to its threads after each barrier.
 __global__ void __launch_bounds__(BIG_TPB) k_big_solve(Geo g, BigArgs a, double2* __restrict__ B64,
                                                        float2* __restrict__ B32) {
+    if (a.stale && *a.stale) return;
     const BigProb P = a.probs[blockIdx.x];
     const int fl = a.fail[P.id];   // 1: non-positive pivot (zero column written), 2: no members known
     if (fl == 2) return;
@@ -482,6 +488,7 @@ __device__ inline void big_block_vec(const double2* D, int64_t ld, int nk, const
 }
 
 __global__ void __launch_bounds__(BIG_TPB) k_big_fwd(BigArgs a, const int4* __restrict__ tasks, int k) {
+    if (a.stale && *a.stale) return;
     constexpr int NP = BIG_TPB / BIG_NB;
     __shared__ double2 s_r[BIG_NB], s_y[BIG_NB];
     __shared__ double2 red[NP][BIG_NB];
@@ -517,6 +524,7 @@ __global__ void __launch_bounds__(BIG_TPB) k_big_fwd(BigArgs a, const int4* __re
 }
 
 __global__ void __launch_bounds__(BIG_TPB) k_big_bwd(BigArgs a, const int4* __restrict__ tasks, int k) {
+    if (a.stale && *a.stale) return;
     constexpr int NP = BIG_TPB / BIG_NB;
     __shared__ double2 s_v[BIG_NB], s_b[BIG_NB];
     __shared__ double2 red[NP][BIG_NB];
@@ -552,6 +560,7 @@ __global__ void __launch_bounds__(BIG_TPB) k_big_bwd(BigArgs a, const int4* __re
 // The solutions into B_opt (zeros for failed problems; nothing for problems without members).
 __global__ void __launch_bounds__(BIG_TPB) k_big_write(Geo g, BigArgs a, double2* __restrict__ B64,
                                                        float2* __restrict__ B32) {
+    if (a.stale && *a.stale) return;
     const BigProb P = a.probs[blockIdx.x];
     const int fl = a.fail[P.id];
     if (fl == 2) return;
@@ -601,6 +610,118 @@ __global__ void __launch_bounds__(256) k_big_stats(const int* fail, int n, int n
 
 void launch_big_stats(const int* fail, int n, int nmin, int nmax, long long* rec, hipStream_t s) {
     hipLaunchKernelGGL(k_big_stats, dim3(1), dim3(256), 0, s, fail, n, nmin, nmax, rec);
+}
+
+
+// ------------------------------------------------------------------ recorded problems under capture
+
+__global__ void k_big_slots(const BigProb* __restrict__ probs, int count, int* __restrict__ slot) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) slot[probs[i].l] = i;
+}
+
+void launch_big_slots(const BigProb* probs, int count, int* slot, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_big_slots, dim3((count + 255) / 256), dim3(256), 0, s, probs, count, slot);
+}
+
+constexpr int CHECK_BLOCKS = 256;
+
+__global__ void __launch_bounds__(CELL_TPB) k_big_check(Geo g, NodesDev nd, const int* __restrict__ list,
+                                                        const int* __restrict__ count, const int* __restrict__ slot,
+                                                        const BigProb* __restrict__ probs, int rec_count, int gen,
+                                                        int* __restrict__ stale) {
+    __shared__ int s_sum[CELL_TPB];
+    const int cnt = *count;
+    if (stale[1] != gen) {   // a newer record replaced the one this launch was made for
+        if (blockIdx.x == 0 && threadIdx.x == 0) stale[0] = 1;
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && cnt != rec_count) stale[0] = 1;
+    const int lim = min(cnt, rec_count);
+    for (int i = blockIdx.x; i < lim; i += gridDim.x) {
+        const int l = list[i];
+        int n = 0;
+        for (int c = threadIdx.x; c < num_cells(g); c += CELL_TPB) n += big_cell_count(g, nd, l, c);
+        s_sum[threadIdx.x] = n;
+        __syncthreads();
+        for (int w = CELL_TPB / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) s_sum[threadIdx.x] += s_sum[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const int k = slot[l];
+            if (k < 0 || k >= rec_count || probs[k].n != s_sum[0]) stale[0] = 1;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_big_check(const Geo& g, NodesDev nd, const int* list, const int* count, const int* slot,
+                      const BigProb* probs, int rec_count, int gen, int* stale, hipStream_t s) {
+    hipLaunchKernelGGL(k_big_check, dim3(CHECK_BLOCKS), dim3(CELL_TPB), 0, s, g, nd, list, count, slot, probs,
+                       rec_count, gen, stale);
+}
+
+// Zeroes the B_opt entries of the listed problems and counts them as oversized.
+// The count goes to statistics record 0, which nfft_plan_status folds into the status block, and
+// to the status word itself, which the host reads as is when it has not seen a precompute since
+// its last nfft_set_nodes (a replayed graph does not tell the host).
+__device__ inline void big_zero_listed(const Geo& g, const NodesDev& nd, const int* __restrict__ list, int cnt,
+                                       double2* __restrict__ B64, float2* __restrict__ B32, long long* rec0,
+                                       long long* status) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        rec0[4] = cnt;
+        status[ST_OVERSIZED] = cnt;
+    }
+    if (g.d != 1) return;   // 2-D columns were cleared before the tiers ran
+    for (int i = blockIdx.x; i < cnt; i += gridDim.x) {
+        const int l = list[i];
+        for (int c = 0; c < num_cells(g); ++c) {
+            int st, e;
+            bool e0, e1;
+            big_cell(g, nd, l, c, st, e, e0, e1);
+            for (int q = st + (int)threadIdx.x; q < e; q += CELL_TPB) {
+                if (!big_member(g, nd, q, e0, e1)) continue;
+                int tau = l - nd.l0s[q];
+                if (tau < 0) tau += g.Ms[0];
+                const int64_t idx = (int64_t)tau * g.N + q;
+                B64[idx] = make_double2(0.0, 0.0);
+                if (B32) B32[idx] = make_float2(0.0f, 0.0f);
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(CELL_TPB) k_big_zero_stale(Geo g, NodesDev nd, const int* __restrict__ list,
+                                                             const int* __restrict__ count,
+                                                             const int* __restrict__ stale, double2* __restrict__ B64,
+                                                             float2* __restrict__ B32, long long* rec0,
+                                                             long long* status) {
+    if (!*stale) return;
+    big_zero_listed(g, nd, list, *count, B64, B32, rec0, status);
+}
+
+__global__ void __launch_bounds__(CELL_TPB) k_big_guard_empty(Geo g, NodesDev nd, const int* __restrict__ list,
+                                                              const int* __restrict__ count,
+                                                              const int* __restrict__ gen_dev, int gen,
+                                                              double2* __restrict__ B64, float2* __restrict__ B32,
+                                                              long long* rec0, long long* status) {
+    const int cnt = *count;
+    if (cnt == 0 && *gen_dev == gen) return;
+    big_zero_listed(g, nd, list, cnt, B64, B32, rec0, status);
+}
+
+void launch_big_guard_empty(const Geo& g, NodesDev nd, const int* list, const int* count, const int* gen_dev, int gen,
+                            double2* B64, float2* B32, long long* rec0, long long* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_big_guard_empty, dim3(CHECK_BLOCKS), dim3(CELL_TPB), 0, s, g, nd, list, count, gen_dev, gen,
+                       B64, B32, rec0, status);
+}
+
+void launch_big_zero_stale(const Geo& g, NodesDev nd, const int* list, const int* count, const int* stale,
+                           double2* B64, float2* B32, long long* rec0, long long* status, hipStream_t s) {
+    hipLaunchKernelGGL(k_big_zero_stale, dim3(CHECK_BLOCKS), dim3(CELL_TPB), 0, s, g, nd, list, count, stale, B64,
+                       B32, rec0, status);
 }
 
 }  // namespace infft

@@ -29,11 +29,14 @@ class NfftPlan:
     kernel     kernel of the inverse: "window" (the NFFT's window) or "dirichlet" (Remark 3.19)
     work_slots sets of transform work buffers; `set_slot` picks one, so that transforms on different
                slots and streams may overlap
+    workspace  True: the plan lives in one torch-allocated device buffer (nfft_plan_ws), and no call
+               on it allocates device memory; large_mib and ansatz1 size its parts for large local
+               problems and for Algorithm 3.10
     """
 
     def __init__(self, M, x: torch.Tensor, sigma: float = 2.0, m: int = 4, precision: str = "f64",
                  rho: float = 1e-8, max_rhs: int = 1, tile=None, kernel: str = "window",
-                 work_slots: int = 1):
+                 work_slots: int = 1, workspace: bool = False, large_mib: int = 0, ansatz1: bool = False):
         lib = load()
         self.M = tuple(int(v) for v in (M if isinstance(M, (tuple, list)) else (M,)))
         self.d = len(self.M)
@@ -55,8 +58,18 @@ class NfftPlan:
                 o.tile[t] = int(v)
         Ms = (C.c_int64 * self.d)(*self.M)
         h = C.c_void_p()
-        check(lib.nfft_plan(C.byref(h), self.d, Ms, self.N, self.sigma, self.m, C.c_void_p(_ptr(x)),
-                            C.byref(o), C.c_void_p(_stream_handle())))
+        self._ws = None
+        if workspace:
+            o.large_mib = int(large_mib)
+            o.ansatz1 = int(bool(ansatz1))
+            nb = C.c_size_t()
+            check(lib.nfft_plan_workspace_bytes(self.d, Ms, self.N, self.sigma, self.m, C.byref(o), C.byref(nb)))
+            self._ws = torch.empty(int(nb.value), dtype=torch.uint8, device=x.device)
+            check(lib.nfft_plan_ws(C.byref(h), self.d, Ms, self.N, self.sigma, self.m, C.c_void_p(_ptr(x)),
+                                   C.byref(o), C.c_void_p(_ptr(self._ws)), nb, C.c_void_p(_stream_handle())))
+        else:
+            check(lib.nfft_plan(C.byref(h), self.d, Ms, self.N, self.sigma, self.m, C.c_void_p(_ptr(x)),
+                                C.byref(o), C.c_void_p(_stream_handle())))
         self._h = h
         self._x = x
         self.device = x.device
@@ -194,6 +207,29 @@ class NfftPlan:
         check(load().infft_get_B(self._h, C.c_void_p(_ptr(out))))
         return out
 
+    def export_B(self) -> bytes:
+        """B_opt with the parameters and nodes it belongs to, serialised (infft_plan_export)."""
+        lib = load()
+        nb = C.c_size_t()
+        check(lib.infft_plan_export(self._h, None, C.byref(nb)))
+        buf = C.create_string_buffer(int(nb.value))
+        self._sync_stream()
+        check(lib.infft_plan_export(self._h, buf, C.byref(nb)))
+        return buf.raw[: int(nb.value)]
+
+    def import_B(self, data: bytes) -> None:
+        """Loads an exported B_opt (and its nodes) into this plan (infft_plan_import)."""
+        self._sync_stream()
+        buf = C.create_string_buffer(bytes(data), len(data))
+        check(load().infft_plan_import(self._h, buf, len(data)))
+        # the plan's nodes are now the exported ones (they follow the 72-byte header)
+        import numpy as np
+        nd = self.N * self.d
+        self._x = torch.from_numpy(np.frombuffer(data, dtype=np.float64, count=nd, offset=72).copy()).reshape(
+            self.N, self.d).to(self.device)
+        self.nodes_version += 1
+        self.bopt_version = self.nodes_version
+
     def status(self) -> dict:
         st = Status()
         code = load().nfft_plan_status(self._h, C.byref(st))
@@ -229,6 +265,7 @@ class NfftPlan:
         if getattr(self, "_h", None):
             load().nfft_plan_destroy(self._h)
             self._h = None
+        self._ws = None   # a workspace plan's memory, released after the plan
 
     def __del__(self):
         try:

@@ -80,3 +80,64 @@ def test_product_path_has_no_oracle_import():
             if fn.endswith((".py", ".cpp", ".hip", ".hpp")):
                 txt = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, fn
+
+
+def _ws_bytes(lib, M, N, m=4, sigma=2.0, **opt):
+    from paper_1811_05335_amd import _lib
+    o = _lib.Options()
+    lib.infft_default_options(C.byref(o))
+    for k, v in opt.items():
+        setattr(o, k, v)
+    Ms = (C.c_int64 * len(M))(*M)
+    nb = C.c_size_t(123)
+    rc = lib.nfft_plan_workspace_bytes(len(M), Ms, N, sigma, m, C.byref(o), C.byref(nb))
+    return rc, nb.value
+
+
+def test_workspace_size_query_is_host_only_and_consistent(lib):
+    """The size query validates like nfft_plan and runs no device work, so it answers here.  The
+    size grows with every buffer it must hold: right-hand sides per pass (grids), work slots, the
+    memory kept for large local problems (exactly large_mib MiB more), the FP32 copy of B_opt, and
+    the inner plans of Algorithm 3.10."""
+    from paper_1811_05335_amd import _lib
+    rc, base = _ws_bytes(lib, (65536,), 131072, m=6, precision=_lib.INFFT_F32)
+    assert rc == 0 and base > 0
+    G, cs = 131072, 8
+    rc, r4 = _ws_bytes(lib, (65536,), 131072, m=6, precision=_lib.INFFT_F32, max_rhs=4)
+    assert rc == 0 and r4 - base >= 3 * 2 * G * cs          # two grids per slot, 3 more RHS
+    rc, s2 = _ws_bytes(lib, (65536,), 131072, m=6, precision=_lib.INFFT_F32, work_slots=2)
+    assert rc == 0 and s2 - base >= 2 * G * cs
+    rc, l8 = _ws_bytes(lib, (65536,), 131072, m=6, precision=_lib.INFFT_F32, large_mib=8)
+    rc2, l9 = _ws_bytes(lib, (65536,), 131072, m=6, precision=_lib.INFFT_F32, large_mib=9)
+    assert rc == rc2 == 0 and l9 - l8 == 1 << 20
+    rc, f64 = _ws_bytes(lib, (65536,), 131072, m=6, precision=_lib.INFFT_F64)
+    # FP32 plans hold an FP32 copy of B_opt (13 taps x N x 8 bytes); FP64 plans grids twice as large
+    assert rc == 0 and base - f64 >= 13 * 131072 * 8 - 5 * 2 * G * 8
+    rc, a1 = _ws_bytes(lib, (16384,), 4096, m=4, precision=_lib.INFFT_F32, ansatz1=1)
+    rc2, na1 = _ws_bytes(lib, (16384,), 4096, m=4, precision=_lib.INFFT_F32)
+    assert rc == rc2 == 0 and a1 > na1
+    # invalid arguments: the same messages as nfft_plan, *bytes = 0
+    rc, b = _ws_bytes(lib, (15,), 100)
+    assert rc == _lib.INFFT_EINVAL and b == 0 and "even" in lib.infft_last_error().decode()
+    rc, b = _ws_bytes(lib, (16, 16), 100, ansatz1=1)
+    assert rc == _lib.INFFT_EINVAL and "d = 1" in lib.infft_last_error().decode()
+
+
+def test_workspace_plan_rejects_bad_workspace_on_host(lib):
+    from paper_1811_05335_amd import _lib
+    h = C.c_void_p()
+    Ms = (C.c_int64 * 1)(64)
+    assert lib.nfft_plan_ws(C.byref(h), 1, Ms, 100, 2.0, 4, C.c_void_p(8), None, None, 0, None) == _lib.INFFT_EINVAL
+    assert "workspace is null" in lib.infft_last_error().decode()
+    assert lib.nfft_plan_ws(C.byref(h), 1, Ms, 100, 2.0, 4, C.c_void_p(8), None, C.c_void_p(4096 + 8), 1 << 30,
+                            None) == _lib.INFFT_EINVAL
+    assert "aligned" in lib.infft_last_error().decode()
+    assert lib.nfft_plan_ws(C.byref(h), 1, Ms, 100, 2.0, 4, C.c_void_p(8), None, C.c_void_p(4096), 1024,
+                            None) == _lib.INFFT_ENOMEM
+    assert not h.value
+    o = _lib.Options()
+    lib.infft_default_options(C.byref(o))
+    o.large_mib = 4
+    assert lib.nfft_plan(C.byref(h), 1, Ms, 100, 2.0, 4, C.c_void_p(8), C.byref(o), None) == _lib.INFFT_EINVAL
+    assert lib.infft_plan_export(None, None, None) == _lib.INFFT_EINVAL
+    assert lib.infft_plan_import(None, None, 0) == _lib.INFFT_EINVAL

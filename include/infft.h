@@ -189,6 +189,19 @@ int infft_precompute_Bstar(infft_plan p);
  * fcheck [nrhs][M...].  Returns INFFT_ESTATE before infft_precompute_B. */
 int infft_apply(infft_plan p, const void* f, void* fcheck, int nrhs);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): infft_apply with its work buffers -- two oversampled
+ * grids and the spreading halos for as many of the plan's max_rhs right-hand sides per pass as
+ * fit -- in a static device array of the library (64 MiB on each device it runs on, held until
+ * the process ends) instead of the plan's.  Allocates nothing and leaves the plan's buffers alone
+ * (the grid a preceding nfft_trafo left stays valid for nfft_grad_x_after_trafo).  Every call on a
+ * device shares that array, keeping the last call's contents: calls that overlap on one device
+ * (other streams, threads or plans) race, and the caller must order them.  The plan's device must
+ * be current (INFFT_EINVAL otherwise).  INFFT_EINVAL when one right-hand side needs more work
+ * memory than the array holds (about 2 x 8 M_sigma^d bytes for FP32 plans, 2 x 16 for FP64, plus
+ * halos in 2-D) and for batch plans; INFFT_ESTATE before infft_precompute_B. */
+int infft_apply_noalloc(infft_plan p, const void* f, void* fcheck, int nrhs);
+
 /* Adjoint of infft_apply: f = B_opt F D h (the inverse adjoint NFFT of Remark 3.24).
  * h [nrhs][M...], f [nrhs][N].  Returns INFFT_ESTATE before infft_precompute_B. */
 int infft_apply_adjoint(infft_plan p, const void* h, void* f, int nrhs);

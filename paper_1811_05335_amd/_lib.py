@@ -98,6 +98,7 @@ def load() -> C.CDLL:
         "infft_precompute_Bstar": (i32, [vp]),
         "infft_apply": (i32, [vp, vp, vp, i32]),
         "infft_apply_adjoint": (i32, [vp, vp, vp, i32]),
+        "infft_apply_noalloc": (i32, [vp, vp, vp, i32]),
         "nfft_grad_x": (i32, [vp, vp, vp, vp, i32]),
         "nfft_grad_x_after_trafo": (i32, [vp, vp, vp, i32]),
         "infft_grad_x_bopt": (i32, [vp, vp, vp, vp, i32]),

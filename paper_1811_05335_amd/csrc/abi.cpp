@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -119,6 +120,7 @@ struct infft_plan_s {
     double rho = 1e-8;
     double sigma = 2.0;
     hipStream_t stream = nullptr;
+    int device = -1;   // the device current when the plan was made
     std::vector<void*> allocs;
     int64_t bytes = 0;
     // workspace plans carve every buffer from the caller's workspace (ws_base, ws_size); a
@@ -1561,9 +1563,15 @@ int plan_measure(const PlanSpec& S, size_t* bytes) {
 }
 
 // A plan on a caller's workspace (or, with workspace == nullptr, on its own allocations).
+int static_scratch_init(int device);
 int plan_create(infft_plan* out, const PlanSpec& S, const double* x, void* workspace, size_t workspace_bytes,
                 void* stream) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int rc0 = static_scratch_init(dev);
+    if (rc0) return rc0;
     infft_plan_s* P = plan_new(S, stream);
+    P->device = dev;
     if (workspace) {
         P->ws_mode = true;
         P->ws_base = (char*)workspace;
@@ -1576,6 +1584,35 @@ int plan_create(infft_plan* out, const PlanSpec& S, const double* x, void* works
         return rc;
     }
     *out = P;
+    return INFFT_OK;
+}
+
+// ------------------------------------------------------------------ static scratch
+// Work buffers of infft_apply_noalloc, for callers that cannot allocate device memory: a file-scope
+// device array (each device the library runs on holds its own copy until the process ends).  Host
+// code never passes the array's name to a kernel: its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current (at the first plan made on
+// it) and kept in g_scratch_ptr.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+
+int static_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return fail(INFFT_EDEVICE, "device index %d out of range", device);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return INFFT_OK;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(INFFT_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[device] = ptr;
     return INFFT_OK;
 }
 
@@ -1931,6 +1968,55 @@ int infft_apply(infft_plan p, const void* f, void* fcheck, int nrhs) {
         return run_fft_batched(p, p->batch->to_coeff, nullptr, fcheck, nrhs, true);
     }
     return spread_then_coeffs(p, f, fcheck, nrhs, true);
+}
+
+int infft_apply_noalloc(infft_plan p, const void* f, void* fcheck, int nrhs) {
+    int rc = check_rhs(p, nrhs);
+    if (rc) return rc;
+    if (!f || !fcheck) return fail(INFFT_EINVAL, "null data pointer");
+    if (p->batch) return fail(INFFT_EINVAL, "infft_apply_noalloc takes a single-problem plan");
+    if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_apply_noalloc before infft_precompute_B");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != p->device) return fail(INFFT_EINVAL, "call infft_apply_noalloc with the plan's device (%d) current", p->device);
+    char* base = (char*)g_scratch_ptr[dev];
+    if (!base) return fail(INFFT_ESTATE, "the static scratch of device %d is not set up", dev);
+    // right-hand sides per pass: as many of the plan's max_rhs as two grids and the halos of that
+    // many fit into the static scratch
+    const Geo& g = p->g;
+    const size_t cs = p->csize();
+    auto al = [](size_t b) { return (b + WS_ALIGN - 1) / WS_ALIGN * WS_ALIGN; };
+    auto need = [&](int c) {
+        return 2 * al(cs * (size_t)g.G * c) + al(cs * (size_t)std::max<int64_t>(p->hrs0, 1) * c) +
+               al(cs * (size_t)std::max<int64_t>(p->hrs1, 1) * c) + al(cs * (size_t)std::max<int64_t>(p->hrs01, 1) * c);
+    };
+    int chunk = p->max_rhs;
+    while (chunk > 1 && need(chunk) > STATIC_SCRATCH_BYTES) --chunk;
+    if (need(chunk) > STATIC_SCRATCH_BYTES)
+        return fail(INFFT_EINVAL, "one right-hand side needs %zu bytes of work buffers; the static scratch holds %zu",
+                    need(1), STATIC_SCRATCH_BYTES);
+    // the modified adjoint with the plan's work buffers swapped for the static ones during the call
+    void* saved[5] = {p->grid, p->grid2, p->h0, p->h1, p->h01};
+    const int saved_rhs = p->max_rhs;
+    size_t off = 0;
+    p->grid = base + off;
+    off += al(cs * (size_t)g.G * chunk);
+    p->grid2 = base + off;
+    off += al(cs * (size_t)g.G * chunk);
+    p->h0 = base + off;
+    off += al(cs * (size_t)std::max<int64_t>(p->hrs0, 1) * chunk);
+    p->h1 = base + off;
+    off += al(cs * (size_t)std::max<int64_t>(p->hrs1, 1) * chunk);
+    p->h01 = base + off;
+    p->max_rhs = chunk;
+    rc = spread_then_coeffs(p, f, fcheck, nrhs, true);
+    p->grid = saved[0];
+    p->grid2 = saved[1];
+    p->h0 = saved[2];
+    p->h1 = saved[3];
+    p->h01 = saved[4];
+    p->max_rhs = saved_rhs;
+    return rc;
 }
 
 int infft_apply_adjoint(infft_plan p, const void* h, void* f, int nrhs) {

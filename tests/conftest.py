@@ -14,5 +14,6 @@ def pytest_configure(config):
 
 
 def pytest_collection_modifyitems(config, items):
-    # GPU tests that run the full-size workloads go last so a failure there hides nothing.
-    items.sort(key=lambda it: (1 if "full" in it.name else 0))
+    # GPU tests that run the full-size workloads go last so a failure there hides nothing, and
+    # the static-scratch entry point's file after them.
+    items.sort(key=lambda it: (2 if "test_zz_" in it.nodeid else 1 if "full" in it.name else 0))

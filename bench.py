@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--rhs", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=192, help="grid indices of the sampled oracle B solve")
+    ap.add_argument("--cpu-sample", type=int, default=48, help="grid indices of the sampled oracle B solve")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph replay")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run every call on the main stream (same as --overlap none)")
@@ -197,6 +197,9 @@ def gpu_run(precision, x, fh, gf, steps, warmup, rho, m, sigma, M, use_graph=Tru
         ms_graph = (time.perf_counter() - t0) * 1e3 / steps
         graph_host = [o.cpu().numpy() for o in gouts]
         graph_dev = max(rel(a, b) for a, b in zip(graph_host, eager_host))
+        # per replay with HIP events, warm (back to back) and with the last-level cache flushed
+        # before each replay (a 512 MiB write between replays, outside the events)
+        warm_ms, flushed_ms = replay_times(torch, graph, max(10, min(steps, 20)))
     # per kernel class: average launch duration from HIP events the library records around each
     # launch on the plan's stream (eager launches, one class at a time)
     kclass = {}
@@ -213,7 +216,34 @@ def gpu_run(precision, x, fh, gf, steps, warmup, rho, m, sigma, M, use_graph=Tru
     torch.cuda.synchronize()
     P.close()
     return dict(ms_eager=ms_eager, ms_graph=ms_graph, breakdown=st.mean_ms(), status=status, outs=eager_host,
-                rows=rows, graph_vs_eager=graph_dev, kclass=kclass, tuned=tuned)
+                rows=rows, graph_vs_eager=graph_dev, kclass=kclass, tuned=tuned,
+                replay_warm_ms=warm_ms if use_graph else None, replay_flushed_ms=flushed_ms if use_graph else None)
+
+
+FLUSH_BYTES = 512 << 20   # twice the 256 MB Infinity Cache (MALL)
+
+
+def replay_times(torch, graph, reps):
+    """Median milliseconds of one graph replay timed with events on the current stream: warm
+    (replays back to back) and flushed (a 512 MiB buffer written between replays, so the step's
+    inputs and tables come from HBM rather than the MALL)."""
+    buf = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda")
+    out = {}
+    for mode in ("warm", "flushed"):
+        ts = []
+        for _ in range(reps):
+            if mode == "flushed":
+                buf.fill_(1.0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            graph.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        out[mode] = float(np.median(ts))
+    del buf
+    return out["warm"], out["flushed"]
 
 
 def algorithmic_bytes(N, M, G, T, R, csize, wsize):
@@ -350,6 +380,40 @@ def secondary_batched(steps, warmup):
     out["nodes_per_s_trafo_plus_apply"] = N_ * R / ((out["ms_trafo"] + out["ms_apply"]) * 1e-3)
     out["config"] = dict(problems=len(Ms), sum_M=P_, sum_N=N_, rhs=R, m=m, sigma=cfg["sigma"], dtype="f32")
     B.close()
+    return out
+
+
+def secondary_rhs8(steps, warmup):
+    """The 1-D jittered workload with 8 right-hand sides (FP32): per-call graph replays and the
+    spreading kernels against their algorithmic bytes, where R amortises the node data."""
+    import torch
+    from paper_1811_05335_amd import NfftPlan
+    cfg = W.CONFIGS["c2"]
+    R, m = 8, cfg["m"]
+    x, fh = W.make_problem(cfg, seed=0, rhs=R)
+    N, M = cfg["N"], cfg["M"][0]
+    G = 2 * M
+    xd = torch.from_numpy(x).cuda()
+    fhd = torch.from_numpy(W.round_to(fh, "f32")).to(torch.complex64).cuda()
+    P = NfftPlan(cfg["M"], xd, sigma=cfg["sigma"], m=m, precision="f32", rho=cfg["rho"], max_rhs=R)
+    P.autotune()
+    P.precompute_B()
+    f = P.trafo(fhd)
+    fc = P.apply(f)
+    out = {"rhs": R}
+    out["ms_trafo"] = timed_graph(torch, lambda: P.trafo(fhd), steps, warmup)
+    out["ms_adjoint"] = timed_graph(torch, lambda: P.adjoint(f), steps, warmup)
+    out["ms_apply"] = timed_graph(torch, lambda: P.apply(f), steps, warmup)
+    out["ms_apply_adjoint"] = timed_graph(torch, lambda: P.apply_adjoint(fc), steps, warmup)
+    T, c = 2 * m + 1, 8
+    # spreading: samples, stencil base and offset (or the B_opt row) read once, the grid written once
+    for name, fn, wbytes in (("spread_adjoint_kernel", lambda: P.adjoint(f), 12),
+                             ("spread_apply_kernel", lambda: P.apply(f), T * 8 + 4)):
+        ms_k, _ = class_ms(P, "spread", fn, 10)
+        b = R * N * c + N * wbytes + R * G * c
+        out[name] = dict(ms=ms_k, bytes=b, GBps=b / (ms_k * 1e-3) / 1e9, frac=b / (ms_k * 1e-3) / 1e9 / HBM_PEAK_GBS)
+    out["nodes_rhs_per_s_trafo_plus_apply"] = N * R / ((out["ms_trafo"] + out["ms_apply"]) * 1e-3)
+    P.close()
     return out
 
 
@@ -529,42 +593,69 @@ def secondary_ansatz1(steps, warmup):
     return out
 
 
-def cpu_baseline(x, fh, gf, rho, m, sigma, M, sample):
-    from oracle import bopt, grad, nfft
-
+def cpu_description():
+    """Host CPU: logical cores, model name and the thread settings the oracle runs under."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh_:
+            for ln in fh_:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     try:
         from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        pools = [{"api": d.get("internal_api"), "threads": d.get("num_threads")} for d in threadpool_info()]
     except Exception:
-        threads = 1
+        pools = []
+    return {"os_cpu_count": os.cpu_count(), "model": model, "thread_pools": pools,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS"),
+            "fft": "numpy.fft (pocketfft, one thread)"}
+
+
+def cpu_baseline(x, fh, gf, rho, m, sigma, M, sample):
+    """The FP64 oracle as it stands on this host's cores, twice: with every BLAS thread and with one.
+    The NFFT, adjoint, modified adjoint, its adjoint and the node gradient run in full; the B
+    optimisation runs the Gram route (closed-form normal equations by direct O(M) sums, then a
+    dense solve) on `sample` grid indices and its time is scaled to all of them."""
+    from contextlib import nullcontext
+    from oracle import bopt, grad, nfft
+    from threadpoolctl import threadpool_info, threadpool_limits
+
     p = nfft.Params(M, sigma, m)
-    t = {}
-    c0 = time.perf_counter()
-    f = nfft.trafo(x, fh, p)
-    t["trafo"] = time.perf_counter() - c0
-    c0 = time.perf_counter()
-    h = nfft.adjoint(x, f, p)
-    t["adjoint"] = time.perf_counter() - c0
     mem = bopt.Members(x, p)
     g = np.random.default_rng(1)
     ls = np.sort(g.choice(mem.G, size=min(sample, mem.G), replace=False))
-    c0 = time.perf_counter()
-    rows, solved = bopt.bopt_rows(x, p, rho, route="R", ls=ls, members=mem)
-    t_s = time.perf_counter() - c0
-    t["precompute_B_sampled"] = t_s
-    t["precompute_B_scaled"] = t_s * mem.G / len(ls)
-    c0 = time.perf_counter()
-    fc = bopt.apply(x, f, rows, p)
-    t["apply"] = time.perf_counter() - c0
-    c0 = time.perf_counter()
-    fa = bopt.apply_adjoint(x, fc, rows, p)
-    t["apply_adjoint"] = time.perf_counter() - c0
-    c0 = time.perf_counter()
-    gx = grad.nfft_grad_x(x, fh, gf, p)
-    t["grad_x"] = time.perf_counter() - c0
-    total = t["trafo"] + t["adjoint"] + t["precompute_B_scaled"] + t["apply"] + t["apply_adjoint"] + t["grad_x"]
-    return dict(total_s=total, parts=t, threads=threads, sample=len(ls), f=f, h=h, ls=ls, solved=solved,
-                rows=rows, gx=gx, p=p)
+    runs = {}
+    for label, nthreads in (("all_cores", None), ("one_thread", 1)):
+        with (threadpool_limits(limits=nthreads) if nthreads else nullcontext()):
+            threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+            t = {}
+            c0 = time.perf_counter()
+            f = nfft.trafo(x, fh, p)
+            t["trafo"] = time.perf_counter() - c0
+            c0 = time.perf_counter()
+            h = nfft.adjoint(x, f, p)
+            t["adjoint"] = time.perf_counter() - c0
+            c0 = time.perf_counter()
+            rows, solved = bopt.bopt_rows(x, p, rho, route="G", ls=ls, members=mem)
+            t_s = time.perf_counter() - c0
+            t["precompute_B_sampled"] = t_s
+            t["precompute_B_scaled"] = t_s * mem.G / len(ls)
+            c0 = time.perf_counter()
+            fc = bopt.apply(x, f, rows, p)
+            t["apply"] = time.perf_counter() - c0
+            c0 = time.perf_counter()
+            bopt.apply_adjoint(x, fc, rows, p)
+            t["apply_adjoint"] = time.perf_counter() - c0
+            c0 = time.perf_counter()
+            gx = grad.nfft_grad_x(x, fh, gf, p)
+            t["grad_x"] = time.perf_counter() - c0
+            total = (t["trafo"] + t["adjoint"] + t["precompute_B_scaled"] + t["apply"] + t["apply_adjoint"]
+                     + t["grad_x"])
+            runs[label] = dict(total_s=total, parts_s=t, threads=threads)
+    return dict(runs=runs, sample=len(ls), f=f, h=h, ls=ls, solved=solved, rows=rows, gx=gx, p=p)
 
 
 def main():
@@ -602,6 +693,7 @@ def main():
         out64, rows64 = r64["outs"], r64["rows"]
         log(f"[bench] FP64 graph {r64['ms_graph']} ms/step, eager {r64['ms_eager']:.3f} ms/step {r64['breakdown']}")
         res64 = dict(value=N * R / (ms64 * 1e-3), ms_per_step=ms64, eager_ms_per_step=r64["ms_eager"],
+                     replay_ms={"warm": r64["replay_warm_ms"], "mall_flushed": r64["replay_flushed_ms"]},
                      breakdown_ms=r64["breakdown"], graph_vs_eager_rel=r64["graph_vs_eager"])
 
     G = int(np.prod([int(round(sigma * v)) for v in M]))
@@ -674,6 +766,9 @@ def main():
                              "optimisation with the NFFT and the adjoint, the adjoint with the B optimisation, "
                              "the node gradient with the rest"}[ovl],
         "eager_ms_per_step": r32["ms_eager"],
+        # one replay timed with HIP events: back to back, and after a 512 MiB write that evicts the
+        # step's working set (about 90 MB) from the 256 MB Infinity Cache
+        "replay_ms": {"warm": r32["replay_warm_ms"], "mall_flushed": r32["replay_flushed_ms"]},
         "graph_vs_eager_rel": r32["graph_vs_eager"],
         "breakdown_ms": br32,
         # the metric as defined for the paper's path, N R / (t_trafo + t_apply), from the eager
@@ -687,7 +782,9 @@ def main():
     }
     if not a.no_secondary:
         log("[bench] batched workload (256 uneven 1-D problems, 8 right-hand sides)")
-        line["secondary"] = {"batched_1d": secondary_batched(max(5, a.steps // 2), 2)}
+        line["secondary"] = {"rhs8_1d": secondary_rhs8(max(10, a.steps), 3)}
+        log(f"[bench] 8 right-hand sides: {line['secondary']['rhs8_1d']}")
+        line["secondary"]["batched_1d"] = secondary_batched(max(5, a.steps // 2), 2)
         log(f"[bench] batched: {line['secondary']['batched_1d']}")
         log("[bench] polar workload (512 x 512, N = 524288)")
         line["secondary"]["polar_2d"] = secondary_polar(max(5, a.steps // 2), 2)
@@ -706,6 +803,7 @@ def main():
     if not a.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline (B optimisation sampled on {a.cpu_sample} grid indices)")
         cb = cpu_baseline(x, fh, gf, rho, m, sigma, M, a.cpu_sample)
+        allc, one = cb["runs"]["all_cores"], cb["runs"]["one_thread"]
         f_o, h_o = cb["f"], cb["h"]
         err = {
             "f32_trafo": rel(out32[0], nfft_ref(cb, x, fh32)),
@@ -720,15 +818,19 @@ def main():
             err["f32_bopt_sampled"] = rel(rows32[mask], cb["rows"][mask])
         line["rel_err"] = err
         line["cpu_baseline"] = {
-            "value": N * R / cb["total_s"],
+            "value": N * R / allc["total_s"],
             "unit": "nodes/s",
-            "cores": cb["threads"],
+            "cores": allc["threads"],
             "kind": "oracle",
-            "sample": (f"full NFFT, adjoint, modified adjoint, its adjoint and node gradient; B optimisation "
-                       f"on {cb['sample']} of {G} grid indices (route R), time scaled by {G / cb['sample']:.0f}"),
-            "parts_s": cb["parts"],
+            "sample": (f"full NFFT, adjoint, modified adjoint, its adjoint and node gradient; B optimisation by the "
+                       f"Gram route (direct O(M) kernel sums, dense solve) on {cb['sample']} of {G} grid indices, "
+                       f"time scaled by {G / cb['sample']:.0f}"),
+            "parts_s": allc["parts_s"],
+            "one_thread": {"value": N * R / one["total_s"], "threads": one["threads"], "parts_s": one["parts_s"]},
+            "host": cpu_description(),
         }
-        log(f"[bench] CPU oracle {cb['total_s']:.2f} s/step, errors {err}")
+        log(f"[bench] CPU oracle {allc['total_s']:.2f} s/step on {allc['threads']} threads, "
+            f"{one['total_s']:.2f} s on one; errors {err}")
     print(json.dumps(line))
 
 

@@ -800,7 +800,8 @@ int big_enqueue(infft_plan_s* p, BigSched& S, const KTabDev& kt, const int* list
         // do; under capture one kernel checks that the tiers still list no problem (and that the
         // record is current), else zeroes the listed problems' columns and counts them
         if (capturing && !grad) {
-            launch_big_guard_empty(g, p->nd, list, count_dev, S.flag + 1, S.gen, p->B64, p->B32, p->stat_rec, p->status, st);
+            launch_big_guard_empty(g, p->nd, list, count_dev, S.flag + 1, S.gen, p->B64, p->B32, p->stat_rec,
+                                   p->status, st);
             LAUNCH_CHECK();
         }
         return INFFT_OK;
@@ -1431,7 +1432,7 @@ int plan_layout(infft_plan_s* P, const PlanSpec& S) {
     LTRY(P->alloc(&P->B64, (int64_t)T * N));
     if (P->prec == INFFT_F32) LTRY(P->alloc(&P->B32, (int64_t)T * N));
     LTRY(P->alloc(&P->lists, 2 * g.G));
-    LTRY(P->alloc(&P->lcount, 4));
+    LTRY(P->alloc(&P->lcount, 8));   // list counters of the solver tiers
     // records: one per block of each solve tier (first tier G/128 blocks at most, the others capped)
     LTRY(P->alloc(&P->stat_rec, (g.G / 64 + 8192) * 5));
     // coefficient buffer of the autotuner (max_rhs x prod(M))
@@ -1783,7 +1784,9 @@ int infft_precompute_B(infft_plan p) {
     const Geo& g = p->g;
     const int64_t TN = (int64_t)p->taps() * g.N;
     p->bopt_ready = false;
-    launch_solve_reset(p->status, p->lcount, p->stat_rec, p->stream);
+    // no reset launch: the first tier resets statistics record 0, and the tiers clear the list
+    // counters that later launches append to once nothing reads them (the first call of a plan
+    // starts from zeros)
     if (g.d == 2) {
         // 1-D tiers write every entry of B_opt themselves (zeros where no problem reaches)
         launch_fill_bytes0(p->B64, TN * (int64_t)sizeof(double2), p->stream);
@@ -1796,6 +1799,7 @@ int infft_precompute_B(infft_plan p) {
     a.status = p->status;
     a.stat_rec = p->stat_rec;
     a.stat_off = 1;   // record 0: the large-problem guard
+    a.rec0 = p->stat_rec;
     int* listA = p->lists;
     int* listB = p->lists + g.G;
     const int* last_list;
@@ -1809,22 +1813,29 @@ int infft_precompute_B(infft_plan p) {
         a.in_count = nullptr;
         a.out_list = listA;
         a.out_count = p->lcount;
+        // counters 1 (read by the last call's 64-lane tier) and 2 (by its large-problem pass)
+        a.zero0 = p->lcount + 1;
+        a.zero1 = p->lcount + 2;
         {
             ProfScope ps(p, INFFT_K_SOLVE);  // the first tier carries nearly all problems
             a.stat_off += launch_solve_thread_1d(g, p->nd, kt, a, p->stream);
         }
         LAUNCH_CHECK();
+        a.rec0 = nullptr;
+        a.zero0 = a.zero1 = nullptr;
         a.in_list = listA;
         a.in_count = p->lcount;
         a.out_list = listB;
         a.out_count = p->lcount + 1;
         a.stat_off += launch_solve_tier(g, p->nd, kt, a, 16, p->stream);
         LAUNCH_CHECK();
-        // 1-D: a wavefront per problem up to 64 members (also under capture)
+        // 1-D: a wavefront per problem up to 64 members (also under capture); it clears counter 0,
+        // read by the 16-lane tier that has finished, for the next call's thread tier
         a.in_list = listB;
         a.in_count = p->lcount + 1;
         a.out_list = listA;
         a.out_count = p->lcount + 2;
+        a.zero0 = p->lcount;
         last_list = listA;
         last_count = p->lcount + 2;
     } else {
@@ -1832,11 +1843,14 @@ int infft_precompute_B(infft_plan p) {
         a.in_count = nullptr;
         a.out_list = listA;
         a.out_count = p->lcount;
+        a.zero0 = p->lcount + 1;   // read by the last call's large-problem pass
         {
             ProfScope ps(p, INFFT_K_SOLVE);
             a.stat_off += launch_solve_tier(g, p->nd, kt, a, 16, p->stream);
         }
         LAUNCH_CHECK();
+        a.rec0 = nullptr;
+        a.zero0 = nullptr;
         a.in_list = listA;
         a.in_count = p->lcount;
         a.out_list = listB;
@@ -1846,6 +1860,11 @@ int infft_precompute_B(infft_plan p) {
     }
     a.stat_off += launch_solve_tier(g, p->nd, kt, a, g.d == 1 ? 64 : 32, p->stream);
     LAUNCH_CHECK();
+    if (g.d == 2) {
+        // counter 0, read by the 32-lane tier just launched, is zero again for the next call
+        launch_fill_i32(p->lcount, 1, 0, p->stream);
+        LAUNCH_CHECK();
+    }
     // problems beyond the register tiers: recorded outside graph capture, replayed under it
     int stat_off = a.stat_off;
     int rc = solve_large(p, kt, last_list, last_count, stat_off);
@@ -2114,7 +2133,7 @@ int infft_grad_x_bopt(infft_plan p, const void* f, const void* gradfc, double* g
         if ((rc = schedule_for(p, c))) return rc;
         // upstream gradient on the grid: F D gfc with the inverse's D
         if ((rc = run_fft(p, p->to_grid, cptr(p, gradfc, r0 * g.P), nullptr, true))) return rc;
-        launch_fill_i32(p->lcount, 4, 0, p->stream);
+        launch_fill_i32(p->lcount, 8, 0, p->stream);
         BoptGradArgs ga{};
         ga.B64 = p->B64;
         ga.grid = p->grid;
@@ -2138,6 +2157,9 @@ int infft_grad_x_bopt(infft_plan p, const void* f, const void* gradfc, double* g
         int unused = 0;
         if ((rc = solve_large(p, kt, listB, p->lcount + 1, unused, &ga))) return rc;
     }
+    // the B optimisation expects its list counters at zero
+    launch_fill_i32(p->lcount, 8, 0, p->stream);
+    LAUNCH_CHECK();
     return INFFT_OK;
 }
 

@@ -405,7 +405,6 @@ void launch_cell_sort(const Geo& g, NodesDev nd, int* counts, int* fill, const i
                       hipStream_t s);
 void launch_export_B(const Geo& g, const int* perm, const double2* B, double2* rows, hipStream_t s);
 void launch_status_init(long long* status, int keep_node_words, hipStream_t s);
-void launch_solve_reset(long long* status, int* lcount, long long* rec0, hipStream_t s);
 void launch_nodes_reset(long long* status, int* counts, int64_t ncounts, int* fill, int64_t nfill, int* lcount,
                         hipStream_t s);
 
@@ -472,6 +471,9 @@ struct SolveArgs {
     long long* stat_rec;    // per-block statistics records [block][5]
     int stat_off;           // first record of this launch
     int tables_in_lds;      // set by the launcher (1-D plans whose kernel tables fit in LDS)
+    long long* rec0;        // first tier of a B optimisation: statistics record 0 to reset (else nullptr)
+    int* zero0;             // list counters this launch clears (workgroup 0) for a later launch: ones
+    int* zero1;             // no kernel reads any more, in place of a reset launch (nullptr: none)
 };
 int launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl, hipStream_t s);
 // One 1-D problem of a batch for the solve kernels (its own tables, lists and statistics slots).
@@ -532,7 +534,7 @@ void launch_big_check(const Geo& g, NodesDev nd, const int* list, const int* cou
                       const BigProb* probs, int rec_count, int gen, int* stale, hipStream_t s);
 // A record without problems, replayed: if the tiers list any problem or *gen_dev is no longer
 // gen, zero the listed problems' B_opt entries (1-D) and count them as oversized in statistics
-// record 0 (one launch).
+// record 0, in one launch.
 void launch_big_guard_empty(const Geo& g, NodesDev nd, const int* list, const int* count, const int* gen_dev, int gen,
                             double2* B64, float2* B32, long long* rec0, long long* status, hipStream_t s);
 // When *stale: zero the B_opt entries of every listed problem (1-D; 2-D columns start zeroed) and

@@ -50,21 +50,6 @@ void launch_status_init(long long* status, int keep_node_words, hipStream_t s) {
     hipLaunchKernelGGL(k_status_init, dim3(1), dim3(64), 0, s, status, keep_node_words);
 }
 
-// Start of a B optimisation: the solve words of the status block (the node words are kept) and
-// the four list counters, in one launch.
-__global__ void k_solve_reset(long long* st, int* lcount, long long* rec0) {
-    const int i = threadIdx.x;
-    if (i < 4) lcount[i] = 0;
-    // statistics record 0: the large-problem guard's (no problem, nothing oversized) until a
-    // replayed pass finds its record stale
-    if (i < 5) rec0[i] = (i == 0) ? -1LL : 0;
-    if (i >= STATUS_WORDS || i == ST_NONFINITE) return;
-    st[i] = (i == ST_MIN_N) ? LLONG_MAX : 0;
-}
-
-void launch_solve_reset(long long* status, int* lcount, long long* rec0, hipStream_t s) {
-    hipLaunchKernelGGL(k_solve_reset, dim3(1), dim3(64), 0, s, status, lcount, rec0);
-}
 
 // Start of the node preprocessing in one launch: the status block, the per-cell counters and fill
 // cursors, and the four list counters.
@@ -72,7 +57,7 @@ __global__ void k_nodes_reset(long long* st, int* counts, int64_t ncounts, int* 
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < ncounts) counts[i] = 0;
     if (i < nfill) fill[i] = 0;
-    if (i < 4) lcount[i] = 0;
+    if (i < 8) lcount[i] = 0;   // list counters and the tickets of the tiers that clear them
     if (i < STATUS_WORDS) st[i] = (i == ST_MIN_N) ? LLONG_MAX : 0;
 }
 

@@ -82,6 +82,21 @@ __device__ inline void write_block_stats(long long* rec, int64_t blk, unsigned l
     }
 }
 
+// First tier of a B optimisation: statistics record 0 (the large-problem guard's) back to "no
+// problem, nothing oversized".
+__device__ inline void reset_rec0(const SolveArgs& a) {
+    if (a.rec0 && blockIdx.x == 0 && threadIdx.x < 5) a.rec0[threadIdx.x] = (threadIdx.x == 0) ? -1LL : 0;
+}
+
+// The list counters start at zero without a reset launch: each launch of a B optimisation clears,
+// from workgroup 0, counters that no kernel reads any more and a later launch appends to.
+__device__ inline void clear_counters(const SolveArgs& a) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (a.zero0) *a.zero0 = 0;
+        if (a.zero1) *a.zero1 = 0;
+    }
+}
+
 __global__ void __launch_bounds__(256) k_solve_stats(const long long* rec, int nrec, long long* status) {
     __shared__ unsigned long long sh[5][256];
     unsigned long long mn = ULLONG_MAX, mx = 0, fail = 0, empty = 0, over = 0;
@@ -123,7 +138,17 @@ void launch_solve_stats(const long long* rec, int nrec, long long* status, hipSt
 }
 
 template <int D, int NL>
+__device__ inline void solve_group_body(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a);
+
+template <int D, int NL>
 __global__ void __launch_bounds__(256) k_solve(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
+    reset_rec0(a);
+    clear_counters(a);
+    solve_group_body<D, NL>(g, nd, kt, a);
+}
+
+template <int D, int NL>
+__device__ inline void solve_group_body(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a) {
     __shared__ double2 s_col[256];   // per-thread exchange slot (column broadcasts, reductions)
     __shared__ double2 s_z[256];     // z of each member (x: dimension 0, y: dimension 1)
     extern __shared__ double2 s_tab[];
@@ -510,6 +535,7 @@ __device__ inline void solve_r1_body(const Geo& g, const NodesDev& nd, const KTa
 
 template <int NL>
 __global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
+    clear_counters(a);
     solve_r1_body<NL, true>(g, nd, kt, a, blockIdx.x, gridDim.x);
 }
 
@@ -760,6 +786,8 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
 
 template <int NMAX>
 __global__ void __launch_bounds__(T1_TPB, 2) k_solve_t1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
+    reset_rec0(a);
+    clear_counters(a);
     solve_t1_body<NMAX>(g, nd, kt, a, blockIdx.x);
 }
 

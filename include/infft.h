@@ -158,8 +158,10 @@ int nfft_adjoint(infft_plan p, const void* f, void* h, int nrhs);
 
 /* Algorithm 3.17: optimises the nonzero entries of B, one regularised least-squares problem
  * per oversampled grid index l over the nodes I(l) of (3.29), solved through its normal
- * equations in FP64 on the GPU (whatever the plan precision).  Stores B_opt in the plan.
- * Problems with more than 64 members (1-D; 32 in 2-D) go to a blocked Cholesky pass.  Outside
+ * equations in FP64 on the GPU (whatever the plan precision).  Stores B_opt in the plan: FP64
+ * plans keep it in FP64; FP32 plans keep only its FP32 rounding, which infft_apply and
+ * infft_apply_adjoint read (infft_get_B, infft_plan_export and infft_grad_x_bopt recompute the FP64
+ * values first).  Problems with more than 64 members (1-D; 32 in 2-D) go to a blocked Cholesky pass.  Outside
  * graph capture the call records that pass: it reads the number and sizes of those problems back
  * (synchronising the stream), packs them into batches and uploads their task lists.  Under HIP
  * graph capture it replays the last record without touching the host: a kernel first checks that
@@ -230,20 +232,25 @@ int nfft_grad_x_after_trafo(infft_plan p, const void* gradf, double* gradx, int 
  * plan precision; gradx float64 [N][d] is overwritten.  The total node gradient of a loss through
  * both the NFFT and the modified adjoint is the sum of nfft_grad_x and this.  Synchronises the
  * stream (it reads the sizes of local problems above 32 members back, like infft_precompute_B, and
- * solves those on the blocked Cholesky pass); returns INFFT_ESTATE before infft_precompute_B, for
- * batch plans, and when B holds the result of infft_precompute_Bstar. */
+ * solves those on the blocked Cholesky pass; an FP32 plan first recomputes its FP64 B_opt, as in
+ * infft_get_B); returns INFFT_ESTATE before infft_precompute_B, for batch plans, and when B holds
+ * the result of infft_precompute_Bstar. */
 int infft_grad_x_bopt(infft_plan p, const void* f, const void* gradfc, double* gradx, int nrhs);
 
 /* Copies B_opt to `rows` (device, complex128 [N][(2m+1)^d], caller node order, tap index
  * tau flattened with the first dimension slowest; entry (j, tau) multiplies grid index
- * (l0_j + tau) mod M_sigma).  Returns INFFT_ESTATE before infft_precompute_B. */
+ * (l0_j + tau) mod M_sigma).  Returns INFFT_ESTATE before infft_precompute_B.  For an FP32 plan
+ * whose B_opt came from infft_precompute_B the FP64 values are first recomputed on the stream (the
+ * same B optimisation, so the plan's FP32 copy is their rounding; it replays the plan's record of
+ * the large-problem pass where one exists, so graphs captured on that record stay valid). */
 int infft_get_B(infft_plan p, void* rows);
 
 /* Serialises B_opt with what identifies it: plan parameters (d, M, N, sigma, m, rho, kernel of
  * the inverse, which algorithm made it), the wrapped nodes and the rows of B_opt in caller order
  * (the layout of infft_get_B), into host memory `host_buf` of *bytes bytes.  host_buf == NULL:
- * only sets *bytes to the size needed.  Synchronises the stream.  INFFT_ESTATE before a
- * precompute, INFFT_EINVAL for a short buffer or a batch plan. */
+ * only sets *bytes to the size needed.  Synchronises the stream (an FP32 plan first recomputes
+ * its FP64 B_opt, as in infft_get_B).  INFFT_ESTATE before a precompute, INFFT_EINVAL for a short
+ * buffer or a batch plan. */
 int infft_plan_export(infft_plan p, void* host_buf, size_t* bytes);
 
 /* Loads what infft_plan_export wrote (host memory) into a plan made with the same d, M, N, sigma,

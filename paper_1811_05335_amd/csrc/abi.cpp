@@ -189,8 +189,14 @@ struct infft_plan_s {
     // rows per FFT workgroup chosen by infft_autotune, per step of each direction (0: default)
     int fft_rows[2][2] = {{0, 0}, {0, 0}};
 
+    // B_opt in sorted order.  FP64 plans keep B64 only; FP32 plans apply B32, and their B
+    // optimisation writes B32 alone: the FP64 values (infft_get_B, export, the node gradient
+    // through B_opt(x)) are recomputed into B64 on demand.  Algorithm 3.10 and an import write both.
     double2* B64 = nullptr;
     float2* B32 = nullptr;
+    // the copies the tiers of the current B optimisation write (the large-problem pass reads them)
+    double2* out_B64 = nullptr;
+    float2* out_B32 = nullptr;
     int bopt_kind = 0;         // what B holds: 0 B_opt of Algorithm 3.17, 1 B_opt^* of Algorithm 3.10
     // Algorithm 3.10: inner FP64 plans and work arrays, made on first use
     infft_plan_s* a1_pplan = nullptr;   // bandwidth 2M, sigma 2: the Toeplitz symbol P(q)
@@ -800,7 +806,7 @@ int big_enqueue(infft_plan_s* p, BigSched& S, const KTabDev& kt, const int* list
         // do; under capture one kernel checks that the tiers still list no problem (and that the
         // record is current), else zeroes the listed problems' columns and counts them
         if (capturing && !grad) {
-            launch_big_guard_empty(g, p->nd, list, count_dev, S.flag + 1, S.gen, p->B64, p->B32, p->stat_rec,
+            launch_big_guard_empty(g, p->nd, list, count_dev, S.flag + 1, S.gen, p->out_B64, p->out_B32, p->stat_rec,
                                    p->status, st);
             LAUNCH_CHECK();
         }
@@ -851,14 +857,14 @@ int big_enqueue(infft_plan_s* p, BigSched& S, const KTabDev& kt, const int* list
                     launch_big_bwd(a, S.tasks + b.bseg[k], (int)(b.bseg[k + 1] - b.bseg[k]), k, st);
                     LAUNCH_CHECK();
                 }
-                launch_big_write(g, a, b.np, p->B64, p->B32, st);
+                launch_big_write(g, a, b.np, p->out_B64, p->out_B32, st);
             }
             LAUNCH_CHECK();
         }
     }
     if (grad) return INFFT_OK;   // the precompute's statistics stay as they are
     if (capturing) {
-        launch_big_zero_stale(g, p->nd, list, count_dev, S.flag, p->B64, p->B32, p->stat_rec, p->status, st);
+        launch_big_zero_stale(g, p->nd, list, count_dev, S.flag, p->out_B64, p->out_B32, p->stat_rec, p->status, st);
         LAUNCH_CHECK();
     }
     launch_big_stats(S.fail, S.count, S.nmin, S.nmax, p->stat_rec + (int64_t)stat_off * 5, st);
@@ -869,14 +875,15 @@ int big_enqueue(infft_plan_s* p, BigSched& S, const KTabDev& kt, const int* list
 
 // Local problems with more members than the register tiers hold (list of grid indices and its
 // device count from the last tier): recorded anew outside graph capture, replayed from the last
-// record under capture (INFFT_ESTATE when there is none).  Record 0 serves the precompute, record 1
-// the node gradient through B_opt(x), whose tiers pass on a different set of problems.
+// record under capture or when `replay` asks for it (INFFT_ESTATE when there is none).  Record 0
+// serves the precompute, record 1 the node gradient through B_opt(x), whose tiers pass on a
+// different set of problems.
 int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* count_dev, int& stat_off,
-                const BoptGradArgs* grad = nullptr) {
+                const BoptGradArgs* grad = nullptr, bool replay = false) {
     BigSched& S = p->big_sched[grad ? 1 : 0];
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIP_TRY(hipStreamIsCapturing(p->stream, &cs));
-    const bool capturing = cs != hipStreamCaptureStatusNone;
+    const bool capturing = replay || cs != hipStreamCaptureStatusNone;
     if (!capturing) {
         int rc = big_record(p, S, list, count_dev);
         if (rc) return rc;
@@ -1034,8 +1041,9 @@ int batch_build(infft_plan_s* P) {
         base.g = sub->g;
         base.nd = sub->nd;
         base.kt = plan_ktab(sub);
-        base.a.B64 = sub->B64;
-        base.a.B32 = sub->B32;
+        // a batch keeps both copies of B_opt (its get_B reads the FP64 one directly)
+        sub->out_B64 = base.a.B64 = sub->B64;
+        sub->out_B32 = base.a.B32 = sub->B32;
         base.a.status = sub->status;
         base.a.stat_rec = sub->stat_rec;
         int* listA = sub->lists;
@@ -1771,31 +1779,39 @@ int nfft_adjoint(infft_plan p, const void* f, void* h, int nrhs) {
     return spread_then_coeffs(p, f, h, nrhs, false);
 }
 
-int infft_precompute_B(infft_plan p) {
-    if (!p) return fail(INFFT_EINVAL, "null plan");
-    if (p->batch) return batch_precompute(p);
-    {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        HIP_TRY(hipStreamIsCapturing(p->stream, &cs));
-        if (cs != hipStreamCaptureStatusNone && !p->big_sched[0].built)
-            return fail(INFFT_ESTATE, "infft_precompute_B under graph capture replays the pass for large local "
-                        "problems recorded by the last call outside capture, and there is none yet");
-    }
+// Algorithm 3.17 for a single-problem plan into the given copies of B_opt (either may be null).
+// keep_record: replay the recorded pass for large problems where one exists, also outside
+// capture (the FP64 recompute of an FP32 plan, which must not replace the record that captured
+// graphs replay).
+static int precompute_impl(infft_plan p, double2* B64, float2* B32, bool keep_record) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(p->stream, &cs));
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    if (capturing && !p->big_sched[0].built)
+        return fail(INFFT_ESTATE, "infft_precompute_B under graph capture replays the pass for large local "
+                    "problems recorded by the last call outside capture, and there is none yet");
+    const bool replay = capturing || (keep_record && p->big_sched[0].built);
+    // Replaying a record that holds no large problem there is no pass to enqueue: the last tier
+    // itself counts a problem it cannot take as oversized and zeroes its column (which is what the
+    // replay would do with a problem the record does not hold), so no launch follows it.
+    const bool last_in_place = replay && p->big_sched[0].count == 0;
     const Geo& g = p->g;
     const int64_t TN = (int64_t)p->taps() * g.N;
     p->bopt_ready = false;
+    p->out_B64 = B64;
+    p->out_B32 = B32;
     // no reset launch: the first tier resets statistics record 0, and the tiers clear the list
     // counters that later launches append to once nothing reads them (the first call of a plan
     // starts from zeros)
     if (g.d == 2) {
         // 1-D tiers write every entry of B_opt themselves (zeros where no problem reaches)
-        launch_fill_bytes0(p->B64, TN * (int64_t)sizeof(double2), p->stream);
-        if (p->B32) launch_fill_bytes0(p->B32, TN * (int64_t)sizeof(float2), p->stream);
+        if (B64) launch_fill_bytes0(B64, TN * (int64_t)sizeof(double2), p->stream);
+        if (B32) launch_fill_bytes0(B32, TN * (int64_t)sizeof(float2), p->stream);
     }
     const KTabDev kt = plan_ktab(p);
     SolveArgs a{};
-    a.B64 = p->B64;
-    a.B32 = p->B32;
+    a.B64 = B64;
+    a.B32 = B32;
     a.status = p->status;
     a.stat_rec = p->stat_rec;
     a.stat_off = 1;   // record 0: the large-problem guard
@@ -1858,6 +1874,7 @@ int infft_precompute_B(infft_plan p) {
         last_list = listB;
         last_count = p->lcount + 1;
     }
+    if (last_in_place) a.out_list = nullptr;
     a.stat_off += launch_solve_tier(g, p->nd, kt, a, g.d == 1 ? 64 : 32, p->stream);
     LAUNCH_CHECK();
     if (g.d == 2) {
@@ -1867,12 +1884,27 @@ int infft_precompute_B(infft_plan p) {
     }
     // problems beyond the register tiers: recorded outside graph capture, replayed under it
     int stat_off = a.stat_off;
-    int rc = solve_large(p, kt, last_list, last_count, stat_off);
-    if (rc) return rc;
+    if (!last_in_place) {
+        int rc = solve_large(p, kt, last_list, last_count, stat_off, nullptr, replay);
+        if (rc) return rc;
+    }
     p->stat_nrec = stat_off;   // folded into the status block by nfft_plan_status
     p->bopt_kind = 0;
     p->bopt_ready = true;
     return INFFT_OK;
+}
+
+int infft_precompute_B(infft_plan p) {
+    if (!p) return fail(INFFT_EINVAL, "null plan");
+    if (p->batch) return batch_precompute(p);
+    return precompute_impl(p, p->prec == INFFT_F32 ? nullptr : p->B64, p->B32, false);
+}
+
+// An FP32 plan's B optimisation keeps only the FP32 copy: before the FP64 values are read, the
+// same B optimisation (deterministic, so the FP32 copy is their rounding) runs again into B64.
+static int ensure_b64(infft_plan p) {
+    if (p->batch || p->prec != INFFT_F32 || p->bopt_kind != 0) return INFFT_OK;
+    return precompute_impl(p, p->B64, nullptr, true);
 }
 
 int infft_precompute_Bstar(infft_plan p) {
@@ -2123,6 +2155,8 @@ int infft_grad_x_bopt(infft_plan p, const void* f, const void* gradfc, double* g
     if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_grad_x_bopt before infft_precompute_B");
     if (p->bopt_kind != 0)
         return fail(INFFT_ESTATE, "infft_grad_x_bopt differentiates the B_opt of infft_precompute_B, not of infft_precompute_Bstar");
+    // the gradient reads the FP64 B_opt
+    if ((rc = ensure_b64(p))) return rc;
     const Geo& g = p->g;
     launch_fill_bytes0(gradx, (int64_t)sizeof(double) * g.N * g.d, p->stream);
     const KTabDev kt = plan_ktab(p);
@@ -2176,6 +2210,8 @@ int infft_get_B(infft_plan p, void* rows) {
         }
         return INFFT_OK;
     }
+    int rc = ensure_b64(p);
+    if (rc) return rc;
     launch_export_B(p->g, p->nd.perm, p->B64, (double2*)rows, p->stream);
     LAUNCH_CHECK();
     return INFFT_OK;
@@ -2216,6 +2252,8 @@ int infft_plan_export(infft_plan p, void* host_buf, size_t* bytes) {
     }
     if (*bytes < need) return fail(INFFT_EINVAL, "buffer of %zu bytes, %zu needed", *bytes, need);
     if (!p->bopt_ready) return fail(INFFT_ESTATE, "infft_plan_export before infft_precompute_B");
+    int rc = ensure_b64(p);
+    if (rc) return rc;
     const Geo& g = p->g;
     const int T = p->taps();
     ExportHeader h{};

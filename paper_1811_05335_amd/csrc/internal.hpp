@@ -95,6 +95,13 @@ __host__ __device__ inline bool edge_tap_member(double u, int m) {
     return fabs(u - 2.0 * (double)m) <= (double)m;
 }
 
+// One entry of B_opt: the FP64 copy and the FP32 copy, each where the launch writes it (an FP32
+// plan's B optimisation writes only the FP32 copy; its FP64 values are recomputed on demand).
+__device__ inline void put_bopt(double2* B64, float2* B32, int64_t idx, double2 v) {
+    if (B64) B64[idx] = v;
+    if (B32) B32[idx] = make_float2((float)v.x, (float)v.y);
+}
+
 struct NodesDev {
     const double* xw;  // [N][d] wrapped nodes, caller order
     int* l0c;          // [N][d] stencil base mod M_sigma, caller order
@@ -465,8 +472,8 @@ struct SolveArgs {
     const int* in_count;
     int* out_list;          // problems too large for this tier
     int* out_count;
-    double2* B64;           // [T][N] sorted order
-    float2* B32;            // [T][N] sorted order (nullptr for FP64 plans)
+    double2* B64;           // [T][N] sorted order (nullptr: the B optimisation of an FP32 plan)
+    float2* B32;            // [T][N] sorted order (nullptr: FP64 plans, and an FP32 plan's FP64 recompute)
     long long* status;
     long long* stat_rec;    // per-block statistics records [block][5]
     int stat_off;           // first record of this launch

@@ -305,8 +305,7 @@ __device__ inline void solve_group_body(const Geo& g, const NodesDev& nd, const 
         // ---- scatter into B_opt ([tap][sorted node])
         if (act) {
             const int64_t idx = (int64_t)my_tau * g.N + my_p;
-            a.B64[idx] = bsol;
-            if (a.B32) a.B32[idx] = make_float2((float)bsol.x, (float)bsol.y);
+            put_bopt(a.B64, a.B32, idx, bsol);
         }
         wave_sync();
     }
@@ -350,8 +349,7 @@ __device__ inline void zero_members_1d(const Geo& g, const NodesDev& nd, int l, 
         for (int p = s + lane; p < e; p += NL) {
             int tau = l - nd.l0s[p];
             if (tau < 0) tau += Ms;
-            a.B64[(int64_t)tau * g.N + p] = make_double2(0.0, 0.0);
-            if (a.B32) a.B32[(int64_t)tau * g.N + p] = make_float2(0.0f, 0.0f);
+            put_bopt(a.B64, a.B32, (int64_t)tau * g.N + p, make_double2(0.0, 0.0));
         }
     }
 }
@@ -524,8 +522,7 @@ __device__ inline void solve_r1_body(const Geo& g, const NodesDev& nd, const KTa
 
         if (act) {
             const int64_t idx = (int64_t)tau * g.N + my_p;
-            a.B64[idx] = bsol;
-            if (a.B32) a.B32[idx] = make_float2((float)bsol.x, (float)bsol.y);
+            put_bopt(a.B64, a.B32, idx, bsol);
         }
         wave_sync();
     }
@@ -564,13 +561,27 @@ __global__ void __launch_bounds__(128) k_solve_r1_batched(const SolveJob* __rest
 // entries directly.  Problems with more members or with a member on the window edge (tap 2m
 // inside the support) are appended to the list of the group kernels.
 constexpr int T1_TPB = T1_CELLS;
+
+// 1 / sqrt(x) for x > 0: the hardware estimate and two Newton steps r <- r + r (1 - x r^2) / 2,
+// each of which squares the relative error (to within a few units in the last place).
+__device__ inline double rsqrt_refined(double x) {
+    double r = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * r, r, 1.0);
+        r = fma(0.5 * r, e, r);
+    }
+    return r;
+}
 constexpr int T1_NODECAP = 224;   // staged nodes per workgroup (density up to ~1.6 per cell)
 
 template <int NMAX>
 __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a,
                                      int blk) {
     extern __shared__ double s_tabk[];                      // Ks Taylor table
-    __shared__ double s_band[T1_NODECAP * NMAX];       // band of the workgroup's nodes
+    __shared__ double s_band[T1_NODECAP * NMAX];       // band of the workgroup's nodes, lambda on its diagonal
+    // rows of the identity in the band's row addressing: entry (i, j) of row i at i + j (NMAX - 1)
+    __shared__ double s_ident[NMAX * (NMAX - 1) + 1];
     __shared__ int s_l0[T1_NODECAP];                   // stencil base of the staged nodes
     __shared__ double s_u[T1_NODECAP];                 // offsets: t_p = l0_p + u_p
     __shared__ double2 s_phi[T1_NODECAP];              // e^{-i pi t_p / sigma}
@@ -619,8 +630,10 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
         // t_{i+d} - t_i with the integer parts subtracted exactly
         if (i + d < nnode)
             v = kt.scaleG * tay_eval_r(kt.Qs, kt.qQ, (double)(s_l0[i + d] - s_l0[i]) + (s_u[i + d] - s_u[i]));
+        if (d == 0) v += kt.lam;
         s_band[e] = v;
     }
+    for (int k = threadIdx.x; k <= NMAX * (NMAX - 1); k += blockDim.x) s_ident[k] = (k % NMAX == 0) ? 1.0 : 0.0;
     __syncthreads();
 
     const double c1 = (double)Ms * kt.dM * kt.dM;
@@ -653,8 +666,7 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
                 if (edge_tap_member(nd.us[p], g.m)) {
                     fallback = true;
                 } else {
-                    a.B64[(int64_t)w2 * g.N + p] = make_double2(0.0, 0.0);
-                    if (a.B32) a.B32[(int64_t)w2 * g.N + p] = make_float2(0.0f, 0.0f);
+                    put_bopt(a.B64, a.B32, (int64_t)w2 * g.N + p, make_double2(0.0, 0.0));
                 }
             }
         }
@@ -672,26 +684,21 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
             double sl, cl;
             sincospi((double)(((int64_t)l * g.M[0]) % (2 * (int64_t)Ms)) / (double)Ms, &sl, &cl);
             // ---- A0 = M_sigma Qs(z_j - z_i) + lambda I from the band, Cholesky A0 = L L^T; the
-            // diagonal keeps 1 / L[k][k]
+            // diagonal keeps 1 / L[k][k].  Entry (i, j <= i) of the band lies at (b0 + j) NMAX + i - j,
+            // so each row is read from one base address; rows past n read the identity instead.
             double A[NMAX * (NMAX + 1) / 2];
 #pragma unroll
             for (int i = 0; i < NMAX; ++i) {
+                const double* row = (i < n) ? s_band + b0 * NMAX + i : s_ident + i;
 #pragma unroll
-                for (int j = 0; j <= i; ++j) {
-                    double v = (i == j) ? 1.0 : 0.0;
-                    if (i < n) {
-                        v = s_band[(b0 + j) * NMAX + (i - j)];
-                        if (i == j) v += kt.lam;
-                    }
-                    A[i * (i + 1) / 2 + j] = v;
-                }
+                for (int j = 0; j <= i; ++j) A[i * (i + 1) / 2 + j] = row[j * (NMAX - 1)];
             }
             bool ok = true;
 #pragma unroll
             for (int k = 0; k < NMAX; ++k) {
                 const double piv = A[k * (k + 1) / 2 + k];
                 ok = ok && piv > 0.0;
-                const double inv = 1.0 / sqrt(piv > 0.0 ? piv : 1.0);
+                const double inv = rsqrt_refined(piv > 0.0 ? piv : 1.0);
                 A[k * (k + 1) / 2 + k] = inv;
 #pragma unroll
                 for (int i = k + 1; i < NMAX; ++i) A[i * (i + 1) / 2 + k] *= inv;
@@ -774,8 +781,7 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
                         const double2 bb = make_double2(xr[i], xi[i]);
                         const int p = i < n0 ? s0 + i : s1 + (i - n0);   // sorted position
                         const int64_t idx = (int64_t)(l - s_l0[b0 + i]) * g.N + p;
-                        a.B64[idx] = bb;
-                        if (a.B32) a.B32[idx] = make_float2((float)bb.x, (float)bb.y);
+                        put_bopt(a.B64, a.B32, idx, bb);
                     }
                 }
             }

@@ -448,8 +448,7 @@ __global__ void __launch_bounds__(BIG_TPB) k_big_solve(Geo g, BigArgs a, double2
     for (int i = threadIdx.x; i < P.n; i += BIG_TPB) {
         const int64_t idx = (int64_t)a.mtap[P.moff + i] * g.N + a.midx[P.moff + i];
         const double2 b = fl ? make_double2(0.0, 0.0) : y[i];
-        B64[idx] = b;
-        if (B32) B32[idx] = make_float2((float)b.x, (float)b.y);
+        put_bopt(B64, B32, idx, b);
     }
 }
 
@@ -568,8 +567,7 @@ __global__ void __launch_bounds__(BIG_TPB) k_big_write(Geo g, BigArgs a, double2
     for (int i = threadIdx.x; i < P.n; i += BIG_TPB) {
         const int64_t idx = (int64_t)a.mtap[P.moff + i] * g.N + a.midx[P.moff + i];
         const double2 v = fl ? make_double2(0.0, 0.0) : b[i];
-        B64[idx] = v;
-        if (B32) B32[idx] = make_float2((float)v.x, (float)v.y);
+        put_bopt(B64, B32, idx, v);
     }
 }
 
@@ -686,8 +684,7 @@ __device__ inline void big_zero_listed(const Geo& g, const NodesDev& nd, const i
                 int tau = l - nd.l0s[q];
                 if (tau < 0) tau += g.Ms[0];
                 const int64_t idx = (int64_t)tau * g.N + q;
-                B64[idx] = make_double2(0.0, 0.0);
-                if (B32) B32[idx] = make_float2(0.0f, 0.0f);
+                put_bopt(B64, B32, idx, make_double2(0.0, 0.0));
             }
         }
     }

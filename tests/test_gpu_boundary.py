@@ -227,3 +227,83 @@ def test_captured_precompute_with_large_problems(d):
     graph2.replay()
     assert P2.status()["oversized"] == nbig_y > 0
     P2.close()
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_fp32_plan_recomputes_its_fp64_bopt_and_keeps_the_record(d):
+    """An FP32 plan's B optimisation keeps only the FP32 copy of B_opt; infft_get_B recomputes the
+    FP64 values, which equal an FP64 plan's bit for bit (the same FP64 solver), without touching
+    the FP32 copy (the apply is unchanged) and without replacing the record of the large-problem
+    pass: a graph captured on that record still replays with nothing oversized."""
+    from paper_1811_05335_amd import NfftPlan
+    M, N, m, x, fh, f = clustered(d, 70 + d)
+    p = onfft.Params(M, 2.0, m)
+    assert obopt.Members(x, p).sizes().max() > (64 if d == 1 else 32)
+    f32 = dev(W.round_to(f, "f32"), "f32")
+    P64 = NfftPlan(M, nodes_dev(x), m=m, precision="f64", rho=1e-6)
+    P32 = NfftPlan(M, nodes_dev(x), m=m, precision="f32", rho=1e-6)
+    P64.precompute_B()
+    P32.precompute_B()
+    a0 = host(P32.apply(f32))
+    B = P32.get_B()
+    assert torch.equal(B, P64.get_B())
+    # the 1-D spreading is a gather (bitwise repeatable); 2-D sums with atomics
+    tol = 0.0 if d == 1 else 1e-6
+    assert rel(host(P32.apply(f32)), a0) <= tol
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        P32.precompute_B()
+    for rep in range(2):
+        gr.replay()
+        torch.cuda.synchronize()
+        assert P32.status()["oversized"] == 0 and P32.status()["failed_solves"] == 0, rep
+        assert rel(host(P32.apply(f32)), a0) <= tol, rep
+        assert torch.equal(P32.get_B(), B), rep
+    for pl in (P64, P32):
+        pl.close()
+
+
+@pytest.mark.parametrize("d", [1, 2])
+def test_captured_precompute_on_an_empty_record(d):
+    """Recorded on nodes without problems beyond the register tiers, a captured B optimisation has
+    no large-problem pass to replay: its last tier counts such a problem as oversized and zeroes its
+    column.  Nodes with large problems copied into the graph's node buffer give, on replay, zero
+    columns for exactly those problems, counted as oversized, and elsewhere the B_opt of an eager
+    precompute on the same nodes."""
+    from paper_1811_05335_amd import NfftPlan
+    M, N, m, x, fh, f = clustered(d, 80 + d)
+    p = onfft.Params(M, 2.0, m)
+    lim = 64 if d == 1 else 32
+    y = W.uniform_nodes(W.rng(90 + d), N, d)
+    assert obopt.Members(y, p).sizes().max() <= lim
+    mem = obopt.Members(x, p)
+    big = np.nonzero(mem.sizes() > lim)[0]
+    assert len(big) > 0
+    xbuf = nodes_dev(y)
+    P = NfftPlan(M, xbuf, m=m, precision="f64", rho=1e-6)
+    P.precompute_B()
+    eager_y = P.get_B().clone()
+    gr = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gr):
+        P.set_nodes(xbuf)
+        P.precompute_B()
+    for rep in range(2):
+        gr.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(P.get_B(), eager_y), rep
+        assert P.status()["oversized"] == 0, rep
+    Q = NfftPlan(M, nodes_dev(x), m=m, precision="f64", rho=1e-6)
+    Q.precompute_B()
+    ref = host(Q.get_B())
+    xbuf.copy_(nodes_dev(x))
+    gr.replay()
+    torch.cuda.synchronize()
+    assert P.status()["oversized"] == len(big)
+    rows = host(P.get_B())
+    zero = np.zeros(rows.shape, dtype=bool)
+    for l in big:
+        js, ts, _ = mem.of(int(l))
+        zero[js, ts] = True
+    assert np.all(rows[zero] == 0) and np.array_equal(rows[~zero], ref[~zero])
+    for pl in (P, Q):
+        pl.close()

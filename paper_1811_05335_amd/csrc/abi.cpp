@@ -558,9 +558,7 @@ int set_nodes_impl(infft_plan_s* P, const double* x) {
         P->nodes_zeroed = true;
     }
     launch_prep_nodes(g, x, P->nd, P->counts, P->nonfinite, s);
-    launch_exclusive_scan(P->counts, P->nd.start, g.G, P->bsum, s);
-    launch_scatter_nodes(g, P->nd, P->fill, s);
-    launch_cell_sort(g, P->nd, P->counts, P->fill, P->nonfinite, P->status, s);
+    launch_sort_nodes(g, P->nd, P->counts, P->fill, P->bsum, P->nonfinite, P->status, s);
     if (g.d == 2) launch_spread_worklist(g, P->nd, P->spwork, P->sp_offs, P->sp_bsum, s);
     LAUNCH_CHECK();
     P->bopt_ready = false;
@@ -1061,12 +1059,12 @@ int batch_build(infft_plan_s* P) {
         t2.a.in_count = sub->lcount + 1;
         t2.a.out_list = listA;
         t2.a.out_count = sub->lcount + 2;
-        t2.a.stat_off = B.t1_per_prob[i] + B.tier_blocks;
+        t2.a.stat_off = B.t1_per_prob[i] + 1;
         t3.a.in_list = listA;
         t3.a.in_count = sub->lcount + 2;
         t3.a.out_list = listB;
         t3.a.out_count = sub->lcount + 3;
-        t3.a.stat_off = B.t1_per_prob[i] + 2 * B.tier_blocks;
+        t3.a.stat_off = B.t1_per_prob[i] + 2;
         SolveJob t4 = t3;
         t4.a.out_list = nullptr;
         t4.a.out_count = nullptr;
@@ -1141,7 +1139,7 @@ int batch_precompute(infft_plan_s* P) {
     launch_solve_tier_batched(B.solve_jobs + (capturing ? 4 : 3) * (size_t)np, np, 64, B.tier_blocks, P->stream);
     LAUNCH_CHECK();
     for (int i = 0; i < np; ++i) {
-        B.subs[i]->stat_nrec = B.t1_per_prob[i] + 3 * B.tier_blocks;
+        B.subs[i]->stat_nrec = B.t1_per_prob[i] + 3;   // three list tiers: one record each
         B.subs[i]->bopt_ready = true;
     }
     if (!capturing) {

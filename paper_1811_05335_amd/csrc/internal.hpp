@@ -407,9 +407,9 @@ void launch_prep_nodes(const Geo& g, const double* x, NodesDev nd, int* counts, 
 int prep_blocks(const Geo& g);
 void launch_exclusive_scan(const int* in, int* out, int64_t n, int* blocksums, hipStream_t s);
 int64_t scan_blocksum_len(int64_t n);
-void launch_scatter_nodes(const Geo& g, NodesDev nd, int* fill, hipStream_t s);
-void launch_cell_sort(const Geo& g, NodesDev nd, int* counts, int* fill, const int* nonfinite, long long* status,
-                      hipStream_t s);
+// counting sort by cell after launch_prep_nodes (scan, scatter, in-cell sort; writes nd.start)
+void launch_sort_nodes(const Geo& g, NodesDev nd, int* counts, int* fill, int* bsum, const int* nonfinite,
+                       long long* status, hipStream_t s);
 void launch_export_B(const Geo& g, const int* perm, const double2* B, double2* rows, hipStream_t s);
 void launch_status_init(long long* status, int keep_node_words, hipStream_t s);
 void launch_nodes_reset(long long* status, int* counts, int64_t ncounts, int* fill, int64_t nfill, int* lcount,
@@ -496,7 +496,7 @@ void launch_solve_t1_batched(const SolveJob* jobs, const int2* t1_map, int t1_bl
 void launch_batch_solve_reset(const SolveJob* jobs, int njobs, hipStream_t s);
 void launch_batch_counts(const SolveJob* jobs, int njobs, int* out, hipStream_t s);
 constexpr int T1_CELLS = 128;   // cells per workgroup of the thread-per-problem tier
-// Group tier (nl = 16 or 32) over the lists of all problems; each workgroup visits every list.
+// Group tier (nl = 16, 32 or 64) over the lists of all problems of a batch as one flat list.
 void launch_solve_tier_batched(const SolveJob* jobs, int njobs, int nl, int blocks, hipStream_t s);
 int launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s);
 void launch_solve_stats(const long long* rec, int nrec, long long* status, hipStream_t s);

@@ -21,6 +21,38 @@ __global__ void k_fill_u32(uint32_t* p, int64_t n) {
         p[i] = 0u;
 }
 
+// exclusive scan over cells: blocks of SCAN_BLOCK cells, SCAN_T threads x SCAN_ITEMS each
+constexpr int SCAN_T = 256;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_BLOCK = SCAN_T * SCAN_ITEMS;
+// Up to this many scan blocks the node sort adds the block offsets inside the scatter and the
+// cell sort (each workgroup scans the block totals itself) instead of a launch of its own.
+constexpr int SCAT_MAXB = 4096;
+
+// Exclusive prefix sums of v[0..n) (n <= SCAT_MAXB) into s_out[0..n), by a workgroup of 256
+// threads, 256 values at a time.
+__device__ inline void block_prefix_small(const int* __restrict__ v, int n, int* s_out, int* s_w) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int carry = 0;
+    for (int b0 = 0; b0 < n; b0 += 256) {
+        const int i = b0 + (int)threadIdx.x;
+        const int x = i < n ? v[i] : 0;
+        int inc = x;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += t;
+        }
+        if (lane == 63) s_w[wave] = inc;
+        __syncthreads();
+        int run = inc - x + carry;
+        for (int w = 0; w < wave; ++w) run += s_w[w];
+        if (i < n) s_out[i] = run;
+        carry += s_w[0] + s_w[1] + s_w[2] + s_w[3];
+        __syncthreads();
+    }
+}
+
 static int grid_for(int64_t n, int threads, int cap = 65536) {
     int64_t b = (n + threads - 1) / threads;
     if (b < 1) b = 1;
@@ -121,12 +153,19 @@ void launch_prep_nodes(const Geo& g, const double* x, NodesDev nd, int* counts, 
         hipLaunchKernelGGL(k_prep<2>, dim3(blocks), dim3(256), 0, s, g, x, nd, counts, nonfinite);
 }
 
+// local/bsum (bsum non-null): the cell starts are the in-block exclusive sums `local` plus the
+// sum of the preceding blocks' totals, which each workgroup scans itself; else nd.start holds them.
 template <int D>
-__global__ void k_scatter(Geo g, NodesDev nd, int* __restrict__ fill) {
+__global__ void __launch_bounds__(256) k_scatter(Geo g, NodesDev nd, const int* __restrict__ local,
+                                                 const int* __restrict__ bsum, int nb, int* __restrict__ fill) {
+    __shared__ int s_off[SCAT_MAXB + 1];
+    __shared__ int s_w[4];
+    if (bsum) block_prefix_small(bsum, nb, s_off, s_w);
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= g.N) return;
     const int key = nd.key[j];
-    const int pos = nd.start[key] + atomicAdd(&fill[key], 1);
+    const int base = bsum ? local[key] + s_off[key / SCAN_BLOCK] : nd.start[key];
+    const int pos = base + atomicAdd(&fill[key], 1);
     nd.perm[pos] = (int)j;
 #pragma unroll
     for (int t = 0; t < D; ++t) {
@@ -135,13 +174,7 @@ __global__ void k_scatter(Geo g, NodesDev nd, int* __restrict__ fill) {
     }
 }
 
-void launch_scatter_nodes(const Geo& g, NodesDev nd, int* fill, hipStream_t s) {
-    const int blocks = (int)((g.N + 255) / 256);
-    if (g.d == 1)
-        hipLaunchKernelGGL(k_scatter<1>, dim3(blocks), dim3(256), 0, s, g, nd, fill);
-    else
-        hipLaunchKernelGGL(k_scatter<2>, dim3(blocks), dim3(256), 0, s, g, nd, fill);
-}
+
 
 // ------------------------------------------------------------------ deterministic order in a cell
 // The scatter places the nodes of one cell in atomic order.  Sorting each cell's range by caller
@@ -171,18 +204,31 @@ __device__ inline void refresh_sorted(NodesDev& nd, int pos) {
 // words at their initial values.
 constexpr int CELL_SORT_TPB = 256;
 
+// bsum non-null: counts holds the in-block exclusive sums of the cell counts and fill the counts
+// (the scatter's cursors); the workgroup adds its scan block's offset and writes nd.start.
 template <int D>
 __global__ void __launch_bounds__(CELL_SORT_TPB) k_cell_sort(Geo g, NodesDev nd, int* __restrict__ counts,
-                                                             int* __restrict__ fill,
+                                                             int* __restrict__ fill, const int* __restrict__ bsum,
                                                              const int* __restrict__ nonfinite, int nprep,
                                                              long long* __restrict__ status) {
     __shared__ int buf[CELL_SORT_BIG];
     __shared__ int s_big[CELL_SORT_TPB];
+    __shared__ int s_bigse[CELL_SORT_TPB][2];
     __shared__ int s_nbig;
+    __shared__ int s_off;
     __shared__ long long s_bad;
     if (threadIdx.x == 0) {
         s_nbig = 0;
         s_bad = 0;
+    }
+    if (bsum && threadIdx.x < 64) {
+        // the cells of a workgroup lie in one scan block (SCAN_BLOCK is a multiple of the TPB)
+        const int64_t b = (blockIdx.x * (int64_t)CELL_SORT_TPB) / SCAN_BLOCK;
+        int acc = 0;
+        for (int64_t i = threadIdx.x; i < b; i += 64) acc += bsum[i];
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (threadIdx.x == 0) s_off = acc;
     }
     __syncthreads();
     if (blockIdx.x == 0) {
@@ -192,12 +238,24 @@ __global__ void __launch_bounds__(CELL_SORT_TPB) k_cell_sort(Geo g, NodesDev nd,
     }
     const int64_t c = blockIdx.x * (int64_t)CELL_SORT_TPB + threadIdx.x;
     if (c < g.G) {
+        int s, e;
+        if (bsum) {
+            s = counts[c] + s_off;
+            e = s + fill[c];
+            nd.start[c] = s;
+            if (c == g.G - 1) nd.start[g.G] = e;
+        } else {
+            s = nd.start[c];
+            e = nd.start[c + 1];
+        }
         counts[c] = 0;
         fill[c] = 0;
-        const int s = nd.start[c], e = nd.start[c + 1];
         const int cnt = e - s;
         if (cnt > CELL_SORT_SMALL) {
-            s_big[atomicAdd(&s_nbig, 1)] = (int)c;
+            const int k = atomicAdd(&s_nbig, 1);
+            s_big[k] = (int)c;
+            s_bigse[k][0] = s;
+            s_bigse[k][1] = e;
         } else if (cnt > 1) {
             for (int i = s + 1; i < e; ++i) {  // insertion sort of perm[s..e)
                 const int v = nd.perm[i];
@@ -214,8 +272,7 @@ __global__ void __launch_bounds__(CELL_SORT_TPB) k_cell_sort(Geo g, NodesDev nd,
     __syncthreads();
     const int nbig = s_nbig;
     for (int b = 0; b < nbig; ++b) {
-        const int cb = s_big[b];
-        const int s = nd.start[cb], e = nd.start[cb + 1];
+        const int s = s_bigse[b][0], e = s_bigse[b][1];
         const int cnt = e - s;
         if (cnt > CELL_SORT_BIG) continue;  // left in scatter order
         int n2 = 1;
@@ -249,25 +306,12 @@ __global__ void __launch_bounds__(CELL_SORT_TPB) k_cell_sort(Geo g, NodesDev nd,
     }
 }
 
-void launch_cell_sort(const Geo& g, NodesDev nd, int* counts, int* fill, const int* nonfinite, long long* status,
-                      hipStream_t s) {
-    const unsigned blocks = (unsigned)((g.G + CELL_SORT_TPB - 1) / CELL_SORT_TPB);
-    const int np = prep_blocks(g);
-    if (g.d == 1)
-        hipLaunchKernelGGL(k_cell_sort<1>, dim3(blocks), dim3(CELL_SORT_TPB), 0, s, g, nd, counts, fill, nonfinite,
-                           np, status);
-    else
-        hipLaunchKernelGGL(k_cell_sort<2>, dim3(blocks), dim3(CELL_SORT_TPB), 0, s, g, nd, counts, fill, nonfinite,
-                           np, status);
-}
+
 
 // ------------------------------------------------------------------ exclusive scan
 // Three passes: per-block scan (256 threads x 8 items), scan of the block totals in one block,
 // then the block offsets are added.  out has n+1 entries (out[n] = total).
 
-constexpr int SCAN_T = 256;
-constexpr int SCAN_ITEMS = 8;
-constexpr int SCAN_BLOCK = SCAN_T * SCAN_ITEMS;
 
 __device__ inline int block_exclusive_scan(int v, int* sh, int* total) {
     // inclusive scan inside each wave, then across the 4 wave totals
@@ -292,7 +336,8 @@ __device__ inline int block_exclusive_scan(int v, int* sh, int* total) {
     return off + inc - v;
 }
 
-__global__ void k_scan1(const int* __restrict__ in, int* __restrict__ out, int64_t n, int* bsum) {
+// in and out may be the same array (each thread reads its items before writing them).
+__global__ void k_scan1(const int* in, int* out, int64_t n, int* bsum) {
     __shared__ int sh[SCAN_T / 64];
     const int64_t base = blockIdx.x * (int64_t)SCAN_BLOCK + threadIdx.x * SCAN_ITEMS;
     int v[SCAN_ITEMS];
@@ -338,6 +383,41 @@ void launch_exclusive_scan(const int* in, int* out, int64_t n, int* blocksums, h
     hipLaunchKernelGGL(k_scan1, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, out, n, blocksums);
     hipLaunchKernelGGL(k_scan3, dim3((unsigned)((n + 1 + 255) / 256)), dim3(256), 0, s, out, n,
                        (const int*)blocksums, nb);
+}
+
+// ------------------------------------------------------------------ the node sort
+// Counting sort of the nodes by cell from the per-cell counts of k_prep: the scan of the counts,
+// the scatter, and the sort inside each cell (which also writes nd.start and leaves counts and fill
+// cursors at zero).  Up to SCAT_MAXB scan blocks the block offsets are added inside the scatter
+// and the cell sort (three launches), else by a scan pass of their own (four).
+static_assert(SCAN_BLOCK % CELL_SORT_TPB == 0, "a cell-sort workgroup lies in one scan block");
+
+void launch_sort_nodes(const Geo& g, NodesDev nd, int* counts, int* fill, int* bsum, const int* nonfinite,
+                       long long* status, hipStream_t s) {
+    const int64_t nb = (g.G + SCAN_BLOCK - 1) / SCAN_BLOCK;
+    const bool fused = nb <= SCAT_MAXB;
+    const int* bs = nullptr;
+    if (fused) {
+        // in-block exclusive sums in place of the counts
+        hipLaunchKernelGGL(k_scan1, dim3((unsigned)nb), dim3(SCAN_T), 0, s, (const int*)counts, counts, g.G, bsum);
+        bs = bsum;
+    } else {
+        launch_exclusive_scan(counts, nd.start, g.G, bsum, s);
+    }
+    const int* local = fused ? counts : nullptr;
+    const int sblocks = (int)((g.N + 255) / 256);
+    if (g.d == 1)
+        hipLaunchKernelGGL(k_scatter<1>, dim3(sblocks), dim3(256), 0, s, g, nd, local, bs, (int)nb, fill);
+    else
+        hipLaunchKernelGGL(k_scatter<2>, dim3(sblocks), dim3(256), 0, s, g, nd, local, bs, (int)nb, fill);
+    const unsigned cblocks = (unsigned)((g.G + CELL_SORT_TPB - 1) / CELL_SORT_TPB);
+    const int np = prep_blocks(g);
+    if (g.d == 1)
+        hipLaunchKernelGGL(k_cell_sort<1>, dim3(cblocks), dim3(CELL_SORT_TPB), 0, s, g, nd, counts, fill, bs,
+                           nonfinite, np, status);
+    else
+        hipLaunchKernelGGL(k_cell_sort<2>, dim3(cblocks), dim3(CELL_SORT_TPB), 0, s, g, nd, counts, fill, bs,
+                           nonfinite, np, status);
 }
 
 // ------------------------------------------------------------------ B_opt export

@@ -361,26 +361,198 @@ __device__ inline double group_sum(double v) {
     return v;
 }
 
-// One group of NL lanes per grid index l; the group's (n x n, n <= NL) matrix lives in LDS,
-// lane i owns row i.  All loops run to the actual size n.
-// blk / nblk: this workgroup's index and the number of workgroups sharing the problem list.
-// TAB_LDS: the Q table is staged in LDS (one problem per launch) or read through the caches
-// (a batch, where every workgroup visits every problem's list).
-template <int NL, bool TAB_LDS>
-__device__ inline void solve_r1_body(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a,
-                                     int64_t blk, int64_t nblk) {
-    constexpr int GPB = 128 / NL;   // groups per block
-    constexpr int LDA = NL + 1;
-    __shared__ double s_A[GPB * NL * LDA];
-    __shared__ double s_y[3][128];
-    __shared__ double s_z[128];
-    extern __shared__ double s_tabr[];
+// Solve statistics of one lane group (accumulated by its lane 0).
+struct GroupStats {
+    unsigned long long mn = ULLONG_MAX, mx = 0, fail = 0, empty = 0, over = 0;
+};
+
+// One 1-D problem l on a group of NL lanes: lane i owns member i and row i of the real system
+// A0 (registers, lower triangle).  Each step passes the values it needs (a column of the
+// factorisation, one solution entry, partial sums) through the workgroup's exchange slots s_x
+// (three per thread), all reads of a step issued together.  A problem with more than NL members
+// goes to a.out_list, or without one is counted as oversized and its column zeroed.
+template <int NL>
+__device__ inline void r1_problem(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a, int l,
+                                  const double* __restrict__ tQ, double (*s_x)[128], double* s_z, GroupStats& st) {
     const int lane = threadIdx.x & (NL - 1);
     const int sb = threadIdx.x - lane;
     const int gbase = (threadIdx.x & 63) - lane;
     const uint64_t gmask = (NL == 64) ? ~0ull : ((1ull << NL) - 1ull);
-    double* Ag = s_A + (threadIdx.x / NL) * NL * LDA;
-    double* Ai = Ag + lane * LDA;
+    const double c1 = (double)g.Ms[0] * kt.dM * kt.dM;
+    int n = 0, my_p = 0;
+    gather_1d(g, nd, l, lane, NL, gbase, gmask, n, my_p);
+    if (n == 0) {
+        if (lane == 0) ++st.empty;
+        return;
+    }
+    if (n > NL) {
+        if (lane == 0) {
+            if (a.out_list) {
+                const int slot = atomicAdd(a.out_count, 1);
+                a.out_list[slot] = l;
+            } else {
+                ++st.over;
+            }
+        }
+        if (!a.out_list) zero_members_1d(g, nd, l, lane, NL, a);
+        return;
+    }
+    if (lane == 0) {
+        st.mn = min(st.mn, (unsigned long long)n);
+        st.mx = max(st.mx, (unsigned long long)n);
+    }
+    const bool act = lane < n;
+
+    double z = 0.0, t = 0.0, wr = 0.0, wi = 0.0;
+    int tau = 0;
+    if (act) {
+        tau = l - nd.l0s[my_p];
+        if (tau < 0) tau += g.Ms[0];
+        z = (double)tau - nd.us[my_p];
+        t = tay_eval_r(kt.Ks, kt.qK, z);
+        sincospi(z * kt.inv_sigma, &wi, &wr);
+    }
+    double ur = wr, ui = wi;
+    s_z[threadIdx.x] = z;
+    wave_sync();
+
+    // ---- row i of A0 = M_sigma Qs(z_j - z_i) + lambda I, j <= i.  GB entries at a time: their
+    // table rows are loaded before any Horner step, so the loads overlap; a scheduling barrier
+    // after each batch keeps the compiler from hoisting every batch's loads (registers).
+    constexpr int GB = NL >= 64 ? 2 : 4;
+    double A[NL];
+#pragma unroll
+    for (int j0 = 0; j0 < NL; j0 += GB) {
+        double e[GB], cf[GB][TAY_NC];
+#pragma unroll
+        for (int k = 0; k < GB; ++k) {
+            const double az = fabs(s_z[sb + j0 + k] - z);
+            int q = (int)rint(az * (double)TAY_S);
+            if (q > kt.qQ) q = kt.qQ;
+            e[k] = az - (double)q * (1.0 / TAY_S);
+            const double* c = tQ + (int64_t)q * TAY_NC;
+#pragma unroll
+            for (int p = 0; p < TAY_NC; ++p) cf[k][p] = c[p];
+        }
+#pragma unroll
+        for (int k = 0; k < GB; ++k) {
+            const int j = j0 + k;
+            double acc = cf[k][TAY_NC - 1];
+#pragma unroll
+            for (int p = TAY_NC - 2; p >= 0; --p) acc = fma(acc, e[k], cf[k][p]);
+            double v = kt.scaleG * acc;
+            if (j == lane) v += kt.lam;
+            A[j] = (act && j <= lane) ? v : 0.0;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+
+    // ---- Cholesky A0 = L L^T, lane i keeps row i of L.  Step k passes the unscaled column k; with
+    // inv = 1/sqrt(pivot) the update of row i is A[i][j] -= (A[i][k] inv^2) A[j][k] for k < j <= i.
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        if (k < n && ok) {
+            s_x[0][threadIdx.x] = A[k];
+            wave_sync();
+            const double piv = s_x[0][sb + k];
+            ok = piv > 0.0;
+            const double sq = sqrt(ok ? piv : 1.0), inv = 1.0 / sq;
+            const double lk2 = A[k] * inv * inv;
+            // column entries eight at a time (the barrier bounds how many loads are in flight, and
+            // with them the registers)
+#pragma unroll
+            for (int j = k + 1; j < NL; ++j) {
+                if (j < n) {
+                    const double raw = s_x[0][sb + j];
+                    if (lane >= j) A[j] = fma(-lk2, raw, A[j]);
+                }
+                if (((j - k) & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+            }
+            if (lane == k) A[k] = sq;
+            else if (lane > k) A[k] *= inv;
+            wave_sync();
+        }
+    }
+    if (!ok) {
+        if (lane == 0) ++st.fail;
+        return;
+    }
+
+    // ---- forward substitution L y = rhs for the three right-hand sides (Ks, Re w, Im w)
+#pragma unroll
+    for (int k = 0; k < NL; ++k) {
+        if (k < n) {
+            if (lane == k) {
+                const double iv = 1.0 / A[k];
+                t *= iv;
+                ur *= iv;
+                ui *= iv;
+            }
+            s_x[0][threadIdx.x] = t;
+            s_x[1][threadIdx.x] = ur;
+            s_x[2][threadIdx.x] = ui;
+            wave_sync();
+            if (lane > k && act) {
+                t = fma(-A[k], s_x[0][sb + k], t);
+                ur = fma(-A[k], s_x[1][sb + k], ur);
+                ui = fma(-A[k], s_x[2][sb + k], ui);
+            }
+            wave_sync();
+        }
+    }
+    // ---- backward substitution L^T x = y: x_k = (y_k - sum_{i>k} L[i][k] x_i) / L[k][k]
+#pragma unroll
+    for (int k = NL - 1; k >= 0; --k) {
+        if (k < n) {
+            const bool below = lane > k && act;
+            s_x[0][threadIdx.x] = below ? A[k] * t : 0.0;
+            s_x[1][threadIdx.x] = below ? A[k] * ur : 0.0;
+            s_x[2][threadIdx.x] = below ? A[k] * ui : 0.0;
+            wave_sync();
+            if (lane == k) {
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+                for (int j = k + 1; j < NL; ++j) {
+                    s0 += s_x[0][sb + j];
+                    s1 += s_x[1][sb + j];
+                    s2 += s_x[2][sb + j];
+                    if (((j - k) & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+                }
+                const double iv = 1.0 / A[k];
+                t = (t - s0) * iv;
+                ur = (ur - s1) * iv;
+                ui = (ui - s2) * iv;
+            }
+            wave_sync();
+        }
+    }
+
+    // ---- Sherman-Morrison combination
+    const double sdot = group_sum<NL>(act ? wr * ur + wi * ui : 0.0);        // w^* u
+    const double wtr = group_sum<NL>(act ? wr * t : 0.0);                     // Re w^* t
+    const double wti = group_sum<NL>(act ? -wi * t : 0.0);                    // Im w^* t
+    const double den = 1.0 + c1 * sdot;
+    const double cr = (kt.dM - c1 * wtr) / den, ci = (-c1 * wti) / den;
+    const double2 bsol = make_double2(t + ur * cr - ui * ci, ur * ci + ui * cr);
+
+    if (act) {
+        const int64_t idx = (int64_t)tau * g.N + my_p;
+        put_bopt(a.B64, a.B32, idx, bsol);
+    }
+    wave_sync();
+}
+
+// One group of NL lanes per grid index l (r1_problem), over a list or over all grid indices.
+// blk / nblk: this workgroup's index and the number of workgroups sharing the problem list.
+// TAB_LDS: the Q table is staged in LDS (one problem per launch) or read through the caches.
+template <int NL, bool TAB_LDS>
+__device__ inline void solve_r1_body(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a,
+                                     int64_t blk, int64_t nblk) {
+    constexpr int GPB = 128 / NL;   // groups per block
+    __shared__ double s_x[3][128];
+    __shared__ double s_z[128];
+    extern __shared__ double s_tabr[];
     const int64_t gid = (blk * (int64_t)blockDim.x + threadIdx.x) / NL;
     const int64_t ngroups = nblk * blockDim.x / NL;
     const int64_t count = a.in_list ? (int64_t)(*a.in_count) : g.G;
@@ -396,138 +568,12 @@ __device__ inline void solve_r1_body(const Geo& g, const NodesDev& nd, const KTa
         __syncthreads();
         tQ = s_tabr;
     }
-    const double c1 = (double)g.Ms[0] * kt.dM * kt.dM;
-
-    unsigned long long st_min = ULLONG_MAX, st_max = 0, st_fail = 0, st_empty = 0, st_over = 0;
-
+    GroupStats st;
     for (int64_t qi = gid; qi < count; qi += ngroups) {
         const int l = a.in_list ? a.in_list[qi] : (int)qi;
-        int n = 0, my_p = 0;
-        gather_1d(g, nd, l, lane, NL, gbase, gmask, n, my_p);
-        if (n == 0) {
-            if (lane == 0) ++st_empty;
-            continue;
-        }
-        if (n > NL) {
-            if (lane == 0) {
-                if (a.out_list) {
-                    const int slot = atomicAdd(a.out_count, 1);
-                    a.out_list[slot] = l;
-                } else {
-                    ++st_over;
-                }
-            }
-            if (!a.out_list) zero_members_1d(g, nd, l, lane, NL, a);
-            continue;
-        }
-        if (lane == 0) {
-            st_min = min(st_min, (unsigned long long)n);
-            st_max = max(st_max, (unsigned long long)n);
-        }
-        const bool act = lane < n;
-
-        double z = 0.0, t = 0.0, wr = 0.0, wi = 0.0;
-        int tau = 0;
-        if (act) {
-            tau = l - nd.l0s[my_p];
-            if (tau < 0) tau += g.Ms[0];
-            z = (double)tau - nd.us[my_p];
-            t = tay_eval_r(kt.Ks, kt.qK, z);
-            sincospi(z * kt.inv_sigma, &wi, &wr);
-        }
-        double ur = wr, ui = wi;
-        s_z[threadIdx.x] = z;
-        wave_sync();
-
-        // ---- lower triangle of A0 = M_sigma Qs(z_j - z_i) + lambda I, row i by lane i
-        if (act) {
-            for (int j = 0; j <= lane; ++j) Ai[j] = kt.scaleG * tay_eval_r(tQ, kt.qQ, s_z[sb + j] - z);
-            Ai[lane] += kt.lam;
-        }
-        wave_sync();
-
-        // ---- Cholesky A0 = L L^T in place (right-looking)
-        bool ok = true;
-        for (int k = 0; k < n; ++k) {
-            const double piv = Ag[k * LDA + k];
-            if (!(piv > 0.0)) {
-                ok = false;
-                break;
-            }
-            const double sq = sqrt(piv);
-            double lik = 0.0;
-            if (lane == k) Ai[k] = sq;
-            else if (lane > k && act) {
-                lik = Ai[k] / sq;
-                Ai[k] = lik;
-            }
-            wave_sync();
-            if (lane > k && act)
-                for (int j = k + 1; j <= lane; ++j) Ai[j] = fma(-lik, Ag[j * LDA + k], Ai[j]);
-            wave_sync();
-        }
-        if (!ok) {
-            if (lane == 0) ++st_fail;
-            wave_sync();
-            continue;
-        }
-
-        // ---- forward substitution L y = rhs (Ks, Re w, Im w)
-        for (int k = 0; k < n; ++k) {
-            if (lane == k) {
-                const double iv = 1.0 / Ai[k];
-                t *= iv;
-                ur *= iv;
-                ui *= iv;
-                s_y[0][threadIdx.x] = t;
-                s_y[1][threadIdx.x] = ur;
-                s_y[2][threadIdx.x] = ui;
-            }
-            wave_sync();
-            if (lane > k && act) {
-                const double lk = Ai[k];
-                t = fma(-lk, s_y[0][sb + k], t);
-                ur = fma(-lk, s_y[1][sb + k], ur);
-                ui = fma(-lk, s_y[2][sb + k], ui);
-            }
-        }
-        wave_sync();
-        // ---- backward substitution L^T x = y
-        for (int k = n - 1; k >= 0; --k) {
-            if (lane == k) {
-                const double iv = 1.0 / Ai[k];
-                t *= iv;
-                ur *= iv;
-                ui *= iv;
-                s_y[0][threadIdx.x] = t;
-                s_y[1][threadIdx.x] = ur;
-                s_y[2][threadIdx.x] = ui;
-            }
-            wave_sync();
-            if (lane < k) {
-                const double lk = Ag[k * LDA + lane];
-                t = fma(-lk, s_y[0][sb + k], t);
-                ur = fma(-lk, s_y[1][sb + k], ur);
-                ui = fma(-lk, s_y[2][sb + k], ui);
-            }
-        }
-
-        // ---- Sherman-Morrison combination
-        const double sdot = group_sum<NL>(act ? wr * ur + wi * ui : 0.0);        // w^* u
-        const double wtr = group_sum<NL>(act ? wr * t : 0.0);                     // Re w^* t
-        const double wti = group_sum<NL>(act ? -wi * t : 0.0);                    // Im w^* t
-        const double den = 1.0 + c1 * sdot;
-        const double cr = (kt.dM - c1 * wtr) / den, ci = (-c1 * wti) / den;
-        const double2 bsol = make_double2(t + ur * cr - ui * ci, ur * ci + ui * cr);
-
-        if (act) {
-            const int64_t idx = (int64_t)tau * g.N + my_p;
-            put_bopt(a.B64, a.B32, idx, bsol);
-        }
-        wave_sync();
+        r1_problem<NL>(g, nd, kt, a, l, tQ, s_x, s_z, st);
     }
-
-    write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, blk, st_min, st_max, st_fail, st_empty, st_over);
+    write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, blk, st.mn, st.mx, st.fail, st.empty, st.over);
 }
 
 template <int NL>
@@ -536,13 +582,88 @@ __global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt
     solve_r1_body<NL, true>(g, nd, kt, a, blockIdx.x, gridDim.x);
 }
 
-// Every workgroup walks the lists of all problems of a batch in turn.
+// A tier over the lists of all problems of a batch as one flat list: every workgroup reads the
+// problems' list counts (FLAT_JOBS at a time) and their prefix sums, and each lane group takes one
+// contiguous chunk of the concatenated lists (the problem of an entry by binary search).  A group's
+// statistics go to each problem's one record of the tier with atomics, once per problem it visited;
+// the records start neutral (k_batch_solve_reset).
+constexpr int FLAT_JOBS = 1024;
+
 template <int NL>
-__global__ void __launch_bounds__(128) k_solve_r1_batched(const SolveJob* __restrict__ jobs, int njobs) {
-    for (int j = 0; j < njobs; ++j) {
-        const SolveJob& J = jobs[j];
-        solve_r1_body<NL, false>(J.g, J.nd, J.kt, J.a, blockIdx.x, gridDim.x);
+__global__ void __launch_bounds__(128) k_solve_r1_flat(const SolveJob* __restrict__ jobs, int njobs) {
+    constexpr int PER = FLAT_JOBS / 128;
+    __shared__ double s_x[3][128];
+    __shared__ double s_z[128];
+    __shared__ int s_pre[FLAT_JOBS + 1];
+    __shared__ int s_wsum[2];
+    const int lane = threadIdx.x & (NL - 1);
+    const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / NL;
+    const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / NL;
+    for (int j0 = 0; j0 < njobs; j0 += FLAT_JOBS) {
+        const int nj = min(FLAT_JOBS, njobs - j0);
+        // exclusive prefix sums of the counts, PER consecutive problems per thread
+        int c[PER];
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int jj = threadIdx.x * PER + k;
+            c[k] = jj < nj ? *jobs[j0 + jj].a.in_count : 0;
+            sum += c[k];
+        }
+        const int wl = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        int inc = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(inc, o, 64);
+            if (wl >= o) inc += t;
+        }
+        if (wl == 63) s_wsum[wv] = inc;
         __syncthreads();
+        int run = inc - sum + (wv ? s_wsum[0] : 0);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            s_pre[threadIdx.x * PER + k] = run;
+            run += c[k];
+        }
+        if (threadIdx.x == 0) s_pre[FLAT_JOBS] = s_wsum[0] + s_wsum[1];
+        __syncthreads();
+        const int total = s_pre[nj];
+        // contiguous chunks per group, so that a group's problems mostly share a job and its
+        // statistics go out once per job (same-address atomics from every problem would serialise)
+        const int64_t chunk = (total + ngroups - 1) / ngroups;
+        const int64_t q0 = gid * chunk, q1 = min((int64_t)total, q0 + chunk);
+        int cur = -1;
+        GroupStats st;
+        auto flush = [&]() {
+            if (cur >= 0 && lane == 0) {
+                const SolveJob& F = jobs[j0 + cur];
+                unsigned long long* rec = (unsigned long long*)(F.a.stat_rec + (int64_t)F.a.stat_off * 5);
+                if (st.mn != ULLONG_MAX) atomicMin(rec + 0, st.mn);
+                if (st.mx) atomicMax(rec + 1, st.mx);
+                if (st.fail) atomicAdd(rec + 2, st.fail);
+                if (st.empty) atomicAdd(rec + 3, st.empty);
+                if (st.over) atomicAdd(rec + 4, st.over);
+            }
+            st = GroupStats();
+        };
+        for (int64_t q = q0; q < q1; ++q) {
+            // the last problem whose list starts at or before q (its count is then > 0)
+            int lo = 0, hi = nj - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_pre[mid] <= q) lo = mid;
+                else hi = mid - 1;
+            }
+            if (lo != cur) {
+                flush();
+                cur = lo;
+            }
+            const SolveJob& J = jobs[j0 + lo];
+            const int l = J.a.in_list[q - s_pre[lo]];
+            r1_problem<NL>(J.g, J.nd, J.kt, J.a, l, J.kt.Qs, s_x, s_z, st);
+        }
+        flush();
+        __syncthreads();   // s_pre and s_wsum are refilled for the next problems
     }
 }
 
@@ -798,10 +919,12 @@ __global__ void __launch_bounds__(T1_TPB, 2) k_solve_t1(Geo g, NodesDev nd, KTab
 }
 
 template <int NMAX>
-__global__ void __launch_bounds__(T1_TPB) k_solve_t1_batched(const SolveJob* __restrict__ jobs,
+__global__ void __launch_bounds__(T1_TPB, 2) k_solve_t1_batched(const SolveJob* __restrict__ jobs,
                                                              const int2* __restrict__ bmap) {
     const int2 b = bmap[blockIdx.x];
-    const SolveJob& J = jobs[b.x];
+    // the job by value: its fields then live in scalar registers (through a reference into
+    // global memory they are reloaded around every store, which costs scratch)
+    const SolveJob J = jobs[b.x];
     solve_t1_body<NMAX>(J.g, J.nd, J.kt, J.a, b.y);
 }
 
@@ -812,9 +935,11 @@ void launch_solve_t1_batched(const SolveJob* jobs, const int2* t1_map, int t1_bl
         hipLaunchKernelGGL((k_solve_t1_batched<13>), dim3(t1_blocks), dim3(T1_TPB), shm, s, jobs, t1_map);
 }
 
-// Per problem of a batch: reset the solver's status words (the node word stays) and the four
-// list counters (jobs of the thread tier, whose out_count is the first counter).
-__global__ void k_batch_solve_reset(const SolveJob* __restrict__ jobs, int njobs) {
+// Per problem of a batch: reset the solver's status words (the node word stays), the four list
+// counters (jobs of the thread tier, whose out_count is the first counter) and the one statistics
+// record of each of the three list tiers (from the 16-lane tier's record on) to neutral.
+__global__ void k_batch_solve_reset(const SolveJob* __restrict__ jobs, const SolveJob* __restrict__ tier_jobs,
+                                    int njobs) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= njobs) return;
     long long* st = jobs[j].a.status;
@@ -822,6 +947,8 @@ __global__ void k_batch_solve_reset(const SolveJob* __restrict__ jobs, int njobs
         if (w != ST_NONFINITE) st[w] = (w == ST_MIN_N) ? LLONG_MAX : 0;
     int* c = jobs[j].a.out_count;
     for (int i = 0; i < 4; ++i) c[i] = 0;
+    long long* rec = tier_jobs[j].a.stat_rec + (int64_t)tier_jobs[j].a.stat_off * 5;
+    for (int i = 0; i < 3 * 5; ++i) rec[i] = (i % 5 == 0) ? -1LL : 0;   // min as unsigned: ULLONG_MAX
 }
 
 // out[j] = the count of the list the job's tier wrote.
@@ -831,7 +958,8 @@ __global__ void k_batch_counts(const SolveJob* __restrict__ jobs, int njobs, int
 }
 
 void launch_batch_solve_reset(const SolveJob* jobs, int njobs, hipStream_t s) {
-    if (njobs > 0) hipLaunchKernelGGL(k_batch_solve_reset, dim3((njobs + 255) / 256), dim3(256), 0, s, jobs, njobs);
+    if (njobs > 0)
+        hipLaunchKernelGGL(k_batch_solve_reset, dim3((njobs + 255) / 256), dim3(256), 0, s, jobs, jobs + njobs, njobs);
 }
 
 void launch_batch_counts(const SolveJob* jobs, int njobs, int* out, hipStream_t s) {
@@ -840,9 +968,9 @@ void launch_batch_counts(const SolveJob* jobs, int njobs, int* out, hipStream_t 
 
 void launch_solve_tier_batched(const SolveJob* jobs, int njobs, int nl, int blocks, hipStream_t s) {
     if (njobs <= 0 || blocks <= 0) return;
-    if (nl == 16) hipLaunchKernelGGL((k_solve_r1_batched<16>), dim3(blocks), dim3(128), 0, s, jobs, njobs);
-    else if (nl == 32) hipLaunchKernelGGL((k_solve_r1_batched<32>), dim3(blocks), dim3(128), 0, s, jobs, njobs);
-    else hipLaunchKernelGGL((k_solve_r1_batched<64>), dim3(blocks), dim3(128), 0, s, jobs, njobs);
+    if (nl == 16) hipLaunchKernelGGL((k_solve_r1_flat<16>), dim3(blocks), dim3(128), 0, s, jobs, njobs);
+    else if (nl == 32) hipLaunchKernelGGL((k_solve_r1_flat<32>), dim3(blocks), dim3(128), 0, s, jobs, njobs);
+    else hipLaunchKernelGGL((k_solve_r1_flat<64>), dim3(blocks), dim3(128), 0, s, jobs, njobs);
 }
 
 int launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s) {

@@ -55,6 +55,9 @@ def parse():
                     help="run one device-to-device copy of this size first (counter calibration under a profiler)")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the batched and polar workloads reported beside the headline")
+    ap.add_argument("--leg", choices=("rhs8", "batched", "polar", "spiral", "small", "ansatz1", "variants"),
+                    help="run only this workload beside the headline and print its figures as one JSON line "
+                         "(for profiling one workload; not a bench line)")
     ap.add_argument("--fp64", dest="fp64", action="store_true", default=True)
     ap.add_argument("--no-fp64", dest="fp64", action="store_false")
     return ap.parse_args()
@@ -671,6 +674,16 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if a.leg:
+        legs = {"rhs8": lambda: secondary_rhs8(max(10, a.steps), 3),
+                "batched": lambda: secondary_batched(max(5, a.steps // 2), 2),
+                "polar": lambda: secondary_polar(max(5, a.steps // 2), 2),
+                "spiral": lambda: secondary_spiral(5, 1),
+                "small": lambda: secondary_small(max(20, a.steps), 3),
+                "ansatz1": lambda: secondary_ansatz1(max(10, a.steps), 3),
+                "variants": lambda: secondary_variants(max(10, a.steps // 2), 3)}
+        print(json.dumps({"leg": a.leg, "figures": legs[a.leg]()}, default=str))
+        return
     cfg = WORKLOAD
     M, N, sigma, m, rho = cfg["M"], cfg["N"], cfg["sigma"], cfg["m"], cfg["rho"]
     R = a.rhs

@@ -410,7 +410,7 @@ __device__ inline void fft_block_d(const FftPass& P, int64_t nseq, const FftIO& 
 
 template <typename R, int E, int LD, int ST>
 __global__ void __launch_bounds__(FFT_THREADS) k_fft(FftPass P, FftIO io, Geo g) {
-    fft_block_d<R, E, LD, ST>(P, P.nseq, io, g, blockIdx.x);
+    fft_block_d<R, E, LD, ST>(P, P.nseq, io, g, xcd_block(blockIdx.x, gridDim.x));
 }
 
 // Passes of many problems in one launch: workgroup -> (job, block of that job's pass).  A job's
@@ -421,7 +421,7 @@ template <typename R, int E, int LD, int ST>
 __global__ void __launch_bounds__(FFT_THREADS) k_fft_batched(const FftJob* __restrict__ jobs,
                                                              const int2* __restrict__ bmap, const void* user_in,
                                                              void* user_out, int nrhs) {
-    const int2 b = bmap[blockIdx.x];
+    const int2 b = bmap[xcd_block(blockIdx.x, gridDim.x)];
     const FftJob& J = jobs[b.x];
     // the pass is read in place (a local copy would put its radix table, indexed per stage, in
     // scratch); only the sequence count follows the call's nrhs

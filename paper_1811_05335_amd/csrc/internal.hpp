@@ -342,6 +342,17 @@ __device__ inline void big_substitute(const BigProb& P, const double2* A, double
 // ------------------------------------------------------------------ FFT pass description
 
 constexpr int FFT_THREADS = 256;
+
+// Workgroups of a launch go to the eight XCDs (each with its own L2) in turn: workgroup b runs on
+// XCD b mod 8.  This maps the launch index to a logical block so that each XCD takes one
+// contiguous range of logical blocks (a bijection on [0, n)): neighbouring blocks, which read the
+// same cache lines of a strided pass, then share one L2 instead of fetching the lines eight times.
+constexpr int NUM_XCD = 8;
+__device__ inline int64_t xcd_block(int64_t b, int64_t n) {
+    const int64_t per = n / NUM_XCD, rem = n % NUM_XCD;
+    const int64_t x = b % NUM_XCD, k = b / NUM_XCD;
+    return x * per + (x < rem ? x : rem) + k;
+}
 constexpr int FFT_MAX_STAGES = 16;
 enum LoadMode { LD_GRID = 0, LD_DECONV = 1, LD_HALO = 2 };
 enum StoreMode { ST_GRID = 0, ST_TWIDDLE = 1, ST_DECONV = 2 };

@@ -271,11 +271,13 @@ int64_t nfft_plan_device_bytes(infft_plan p);
  * allocated; a workspace passed to nfft_plan_ws stays the caller's. */
 void nfft_plan_destroy(infft_plan p);
 
-/* Autotuner: times every FFT pass of the plan's two schedules (coefficients -> grid and back)
- * with 1, 2, 4, 8 and 16 sub-transforms per workgroup (as far as LDS holds them), `reps` launches
- * each on the plan's buffers (and a coefficient buffer placed with the plan), and keeps the
+/* Autotuner: times each direction of the plan's FFT (coefficients -> grid and back, both passes)
+ * with the default shapes and with every pair of 1, 2, 4, 8 and 16 sub-transforms per workgroup
+ * (as far as LDS holds them): `reps` runs captured in a HIP graph on a stream of its own and
+ * replayed, on the plan's buffers (and a coefficient buffer placed with the plan); keeps the
  * fastest for later calls.  Synchronous; not under graph capture (INFFT_ESTATE).  A no-op for
- * batch plans, whose launches pack workgroups as full as LDS allows. */
+ * batch plans, whose launches pack workgroups as full as LDS allows; a workspace plan (which must
+ * not allocate, and graph instantiation does) returns to the default shapes. */
 int infft_autotune(infft_plan p, int reps);
 
 /* Sub-transforms per workgroup the autotuner chose for step `step` (0 or 1) of direction `dir`

@@ -2406,13 +2406,25 @@ int infft_autotune(infft_plan p, int reps) {
     if (reps < 1) reps = 10;
     const Geo& g = p->g;
     const int R = p->max_rhs;
+    if (p->ws_mode) {
+        // timing in a graph allocates (the graph's executable form): a workspace plan keeps the
+        // default shapes
+        p->fft_rows[0][0] = p->fft_rows[0][1] = p->fft_rows[1][0] = p->fft_rows[1][1] = 0;
+        return build_schedule(p, R, p->to_grid, p->to_coeff);
+    }
     void* tmp = p->tune_buf;   // max_rhs x prod(M) coefficients, placed with the plan
     const size_t tbytes = (size_t)R * (size_t)g.P * p->csize();
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-        return fail(INFFT_EDEVICE, "hipEventCreate failed");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipStream_t ts = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+        hipStreamCreateWithFlags(&ts, hipStreamNonBlocking) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        return fail(INFFT_EDEVICE, "hipEventCreate / hipStreamCreate failed");
+    }
     int rc = INFFT_OK;
-    if (hipMemsetAsync(tmp, 0, tbytes, p->stream) != hipSuccess) rc = fail(INFFT_EDEVICE, "hipMemsetAsync failed");
+    if (hipMemsetAsync(tmp, 0, tbytes, p->stream) != hipSuccess || hipStreamSynchronize(p->stream) != hipSuccess)
+        rc = fail(INFFT_EDEVICE, "hipMemsetAsync failed");
     const bool f32 = p->prec == INFFT_F32;
     auto launch = [&](const FftStep& st) {
         FftIO io{};
@@ -2426,38 +2438,53 @@ int infft_autotune(infft_plan p, int reps) {
         io.halo_rs0 = p->hrs0;
         io.halo_rs1 = p->hrs1;
         io.halo_rs01 = p->hrs01;
-        if (f32) launch_fft_pass<float>(st.pass, io, g, st.ld, st.st, p->stream);
-        else launch_fft_pass<double>(st.pass, io, g, st.ld, st.st, p->stream);
+        if (f32) launch_fft_pass<float>(st.pass, io, g, st.ld, st.st, ts);
+        else launch_fft_pass<double>(st.pass, io, g, st.ld, st.st, ts);
     };
-    // Each direction is timed as it runs: its passes in sequence, each consuming the last one's
-    // output, `reps` times back to back.  Every pair of row counts (1, 2, 4, 8, 16 sub-transforms
-    // per workgroup, as far as LDS holds them) is tried; timing a pass alone, repeated on the same
-    // data, favoured packings that lose once the pass reads what the previous kernel wrote.
+    // Each direction is timed as it runs in a HIP graph: its passes in sequence, each consuming the
+    // last one's output, `reps` times, captured once and replayed.  Eager launches of passes of a
+    // few microseconds are paced by the host, which hid the differences between shapes (the shapes
+    // chosen that way were up to a fifth slower in graph replays than the defaults).  Candidates:
+    // the default shape (0) and every pair of row counts (1, 2, 4, 8, 16 sub-transforms per
+    // workgroup, as far as LDS holds them).
     for (int dir = 0; dir < 2 && rc == INFFT_OK; ++dir) {
         float best = 1e30f;
         int best_r[2] = {0, 0};
-        for (int ra = 1; ra <= 16 && rc == INFFT_OK; ra *= 2) {
-            for (int rb = 1; rb <= 16 && rc == INFFT_OK; rb *= 2) {
+        for (int ra = 0; ra <= 16 && rc == INFFT_OK; ra = ra ? 2 * ra : 1) {
+            for (int rb = 0; rb <= 16 && rc == INFFT_OK; rb = rb ? 2 * rb : 1) {
+                if ((ra == 0) != (rb == 0)) continue;
                 p->fft_rows[dir][0] = ra;
                 p->fft_rows[dir][1] = rb;
                 if ((rc = build_schedule(p, R, p->to_grid, p->to_coeff))) break;
                 const std::vector<FftStep>& v = dir == 0 ? p->to_grid : p->to_coeff;
                 if (v.empty()) break;
-                bool valid = v[0].pass.rows == ra && (ra == 1 || ra <= v[0].pass.nseq);
-                if (v.size() > 1) valid = valid && v[1].pass.rows == rb && (rb == 1 || rb <= v[1].pass.nseq);
-                else valid = valid && rb == 1;
-                if (!valid) continue;
-                for (const FftStep& st : v) launch(st);   // warm-up
-                (void)hipEventRecord(e0, p->stream);
-                for (int i = 0; i < reps; ++i)
-                    for (const FftStep& st : v) launch(st);
-                (void)hipEventRecord(e1, p->stream);
-                if (hipGetLastError() != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                    rc = fail(INFFT_EDEVICE, "autotune launch failed");
+                if (ra) {
+                    bool valid = v[0].pass.rows == ra && (ra == 1 || ra <= v[0].pass.nseq);
+                    if (v.size() > 1) valid = valid && v[1].pass.rows == rb && (rb == 1 || rb <= v[1].pass.nseq);
+                    else valid = valid && rb == 1;
+                    if (!valid) continue;
+                }
+                hipGraph_t graph = nullptr;
+                hipGraphExec_t exec = nullptr;
+                bool ok = hipStreamBeginCapture(ts, hipStreamCaptureModeThreadLocal) == hipSuccess;
+                if (ok) {
+                    for (int i = 0; i < reps; ++i)
+                        for (const FftStep& st : v) launch(st);
+                    ok = hipStreamEndCapture(ts, &graph) == hipSuccess && graph;
+                }
+                ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+                float ms = 0.0f;
+                ok = ok && hipGraphLaunch(exec, ts) == hipSuccess;   // warm-up
+                ok = ok && hipEventRecord(e0, ts) == hipSuccess;
+                for (int i = 0; ok && i < 3; ++i) ok = hipGraphLaunch(exec, ts) == hipSuccess;
+                ok = ok && hipEventRecord(e1, ts) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                     hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+                if (exec) (void)hipGraphExecDestroy(exec);
+                if (graph) (void)hipGraphDestroy(graph);
+                if (!ok) {
+                    rc = fail(INFFT_EDEVICE, "autotune graph timing failed");
                     break;
                 }
-                float ms = 0.0f;
-                (void)hipEventElapsedTime(&ms, e0, e1);
                 if (ms < best) {
                     best = ms;
                     best_r[0] = ra;
@@ -2468,9 +2495,10 @@ int infft_autotune(infft_plan p, int reps) {
         p->fft_rows[dir][0] = best_r[0];
         p->fft_rows[dir][1] = best_r[1];
     }
+    (void)hipStreamSynchronize(ts);
+    (void)hipStreamDestroy(ts);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    (void)hipStreamSynchronize(p->stream);
     if (rc == INFFT_OK) rc = build_schedule(p, R, p->to_grid, p->to_coeff);
     return rc;
 }

@@ -250,8 +250,9 @@ class NfftPlan:
         return ms.value, n.value
 
     def autotune(self, reps: int = 10) -> dict:
-        """Times the FFT passes with 1..16 sub-transforms per workgroup and keeps the fastest;
-        returns the choice per direction and step."""
+        """Times each FFT direction in a HIP graph with the default shapes and with 1..16
+        sub-transforms per workgroup per pass, and keeps the fastest; returns the choice per
+        direction and step (0: the default)."""
         self._sync_stream()
         check(load().infft_autotune(self._h, int(reps)))
         lib = load()

@@ -543,13 +543,185 @@ __device__ inline void r1_problem(const Geo& g, const NodesDev& nd, const KTabDe
     wave_sync();
 }
 
-// One group of NL lanes per grid index l (r1_problem), over a list or over all grid indices.
+// The same problem with the group's (n x n) matrix in LDS at Ag, row i of lane i at Ai (wide
+// groups: 64 rows in registers would spill); s_y / s_z are the workgroup's exchange slots.
+template <int NL>
+__device__ inline void r1_problem_lds(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a,
+                                      int l, const double* __restrict__ tQ, double* Ag, double* Ai,
+                                      double (*s_y)[128], double* s_z, GroupStats& st) {
+    constexpr int LDA = NL + 1;
+    const int lane = threadIdx.x & (NL - 1);
+    const int sb = threadIdx.x - lane;
+    const int gbase = (threadIdx.x & 63) - lane;
+    const uint64_t gmask = (NL == 64) ? ~0ull : ((1ull << NL) - 1ull);
+    const double c1 = (double)g.Ms[0] * kt.dM * kt.dM;
+    int n = 0, my_p = 0;
+    gather_1d(g, nd, l, lane, NL, gbase, gmask, n, my_p);
+    if (n == 0) {
+        if (lane == 0) ++st.empty;
+        return;
+    }
+    if (n > NL) {
+        if (lane == 0) {
+            if (a.out_list) {
+                const int slot = atomicAdd(a.out_count, 1);
+                a.out_list[slot] = l;
+            } else {
+                ++st.over;
+            }
+        }
+        if (!a.out_list) zero_members_1d(g, nd, l, lane, NL, a);
+        return;
+    }
+    if (lane == 0) {
+        st.mn = min(st.mn, (unsigned long long)n);
+        st.mx = max(st.mx, (unsigned long long)n);
+    }
+    const bool act = lane < n;
+
+    double z = 0.0, t = 0.0, wr = 0.0, wi = 0.0;
+    int tau = 0;
+    if (act) {
+        tau = l - nd.l0s[my_p];
+        if (tau < 0) tau += g.Ms[0];
+        z = (double)tau - nd.us[my_p];
+        t = tay_eval_r(kt.Ks, kt.qK, z);
+        sincospi(z * kt.inv_sigma, &wi, &wr);
+    }
+    double ur = wr, ui = wi;
+    s_z[threadIdx.x] = z;
+    wave_sync();
+
+    // ---- lower triangle of A0 = M_sigma Qs(z_j - z_i) + lambda I, row i by lane i
+    if (act) {
+        for (int j0 = 0; j0 <= lane; j0 += 4) {
+            double e[4], cf[4][TAY_NC];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const double az = fabs(s_z[sb + min(j0 + k, lane)] - z);
+                int q = (int)rint(az * (double)TAY_S);
+                if (q > kt.qQ) q = kt.qQ;
+                e[k] = az - (double)q * (1.0 / TAY_S);
+                const double* c = tQ + (int64_t)q * TAY_NC;
+#pragma unroll
+                for (int p = 0; p < TAY_NC; ++p) cf[k][p] = c[p];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                double acc = cf[k][TAY_NC - 1];
+#pragma unroll
+                for (int p = TAY_NC - 2; p >= 0; --p) acc = fma(acc, e[k], cf[k][p]);
+                if (j0 + k <= lane) Ai[j0 + k] = kt.scaleG * acc;
+            }
+        }
+        Ai[lane] += kt.lam;
+    }
+    wave_sync();
+
+    // ---- Cholesky A0 = L L^T in place (right-looking)
+    bool ok = true;
+    for (int k = 0; k < n; ++k) {
+        const double piv = Ag[k * LDA + k];
+        if (!(piv > 0.0)) {
+            ok = false;
+            break;
+        }
+        const double sq = sqrt(piv);
+        double lik = 0.0;
+        if (lane == k) Ai[k] = sq;
+        else if (lane > k && act) {
+            lik = Ai[k] / sq;
+            Ai[k] = lik;
+        }
+        wave_sync();
+        if (lane > k && act)
+            for (int j = k + 1; j <= lane; ++j) Ai[j] = fma(-lik, Ag[j * LDA + k], Ai[j]);
+        wave_sync();
+    }
+    if (!ok) {
+        if (lane == 0) ++st.fail;
+        wave_sync();
+        return;
+    }
+
+    // ---- forward substitution L y = rhs (Ks, Re w, Im w)
+    for (int k = 0; k < n; ++k) {
+        if (lane == k) {
+            const double iv = 1.0 / Ai[k];
+            t *= iv;
+            ur *= iv;
+            ui *= iv;
+            s_y[0][threadIdx.x] = t;
+            s_y[1][threadIdx.x] = ur;
+            s_y[2][threadIdx.x] = ui;
+        }
+        wave_sync();
+        if (lane > k && act) {
+            const double lk = Ai[k];
+            t = fma(-lk, s_y[0][sb + k], t);
+            ur = fma(-lk, s_y[1][sb + k], ur);
+            ui = fma(-lk, s_y[2][sb + k], ui);
+        }
+    }
+    wave_sync();
+    // ---- backward substitution L^T x = y
+    for (int k = n - 1; k >= 0; --k) {
+        if (lane == k) {
+            const double iv = 1.0 / Ai[k];
+            t *= iv;
+            ur *= iv;
+            ui *= iv;
+            s_y[0][threadIdx.x] = t;
+            s_y[1][threadIdx.x] = ur;
+            s_y[2][threadIdx.x] = ui;
+        }
+        wave_sync();
+        if (lane < k) {
+            const double lk = Ag[k * LDA + lane];
+            t = fma(-lk, s_y[0][sb + k], t);
+            ur = fma(-lk, s_y[1][sb + k], ur);
+            ui = fma(-lk, s_y[2][sb + k], ui);
+        }
+    }
+
+    // ---- Sherman-Morrison combination
+    const double sdot = group_sum<NL>(act ? wr * ur + wi * ui : 0.0);        // w^* u
+    const double wtr = group_sum<NL>(act ? wr * t : 0.0);                     // Re w^* t
+    const double wti = group_sum<NL>(act ? -wi * t : 0.0);                    // Im w^* t
+    const double den = 1.0 + c1 * sdot;
+    const double cr = (kt.dM - c1 * wtr) / den, ci = (-c1 * wti) / den;
+    const double2 bsol = make_double2(t + ur * cr - ui * ci, ur * ci + ui * cr);
+
+    if (act) {
+        const int64_t idx = (int64_t)tau * g.N + my_p;
+        put_bopt(a.B64, a.B32, idx, bsol);
+    }
+    wave_sync();
+}
+
+// One problem on a group of NL lanes: rows in registers up to 16 lanes, the matrix in LDS for wider
+// groups (their rows would not fit the registers).  s_A holds the LDS matrices of the workgroup's
+// groups (unused below 32 lanes).
+template <int NL>
+__device__ inline void r1_solve(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a, int l,
+                                const double* __restrict__ tQ, double* s_A, double (*s_x)[128], double* s_z,
+                                GroupStats& st) {
+    if constexpr (NL >= 32) {
+        double* Ag = s_A + (threadIdx.x / NL) * NL * (NL + 1);
+        r1_problem_lds<NL>(g, nd, kt, a, l, tQ, Ag, Ag + (threadIdx.x & (NL - 1)) * (NL + 1), s_x, s_z, st);
+    } else {
+        r1_problem<NL>(g, nd, kt, a, l, tQ, s_x, s_z, st);
+    }
+}
+
+// One group of NL lanes per grid index l (r1_solve), over a list or over all grid indices.
 // blk / nblk: this workgroup's index and the number of workgroups sharing the problem list.
 // TAB_LDS: the Q table is staged in LDS (one problem per launch) or read through the caches.
 template <int NL, bool TAB_LDS>
 __device__ inline void solve_r1_body(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a,
                                      int64_t blk, int64_t nblk) {
     constexpr int GPB = 128 / NL;   // groups per block
+    __shared__ double s_A[NL >= 32 ? GPB * NL * (NL + 1) : 1];
     __shared__ double s_x[3][128];
     __shared__ double s_z[128];
     extern __shared__ double s_tabr[];
@@ -571,7 +743,7 @@ __device__ inline void solve_r1_body(const Geo& g, const NodesDev& nd, const KTa
     GroupStats st;
     for (int64_t qi = gid; qi < count; qi += ngroups) {
         const int l = a.in_list ? a.in_list[qi] : (int)qi;
-        r1_problem<NL>(g, nd, kt, a, l, tQ, s_x, s_z, st);
+        r1_solve<NL>(g, nd, kt, a, l, tQ, s_A, s_x, s_z, st);
     }
     write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, blk, st.mn, st.mx, st.fail, st.empty, st.over);
 }
@@ -592,6 +764,7 @@ constexpr int FLAT_JOBS = 1024;
 template <int NL>
 __global__ void __launch_bounds__(128) k_solve_r1_flat(const SolveJob* __restrict__ jobs, int njobs) {
     constexpr int PER = FLAT_JOBS / 128;
+    __shared__ double s_A[NL >= 32 ? (128 / NL) * NL * (NL + 1) : 1];
     __shared__ double s_x[3][128];
     __shared__ double s_z[128];
     __shared__ int s_pre[FLAT_JOBS + 1];
@@ -660,7 +833,7 @@ __global__ void __launch_bounds__(128) k_solve_r1_flat(const SolveJob* __restric
             }
             const SolveJob& J = jobs[j0 + lo];
             const int l = J.a.in_list[q - s_pre[lo]];
-            r1_problem<NL>(J.g, J.nd, J.kt, J.a, l, J.kt.Qs, s_x, s_z, st);
+            r1_solve<NL>(J.g, J.nd, J.kt, J.a, l, J.kt.Qs, s_A, s_x, s_z, st);
         }
         flush();
         __syncthreads();   // s_pre and s_wsum are refilled for the next problems

@@ -1049,6 +1049,8 @@ int batch_build(infft_plan_s* P) {
         SolveJob t0 = base, t1 = base, t2 = base, t3 = base;
         t0.a.out_list = listA;
         t0.a.out_count = sub->lcount;
+        t0.a.out_list2 = listB;   // 17 to 32 members: straight to the 32-member tier's list
+        t0.a.out_count2 = sub->lcount + 1;
         t0.a.stat_off = 0;
         t1.a.in_list = listA;
         t1.a.in_count = sub->lcount;

@@ -483,6 +483,8 @@ struct SolveArgs {
     const int* in_count;
     int* out_list;          // problems too large for this tier
     int* out_count;
+    int* out_list2;         // thread tier of a batch: problems of 17 to 32 members (count exact) go
+    int* out_count2;        // here, past the 16-lane tier (nullptr: all go to out_list)
     double2* B64;           // [T][N] sorted order (nullptr: the B optimisation of an FP32 plan)
     float2* B32;            // [T][N] sorted order (nullptr: FP64 plans, and an FP32 plan's FP64 recompute)
     long long* status;

@@ -20,6 +20,7 @@
 #include "internal.hpp"
 
 #include <limits.h>
+#include <utility>
 
 namespace infft {
 
@@ -366,26 +367,256 @@ struct GroupStats {
     unsigned long long mn = ULLONG_MAX, mx = 0, fail = 0, empty = 0, over = 0;
 };
 
-// One 1-D problem l on a group of NL lanes: lane i owns member i and row i of the real system
-// A0 (registers, lower triangle).  Each step passes the values it needs (a column of the
-// factorisation, one solution entry, partial sums) through the workgroup's exchange slots s_x
-// (three per thread), all reads of a step issued together.  A problem with more than NL members
-// goes to a.out_list, or without one is counted as oversized and its column zeroed.
-template <int NL>
-__device__ inline void r1_problem(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a, int l,
-                                  const double* __restrict__ tQ, double (*s_x)[128], double* s_z, GroupStats& st) {
-    const int lane = threadIdx.x & (NL - 1);
-    const int sb = threadIdx.x - lane;
+// ---- 16-lane groups: exchanges through DPP within a row of 16 lanes (no LDS, no wave barrier)
+
+// Lane K of the caller's row of 16 lanes, to every lane of that row.
+template <int K> __device__ __forceinline__ double row_bcast(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + K, 0xf, 0xf, true);
+}
+
+// Sum over the 16 lanes of a row: two quad permutations, then rotations by 4 and 8 in the row.
+__device__ __forceinline__ double row_sum16(double v) {
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0xB1, 0xf, 0xf, true);   // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x4E, 0xf, 0xf, true);   // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x124, 0xf, 0xf, true);  // row_ror:4
+    v += __builtin_amdgcn_update_dpp(0.0, v, 0x128, 0xf, 0xf, true);  // row_ror:8
+    return v;
+}
+
+// 1 / x for x > 0: the hardware estimate and two Newton steps r <- r + r (1 - x r).
+__device__ __forceinline__ double rcp_refined(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
+// Members of a 1-D problem for a group of 16 lanes holding R rows each: row 16 r + lane is member
+// 16 r + lane (the order of gather_1d: the cells l-2m+1 .. l, then the edge-tap members of l-2m).
+template <int R>
+__device__ __forceinline__ void gather_1d_rows(const Geo& g, const NodesDev& nd, int l, int lane, int gbase, int& n,
+                                      int (&my_p)[R]) {
+    const int w2 = 2 * g.m, Ms = g.Ms[0];
+    const int clo = l - w2 + 1;
+    int s0, e0, s1 = 0, e1 = 0;
+    if (clo >= 0) {
+        s0 = nd.start[clo];
+        e0 = nd.start[l + 1];
+    } else {
+        s0 = nd.start[clo + Ms];
+        e0 = nd.start[Ms];
+        s1 = nd.start[0];
+        e1 = nd.start[l + 1];
+    }
+    const int n0 = e0 - s0, n1 = e1 - s1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int gi = 16 * r + lane;
+        my_p[r] = gi < n0 ? s0 + gi : (gi - n0 < n1 ? s1 + (gi - n0) : 0);
+    }
+    n = n0 + n1;
+    int ce = l - w2;
+    if (ce < 0) ce += Ms;
+    const int s = nd.start[ce], e = nd.start[ce + 1];
+    for (int base = s; base < e; base += 16) {
+        const int p = base + lane;
+        const bool mem = p < e && edge_tap_member(nd.us[p], g.m);
+        const uint32_t gm = (uint32_t)(__ballot(mem) >> gbase) & 0xffffu;
+        const int cnt = __popc(gm);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int k = 16 * r + lane - n;
+            if (k >= 0 && k < cnt) {
+                uint32_t mm = gm;
+                for (int i = 0; i < k; ++i) mm &= mm - 1u;
+                my_p[r] = base + (__ffs(mm) - 1);
+            }
+        }
+        n += cnt;
+    }
+}
+
+// The state of one problem on its 16-lane group: R rows per lane (row 16 r + lane) of the real
+// system and of the three right-hand sides (Ks, Re w, Im w).  One row per lane keeps full rows;
+// with more, row array r keeps columns 0 .. 16 r + 15 (the lower triangle and the rest of its
+// block), which the elimination in lower form needs.
+template <int R> struct GeRows {
+    static constexpr int NC = 16 * R;
+    static constexpr bool FULL = R == 1;
+    static constexpr int width(int r) { return FULL ? NC : 16 * (r + 1); }
+    static constexpr int off(int r) { return FULL ? r * NC : 8 * r * (r + 1); }
+    double A[off(R)];
+    double t[R], ur[R], ui[R];
+    double dinv[R];   // 1 / d of the lane's rows once eliminated
+    __device__ __forceinline__ double& a(int r, int j) { return A[off(r) + j]; }
+    __device__ __forceinline__ double a(int r, int j) const { return A[off(r) + j]; }
+};
+
+// Column J of the lane's rows of A0 = M_sigma Qs(z_j - z_i) + lambda I (identity rows and columns
+// past n): the table rows, then the Horner steps.
+template <int R, int J>
+__device__ __forceinline__ void ge_gram_load(const double (&z)[R], const KTabDev& kt, const double* __restrict__ tQ,
+                                    double (&e)[R], double (&cf)[R][TAY_NC]) {
+    const double zj = row_bcast<J % 16>(z[J / 16]);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (J >= GeRows<R>::width(r)) continue;
+        const double az = fabs(zj - z[r]);
+        int q = (int)rint(az * (double)TAY_S);
+        if (q > kt.qQ) q = kt.qQ;
+        e[r] = az - (double)q * (1.0 / TAY_S);
+        const double* c = tQ + (int64_t)q * TAY_NC;
+#pragma unroll
+        for (int p = 0; p < TAY_NC; ++p) cf[r][p] = c[p];
+    }
+}
+
+template <int R, int J>
+__device__ __forceinline__ void ge_gram_store(GeRows<R>& S, int lane, int n, const KTabDev& kt, const double (&e)[R],
+                                     const double (&cf)[R][TAY_NC]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (J >= GeRows<R>::width(r)) continue;
+        const int gi = 16 * r + lane;
+        double acc = cf[r][TAY_NC - 1];
+#pragma unroll
+        for (int p = TAY_NC - 2; p >= 0; --p) acc = fma(acc, e[r], cf[r][p]);
+        double v = kt.scaleG * acc;
+        if (J == gi) v += kt.lam;
+        S.a(r, J) = (gi < n && J < n) ? v : (J == gi ? 1.0 : 0.0);
+    }
+}
+
+// Columns J .. J+JB-1: every table row of the step is loaded before the first Horner step, and no
+// later step's loads are hoisted above it (registers).
+template <int R, int J, int... B>
+__device__ __forceinline__ void ge_gram(GeRows<R>& S, const double (&z)[R], int lane, int n, const KTabDev& kt,
+                                        const double* __restrict__ tQ, std::integer_sequence<int, B...>) {
+    double e[sizeof...(B)][R], cf[sizeof...(B)][R][TAY_NC];
+    (ge_gram_load<R, J + B>(z, kt, tQ, e[B], cf[B]), ...);
+    (ge_gram_store<R, J + B>(S, lane, n, kt, e[B], cf[B]), ...);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int R, int JB, int... Jb>
+__device__ __forceinline__ void ge_gram_all(GeRows<R>& S, const double (&z)[R], int lane, int n, const KTabDev& kt,
+                                   const double* __restrict__ tQ, std::integer_sequence<int, Jb...>) {
+    (ge_gram<R, Jb * JB>(S, z, lane, n, kt, tQ, std::make_integer_sequence<int, JB>{}), ...);
+}
+
+// Column J > K of elimination step K (the pivot row's entry a_KJ, then the update of the lane's rows).
+template <int R, int K, int J>
+__device__ __forceinline__ void ge_elim_col(GeRows<R>& S, const double (&m)[R]) {
+    constexpr int RK = K / 16, LK = K % 16;
+    double pj;
+    if constexpr (GeRows<R>::FULL) pj = row_bcast<LK>(S.a(RK, J));
+    else pj = row_bcast<J % 16>(S.a(J / 16, K));
+#pragma unroll
+    for (int r = RK; r < R; ++r)
+        if (J < GeRows<R>::width(r)) S.a(r, J) = fma(-m[r], pj, S.a(r, J));
+    // a few pivot-row entries in flight at a time (registers)
+    if constexpr (((J - K) & 7) == 0) __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int R, int K, int... J>
+__device__ __forceinline__ void ge_elim_cols(GeRows<R>& S, const double (&m)[R], std::integer_sequence<int, J...>) {
+    (ge_elim_col<R, K, K + 1 + J>(S, m), ...);
+}
+
+// Elimination step K: every row i > K loses l_iK = a_iK / a_KK times the pivot row K (the
+// multiplier is zero on the other rows, which keeps them), right-hand sides included.  Full rows
+// take the pivot row's entries from the pivot lane; in lower form row i takes a_Kj = a_jK from row
+// j's lane (the remaining block stays symmetric) and keeps l_iK in place of a_iK.
+template <int R, int K>
+__device__ __forceinline__ void ge_elim(GeRows<R>& S, int lane, bool& ok) {
+    constexpr int NC = 16 * R, RK = K / 16, LK = K % 16;
+    const double piv = row_bcast<LK>(S.a(RK, K));
+    ok = ok && piv > 0.0;
+    const double inv = rcp_refined(piv > 0.0 ? piv : 1.0);
+    if (lane == LK) S.dinv[RK] = inv;
+    double m[R];
+#pragma unroll
+    for (int r = RK; r < R; ++r) m[r] = (16 * r + lane > K) ? S.a(r, K) * inv : 0.0;
+    ge_elim_cols<R, K>(S, m, std::make_integer_sequence<int, NC - K - 1>{});
+    if constexpr (!GeRows<R>::FULL) {
+#pragma unroll
+        for (int r = RK; r < R; ++r)
+            if (16 * r + lane > K) S.a(r, K) = m[r];
+    }
+    const double pt = row_bcast<LK>(S.t[RK]), pr = row_bcast<LK>(S.ur[RK]), pi = row_bcast<LK>(S.ui[RK]);
+#pragma unroll
+    for (int r = RK; r < R; ++r) {
+        S.t[r] = fma(-m[r], pt, S.t[r]);
+        S.ur[r] = fma(-m[r], pr, S.ur[r]);
+        S.ui[r] = fma(-m[r], pi, S.ui[r]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int R, int... K>
+__device__ __forceinline__ void ge_elim_all(GeRows<R>& S, int lane, bool& ok, std::integer_sequence<int, K...>) {
+    (ge_elim<R, K>(S, lane, ok), ...);
+}
+
+// Back substitution step K.  Full rows solve U b = z' (U = D L^T): b_K = z'_K / d_K from the
+// pivot lane, then every row i < K loses U[i][K] b_K (the lane's own row entry).  Lower form solves
+// L^T b = D^{-1} z' (z already scaled): b_K loses the sum over rows j > K of l_jK b_j, a row sum.
+template <int R, int K>
+__device__ __forceinline__ void ge_back(const GeRows<R>& S, double (&zr)[R], double (&zi)[R], int lane) {
+    constexpr int RK = K / 16, LK = K % 16;
+    if constexpr (GeRows<R>::FULL) {
+        const double br = row_bcast<LK>(zr[RK] * S.dinv[RK]);
+        const double bi = row_bcast<LK>(zi[RK] * S.dinv[RK]);
+#pragma unroll
+        for (int r = 0; r <= RK; ++r) {
+            const double u = (r < RK || lane < LK) ? S.a(r, K) : 0.0;
+            zr[r] = fma(-u, br, zr[r]);
+            zi[r] = fma(-u, bi, zi[r]);
+        }
+    } else {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int r = RK; r < R; ++r) {
+            const double l = (16 * r + lane > K) ? S.a(r, K) : 0.0;
+            sr = fma(l, zr[r], sr);
+            si = fma(l, zi[r], si);
+        }
+        sr = row_sum16(sr);
+        si = row_sum16(si);
+        if (lane == LK) {
+            zr[RK] -= sr;
+            zi[RK] -= si;
+        }
+    }
+}
+
+template <int R, int... K>
+__device__ __forceinline__ void ge_back_all(const GeRows<R>& S, double (&zr)[R], double (&zi)[R], int lane,
+                                   std::integer_sequence<int, K...>) {
+    (ge_back<R, 16 * R - 1 - K>(S, zr, zi, lane), ...);
+}
+
+// One 1-D problem l of up to 16 R members on a group of 16 lanes (GeRows).  Gaussian elimination
+// without pivoting (A0 is SPD: A0 = L D L^T) applied to the rows and the right-hand sides together
+// leaves U = D L^T in the rows and y = L^{-1} r in the right-hand sides; the Sherman-Morrison sums
+// are then y^T D^{-1} y' and the solution comes from one back substitution with U, each step reading
+// the lane's own row.  Every exchange is a DPP broadcast from the pivot lane; rows past n are padded
+// with the identity.  A problem with more than 16 R members goes to a.out_list, or without one is
+// counted as oversized and its column zeroed.
+template <int R>
+__device__ __forceinline__ void r1_problem_ge(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a, int l,
+                                     const double* __restrict__ tQ, GroupStats& st) {
+    constexpr int NC = 16 * R;
+    const int lane = threadIdx.x & 15;
     const int gbase = (threadIdx.x & 63) - lane;
-    const uint64_t gmask = (NL == 64) ? ~0ull : ((1ull << NL) - 1ull);
     const double c1 = (double)g.Ms[0] * kt.dM * kt.dM;
-    int n = 0, my_p = 0;
-    gather_1d(g, nd, l, lane, NL, gbase, gmask, n, my_p);
+    int n = 0, my_p[R];
+    gather_1d_rows<R>(g, nd, l, lane, gbase, n, my_p);
     if (n == 0) {
         if (lane == 0) ++st.empty;
         return;
     }
-    if (n > NL) {
+    if (n > NC) {
         if (lane == 0) {
             if (a.out_list) {
                 const int slot = atomicAdd(a.out_count, 1);
@@ -394,153 +625,75 @@ __device__ inline void r1_problem(const Geo& g, const NodesDev& nd, const KTabDe
                 ++st.over;
             }
         }
-        if (!a.out_list) zero_members_1d(g, nd, l, lane, NL, a);
+        if (!a.out_list) zero_members_1d(g, nd, l, lane, 16, a);
         return;
     }
     if (lane == 0) {
         st.mn = min(st.mn, (unsigned long long)n);
         st.mx = max(st.mx, (unsigned long long)n);
     }
-    const bool act = lane < n;
 
-    double z = 0.0, t = 0.0, wr = 0.0, wi = 0.0;
-    int tau = 0;
-    if (act) {
-        tau = l - nd.l0s[my_p];
-        if (tau < 0) tau += g.Ms[0];
-        z = (double)tau - nd.us[my_p];
-        t = tay_eval_r(kt.Ks, kt.qK, z);
-        sincospi(z * kt.inv_sigma, &wi, &wr);
-    }
-    double ur = wr, ui = wi;
-    s_z[threadIdx.x] = z;
-    wave_sync();
-
-    // ---- row i of A0 = M_sigma Qs(z_j - z_i) + lambda I, j <= i.  GB entries at a time: their
-    // table rows are loaded before any Horner step, so the loads overlap; a scheduling barrier
-    // after each batch keeps the compiler from hoisting every batch's loads (registers).
-    constexpr int GB = NL >= 64 ? 2 : 4;
-    double A[NL];
+    // ---- member data: tap tau, z = tau - u, Ks(z), w = e^{i pi z / sigma}
+    GeRows<R> S;
+    double z[R];
+    int tau[R];
 #pragma unroll
-    for (int j0 = 0; j0 < NL; j0 += GB) {
-        double e[GB], cf[GB][TAY_NC];
-#pragma unroll
-        for (int k = 0; k < GB; ++k) {
-            const double az = fabs(s_z[sb + j0 + k] - z);
-            int q = (int)rint(az * (double)TAY_S);
-            if (q > kt.qQ) q = kt.qQ;
-            e[k] = az - (double)q * (1.0 / TAY_S);
-            const double* c = tQ + (int64_t)q * TAY_NC;
-#pragma unroll
-            for (int p = 0; p < TAY_NC; ++p) cf[k][p] = c[p];
+    for (int r = 0; r < R; ++r) {
+        z[r] = S.t[r] = S.ur[r] = S.ui[r] = 0.0;
+        S.dinv[r] = 1.0;
+        tau[r] = 0;
+        if (16 * r + lane < n) {
+            int tr = l - nd.l0s[my_p[r]];
+            if (tr < 0) tr += g.Ms[0];
+            tau[r] = tr;
+            z[r] = (double)tr - nd.us[my_p[r]];
+            S.t[r] = tay_eval_r(kt.Ks, kt.qK, z[r]);
+            sincospi(z[r] * kt.inv_sigma, &S.ui[r], &S.ur[r]);
         }
-#pragma unroll
-        for (int k = 0; k < GB; ++k) {
-            const int j = j0 + k;
-            double acc = cf[k][TAY_NC - 1];
-#pragma unroll
-            for (int p = TAY_NC - 2; p >= 0; --p) acc = fma(acc, e[k], cf[k][p]);
-            double v = kt.scaleG * acc;
-            if (j == lane) v += kt.lam;
-            A[j] = (act && j <= lane) ? v : 0.0;
-        }
-        __builtin_amdgcn_sched_barrier(0);
     }
+    constexpr int JB = R == 1 ? 4 : 1;   // columns per Gram step (4 or 2 table rows in flight)
+    ge_gram_all<R, JB>(S, z, lane, n, kt, tQ, std::make_integer_sequence<int, NC / JB>{});
 
-    // ---- Cholesky A0 = L L^T, lane i keeps row i of L.  Step k passes the unscaled column k; with
-    // inv = 1/sqrt(pivot) the update of row i is A[i][j] -= (A[i][k] inv^2) A[j][k] for k < j <= i.
     bool ok = true;
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        if (k < n && ok) {
-            s_x[0][threadIdx.x] = A[k];
-            wave_sync();
-            const double piv = s_x[0][sb + k];
-            ok = piv > 0.0;
-            const double sq = sqrt(ok ? piv : 1.0), inv = 1.0 / sq;
-            const double lk2 = A[k] * inv * inv;
-            // column entries eight at a time (the barrier bounds how many loads are in flight, and
-            // with them the registers)
-#pragma unroll
-            for (int j = k + 1; j < NL; ++j) {
-                if (j < n) {
-                    const double raw = s_x[0][sb + j];
-                    if (lane >= j) A[j] = fma(-lk2, raw, A[j]);
-                }
-                if (((j - k) & 7) == 0) __builtin_amdgcn_sched_barrier(0);
-            }
-            if (lane == k) A[k] = sq;
-            else if (lane > k) A[k] *= inv;
-            wave_sync();
-        }
-    }
+    ge_elim_all<R>(S, lane, ok, std::make_integer_sequence<int, NC>{});
     if (!ok) {
         if (lane == 0) ++st.fail;
         return;
     }
 
-    // ---- forward substitution L y = rhs for the three right-hand sides (Ks, Re w, Im w)
+    // ---- Sherman-Morrison: s = w^* A0^{-1} w and w^* A0^{-1} Ks, each a sum y^T D^{-1} y'
+    double ps = 0.0, pr = 0.0, pi = 0.0;
 #pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        if (k < n) {
-            if (lane == k) {
-                const double iv = 1.0 / A[k];
-                t *= iv;
-                ur *= iv;
-                ui *= iv;
-            }
-            s_x[0][threadIdx.x] = t;
-            s_x[1][threadIdx.x] = ur;
-            s_x[2][threadIdx.x] = ui;
-            wave_sync();
-            if (lane > k && act) {
-                t = fma(-A[k], s_x[0][sb + k], t);
-                ur = fma(-A[k], s_x[1][sb + k], ur);
-                ui = fma(-A[k], s_x[2][sb + k], ui);
-            }
-            wave_sync();
-        }
+    for (int r = 0; r < R; ++r) {
+        ps = fma(S.dinv[r], fma(S.ur[r], S.ur[r], S.ui[r] * S.ui[r]), ps);
+        pr = fma(S.dinv[r], S.ur[r] * S.t[r], pr);
+        pi = fma(-S.dinv[r], S.ui[r] * S.t[r], pi);
     }
-    // ---- backward substitution L^T x = y: x_k = (y_k - sum_{i>k} L[i][k] x_i) / L[k][k]
-#pragma unroll
-    for (int k = NL - 1; k >= 0; --k) {
-        if (k < n) {
-            const bool below = lane > k && act;
-            s_x[0][threadIdx.x] = below ? A[k] * t : 0.0;
-            s_x[1][threadIdx.x] = below ? A[k] * ur : 0.0;
-            s_x[2][threadIdx.x] = below ? A[k] * ui : 0.0;
-            wave_sync();
-            if (lane == k) {
-                double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-                for (int j = k + 1; j < NL; ++j) {
-                    s0 += s_x[0][sb + j];
-                    s1 += s_x[1][sb + j];
-                    s2 += s_x[2][sb + j];
-                    if (((j - k) & 7) == 0) __builtin_amdgcn_sched_barrier(0);
-                }
-                const double iv = 1.0 / A[k];
-                t = (t - s0) * iv;
-                ur = (ur - s1) * iv;
-                ui = (ui - s2) * iv;
-            }
-            wave_sync();
-        }
-    }
-
-    // ---- Sherman-Morrison combination
-    const double sdot = group_sum<NL>(act ? wr * ur + wi * ui : 0.0);        // w^* u
-    const double wtr = group_sum<NL>(act ? wr * t : 0.0);                     // Re w^* t
-    const double wti = group_sum<NL>(act ? -wi * t : 0.0);                    // Im w^* t
+    const double sdot = row_sum16(ps), wtr = row_sum16(pr), wti = row_sum16(pi);
     const double den = 1.0 + c1 * sdot;
     const double cr = (kt.dM - c1 * wtr) / den, ci = (-c1 * wti) / den;
-    const double2 bsol = make_double2(t + ur * cr - ui * ci, ur * ci + ui * cr);
-
-    if (act) {
-        const int64_t idx = (int64_t)tau * g.N + my_p;
-        put_bopt(a.B64, a.B32, idx, bsol);
+    // z' = y_k + c' y_w, then the back substitution from the last row up (b = U^{-1} z' with full
+    // rows, b = L^{-T} D^{-1} z' in lower form)
+    constexpr bool FULL = GeRows<R>::FULL;
+    double zr[R], zi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        zr[r] = S.t[r] + cr * S.ur[r] - ci * S.ui[r];
+        zi[r] = cr * S.ui[r] + ci * S.ur[r];
+        if (!FULL) {
+            zr[r] *= S.dinv[r];
+            zi[r] *= S.dinv[r];
+        }
     }
-    wave_sync();
+    ge_back_all<R>(S, zr, zi, lane, std::make_integer_sequence<int, NC>{});
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (16 * r + lane < n) {
+            const int64_t idx = (int64_t)tau[r] * g.N + my_p[r];
+            const double sc = FULL ? S.dinv[r] : 1.0;
+            put_bopt(a.B64, a.B32, idx, make_double2(zr[r] * sc, zi[r] * sc));
+        }
+    }
 }
 
 // The same problem with the group's (n x n) matrix in LDS at Ag, row i of lane i at Ai (wide
@@ -699,18 +852,20 @@ __device__ inline void r1_problem_lds(const Geo& g, const NodesDev& nd, const KT
     wave_sync();
 }
 
-// One problem on a group of NL lanes: rows in registers up to 16 lanes, the matrix in LDS for wider
-// groups (their rows would not fit the registers).  s_A holds the LDS matrices of the workgroup's
-// groups (unused below 32 lanes).
-template <int NL>
+// One problem of up to CAP members: 16-lane groups with CAP / 16 rows per lane up to 32 members
+// (registers, DPP exchanges), a 64-lane group with the matrix in LDS beyond (64 rows would not fit
+// the registers).  s_A holds the LDS matrices of the workgroup's groups (unused below 64).
+template <int CAP> constexpr int group_lanes() { return CAP <= 32 ? 16 : CAP; }
+
+template <int CAP>
 __device__ inline void r1_solve(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a, int l,
                                 const double* __restrict__ tQ, double* s_A, double (*s_x)[128], double* s_z,
                                 GroupStats& st) {
-    if constexpr (NL >= 32) {
-        double* Ag = s_A + (threadIdx.x / NL) * NL * (NL + 1);
-        r1_problem_lds<NL>(g, nd, kt, a, l, tQ, Ag, Ag + (threadIdx.x & (NL - 1)) * (NL + 1), s_x, s_z, st);
+    if constexpr (CAP > 32) {
+        double* Ag = s_A + (threadIdx.x / CAP) * CAP * (CAP + 1);
+        r1_problem_lds<CAP>(g, nd, kt, a, l, tQ, Ag, Ag + (threadIdx.x & (CAP - 1)) * (CAP + 1), s_x, s_z, st);
     } else {
-        r1_problem<NL>(g, nd, kt, a, l, tQ, s_x, s_z, st);
+        r1_problem_ge<CAP / 16>(g, nd, kt, a, l, tQ, st);
     }
 }
 
@@ -720,13 +875,14 @@ __device__ inline void r1_solve(const Geo& g, const NodesDev& nd, const KTabDev&
 template <int NL, bool TAB_LDS>
 __device__ inline void solve_r1_body(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a,
                                      int64_t blk, int64_t nblk) {
-    constexpr int GPB = 128 / NL;   // groups per block
-    __shared__ double s_A[NL >= 32 ? GPB * NL * (NL + 1) : 1];
-    __shared__ double s_x[3][128];
-    __shared__ double s_z[128];
+    constexpr int GL = group_lanes<NL>();
+    constexpr int GPB = 128 / GL;   // groups per block
+    __shared__ double s_A[NL > 32 ? GPB * NL * (NL + 1) : 1];
+    __shared__ double s_x[NL > 32 ? 3 : 1][128];
+    __shared__ double s_z[NL > 32 ? 128 : 1];
     extern __shared__ double s_tabr[];
-    const int64_t gid = (blk * (int64_t)blockDim.x + threadIdx.x) / NL;
-    const int64_t ngroups = nblk * blockDim.x / NL;
+    const int64_t gid = (blk * (int64_t)blockDim.x + threadIdx.x) / GL;
+    const int64_t ngroups = nblk * blockDim.x / GL;
     const int64_t count = a.in_list ? (int64_t)(*a.in_count) : g.G;
     if (blk * (int64_t)GPB >= count) {
         // no problem for this workgroup (a short list): skip the table staging, leave a neutral record
@@ -748,10 +904,54 @@ __device__ inline void solve_r1_body(const Geo& g, const NodesDev& nd, const KTa
     write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, blk, st.mn, st.mx, st.fail, st.empty, st.over);
 }
 
+// The list of problems of 17 to 64 members (single 1-D plans): each wave takes four entries at a
+// time, one per 16-lane group; those of up to 32 members are solved at once by their group (two
+// rows per lane), the larger ones afterwards one at a time by the whole wave with the matrix in
+// LDS.  Every problem meets the routine the batched tiers give a problem of its size.
+__device__ inline void solve_r1_body_wide(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a,
+                                          int64_t blk, int64_t nblk) {
+    __shared__ double s_A[2 * 64 * 65];   // one matrix per wave
+    __shared__ double s_x[3][128];
+    __shared__ double s_z[128];
+    extern __shared__ double s_tabr[];
+    const int64_t count = *a.in_count;
+    if (blk * 8 >= count) {
+        write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, blk, ULLONG_MAX, 0, 0, 0, 0);
+        return;
+    }
+    stage_to_lds(s_tabr, kt.Qs, (kt.qQ + 1) * TAY_NC);
+    __syncthreads();
+    const double* tQ = s_tabr;
+    const int wave = threadIdx.x >> 6, lane16 = threadIdx.x & 15, grp = (threadIdx.x & 63) >> 4;
+    const int gbase = (threadIdx.x & 63) - lane16;
+    double* Ag = s_A + wave * 64 * 65;
+    double* Ai = Ag + (threadIdx.x & 63) * 65;
+    GroupStats st;
+    for (int64_t base = (blk * 2 + wave) * 4; base < count; base += nblk * 8) {
+        const int64_t qi = base + grp;
+        const int l = qi < count ? a.in_list[qi] : -1;
+        int n = 0;
+        if (l >= 0) {
+            int p1[1];
+            gather_1d_rows<1>(g, nd, l, lane16, gbase, n, p1);
+            if (n <= 32) r1_problem_ge<2>(g, nd, kt, a, l, tQ, st);
+        }
+        uint64_t wide = __ballot(l >= 0 && n > 32 && lane16 == 0);
+        while (wide) {
+            const int src = __ffsll((unsigned long long)wide) - 1;
+            wide &= wide - 1ull;
+            const int lw = __shfl(l, src, 64);
+            r1_problem_lds<64>(g, nd, kt, a, lw, tQ, Ag, Ai, s_x, s_z, st);
+        }
+    }
+    write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, blk, st.mn, st.mx, st.fail, st.empty, st.over);
+}
+
 template <int NL>
-__global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
+__global__ void __launch_bounds__(128, 2) k_solve_r1(Geo g, NodesDev nd, KTabDev kt, SolveArgs a) {
     clear_counters(a);
-    solve_r1_body<NL, true>(g, nd, kt, a, blockIdx.x, gridDim.x);
+    if constexpr (NL == 64) solve_r1_body_wide(g, nd, kt, a, blockIdx.x, gridDim.x);
+    else solve_r1_body<NL, true>(g, nd, kt, a, blockIdx.x, gridDim.x);
 }
 
 // A tier over the lists of all problems of a batch as one flat list: every workgroup reads the
@@ -762,16 +962,17 @@ __global__ void __launch_bounds__(128) k_solve_r1(Geo g, NodesDev nd, KTabDev kt
 constexpr int FLAT_JOBS = 1024;
 
 template <int NL>
-__global__ void __launch_bounds__(128) k_solve_r1_flat(const SolveJob* __restrict__ jobs, int njobs) {
+__global__ void __launch_bounds__(128, 2) k_solve_r1_flat(const SolveJob* __restrict__ jobs, int njobs) {
     constexpr int PER = FLAT_JOBS / 128;
-    __shared__ double s_A[NL >= 32 ? (128 / NL) * NL * (NL + 1) : 1];
-    __shared__ double s_x[3][128];
-    __shared__ double s_z[128];
+    constexpr int GL = group_lanes<NL>();
+    __shared__ double s_A[NL > 32 ? (128 / NL) * NL * (NL + 1) : 1];
+    __shared__ double s_x[NL > 32 ? 3 : 1][128];
+    __shared__ double s_z[NL > 32 ? 128 : 1];
     __shared__ int s_pre[FLAT_JOBS + 1];
     __shared__ int s_wsum[2];
-    const int lane = threadIdx.x & (NL - 1);
-    const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / NL;
-    const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / NL;
+    const int lane = threadIdx.x & (GL - 1);
+    const int64_t gid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / GL;
+    const int64_t ngroups = (int64_t)gridDim.x * blockDim.x / GL;
     for (int j0 = 0; j0 < njobs; j0 += FLAT_JOBS) {
         const int nj = min(FLAT_JOBS, njobs - j0);
         // exclusive prefix sums of the counts, PER consecutive problems per thread
@@ -950,6 +1151,7 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
         // unstaged node ranges, oversized problems and (on short grids) windows that wrap around
         // the torus go to the group kernels
         bool fallback = (wrap && !circ) || n > NMAX || !staged;
+        bool edge = false;
         {
             // the cell l-2m reaches l through its tap 2m only for nodes with u at m; the tap
             // 2m of every other node belongs to no problem and is zeroed here
@@ -958,15 +1160,19 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
             const int es = nd.start[ce], ee = nd.start[ce + 1];
             for (int p = es; p < ee; ++p) {
                 if (edge_tap_member(nd.us[p], g.m)) {
-                    fallback = true;
+                    edge = true;
                 } else {
                     put_bopt(a.B64, a.B32, (int64_t)w2 * g.N + p, make_double2(0.0, 0.0));
                 }
             }
         }
-        if (fallback) {
-            const int slot = atomicAdd(a.out_count, 1);
-            a.out_list[slot] = l;
+        if (fallback || edge) {
+            // a batch sends a problem of 17 to 32 members whose count is exact (staged, no edge-tap
+            // member, no wrap left to the group tiers) straight to its 32-member tier
+            const bool wide = a.out_list2 && !edge && staged && !(wrap && !circ) && n > 16 && n <= 32;
+            int* list = wide ? a.out_list2 : a.out_list;
+            const int slot = atomicAdd(wide ? a.out_count2 : a.out_count, 1);
+            list[slot] = l;
         } else if (n == 0) {
             ++st_empty;
         } else {
@@ -1161,13 +1367,12 @@ int launch_solve_tier(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, int nl
         a.tables_in_lds = 1;
         int64_t b1 = (g.G + (128 / nl) - 1) / (128 / nl);
         // A list tier's problems are counted on the device, so its grid is sized for the longest
-        // list; workgroups past the list exit at once.  Their LDS (matrices plus the Q table, about
-        // 37, 53 and 86 KB for 16, 32 and 64 lanes) still bounds how many are resident per CU, so
-        // the cap is one dispatch round of 256 CUs: 4, 3 and 1 workgroups per CU.
-        const int64_t cap1 = !a.in_list ? 4096 : nl == 16 ? 1024 : nl == 32 ? 768 : 256;
+        // list; workgroups past the list exit at once.  Their registers (16-lane tier: two waves
+        // per SIMD) and LDS (wide tier: the Q table and two 64 x 65 matrices, about 88 KB) bound how
+        // many are resident per CU, so the cap is one dispatch round of 256 CUs: 4 and 1 per CU.
+        const int64_t cap1 = !a.in_list ? 4096 : nl == 16 ? 1024 : 256;
         if (b1 > cap1) b1 = cap1;
         if (nl == 16) hipLaunchKernelGGL((k_solve_r1<16>), dim3((unsigned)b1), dim3(128), shm, s, g, nd, kt, a);
-        else if (nl == 32) hipLaunchKernelGGL((k_solve_r1<32>), dim3((unsigned)b1), dim3(128), shm, s, g, nd, kt, a);
         else hipLaunchKernelGGL((k_solve_r1<64>), dim3((unsigned)b1), dim3(128), shm, s, g, nd, kt, a);
         return (int)b1;
     }

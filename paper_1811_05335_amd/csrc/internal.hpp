@@ -13,6 +13,13 @@
 
 namespace infft {
 
+// Pointers read from device memory (the job tables of the batch kernels) are generic to the
+// compiler, which then emits flat instructions, whose completion is counted with the LDS operations
+// (an LDS wait also waits for them).  Accesses to arrays that always lie in global memory go
+// through this cast and become global instructions.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> glb(T* p) { return (gptr<T>)p; }
+
 // ------------------------------------------------------------------ complex helpers
 
 template <typename R> struct CxT;
@@ -98,8 +105,10 @@ __host__ __device__ inline bool edge_tap_member(double u, int m) {
 // One entry of B_opt: the FP64 copy and the FP32 copy, each where the launch writes it (an FP32
 // plan's B optimisation writes only the FP32 copy; its FP64 values are recomputed on demand).
 __device__ inline void put_bopt(double2* B64, float2* B32, int64_t idx, double2 v) {
-    if (B64) B64[idx] = v;
-    if (B32) B32[idx] = make_float2((float)v.x, (float)v.y);
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    if (B64) *(gptr<d2v>)(B64 + idx) = d2v{v.x, v.y};
+    if (B32) *(gptr<f2v>)(B32 + idx) = f2v{(float)v.x, (float)v.y};
 }
 
 struct NodesDev {
@@ -168,13 +177,13 @@ __device__ inline void gather_1d(const Geo& g, const NodesDev& nd, int l, int la
     const int clo = l - w2 + 1;
     int s0, e0, s1 = 0, e1 = 0;
     if (clo >= 0) {
-        s0 = nd.start[clo];
-        e0 = nd.start[l + 1];
+        s0 = glb(nd.start)[clo];
+        e0 = glb(nd.start)[l + 1];
     } else {
-        s0 = nd.start[clo + Ms];
-        e0 = nd.start[Ms];
-        s1 = nd.start[0];
-        e1 = nd.start[l + 1];
+        s0 = glb(nd.start)[clo + Ms];
+        e0 = glb(nd.start)[Ms];
+        s1 = glb(nd.start)[0];
+        e1 = glb(nd.start)[l + 1];
     }
     const int n0 = e0 - s0, n1 = e1 - s1;
     if (lane < n0) my_p = s0 + lane;
@@ -182,10 +191,10 @@ __device__ inline void gather_1d(const Geo& g, const NodesDev& nd, int l, int la
     n = n0 + n1;
     int ce = l - w2;
     if (ce < 0) ce += Ms;
-    const int s = nd.start[ce], e = nd.start[ce + 1];
+    const int s = glb(nd.start)[ce], e = glb(nd.start)[ce + 1];
     for (int base = s; base < e; base += NL) {
         const int p = base + lane;
-        const bool mem = p < e && edge_tap_member(nd.us[p], g.m);
+        const bool mem = p < e && edge_tap_member(glb(nd.us)[p], g.m);
         const uint64_t gm = (__ballot(mem) >> gbase) & gmask;
         const int cnt = __popcll(gm);
         const int k = lane - n;

@@ -32,7 +32,7 @@ __device__ inline void stage_to_lds(double* dst, const double* __restrict__ src,
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int i = i0 + k * blockDim.x;
-            v[k] = (i < n) ? src[i] : 0.0;
+            v[k] = (i < n) ? glb(src)[i] : 0.0;
         }
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -175,7 +175,7 @@ __device__ inline void solve_group_body(const Geo& g, const NodesDev& nd, const 
     unsigned long long st_min = ULLONG_MAX, st_max = 0, st_fail = 0, st_empty = 0, st_over = 0;
 
     for (int64_t qi = gid; qi < count; qi += ngroups) {
-        const int l = a.in_list ? a.in_list[qi] : (int)qi;
+        const int l = a.in_list ? glb(a.in_list)[qi] : (int)qi;
         int n = 0, my_p = 0;
         if (D == 1) gather_1d(g, nd, l, lane, NL, gbase, gmask, n, my_p);
         else gather_2d(g, nd, l, lane, NL, gbase, gmask, n, my_p);
@@ -206,19 +206,19 @@ __device__ inline void solve_group_body(const Geo& g, const NodesDev& nd, const 
         double2 y = make_double2(0.0, 0.0);
         if (act) {
             if (D == 1) {
-                int tau0 = l - nd.l0s[my_p];
+                int tau0 = l - glb(nd.l0s)[my_p];
                 if (tau0 < 0) tau0 += g.Ms[0];
-                z0 = (double)tau0 - nd.us[my_p];
+                z0 = (double)tau0 - glb(nd.us)[my_p];
                 my_tau = tau0;
                 y = cconj(tay_eval(tK0, kt.qK, z0));
             } else {
                 const int lc0 = l / g.Ms[1], lc1 = l - lc0 * g.Ms[1];
-                int tau0 = lc0 - nd.l0s[(int64_t)my_p * 2];
+                int tau0 = lc0 - glb(nd.l0s)[(int64_t)my_p * 2];
                 if (tau0 < 0) tau0 += g.Ms[0];
-                int tau1 = lc1 - nd.l0s[(int64_t)my_p * 2 + 1];
+                int tau1 = lc1 - glb(nd.l0s)[(int64_t)my_p * 2 + 1];
                 if (tau1 < 0) tau1 += g.Ms[1];
-                z0 = (double)tau0 - nd.us[(int64_t)my_p * 2];
-                z1 = (double)tau1 - nd.us[(int64_t)my_p * 2 + 1];
+                z0 = (double)tau0 - glb(nd.us)[(int64_t)my_p * 2];
+                z1 = (double)tau1 - glb(nd.us)[(int64_t)my_p * 2 + 1];
                 my_tau = tau0 * W + tau1;
                 y = cconj(cmul(tay_eval(kt.K[0], kt.qK, z0), tay_eval(kt.K[1], kt.qK, z1)));
             }
@@ -325,12 +325,13 @@ __device__ inline void solve_group_body(const Geo& g, const NodesDev& nd, const 
 //     b = t + u (d - c w^* t) / (1 + c s),
 // whose denominator is at least one.
 
-__device__ inline double tay_eval_r(const double* __restrict__ tab, int qmax, double z) {
+template <typename P>
+__device__ inline double tay_eval_r(P tab, int qmax, double z) {
     const double az = fabs(z);
     int q = (int)rint(az * (double)TAY_S);
     if (q > qmax) q = qmax;
     const double e = az - (double)q * (1.0 / TAY_S);
-    const double* c = tab + (int64_t)q * TAY_NC;
+    const auto c = tab + (int64_t)q * TAY_NC;
     double acc = c[TAY_NC - 1];
 #pragma unroll
     for (int p = TAY_NC - 2; p >= 0; --p) acc = fma(acc, e, c[p]);
@@ -346,9 +347,9 @@ __device__ inline void zero_members_1d(const Geo& g, const NodesDev& nd, int l, 
     for (int c = 0; c <= w2; ++c) {
         int cell = lo + c;
         if (cell >= Ms) cell -= Ms;
-        const int s = nd.start[cell], e = nd.start[cell + 1];
+        const int s = glb(nd.start)[cell], e = glb(nd.start)[cell + 1];
         for (int p = s + lane; p < e; p += NL) {
-            int tau = l - nd.l0s[p];
+            int tau = l - glb(nd.l0s)[p];
             if (tau < 0) tau += Ms;
             put_bopt(a.B64, a.B32, (int64_t)tau * g.N + p, make_double2(0.0, 0.0));
         }
@@ -400,13 +401,13 @@ __device__ __forceinline__ void gather_1d_rows(const Geo& g, const NodesDev& nd,
     const int clo = l - w2 + 1;
     int s0, e0, s1 = 0, e1 = 0;
     if (clo >= 0) {
-        s0 = nd.start[clo];
-        e0 = nd.start[l + 1];
+        s0 = glb(nd.start)[clo];
+        e0 = glb(nd.start)[l + 1];
     } else {
-        s0 = nd.start[clo + Ms];
-        e0 = nd.start[Ms];
-        s1 = nd.start[0];
-        e1 = nd.start[l + 1];
+        s0 = glb(nd.start)[clo + Ms];
+        e0 = glb(nd.start)[Ms];
+        s1 = glb(nd.start)[0];
+        e1 = glb(nd.start)[l + 1];
     }
     const int n0 = e0 - s0, n1 = e1 - s1;
 #pragma unroll
@@ -417,10 +418,10 @@ __device__ __forceinline__ void gather_1d_rows(const Geo& g, const NodesDev& nd,
     n = n0 + n1;
     int ce = l - w2;
     if (ce < 0) ce += Ms;
-    const int s = nd.start[ce], e = nd.start[ce + 1];
+    const int s = glb(nd.start)[ce], e = glb(nd.start)[ce + 1];
     for (int base = s; base < e; base += 16) {
         const int p = base + lane;
-        const bool mem = p < e && edge_tap_member(nd.us[p], g.m);
+        const bool mem = p < e && edge_tap_member(glb(nd.us)[p], g.m);
         const uint32_t gm = (uint32_t)(__ballot(mem) >> gbase) & 0xffffu;
         const int cnt = __popc(gm);
 #pragma unroll
@@ -454,8 +455,8 @@ template <int R> struct GeRows {
 
 // Column J of the lane's rows of A0 = M_sigma Qs(z_j - z_i) + lambda I (identity rows and columns
 // past n): the table rows, then the Horner steps.
-template <int R, int J>
-__device__ __forceinline__ void ge_gram_load(const double (&z)[R], const KTabDev& kt, const double* __restrict__ tQ,
+template <int R, int J, typename TP>
+__device__ __forceinline__ void ge_gram_load(const double (&z)[R], const KTabDev& kt, TP tQ,
                                     double (&e)[R], double (&cf)[R][TAY_NC]) {
     const double zj = row_bcast<J % 16>(z[J / 16]);
 #pragma unroll
@@ -465,7 +466,7 @@ __device__ __forceinline__ void ge_gram_load(const double (&z)[R], const KTabDev
         int q = (int)rint(az * (double)TAY_S);
         if (q > kt.qQ) q = kt.qQ;
         e[r] = az - (double)q * (1.0 / TAY_S);
-        const double* c = tQ + (int64_t)q * TAY_NC;
+        const auto c = tQ + (int64_t)q * TAY_NC;
 #pragma unroll
         for (int p = 0; p < TAY_NC; ++p) cf[r][p] = c[p];
     }
@@ -489,18 +490,18 @@ __device__ __forceinline__ void ge_gram_store(GeRows<R>& S, int lane, int n, con
 
 // Columns J .. J+JB-1: every table row of the step is loaded before the first Horner step, and no
 // later step's loads are hoisted above it (registers).
-template <int R, int J, int... B>
+template <int R, int J, typename TP, int... B>
 __device__ __forceinline__ void ge_gram(GeRows<R>& S, const double (&z)[R], int lane, int n, const KTabDev& kt,
-                                        const double* __restrict__ tQ, std::integer_sequence<int, B...>) {
+                                        TP tQ, std::integer_sequence<int, B...>) {
     double e[sizeof...(B)][R], cf[sizeof...(B)][R][TAY_NC];
     (ge_gram_load<R, J + B>(z, kt, tQ, e[B], cf[B]), ...);
     (ge_gram_store<R, J + B>(S, lane, n, kt, e[B], cf[B]), ...);
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int R, int JB, int... Jb>
+template <int R, int JB, typename TP, int... Jb>
 __device__ __forceinline__ void ge_gram_all(GeRows<R>& S, const double (&z)[R], int lane, int n, const KTabDev& kt,
-                                   const double* __restrict__ tQ, std::integer_sequence<int, Jb...>) {
+                                   TP tQ, std::integer_sequence<int, Jb...>) {
     (ge_gram<R, Jb * JB>(S, z, lane, n, kt, tQ, std::make_integer_sequence<int, JB>{}), ...);
 }
 
@@ -603,9 +604,9 @@ __device__ __forceinline__ void ge_back_all(const GeRows<R>& S, double (&zr)[R],
 // the lane's own row.  Every exchange is a DPP broadcast from the pivot lane; rows past n are padded
 // with the identity.  A problem with more than 16 R members goes to a.out_list, or without one is
 // counted as oversized and its column zeroed.
-template <int R>
+template <int R, typename TP>
 __device__ __forceinline__ void r1_problem_ge(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a, int l,
-                                     const double* __restrict__ tQ, GroupStats& st) {
+                                     TP tQ, GroupStats& st) {
     constexpr int NC = 16 * R;
     const int lane = threadIdx.x & 15;
     const int gbase = (threadIdx.x & 63) - lane;
@@ -643,11 +644,11 @@ __device__ __forceinline__ void r1_problem_ge(const Geo& g, const NodesDev& nd, 
         S.dinv[r] = 1.0;
         tau[r] = 0;
         if (16 * r + lane < n) {
-            int tr = l - nd.l0s[my_p[r]];
+            int tr = l - glb(nd.l0s)[my_p[r]];
             if (tr < 0) tr += g.Ms[0];
             tau[r] = tr;
-            z[r] = (double)tr - nd.us[my_p[r]];
-            S.t[r] = tay_eval_r(kt.Ks, kt.qK, z[r]);
+            z[r] = (double)tr - glb(nd.us)[my_p[r]];
+            S.t[r] = tay_eval_r(glb(kt.Ks), kt.qK, z[r]);
             sincospi(z[r] * kt.inv_sigma, &S.ui[r], &S.ur[r]);
         }
     }
@@ -698,9 +699,9 @@ __device__ __forceinline__ void r1_problem_ge(const Geo& g, const NodesDev& nd, 
 
 // The same problem with the group's (n x n) matrix in LDS at Ag, row i of lane i at Ai (wide
 // groups: 64 rows in registers would spill); s_y / s_z are the workgroup's exchange slots.
-template <int NL>
+template <int NL, typename TP>
 __device__ inline void r1_problem_lds(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a,
-                                      int l, const double* __restrict__ tQ, double* Ag, double* Ai,
+                                      int l, TP tQ, double* Ag, double* Ai,
                                       double (*s_y)[128], double* s_z, GroupStats& st) {
     constexpr int LDA = NL + 1;
     const int lane = threadIdx.x & (NL - 1);
@@ -735,10 +736,10 @@ __device__ inline void r1_problem_lds(const Geo& g, const NodesDev& nd, const KT
     double z = 0.0, t = 0.0, wr = 0.0, wi = 0.0;
     int tau = 0;
     if (act) {
-        tau = l - nd.l0s[my_p];
+        tau = l - glb(nd.l0s)[my_p];
         if (tau < 0) tau += g.Ms[0];
-        z = (double)tau - nd.us[my_p];
-        t = tay_eval_r(kt.Ks, kt.qK, z);
+        z = (double)tau - glb(nd.us)[my_p];
+        t = tay_eval_r(glb(kt.Ks), kt.qK, z);
         sincospi(z * kt.inv_sigma, &wi, &wr);
     }
     double ur = wr, ui = wi;
@@ -755,7 +756,7 @@ __device__ inline void r1_problem_lds(const Geo& g, const NodesDev& nd, const KT
                 int q = (int)rint(az * (double)TAY_S);
                 if (q > kt.qQ) q = kt.qQ;
                 e[k] = az - (double)q * (1.0 / TAY_S);
-                const double* c = tQ + (int64_t)q * TAY_NC;
+                const auto c = tQ + (int64_t)q * TAY_NC;
 #pragma unroll
                 for (int p = 0; p < TAY_NC; ++p) cf[k][p] = c[p];
             }
@@ -857,10 +858,9 @@ __device__ inline void r1_problem_lds(const Geo& g, const NodesDev& nd, const KT
 // the registers).  s_A holds the LDS matrices of the workgroup's groups (unused below 64).
 template <int CAP> constexpr int group_lanes() { return CAP <= 32 ? 16 : CAP; }
 
-template <int CAP>
+template <int CAP, typename TP>
 __device__ inline void r1_solve(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a, int l,
-                                const double* __restrict__ tQ, double* s_A, double (*s_x)[128], double* s_z,
-                                GroupStats& st) {
+                                TP tQ, double* s_A, double (*s_x)[128], double* s_z, GroupStats& st) {
     if constexpr (CAP > 32) {
         double* Ag = s_A + (threadIdx.x / CAP) * CAP * (CAP + 1);
         r1_problem_lds<CAP>(g, nd, kt, a, l, tQ, Ag, Ag + (threadIdx.x & (CAP - 1)) * (CAP + 1), s_x, s_z, st);
@@ -898,7 +898,7 @@ __device__ inline void solve_r1_body(const Geo& g, const NodesDev& nd, const KTa
     }
     GroupStats st;
     for (int64_t qi = gid; qi < count; qi += ngroups) {
-        const int l = a.in_list ? a.in_list[qi] : (int)qi;
+        const int l = a.in_list ? glb(a.in_list)[qi] : (int)qi;
         r1_solve<NL>(g, nd, kt, a, l, tQ, s_A, s_x, s_z, st);
     }
     write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, blk, st.mn, st.mx, st.fail, st.empty, st.over);
@@ -929,7 +929,7 @@ __device__ inline void solve_r1_body_wide(const Geo& g, const NodesDev& nd, cons
     GroupStats st;
     for (int64_t base = (blk * 2 + wave) * 4; base < count; base += nblk * 8) {
         const int64_t qi = base + grp;
-        const int l = qi < count ? a.in_list[qi] : -1;
+        const int l = qi < count ? glb(a.in_list)[qi] : -1;
         int n = 0;
         if (l >= 0) {
             int p1[1];
@@ -981,7 +981,7 @@ __global__ void __launch_bounds__(128, 2) k_solve_r1_flat(const SolveJob* __rest
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int jj = threadIdx.x * PER + k;
-            c[k] = jj < nj ? *jobs[j0 + jj].a.in_count : 0;
+            c[k] = jj < nj ? glb(jobs[j0 + jj].a.in_count)[0] : 0;
             sum += c[k];
         }
         const int wl = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1033,8 +1033,8 @@ __global__ void __launch_bounds__(128, 2) k_solve_r1_flat(const SolveJob* __rest
                 cur = lo;
             }
             const SolveJob& J = jobs[j0 + lo];
-            const int l = J.a.in_list[q - s_pre[lo]];
-            r1_solve<NL>(J.g, J.nd, J.kt, J.a, l, J.kt.Qs, s_A, s_x, s_z, st);
+            const int l = glb(J.a.in_list)[q - s_pre[lo]];
+            r1_solve<NL>(J.g, J.nd, J.kt, J.a, l, glb(J.kt.Qs), s_A, s_x, s_z, st);
         }
         flush();
         __syncthreads();   // s_pre and s_wsum are refilled for the next problems
@@ -1096,10 +1096,10 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
     if (threadIdx.x == 0) {
         const int lo = max(L0 - w2 + 1, 0);
         const int hi = min(L0 + T1_TPB, Ms);
-        s_range[0] = nd.start[lo];
-        s_range[1] = nd.start[hi];
-        s_range[2] = circ ? nd.start[Ms - w2 + 1] : 0;
-        s_range[3] = circ ? nd.start[Ms] : 0;
+        s_range[0] = glb(nd.start)[lo];
+        s_range[1] = glb(nd.start)[hi];
+        s_range[2] = circ ? glb(nd.start)[Ms - w2 + 1] : 0;
+        s_range[3] = circ ? glb(nd.start)[Ms] : 0;
     }
     __syncthreads();
     const int P0 = s_range[0];
@@ -1110,12 +1110,12 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
     for (int i = threadIdx.x; i < nnode; i += blockDim.x) {
         const bool tail = i < ntail;
         const int p = tail ? tS + i : P0 + (i - ntail);
-        s_l0[i] = nd.l0s[p] - (tail ? Ms : 0);
-        s_u[i] = nd.us[p];
+        s_l0[i] = glb(nd.l0s)[p] - (tail ? Ms : 0);
+        s_u[i] = glb(nd.us)[p];
         // e^{-i pi t / sigma}, the integer part reduced exactly modulo 2 M_sigma
-        const int64_t lm = ((int64_t)nd.l0s[p] * g.M[0]) % (2 * (int64_t)Ms);
+        const int64_t lm = ((int64_t)glb(nd.l0s)[p] * g.M[0]) % (2 * (int64_t)Ms);
         double sn, cs;
-        sincospi((double)lm / (double)Ms + nd.us[p] * kt.inv_sigma, &sn, &cs);
+        sincospi((double)lm / (double)Ms + glb(nd.us)[p] * kt.inv_sigma, &sn, &cs);
         s_phi[i] = make_double2(cs, -sn);
     }
     __syncthreads();
@@ -1124,7 +1124,7 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
         double v = 0.0;
         // t_{i+d} - t_i with the integer parts subtracted exactly
         if (i + d < nnode)
-            v = kt.scaleG * tay_eval_r(kt.Qs, kt.qQ, (double)(s_l0[i + d] - s_l0[i]) + (s_u[i + d] - s_u[i]));
+            v = kt.scaleG * tay_eval_r(glb(kt.Qs), kt.qQ, (double)(s_l0[i + d] - s_l0[i]) + (s_u[i + d] - s_u[i]));
         if (d == 0) v += kt.lam;
         s_band[e] = v;
     }
@@ -1139,13 +1139,13 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
         const bool wrap = clo < 0;
         int s0, n0, s1 = 0, n1 = 0;
         if (!wrap) {
-            s0 = nd.start[clo];
-            n0 = nd.start[l + 1] - s0;
+            s0 = glb(nd.start)[clo];
+            n0 = glb(nd.start)[l + 1] - s0;
         } else {
-            s0 = nd.start[clo + Ms];
-            n0 = nd.start[Ms] - s0;
-            s1 = nd.start[0];
-            n1 = nd.start[l + 1] - s1;
+            s0 = glb(nd.start)[clo + Ms];
+            n0 = glb(nd.start)[Ms] - s0;
+            s1 = glb(nd.start)[0];
+            n1 = glb(nd.start)[l + 1] - s1;
         }
         const int n = n0 + n1;
         // unstaged node ranges, oversized problems and (on short grids) windows that wrap around
@@ -1157,9 +1157,9 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
             // 2m of every other node belongs to no problem and is zeroed here
             int ce = l - w2;
             if (ce < 0) ce += Ms;
-            const int es = nd.start[ce], ee = nd.start[ce + 1];
+            const int es = glb(nd.start)[ce], ee = glb(nd.start)[ce + 1];
             for (int p = es; p < ee; ++p) {
-                if (edge_tap_member(nd.us[p], g.m)) {
+                if (edge_tap_member(glb(nd.us)[p], g.m)) {
                     edge = true;
                 } else {
                     put_bopt(a.B64, a.B32, (int64_t)w2 * g.N + p, make_double2(0.0, 0.0));

@@ -1068,6 +1068,18 @@ __device__ inline double rsqrt_refined(double x) {
     }
     return r;
 }
+// Appends l to list for every lane with f set: one atomic on the counter per wave, each lane's slot
+// from its rank among the wave's flagged lanes.  Called by whole waves.
+__device__ inline void append_wave(int* list, int* count, bool f, int l) {
+    const uint64_t m = __ballot(f);
+    if (m == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count, __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (f) glb(list)[base + __popcll(m & ((1ull << lane) - 1ull))] = l;
+}
 constexpr int T1_NODECAP = 224;   // staged nodes per workgroup (density up to ~1.6 per cell)
 
 template <int NMAX>
@@ -1133,6 +1145,7 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
 
     const double c1 = (double)Ms * kt.dM * kt.dM;
     unsigned long long st_min = ULLONG_MAX, st_max = 0, st_fail = 0, st_empty = 0, st_over = 0;
+    int push_l = 0;   // 1: to a.out_list, 2: to a.out_list2
     if (l < Ms) {
         // members: cells l-2m+1 .. l, one range, or two when the window wraps (l < 2m-1)
         const int clo = l - w2 + 1;
@@ -1170,9 +1183,7 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
             // a batch sends a problem of 17 to 32 members whose count is exact (staged, no edge-tap
             // member, no wrap left to the group tiers) straight to its 32-member tier
             const bool wide = a.out_list2 && !edge && staged && !(wrap && !circ) && n > 16 && n <= 32;
-            int* list = wide ? a.out_list2 : a.out_list;
-            const int slot = atomicAdd(wide ? a.out_count2 : a.out_count, 1);
-            list[slot] = l;
+            push_l = wide ? 2 : 1;
         } else if (n == 0) {
             ++st_empty;
         } else {
@@ -1287,6 +1298,10 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
             }
         }
     }
+    // problems for the group tiers, appended with one atomic per wave and list (a list's counter is
+    // shared by every workgroup of the problem: one atomic per lane would serialise on it)
+    append_wave(a.out_list, a.out_count, push_l == 1, l);
+    if (a.out_list2) append_wave(a.out_list2, a.out_count2, push_l == 2, l);
     write_block_stats(a.stat_rec + (int64_t)a.stat_off * 5, blk, st_min, st_max, st_fail, st_empty, st_over);
 }
 

@@ -1131,14 +1131,18 @@ __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTa
         s_phi[i] = make_double2(cs, -sn);
     }
     __syncthreads();
+    // offset-major order: the lanes of a wave take one offset d and consecutive nodes i, whose
+    // arguments t_{i+d} - t_i lie close together, so a wave's table loads touch few cache lines
+    // (node order would send each lane to a different part of the table)
+    const uint32_t mg = (uint32_t)(0xFFFFFFFFu / (uint32_t)max(nnode, 1)) + 1u;   // e / nnode = e mg >> 32
     for (int e = threadIdx.x; e < nnode * NMAX; e += blockDim.x) {
-        const int i = e / NMAX, d = e - i * NMAX;
+        const int d = (int)__umulhi((uint32_t)e, mg), i = e - d * nnode;
         double v = 0.0;
         // t_{i+d} - t_i with the integer parts subtracted exactly
         if (i + d < nnode)
             v = kt.scaleG * tay_eval_r(glb(kt.Qs), kt.qQ, (double)(s_l0[i + d] - s_l0[i]) + (s_u[i + d] - s_u[i]));
         if (d == 0) v += kt.lam;
-        s_band[e] = v;
+        s_band[i * NMAX + d] = v;
     }
     for (int k = threadIdx.x; k <= NMAX * (NMAX - 1); k += blockDim.x) s_ident[k] = (k % NMAX == 0) ? 1.0 : 0.0;
     __syncthreads();

@@ -399,7 +399,14 @@ __global__ void __launch_bounds__(256) k_spread_zero_split(Geo g, SpreadWork wk,
 // over the nodes of cells c0+t-2m .. c0+t, a contiguous range of the staged nodes.
 
 constexpr int SP1_TS = 256;     // cells per tile (threads per workgroup)
-constexpr int SP1_CAP = 256;    // staged nodes per chunk
+// Staged nodes per chunk: 256, and for one right-hand side as many as about 40 KB of LDS holds (up
+// to 512), so that a tile at about one node per cell (256 cells plus the 2m-cell halo) is staged
+// in one chunk, with one latency chain of loads, instead of a full chunk and a short second one.
+template <typename Wt, typename C, int W, int RC> constexpr int sp1_cap() {
+    constexpr int per = W * (int)sizeof(Wt) + RC * (int)sizeof(C) + (int)sizeof(int);
+    constexpr int c = 40960 / per / 64 * 64;
+    return (RC > 1 || c < 256) ? 256 : (c > 512 ? 512 : c);
+}
 
 // Position of the first node of tile-relative cell `rel` in the tile's node sequence, and the
 // sorted position of sequence index i.  lo = c0 - 2m may be negative (the window wraps).
@@ -430,6 +437,7 @@ __device__ inline void spread1d_tile(const Geo& g, const NodesDev& nd, const cx<
                                      int nrhs, int tile) {
     using C = cx<R>;
     using Wt = typename std::conditional<USEB, C, R>::type;
+    constexpr int SP1_CAP = sp1_cap<Wt, C, W, RC>();
     __shared__ Wt s_w[SP1_CAP][W];
     __shared__ C s_f[SP1_CAP][RC];
     __shared__ int s_rel[SP1_CAP];

@@ -517,7 +517,7 @@ void launch_solve_t1_batched(const SolveJob* jobs, const int2* t1_map, int t1_bl
                              hipStream_t s);
 void launch_batch_solve_reset(const SolveJob* jobs, int njobs, hipStream_t s);
 void launch_batch_counts(const SolveJob* jobs, int njobs, int* out, hipStream_t s);
-constexpr int T1_CELLS = 128;   // cells per workgroup of the thread-per-problem tier
+constexpr int T1_CELLS = 256;   // cells per workgroup of the thread-per-problem tier
 // Group tier (nl = 16, 32 or 64) over the lists of all problems of a batch as one flat list.
 void launch_solve_tier_batched(const SolveJob* jobs, int njobs, int nl, int blocks, hipStream_t s);
 int launch_solve_thread_1d(const Geo& g, NodesDev nd, KTabDev kt, SolveArgs a, hipStream_t s);

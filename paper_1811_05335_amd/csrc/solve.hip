@@ -1080,7 +1080,7 @@ __device__ inline void append_wave(int* list, int* count, bool f, int l) {
     base = __shfl(base, leader, 64);
     if (f) glb(list)[base + __popcll(m & ((1ull << lane) - 1ull))] = l;
 }
-constexpr int T1_NODECAP = 224;   // staged nodes per workgroup (density up to ~1.6 per cell)
+constexpr int T1_NODECAP = 448;   // staged nodes per workgroup (density up to ~1.7 per cell)
 
 template <int NMAX>
 __device__ inline void solve_t1_body(const Geo& g, const NodesDev& nd, const KTabDev& kt, const SolveArgs& a,

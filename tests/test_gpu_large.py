@@ -47,7 +47,7 @@ def test_large_problems_match_oracle(M, N, d, m, ncl, half, rho):
     big = np.nonzero(sizes > 32)[0]
     g = W.rng(3)
     small = g.choice(np.nonzero((sizes > 0) & (sizes <= 32))[0], size=32, replace=False)
-    # 1-D: every problem of 17..32 members (the wavefront tier takes them after the 16-lane one)
+    # 1-D: every problem of 17..32 members (16-lane groups with two rows per lane solve them)
     mid = np.nonzero((sizes > 16) & (sizes <= 32))[0] if d == 1 else np.zeros(0, dtype=np.int64)
     ls = np.unique(np.concatenate([big, small, mid]))
     check_columns(x, p, rho, mem, ls, rows_gpu)

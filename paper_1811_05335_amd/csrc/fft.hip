@@ -12,8 +12,12 @@
 
 namespace infft {
 
-constexpr int FFT_E32 = 16;  // complex elements per thread (LDS buffer = 256 * E elements)
-constexpr int FFT_E64 = 8;
+// Complex elements per thread at most: a workgroup holds FFT_THREADS * E elements, 4096 (FP32) or
+// 2048 (FP64).  512 threads with fewer elements each keep more loads of a pass in flight than 256
+// threads with twice as many (1-D 2^17-point passes: step 0.149 -> 0.145 ms; 1024 threads were
+// slower again).
+constexpr int FFT_E32 = 8;
+constexpr int FFT_E64 = 4;
 
 size_t fft_lds_bytes(const FftPass& p, size_t csize) {
     return ((size_t)p.rows * (p.n + 1) + (size_t)p.n) * csize;

@@ -350,7 +350,7 @@ __device__ inline void big_substitute(const BigProb& P, const double2* A, double
 
 // ------------------------------------------------------------------ FFT pass description
 
-constexpr int FFT_THREADS = 256;
+constexpr int FFT_THREADS = 512;
 
 // Workgroups of a launch go to the eight XCDs (each with its own L2) in turn: workgroup b runs on
 // XCD b mod 8.  This maps the launch index to a logical block so that each XCD takes one

@@ -617,3 +617,54 @@ def test_ansatz1_reconstruction_and_inverse_adjoint_example_3_14():
     assert r_inv < 1e-2 and r_adj < 1e-2 and r_inv < 1e-1 * r_plain
     hh = W.complex_normal(g, (M,))
     assert abs(np.vdot(f, bopt.apply_adjoint(x, hh, rows, p)) - np.vdot(fc, hh)) < 1e-12 * np.linalg.norm(f) * np.linalg.norm(hh) * np.abs(rows).max() * M
+
+
+# ------------------------------------------------------------------ Theorem 4.3 (frame link, §4.2.1)
+
+def _frame_terms(M, sigma, m, N, seed):
+    """The quantities of Theorem 4.3 from the oracle's matrices: B (2.6); Phi = Phi_l2 of Section 4.2,
+    conj K(x_j - l / M_sigma) with the kernel K of (3.15); Psi = (psi_l(k)) of the discrete frames,
+    e^{-2 pi i k l / M_sigma} / (M_sigma w_hat(-k)); c = B^* f (the adjoint NFFT's coefficients) and
+    d = Phi^+ f (the frame approximation's); and the vector of 1 / w_hat(-k)."""
+    p = nfft.Params((M,), sigma, m)
+    g = W.rng(seed)
+    x = g.uniform(-0.5, 0.5, N)
+    Ms = p.Ms[0]
+    B = nfft.dense_B(x, p)                                    # columns in FFT order of l
+    lpos = np.arange(Ms)
+    lval = np.where(lpos < Ms // 2, lpos, lpos - Ms)
+    Phi = np.conj(bopt.kernel_K_1d((x[:, None] - lval[None, :] / Ms).ravel(), p, 0)).reshape(N, Ms)
+    D = p.deconv(0)                                           # D_k = 1 / (M_sigma w_hat(-k))
+    k = direct.centred(M)
+    Psi = D[:, None] * np.exp(-2j * np.pi * np.outer(k, lval) / Ms)
+    w_inv = Ms * D
+    f = W.complex_normal(g, (N,))
+    Pinv = np.linalg.pinv(Phi)
+    return dict(B=B, Phi=Phi, Psi=Psi, w_inv=w_inv, f=f, Pinv=Pinv, c=B.T @ f, d=Pinv @ f, Ms=Ms, N=N)
+
+
+@pytest.mark.parametrize("M,sigma,N,case", [(16, 2.0, 10, "ii"), (16, 2.0, 12, "ii"),
+                                            (16, 1.0, 40, "i"), (24, 1.0, 60, "i")])
+def test_theorem_4_3_frame_distance_bounds(M, sigma, N, case):
+    """Theorem 4.3: ||h~ - h~~||_2 with h~ = Psi B^* f and h~~ = Psi Phi^+ f is at most
+    ||w_hat||_2 / sqrt(M_sigma) times ||Phi B^* - I_N||_F ||Phi^+ f||_2 (4.11, M_sigma < N) or
+    ||B^* Phi - I_{M_sigma}||_F ||Phi^+ f||_2 (4.12, M_sigma > N).  Pinned with the proof's exact
+    steps: ||Psi||_F equals ||w_hat||_2 / sqrt(M_sigma), and c - d equals
+    Phi^+ (Phi B^* - I) f (full column rank of Phi: sigma = 1, N > M_sigma) or
+    (B^* Phi - I) Phi^+ f (full row rank: N < M; with sigma = 2 Phi has rank at most M < M_sigma,
+    so case (i) needs sigma = 1)."""
+    t = _frame_terms(M, sigma, 3, N, seed=90 + N)
+    Psi, c, d, Ms = t["Psi"], t["c"], t["d"], t["Ms"]
+    fac = np.linalg.norm(t["w_inv"]) / np.sqrt(Ms)
+    assert np.linalg.norm(Psi) == pytest.approx(fac, rel=1e-12)
+    lhs = np.linalg.norm(Psi @ (c - d))
+    if case == "i":
+        assert Ms < N and np.linalg.matrix_rank(t["Phi"]) == Ms
+        E = t["Phi"] @ t["B"].T - np.eye(N)
+        assert rel(c - d, t["Pinv"] @ (E @ t["f"])) < 1e-10
+    else:
+        assert Ms > N and np.linalg.matrix_rank(t["Phi"]) == N
+        E = t["B"].T @ t["Phi"] - np.eye(Ms)
+        assert rel(c - d, E @ d) < 1e-10
+    bound = fac * np.linalg.norm(E) * np.linalg.norm(d)
+    assert lhs <= bound * (1 + 1e-12)

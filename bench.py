@@ -765,7 +765,8 @@ def main():
             "parallelism": "single GPU",
         },
         "precompute_dtype": "f64",
-        "autotuned_fft_rows": r32["tuned"],
+        "autotuned_fft_rows": {k: v for k, v in r32["tuned"].items() if k != "spread_rhs"},
+        "autotuned_spread_rhs": r32["tuned"].get("spread_rhs"),
         "roofline": roof_solve,
         "kernel_classes": kc,
         "dominant_kernel_class": dom_k,

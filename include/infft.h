@@ -274,8 +274,9 @@ void nfft_plan_destroy(infft_plan p);
 /* Autotuner: times each direction of the plan's FFT (coefficients -> grid and back, both passes)
  * with the default shapes and with every pair of 1, 2, 4, 8 and 16 sub-transforms per workgroup
  * (as far as LDS holds them): `reps` runs captured in a HIP graph on a stream of its own and
- * replayed, on the plan's buffers (and a coefficient buffer placed with the plan); keeps the
- * fastest for later calls.  Synchronous; not under graph capture (INFFT_ESTATE).  A no-op for
+ * replayed, on the plan's buffers (and a buffer placed with the plan); keeps the fastest for
+ * later calls.  With max_rhs > 1 it then times the spreading with each chunk of right-hand sides
+ * per pass (infft_autotune_rhs_chunk) the same way.  Synchronous; not under graph capture (INFFT_ESTATE).  A no-op for
  * batch plans, whose launches pack workgroups as full as LDS allows; a workspace plan (which must
  * not allocate, and graph instantiation does) returns to the default shapes. */
 int infft_autotune(infft_plan p, int reps);
@@ -283,6 +284,12 @@ int infft_autotune(infft_plan p, int reps);
 /* Sub-transforms per workgroup the autotuner chose for step `step` (0 or 1) of direction `dir`
  * (0: coefficients -> grid, 1: grid -> coefficients); 0 when not tuned, -1 for bad arguments. */
 int infft_autotune_rows(infft_plan p, int dir, int step);
+
+/* Right-hand sides per pass of the plan's spreading (the adjoint (2.8) and the modified adjoint
+ * (3.32)): in 1-D a cap on the kernel's chunk of 1, 2, 4 or 8 (default 8), in 2-D the chunk of
+ * the LDS tile (default: as many as it holds).  infft_autotune sets it for plans with max_rhs > 1;
+ * 0 for batch plans, -1 for a null plan. */
+int infft_autotune_rhs_chunk(infft_plan p);
 
 /* A batch of nprob independent one-dimensional problems of uneven sizes in one plan (the
  * setting of many small inverse NFFTs): problem i has M[i] coefficients (even) and N[i] nodes;

@@ -110,6 +110,7 @@ def load() -> C.CDLL:
         "infft_profile_begin": (i32, [vp, i32]),
         "infft_autotune": (i32, [vp, i32]),
         "infft_autotune_rows": (i32, [vp, i32, i32]),
+        "infft_autotune_rhs_chunk": (i32, [vp]),
         "infft_profile_end": (i32, [vp, C.POINTER(dbl), C.POINTER(i64)]),
     }
     for name, (res, args) in sig.items():

@@ -1436,17 +1436,19 @@ int plan_layout(infft_plan_s* P, const PlanSpec& S) {
         LTRY(P->alloc(&P->sp_offs, nt));
         LTRY(P->alloc(&P->sp_bsum, scan_blocksum_len(nt)));
     }
-    P->rchunk = spread_rhs_chunk(g);
+    // right-hand sides per spreading pass: 1-D a cap on the kernel's chunk (1, 2, 4 or 8), 2-D the
+    // chunk itself, as many as the LDS tile holds; the autotuner may lower either
+    P->rchunk = g.d == 1 ? 8 : spread_rhs_chunk(g);
     LTRY(P->alloc(&P->B64, (int64_t)T * N));
     if (P->prec == INFFT_F32) LTRY(P->alloc(&P->B32, (int64_t)T * N));
     LTRY(P->alloc(&P->lists, 2 * g.G));
     LTRY(P->alloc(&P->lcount, 8));   // list counters of the solver tiers
     // records: one per block of each solve tier (first tier G/128 blocks at most, the others capped)
     LTRY(P->alloc(&P->stat_rec, (g.G / 64 + 8192) * 5));
-    // coefficient buffer of the autotuner (max_rhs x prod(M))
+    // buffer of the autotuner: max_rhs coefficient vectors or sample vectors, whichever is longer
     {
         char* tmp = nullptr;
-        LTRY(P->alloc(&tmp, (int64_t)cs * g.P * P->max_rhs));
+        LTRY(P->alloc(&tmp, (int64_t)cs * std::max<int64_t>(g.P, N) * P->max_rhs));
         P->tune_buf = tmp;
     }
     if (P->ws_mode) {
@@ -2414,8 +2416,8 @@ int infft_autotune(infft_plan p, int reps) {
         p->fft_rows[0][0] = p->fft_rows[0][1] = p->fft_rows[1][0] = p->fft_rows[1][1] = 0;
         return build_schedule(p, R, p->to_grid, p->to_coeff);
     }
-    void* tmp = p->tune_buf;   // max_rhs x prod(M) coefficients, placed with the plan
-    const size_t tbytes = (size_t)R * (size_t)g.P * p->csize();
+    void* tmp = p->tune_buf;   // max_rhs x max(prod(M), N) values, placed with the plan
+    const size_t tbytes = (size_t)R * (size_t)std::max<int64_t>(g.P, g.N) * p->csize();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipStream_t ts = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
@@ -2497,6 +2499,53 @@ int infft_autotune(infft_plan p, int reps) {
         p->fft_rows[dir][0] = best_r[0];
         p->fft_rows[dir][1] = best_r[1];
     }
+    // Right-hand sides per spreading pass (the adjoint's spreading with window weights, max_rhs
+    // right-hand sides from the zeroed buffer, into the plan's grid), timed the same way.
+    // Candidates: powers of two up to the default (8 in 1-D, the LDS tile's capacity in 2-D) and
+    // max_rhs, and the largest itself.
+    const int cmax = std::min(g.d == 1 ? 8 : spread_rhs_chunk(g), R);
+    if (R > 1 && rc == INFFT_OK) {
+        float best = 1e30f;
+        int best_c = p->rchunk;
+        for (int c = 1; c <= cmax && rc == INFFT_OK; c = (c * 2 > cmax && c < cmax) ? cmax : 2 * c) {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            bool ok = hipStreamBeginCapture(ts, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                for (int i = 0; i < reps; ++i) {
+                    if (f32)
+                        launch_spread<float>(g, p->nd, (const float2*)tmp, nullptr, (float2*)p->grid, g.G,
+                                             (float2*)p->h0, (float2*)p->h1, (float2*)p->h01, p->hrs0, p->hrs1,
+                                             p->hrs01, R, c, p->spwork, ts);
+                    else
+                        launch_spread<double>(g, p->nd, (const double2*)tmp, nullptr, (double2*)p->grid, g.G,
+                                              (double2*)p->h0, (double2*)p->h1, (double2*)p->h01, p->hrs0, p->hrs1,
+                                              p->hrs01, R, c, p->spwork, ts);
+                }
+                ok = hipStreamEndCapture(ts, &graph) == hipSuccess && graph;
+            }
+            ok = ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+            float ms = 0.0f;
+            ok = ok && hipGraphLaunch(exec, ts) == hipSuccess;   // warm-up
+            ok = ok && hipEventRecord(e0, ts) == hipSuccess;
+            for (int i = 0; ok && i < 3; ++i) ok = hipGraphLaunch(exec, ts) == hipSuccess;
+            ok = ok && hipEventRecord(e1, ts) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                 hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (!ok) {
+                rc = fail(INFFT_EDEVICE, "autotune graph timing failed");
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                best_c = c;
+            }
+            if (c == cmax) break;
+        }
+        p->rchunk = best_c;
+        grid_holds(p, 0, true);   // the timing runs wrote the grid
+    }
     (void)hipStreamSynchronize(ts);
     (void)hipStreamDestroy(ts);
     (void)hipEventDestroy(e0);
@@ -2508,6 +2557,11 @@ int infft_autotune(infft_plan p, int reps) {
 int infft_autotune_rows(infft_plan p, int dir, int step) {
     if (!p || dir < 0 || dir > 1 || step < 0 || step > 1) return -1;
     return p->fft_rows[dir][step];
+}
+
+int infft_autotune_rhs_chunk(infft_plan p) {
+    if (!p) return -1;
+    return p->batch ? 0 : p->rchunk;
 }
 
 int nfft_plan_batched(infft_plan* out, int nprob, const int64_t* M, const int64_t* N, double sigma, int m,

@@ -692,8 +692,10 @@ void launch_spread(const Geo& g, NodesDev nd, const cx<R>* f, const cx<R>* B, cx
                    cx<R>* h0, cx<R>* h1, cx<R>* h01, int64_t hrs0, int64_t hrs1, int64_t hrs01, int nrhs,
                    int rchunk, SpreadWork wk, hipStream_t s) {
     if (g.d == 1) {
+        // right-hand sides per pass: the largest power of two up to min(nrhs, rchunk, 8)
         const dim3 nb(spread1d_tiles(g)), bl(SP1_TS);
-        INFFT_SPREAD1D_DISPATCH(nrhs, g.m, B != nullptr,
+        const int rcap = rchunk > 0 ? min(nrhs, rchunk) : nrhs;
+        INFFT_SPREAD1D_DISPATCH(rcap, g.m, B != nullptr,
                                 hipLaunchKernelGGL((k_spread1d<R, W, USEB, RC>), nb, bl, 0, s, g, nd, f, B, grid, grs,
                                                    nrhs))
         return;

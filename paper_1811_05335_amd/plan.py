@@ -252,12 +252,15 @@ class NfftPlan:
     def autotune(self, reps: int = 10) -> dict:
         """Times each FFT direction in a HIP graph with the default shapes and with 1..16
         sub-transforms per workgroup per pass, and keeps the fastest; returns the choice per
-        direction and step (0: the default)."""
+        direction and step (0: the default), and the spreading's right-hand sides per pass
+        (`spread_rhs`, tuned when max_rhs > 1)."""
         self._sync_stream()
         check(load().infft_autotune(self._h, int(reps)))
         lib = load()
-        return {f"{'to_grid' if d == 0 else 'to_coeff'}_{k}": lib.infft_autotune_rows(self._h, d, k)
-                for d in (0, 1) for k in (0, 1)}
+        out = {f"{'to_grid' if d == 0 else 'to_coeff'}_{k}": lib.infft_autotune_rows(self._h, d, k)
+               for d in (0, 1) for k in (0, 1)}
+        out["spread_rhs"] = lib.infft_autotune_rhs_chunk(self._h)
+        return out
 
     def device_bytes(self) -> int:
         return int(load().nfft_plan_device_bytes(self._h))

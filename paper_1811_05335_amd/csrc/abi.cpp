@@ -1031,7 +1031,8 @@ int batch_build(infft_plan_s* P) {
     if ((rc = upload(P, &B.node_jobs, nj)) || (rc = upload(P, &B.node_map, nmap)) ||
         (rc = upload(P, &B.cell_map, cmap)) || (rc = upload(P, &B.t1_map, tmap)))
         return rc;
-    // ---- solver tiers: thread per problem, then 16- and 32-lane groups over each problem's lists
+    // ---- solver tiers: thread per problem, then the 16-, 32- and 64-member tiers over each
+    // problem's lists
     std::vector<SolveJob> sj(5 * (size_t)np);
     for (int i = 0; i < np; ++i) {
         infft_plan_s* sub = B.subs[i];
@@ -1823,15 +1824,15 @@ static int precompute_impl(infft_plan p, double2* B64, float2* B32, bool keep_re
     const int* last_list;
     const int* last_count;
     if (g.d == 1) {
-        // one thread per problem for small I(l); the rest in groups of 16 lanes, then a wavefront
-        // per problem up to 64 members, then the blocked pass.  (No 32-lane tier: each tier is a
-        // launch on the critical path even when its list is empty, and problems of 17-32 members
-        // are rare at the densities this path is built for; the wavefront tier takes them.)
+        // one thread per problem for small I(l); the rest in groups of 16 lanes with one row per
+        // lane, then the wide tier (up to 32 members on 16 lanes with two rows each, up to 64 on a
+        // wavefront), then the blocked pass.  (No separate 32-member launch: each tier is a launch
+        // on the critical path even when its list is empty.)
         a.in_list = nullptr;
         a.in_count = nullptr;
         a.out_list = listA;
         a.out_count = p->lcount;
-        // counters 1 (read by the last call's 64-lane tier) and 2 (by its large-problem pass)
+        // counters 1 (read by the last call's wide tier) and 2 (by its large-problem pass)
         a.zero0 = p->lcount + 1;
         a.zero1 = p->lcount + 2;
         {
@@ -1847,8 +1848,8 @@ static int precompute_impl(infft_plan p, double2* B64, float2* B32, bool keep_re
         a.out_count = p->lcount + 1;
         a.stat_off += launch_solve_tier(g, p->nd, kt, a, 16, p->stream);
         LAUNCH_CHECK();
-        // 1-D: a wavefront per problem up to 64 members (also under capture); it clears counter 0,
-        // read by the 16-lane tier that has finished, for the next call's thread tier
+        // 1-D: the wide tier, up to 64 members (also under capture); it clears counter 0, read by
+        // the 16-lane tier that has finished, for the next call's thread tier
         a.in_list = listB;
         a.in_count = p->lcount + 1;
         a.out_list = listA;

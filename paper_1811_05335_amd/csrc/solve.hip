@@ -11,12 +11,15 @@
 // tau_j = (l - l0_j) mod M_sigma and z_j = tau_j - u_j in [-m, m], K is needed at z_j and Q at
 // z_j - z_i in [-2m, 2m]; both come from the Taylor tables built at plan time.
 //
-// Layout of the work: a group of NL lanes (NL = 16 or 32) owns one grid index at a time.  The
-// members of I(l) are gathered from the (2m+1)^d grid cells whose nodes reach l (the node CSR);
-// lane i owns member i and row i of the Hermitian system.  The Cholesky factorisation, forward
-// and backward substitution run across the group with register rows; each step's column or
-// partial sums pass through a small per-thread LDS slot, so all reads of a step issue together.
-// Problems with more than NL members are passed on to the next, wider group size.
+// Layout of the work.  1-D: a thread per grid index up to 13 members (the band of a workgroup's
+// node range in LDS); then groups of 16 lanes, one or two rows of the real system per lane in
+// registers, reduced by Gaussian elimination with DPP broadcasts (up to 16 or 32 members); then a
+// wavefront with the matrix in LDS (up to 64).  2-D: a group of NL lanes (NL = 16 or 32) owns one
+// grid index at a time; the members of I(l) are gathered from the (2m+1)^2 grid cells whose nodes
+// reach l (the node CSR); lane i owns member i and row i of the Hermitian system, and the Cholesky
+// factorisation, forward and backward substitution pass each step's column or partial sums
+// through a small per-thread LDS slot, so all reads of a step issue together.  Problems beyond a
+// tier's size are passed on to the next tier.
 #include "internal.hpp"
 
 #include <limits.h>

@@ -665,7 +665,7 @@ def main():
     a = parse()
     ovl = "none" if a.no_overlap else a.overlap
     if a.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU (the path has no multi-GPU mode); --gpus must be 1"}))
         sys.exit(2)
     if a.copy_calibration_mb:
         import torch

@@ -135,28 +135,48 @@ template <typename C> struct Dft<C, 7> : DftOdd<C, 7> {};
 
 // ------------------------------------------------------------------ index division
 
-// Division by a workgroup-uniform divisor: a shift when it is a power of two (every length of a
-// power-of-two grid, and the autotuned row counts), the integer division otherwise.  The test is
-// uniform, so only one path runs.
-struct UDiv {
-    uint32_t d;
+// Division by a workgroup-uniform divisor d: a shift when d is a power of two (every length of a
+// power-of-two grid, and the autotuned row counts).  Otherwise, with MD, the high half of x m with
+// m = floor((2^32 - 1) / d) + 1, which is floor(x / d) whenever x d < 2^32 (with m d = 2^32 + e,
+// 0 < e < d: x m / 2^32 = x / d + x e / (d 2^32), and x e < 2^32 keeps the fraction below 1), and
+// the integer division where a dividend up to xmax could break that bound; without MD the integer
+// division.  The tests are uniform, so only one path runs; m is kept in a scalar register.  MD
+// serves the batched passes, whose lengths are rarely powers of two; the single-plan passes keep
+// the plain form, whose registers stay within four waves per SIMD.
+template <bool MD> struct UDiv {
+    uint32_t d, m;
     int sh;
-    bool p2;
-    __device__ explicit UDiv(uint32_t dv) : d(dv), sh(__builtin_ctz(dv)), p2((dv & (dv - 1)) == 0) {}
-    __device__ uint32_t div(uint32_t x) const { return p2 ? (x >> sh) : x / d; }
-    __device__ uint32_t mod(uint32_t x) const { return p2 ? (x & (d - 1)) : x - (x / d) * d; }
+    bool p2, mul;
+    __device__ UDiv(uint32_t dv, uint32_t xmax) : d(dv), sh(__builtin_ctz(dv)), p2((dv & (dv - 1)) == 0) {
+        if (MD) {
+            m = (uint32_t)__builtin_amdgcn_readfirstlane((int)(0xFFFFFFFFu / dv + 1u));
+            mul = (uint64_t)xmax * dv < (1ull << 32);
+        } else {
+            m = 0;
+            mul = false;
+        }
+    }
+    __device__ uint32_t div(uint32_t x) const {
+        if (MD) return p2 ? (x >> sh) : mul ? __umulhi(x, m) : x / d;
+        return p2 ? (x >> sh) : x / d;
+    }
+    __device__ uint32_t mod(uint32_t x) const {
+        if (MD) return x - div(x) * d;
+        return p2 ? (x & (d - 1)) : x - (x / d) * d;
+    }
 };
 
 // ------------------------------------------------------------------ one Stockham stage in LDS
 
-template <typename R, int RADIX, int E>
+template <typename R, int RADIX, int E, bool MD>
 __device__ inline void stage(cx<R>* lds, int ld, int rows, int n, int Ns, int sign,
                              const cx<R>* __restrict__ tw) {
     using C = cx<R>;
     constexpr int CM = (E + RADIX - 1) / RADIX;
     const int nbr = n / RADIX;
     const int nb = rows * nbr;
-    const UDiv dnbr((uint32_t)nbr), dNs((uint32_t)Ns);
+    // dividends: b < nb and j < nbr
+    const UDiv<MD> dnbr((uint32_t)nbr, (uint32_t)nb), dNs((uint32_t)Ns, (uint32_t)nbr);
     C v[CM][RADIX];
 #pragma unroll
     for (int ci = 0; ci < CM; ++ci) {
@@ -198,18 +218,18 @@ __device__ inline void stage(cx<R>* lds, int ld, int rows, int n, int Ns, int si
     __syncthreads();
 }
 
-template <typename R, int E>
+template <typename R, int E, bool MD>
 __device__ inline void lds_fft(cx<R>* lds, int ld, int rows, const FftPass& P, const cx<R>* tw) {
     int Ns = 1;
     for (int s = 0; s < P.nst; ++s) {
         const int r = P.rad[s];
         switch (r) {
-            case 2: stage<R, 2, E>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
-            case 3: stage<R, 3, E>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
-            case 4: stage<R, 4, E>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
-            case 5: stage<R, 5, E>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
-            case 7: stage<R, 7, E>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
-            default: stage<R, 8, E>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
+            case 2: stage<R, 2, E, MD>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
+            case 3: stage<R, 3, E, MD>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
+            case 4: stage<R, 4, E, MD>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
+            case 5: stage<R, 5, E, MD>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
+            case 7: stage<R, 7, E, MD>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
+            default: stage<R, 8, E, MD>(lds, ld, rows, P.n, Ns, P.sign, tw); break;
         }
         Ns *= r;
     }
@@ -329,7 +349,7 @@ __device__ inline void store_elem(const FftIO& io, const FftPass& P, const Geo& 
 // data per workgroup (a few elements per thread), so its time is memory latency: every global
 // load of the workgroup (the elements, the stage twiddle table, the store operands) is issued
 // before the first is used, and the pass waits on memory once instead of once per element.
-template <typename R, int E, int LD, int ST, int D>
+template <typename R, int E, int LD, int ST, int D, bool MD>
 __device__ inline void fft_block(const FftPass& P, int64_t nseq, const FftIO& io, const Geo& g, int64_t blk) {
     using C = cx<R>;
     extern __shared__ char smem_raw[];
@@ -339,7 +359,9 @@ __device__ inline void fft_block(const FftPass& P, int64_t nseq, const FftIO& io
     if (seq0 >= nseq) return;
     const int rows = (int)min((int64_t)P.rows, nseq - seq0);
     const int tot = rows * P.n;   // at most FFT_THREADS * E
-    const UDiv drows((uint32_t)rows), dn((uint32_t)P.n), dnq((uint32_t)P.nq);
+    // dividends: element indices below tot, sequence indices below nseq
+    const UDiv<MD> drows((uint32_t)rows, (uint32_t)tot), dn((uint32_t)P.n, (uint32_t)tot),
+        dnq((uint32_t)P.nq, (uint32_t)min(nseq, (int64_t)0xFFFFFFFF));
     // the stage twiddle table follows the data in LDS
     C* s_tw = lds + (int64_t)P.rows * ld;
     const C* gtw = (const C*)P.tw;
@@ -377,7 +399,7 @@ __device__ inline void fft_block(const FftPass& P, int64_t nseq, const FftIO& io
         lds[slot[it]] = dat[it];
     }
     __syncthreads();
-    lds_fft<R, E>(lds, ld, rows, P, s_tw);
+    lds_fft<R, E, MD>(lds, ld, rows, P, s_tw);
 #pragma unroll
     for (int it = 0; it < E; ++it) {
         const int L = threadIdx.x + it * FFT_THREADS;
@@ -396,20 +418,20 @@ __device__ inline void fft_block(const FftPass& P, int64_t nseq, const FftIO& io
 // The body is instantiated for the elements per thread the pass needs (a power of two up to the
 // capacity E), so no thread loads more than one element past the end; the choice and the
 // dimension are uniform branches at the kernel's entry.
-template <typename R, int E, int LD, int ST, int D>
+template <typename R, int E, int LD, int ST, int D, bool MD>
 __device__ inline void fft_block_e(const FftPass& P, int64_t nseq, const FftIO& io, const Geo& g, int64_t blk) {
     const int ept = (P.rows * P.n + FFT_THREADS - 1) / FFT_THREADS;
-    if (ept <= 1) fft_block<R, 1, LD, ST, D>(P, nseq, io, g, blk);
-    else if (ept <= 2) fft_block<R, 2, LD, ST, D>(P, nseq, io, g, blk);
-    else if (ept <= 4) fft_block<R, 4, LD, ST, D>(P, nseq, io, g, blk);
-    else if (E <= 8 || ept <= 8) fft_block<R, (E < 8 ? E : 8), LD, ST, D>(P, nseq, io, g, blk);
-    else fft_block<R, E, LD, ST, D>(P, nseq, io, g, blk);
+    if (ept <= 1) fft_block<R, 1, LD, ST, D, MD>(P, nseq, io, g, blk);
+    else if (ept <= 2) fft_block<R, 2, LD, ST, D, MD>(P, nseq, io, g, blk);
+    else if (ept <= 4) fft_block<R, 4, LD, ST, D, MD>(P, nseq, io, g, blk);
+    else if (E <= 8 || ept <= 8) fft_block<R, (E < 8 ? E : 8), LD, ST, D, MD>(P, nseq, io, g, blk);
+    else fft_block<R, E, LD, ST, D, MD>(P, nseq, io, g, blk);
 }
 
 template <typename R, int E, int LD, int ST>
 __device__ inline void fft_block_d(const FftPass& P, int64_t nseq, const FftIO& io, const Geo& g, int64_t blk) {
-    if (g.d == 1) fft_block_e<R, E, LD, ST, 1>(P, nseq, io, g, blk);
-    else fft_block_e<R, E, LD, ST, 2>(P, nseq, io, g, blk);
+    if (g.d == 1) fft_block_e<R, E, LD, ST, 1, false>(P, nseq, io, g, blk);
+    else fft_block_e<R, E, LD, ST, 2, false>(P, nseq, io, g, blk);
 }
 
 template <typename R, int E, int LD, int ST>
@@ -432,7 +454,7 @@ __global__ void __launch_bounds__(FFT_THREADS) k_fft_batched(const FftJob* __res
     FftIO io = J.io;
     if (J.user_in) io.in = (const cx<R>*)user_in + (int64_t)nrhs * J.user_off;
     if (J.user_out) io.out = (cx<R>*)user_out + (int64_t)nrhs * J.user_off;
-    fft_block_e<R, E, LD, ST, 1>(J.pass, J.pass.nq * nrhs, io, J.g, b.y);   // batches are 1-D
+    fft_block_e<R, E, LD, ST, 1, true>(J.pass, J.pass.nq * nrhs, io, J.g, b.y);   // batches are 1-D
 }
 
 template <typename R>

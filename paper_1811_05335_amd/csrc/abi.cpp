@@ -902,6 +902,7 @@ int solve_large(infft_plan_s* p, const KTabDev& kt, const int* list, const int* 
 
 struct BatchLaunch {
     int ld = 0, st = 0;
+    bool small = false;   // FP32 passes in the small-capacity kernel
     int64_t map_off = 0;
     int nblocks = 0;
     size_t shm = 0;
@@ -953,11 +954,14 @@ int batch_build(infft_plan_s* P) {
     BatchState& B = *P->batch;
     const int np = (int)B.subs.size();
     const size_t cs = P->csize();
-    // ---- FFT passes, grouped by (step index, load mode, store mode)
+    // ---- FFT passes, grouped by (step index, load mode, store mode, kernel).  FP32 passes of
+    // sub-transforms up to the small kernel's capacity go to that kernel, with at most that many
+    // elements per workgroup (the rows do not change the arithmetic).
     std::vector<FftJob> jobs, jobs_inv;
     std::vector<int2> map;
+    const int small_cap = fft_batched_small_capacity();
     for (int dir = 0; dir < 2; ++dir) {
-        std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+        std::map<std::tuple<int, int, int, int>, std::vector<int>> groups;
         for (int i = 0; i < np; ++i) {
             infft_plan_s* sub = B.subs[i];
             std::vector<FftStep> tg, tc;
@@ -979,7 +983,9 @@ int batch_build(infft_plan_s* P) {
                 J.user_in = st.in_buf == 0;
                 J.user_out = st.out_buf == 0;
                 J.user_off = B.Poff[i];
-                groups[std::make_tuple((int)k, st.ld, st.st)].push_back((int)jobs.size());
+                const bool small = f32 && J.pass.n <= small_cap;
+                if (small) J.pass.rows = std::max(1, std::min(J.pass.rows, small_cap / J.pass.n));
+                groups[std::make_tuple((int)k, st.ld, st.st, (int)small)].push_back((int)jobs.size());
                 jobs.push_back(J);
                 J.io.D0 = f32 ? (const void*)sub->Di32[0] : (const void*)sub->Di64[0];
                 jobs_inv.push_back(J);
@@ -991,6 +997,7 @@ int batch_build(infft_plan_s* P) {
             BatchLaunch L;
             L.ld = std::get<1>(kv.first);
             L.st = std::get<2>(kv.first);
+            L.small = std::get<3>(kv.first) != 0;
             L.map_off = (int64_t)map.size();
             for (int ji : kv.second) {
                 const FftPass& ps = jobs[ji].pass;
@@ -1090,10 +1097,10 @@ int run_fft_batched(infft_plan_s* P, const std::vector<BatchLaunch>& launches, c
         ProfScope ps(P, INFFT_K_FFT);
         if (P->prec == INFFT_F32)
             launch_fft_batched<float>(jobs, B.fft_map + L.map_off, L.nblocks, L.shm, L.ld, L.st, user_in,
-                                      user_out, nrhs, P->stream);
+                                      user_out, nrhs, L.small, P->stream);
         else
             launch_fft_batched<double>(jobs, B.fft_map + L.map_off, L.nblocks, L.shm, L.ld, L.st, user_in,
-                                       user_out, nrhs, P->stream);
+                                       user_out, nrhs, false, P->stream);
         LAUNCH_CHECK();
     }
     return INFFT_OK;

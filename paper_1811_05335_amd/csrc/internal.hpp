@@ -449,10 +449,11 @@ void launch_taylor_table_sym(int M, int Ms, const double* D, int power, int qmax
 template <typename R>
 void launch_fft_pass(const FftPass& p, const FftIO& io, const Geo& g, int ld, int st, hipStream_t s);
 int fft_capacity(bool fp64);   // elements of one workgroup's LDS transform buffer
+int fft_batched_small_capacity();   // elements per workgroup of the small batched FP32 pass kernel
 size_t fft_lds_bytes(const FftPass& p, size_t csize);   // LDS of one pass's workgroup (data + twiddles)
 template <typename R>
 void launch_fft_batched(const FftJob* jobs, const int2* bmap, int nblocks, size_t shm, int ld, int st,
-                        const void* user_in, void* user_out, int nrhs, hipStream_t s);
+                        const void* user_in, void* user_out, int nrhs, bool small, hipStream_t s);
 
 // spread.hip
 template <typename R>

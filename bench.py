@@ -43,6 +43,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=48, help="grid indices of the sampled oracle B solve")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph replay")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the plans' default FFT workgroup shapes and spreading chunk (profiling: the "
+                         "autotuner's timings are perturbed under a profiler)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run every call on the main stream (same as --overlap none)")
     ap.add_argument("--overlap", choices=("none", "pre", "tail", "full"), default="none",
@@ -93,7 +96,7 @@ class Stage:
         return {k: float(np.mean([s.elapsed_time(e) for s, e in v])) for k, v in self.pairs.items()}
 
 
-def gpu_run(precision, x, fh, gf, steps, warmup, rho, m, sigma, M, use_graph=True, overlap="full"):
+def gpu_run(precision, x, fh, gf, steps, warmup, rho, m, sigma, M, use_graph=True, overlap="full", autotune=True):
     import torch
     from paper_1811_05335_amd import NfftPlan
 
@@ -103,7 +106,7 @@ def gpu_run(precision, x, fh, gf, steps, warmup, rho, m, sigma, M, use_graph=Tru
     gfd = torch.from_numpy(gf).to(ct).cuda()
     R = fh.shape[0]
     P = NfftPlan(M, xd, sigma=sigma, m=m, precision=precision, rho=rho, max_rhs=R, work_slots=3)
-    tuned = P.autotune()   # FFT workgroup shapes, measured once per plan like an FFT plan
+    tuned = P.autotune() if autotune else {}   # FFT workgroup shapes, measured once per plan like an FFT plan
 
     side, s_adj, s_grad = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
 
@@ -693,7 +696,7 @@ def main():
     gf32 = W.round_to(gf, "f32")
     log(f"[bench] workload: {WORKLOAD_NAME}, rhs={R}; FP32 run")
     r32 = gpu_run("f32", x, fh32, gf32, a.steps, a.warmup, rho, m, sigma, M, use_graph=not a.eager,
-                  overlap=ovl)
+                  overlap=ovl, autotune=a.autotune)
     ms32 = r32["ms_graph"] if r32["ms_graph"] else r32["ms_eager"]
     br32, st32, out32, rows32 = r32["breakdown"], r32["status"], r32["outs"], r32["rows"]
     log(f"[bench] FP32 graph {r32['ms_graph']} ms/step, eager {r32['ms_eager']:.3f} ms/step {br32}")
@@ -701,7 +704,7 @@ def main():
     if a.fp64:
         log("[bench] FP64 run")
         r64 = gpu_run("f64", x, fh, gf, a.steps, a.warmup, rho, m, sigma, M, use_graph=not a.eager,
-                      overlap=ovl)
+                      overlap=ovl, autotune=a.autotune)
         ms64 = r64["ms_graph"] if r64["ms_graph"] else r64["ms_eager"]
         out64, rows64 = r64["outs"], r64["rows"]
         log(f"[bench] FP64 graph {r64['ms_graph']} ms/step, eager {r64['ms_eager']:.3f} ms/step {r64['breakdown']}")
